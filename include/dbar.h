@@ -1,0 +1,200 @@
+/*
+ * dbar.h -- C ABI of the MI355X (gfx950) solver for complex-geometrical-optics (CGO) solutions of D-bar problems,
+ * after Klein & McLaughlin, "Spectral approach to D-bar problems" (arXiv 1508.02363).
+ *
+ * Problem (Section 1, equations eq:038 and eq:039): for a Schwartz potential Q on R^2 and k in C, find m with
+ *     dbar m = (1/2) e^{conj(kz) - kz} Q (conj(m) + 1),   m -> 0 as |z| -> infinity,
+ * written in Fourier space for S(xi) = xi m^(xi) (equations eq:042 and MainEQa):
+ *     A(S) := S + i F( q_k conj(h(S)) ) = -i F(q_k) =: b,      q_k = Q e^{conj(kz) - kz},
+ * where h(S) = F^{-1}(S/xi) is evaluated with the regularisation of Section 4.2 (equations Sreg, Gchoice, fourreeg4,
+ * fourreg5, fourreg5a, S0Taylor) and A is solved matrix-free by GMRES (Section 4.1) on the real vector
+ * [Re S, Im S] (A is real-linear, not complex-linear).  At convergence m = h(S) and m^(1) = i S(0) (equation m1def).
+ *
+ * Grids (Section 4.1, equations 'domain' and 'xidomain'): N x N points, x_j = y_j = L(-pi + 2 pi j / N), and wave
+ * numbers xi = m / L with m in [-N/2+1, N/2].  The transform F is the continuous one of Section 1,
+ * F(f)(xi) = (1/2pi) int f e^{-i xi.x}, approximated on the grid by (dx^2/2pi) (-1)^(m1+m2) FFT2 (dx = 2 pi L / N).
+ *
+ * Array conventions (all complex arrays interleaved re, im, complex128 unless stated):
+ *   x-space arrays (Q, m, h): row-major a[iy * N + ix] at (x_ix, y_iy).
+ *   xi-space arrays (S):      row-major A[p2 * N + p1] in FFT order: index p means m = p (p <= N/2) or m = p - N,
+ *                             xi1 = m(p1)/L, xi2 = m(p2)/L.  Values approximate the continuous S(xi).
+ *   Per-k outputs are stacked: entry j of an nk-batch starts at element j * N * N.
+ *   k values: interleaved (re, im) pairs, nk of them.
+ *
+ * Ownership: the caller owns every buffer it passes; the library never keeps a caller pointer after a call returns
+ * (the serving queue copies its inputs).  The library owns its device workspace (kept between calls for reuse and
+ * released by dbar_release()).  Device pointers must be device memory on the current HIP device.
+ *
+ * Errors: every entry point returns DBAR_OK (0) or a negative code; dbar_last_error() gives a message (per thread).
+ * Calls are not re-entrant on one device from several threads (the workspace is shared); serialise them.
+ */
+#ifndef DBAR_H
+#define DBAR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DBAR_OK 0
+#define DBAR_EINVAL (-1)   /* bad argument: N not a power of two in [8, 4096], L <= 0, M outside [0, 15], NaN/Inf
+                              in Q or k, nk < 1, tol <= 0, NULL where a buffer is required */
+#define DBAR_ENOMEM (-2)   /* device memory (or the serving HBM budget) exhausted */
+#define DBAR_ENOCONV (-3)  /* GMRES stopped at max_iter before tol for at least one k; outputs are still written and
+                              info[j].status tells which */
+#define DBAR_EDEVICE (-4)  /* HIP runtime error (no device, launch failure, ...) */
+#define DBAR_EAGAIN (-5)   /* serving: result not ready yet */
+#define DBAR_ENOTFOUND (-6)/* serving: unknown ticket */
+
+/* Discretisation (Section 4.1 and equation Gchoice): N x N grid on L[-pi, pi)^2, Taylor order M (n = 0..M). */
+typedef struct {
+  int32_t n;   /* grid points per axis, power of two, 8 <= n <= 4096 */
+  int32_t M;   /* Taylor terms n = 0..M of G (the paper uses M = 11); 0 <= M <= 15 */
+  double L;    /* domain scale: x, y in L[-pi, pi) */
+} dbar_grid;
+
+enum {
+  DBAR_FP64 = 0,  /* everything in FP64 */
+  DBAR_MIXED = 1, /* FP32 transforms and Krylov basis inside, FP64 residuals, moments, phases, Hessenberg (solve) */
+  DBAR_FP32 = 2   /* FP32 transforms (dbar_apply / dbar_transform / dbar_dbar_inverse only) */
+};
+enum {
+  DBAR_MODE_BATCHED = 0, /* many k per launch, device-side convergence flags, HIP graphs */
+  DBAR_MODE_PLAIN = 1    /* one k per launch, the host reads the residual after every iteration */
+};
+
+typedef struct {
+  int32_t restart;     /* Krylov vectors per cycle; default 40 (FP64), 20 (inner FP32 solves); max 64 */
+  int32_t max_iter;    /* cap on GMRES iterations per k, all cycles together; default 1000 */
+  int32_t precision;   /* DBAR_FP64 or DBAR_MIXED */
+  int32_t mode;        /* DBAR_MODE_BATCHED or DBAR_MODE_PLAIN */
+  int32_t batch;       /* k values per launch in batched mode; 0 = choose from free device memory */
+  int32_t use_graph;   /* batched mode: replay Krylov iterations from captured HIP graphs (1 = on) */
+  int32_t reorth;      /* Gram-Schmidt passes: 1 = classical, 2 = classical twice (default) */
+  int32_t check_every; /* batched mode: host reads convergence flags every this many iterations (default 4) */
+  double inner_tol;    /* DBAR_MIXED: residual reduction asked of each FP32 inner solve (default 1e-5) */
+} dbar_opts;
+
+/* Per-k result. */
+typedef struct {
+  int32_t status;       /* DBAR_OK or DBAR_ENOCONV */
+  int32_t iters;        /* GMRES iterations (operator applications inside Krylov cycles) */
+  int32_t outer;        /* FP64 residual evaluations (refinement steps in DBAR_MIXED; restarts + 1 in FP64) */
+  int32_t reserved;
+  double rel_residual;  /* ||b - A(S)||_2 / ||b||_2, recomputed in FP64 with the FP64 operator at the end */
+  double m1_re, m1_im;  /* m^(1) = i S(0), the 1/z coefficient of m (equation m1def) */
+} dbar_info;
+
+/* Fill *opts with the defaults listed above. */
+void dbar_default_opts(dbar_opts* opts);
+
+/*
+ * Solve A(S) = b for each of nk values of k (host buffers).  Q: N*N complex128 (x-space).  k: nk pairs.
+ * tol: stop when ||b - A(S)|| <= tol ||b|| (FP64 residual).  opts may be NULL (defaults).
+ * S_out, m_out: nk*N*N complex128 each, or NULL if not wanted.  info: nk entries, or NULL.
+ * Q = 0 gives S = 0 and m = 0 without iterating.  Returns DBAR_OK, DBAR_ENOCONV or an error.
+ */
+int dbar_solve(const dbar_grid* grid, const double* Q, int64_t nk, const double* k, double tol, const dbar_opts* opts,
+               double* S_out, double* m_out, dbar_info* info);
+
+/*
+ * As dbar_solve, with Q, S_out and m_out in device memory (complex128, same layouts) and all work queued on
+ * `stream` (a hipStream_t, NULL = the default stream).  k and info stay host memory.  Returns after the results are
+ * complete on the device.
+ */
+int dbar_solve_device(const dbar_grid* grid, const void* Q_dev, int64_t nk, const double* k, double tol,
+                      const dbar_opts* opts, void* S_dev, void* m_dev, dbar_info* info, void* stream);
+
+/*
+ * One application of the operator, A(S) = S + i F(q_k conj(h(S))) (Section 4, algorithm step 4, with Q replaced by
+ * q_k = Q e^{conj(kz)-kz}, Section 5.1), on host buffers: Q and S_in N*N complex128, k one (re, im) pair,
+ * AS_out N*N complex128.  precision: DBAR_FP64 or DBAR_FP32 (inputs rounded to FP32, moments and the closed-form
+ * tail in FP64, result widened to FP64).
+ */
+int dbar_apply(const dbar_grid* grid, const double* Q, const double* k, const double* S_in, double* AS_out,
+               int32_t precision);
+
+/*
+ * The grid transform consistent with the continuous F of Section 1: inverse = 0 gives
+ * out = (dx^2/2pi) (-1)^(m1+m2) FFT2(in) (x-space in, xi-space out); inverse = 1 gives
+ * out = (1/(2 pi L^2)) sum_m (-1)^(m1+m2) in_m e^{+2 pi i m.j/N} (xi-space in, x-space out).  Host buffers,
+ * N*N complex128 each; precision DBAR_FP64 or DBAR_FP32.
+ */
+int dbar_transform(const dbar_grid* grid, int32_t inverse, const double* in, double* out, int32_t precision);
+
+/*
+ * The regularised inverse h(S) = F^{-1}(S/xi) of Section 4.2 (equations Sreg, Gchoice, fourreeg4, S0Taylor):
+ * h = F^{-1}((S - G)/xi) + sum_n c_n W_n with the value at xi = 0 taken as the limit dS/dxi(0).  Since
+ * F(dbar u) = (i/2) xi F(u), this is (i/2) dbar^{-1} F^{-1}(S).  Host buffers, N*N complex128 each.
+ */
+int dbar_dbar_inverse(const dbar_grid* grid, const double* S_in, double* h_out, int32_t precision);
+
+/* ------------------------------------------------------------------------------------------------------------
+ * Serving: a request queue with continuous batching.  Requests (one k, one Q, one grid each) are admitted into
+ * device-resident slots when the HBM budget allows, advance together in per-grid-size batches of Krylov
+ * iterations, and leave as soon as they converge; new requests take the freed slots at the next iteration
+ * boundary.  A worker thread drives the device.  All solves use DBAR_MIXED precision to the requested tolerance
+ * (FP64 residual), or DBAR_FP64 if asked.
+ * ------------------------------------------------------------------------------------------------------------ */
+typedef struct dbar_session dbar_session;
+
+typedef struct {
+  size_t hbm_budget_bytes;  /* admission limit on the sum of request footprints (0 = 80% of free device memory) */
+  int32_t max_slots;        /* max requests in flight per grid size (default 64) */
+  int32_t precision;        /* DBAR_MIXED (default) or DBAR_FP64 */
+  int32_t restart;          /* inner Krylov vectors (default 20) */
+  int32_t reserved;
+} dbar_session_opts;
+
+typedef struct {
+  uint64_t submitted, completed, rejected;
+  uint64_t in_flight, queued;
+  size_t bytes_in_use;
+} dbar_session_stats;
+
+/* Create a session (opts may be NULL). */
+int dbar_session_create(const dbar_session_opts* opts, dbar_session** out);
+/* Queue one solve.  Q: host N*N complex128 (copied before return), k one (re, im) pair.  *ticket identifies it. */
+int dbar_submit(dbar_session* s, const dbar_grid* grid, const double* Q, const double* k, double tol,
+                uint64_t* ticket);
+/* Fetch a finished solve: S_out / m_out host N*N complex128 (or NULL), info, and latency_s = seconds from
+ * dbar_submit to the result being on the host (or NULL).  DBAR_EAGAIN while it runs.  A ticket can be fetched
+ * once; afterwards it is unknown (DBAR_ENOTFOUND).  Returns DBAR_OK, DBAR_ENOCONV (max_iter reached) or an error. */
+int dbar_poll(dbar_session* s, uint64_t ticket, double* S_out, double* m_out, dbar_info* info, double* latency_s);
+/* As dbar_poll but blocks until the result is ready. */
+int dbar_wait(dbar_session* s, uint64_t ticket, double* S_out, double* m_out, dbar_info* info, double* latency_s);
+int dbar_session_get_stats(dbar_session* s, dbar_session_stats* st);
+/* Bytes of device memory a request of this grid would hold while in flight. */
+size_t dbar_request_footprint(const dbar_grid* grid, int32_t precision, int32_t restart);
+/* Stop the worker (pending requests are abandoned) and free everything. */
+void dbar_session_destroy(dbar_session* s);
+
+/* ------------------------------------------------------------------------------------------------------------
+ * Measurement.  The paper puts the cost of the method in the 2D FFTs of the GMRES iterations (remark after the
+ * Section 4 algorithm: three 2D transforms per iteration).  These calls time every kernel launch of the library with
+ * HIP events on the stream it is launched on, grouped by stage, and add up the algorithmic HBM bytes of each launch
+ * (every array the stage must read or write counted once, for the batch entries active in that launch).
+ * ------------------------------------------------------------------------------------------------------------ */
+/* on = 1: clear and start recording; on = 0: stop (waits for the device and folds the records into the totals). */
+int dbar_timer_enable(int32_t on);
+/* Number of stage slots (valid stage indices are 0 .. n-1; unused ones report zero launches). */
+int dbar_timer_num_stages(void);
+/* Totals of one stage: its name (NUL-terminated, truncated to name_len), summed launch time in milliseconds,
+ * number of launches and algorithmic bytes.  Any output pointer may be NULL. */
+int dbar_timer_stage(int32_t stage, char* name, int32_t name_len, double* total_ms, int64_t* launches, double* bytes);
+
+/* ------------------------------------------------------------------------------------------------------------ */
+/* Message of the last error on this thread ("" if none). */
+const char* dbar_last_error(void);
+/* Free the cached device workspace. */
+void dbar_release(void);
+/* Library version, e.g. 100 for 0.1.0. */
+int dbar_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DBAR_H */

@@ -1,0 +1,122 @@
+// Host-side launch interface of the D-bar kernels (no kernel code here).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "dbar_common.h"
+
+namespace dbar {
+
+// Which fused line-transform stage to run.  "rows" = lines along x / xi1 (contiguous), "cols" = along y / xi2.
+enum class LineOp : int {
+  RowsInvScaled = 0,  // out = IFFT_rows(phase * ci * in)                          (first pass of F^-1)
+  ColsInvMoments = 1, // IFFT_cols(in), then FP64 moments sum z^n s, sum conj(z) s  -> part  (second pass, no store)
+  RowsInvRegular = 2, // out = IFFT_rows(phase * ci * R),  R = (S - G)/xi, R(0) = (-i/2) dt   (S = in)
+  ColsInvTailFwd = 3, // r = IFFT_cols(in); h = r + sum d_n omega_n; [hout = h]; u = q_k conj(h); out = FFT_cols(u)
+  ColsInvTail = 4,    // r = IFFT_cols(in); hout = r + sum d_n omega_n                 (h only)
+  RowsFwdEpilogue = 5,// X = FFT_rows(in); out = alpha S + beta cf phase X + gamma Y; optional |out|^2 -> part
+  ColsFwdPotential = 6,// out = FFT_cols(Q e_k)                                      (first pass of F(q_k))
+  ColsFwdPlain = 7,   // out = FFT_cols(in)
+  ColsInvPlain = 8,   // out = IFFT_cols(in)
+};
+
+struct LineArgs {
+  int B = 1;                   // batch entries (grid.y)
+  const int* act = nullptr;    // per-entry active flag (nullptr = all active)
+  const void* in = nullptr;    size_t in_bs = 0;   // per-entry strides in complex elements
+  void* out = nullptr;         size_t out_bs = 0;
+  const void* S = nullptr;     size_t S_bs = 0;    // epilogue vector (alpha term)
+  const void* Y = nullptr;     size_t Y_bs = 0;    // epilogue vector (gamma term)
+  const void* Q = nullptr;     size_t Q_bs = 0;    // potential, same precision as the transform; stride 0 = shared
+  const c64* ex = nullptr;     const c64* ey = nullptr;  // [b][N] tables e^{-2i k2 x_j}, e^{-2i k1 y_j}
+  const c64* coefG = nullptr;  // [b][kNMom]: c_0..c_M, slot kMaxM+1 = R(0) = (-i/2) dt
+  const c64* dmom = nullptr;   // [b][kNMom]: d_0..d_M (tail weights)
+  void* hout = nullptr;        size_t hout_bs = 0;
+  double* part = nullptr;      // per-block partial sums [b][tile][nval]
+  const void* tw = nullptr;    // twiddle table exp(-2 pi i j / N), j < N, in the transform's precision
+  double L = 1.0, ci = 1.0, cf = 1.0;
+  int M = 11;
+  double alpha = 0.0, gamma = 0.0;
+  c64 beta{0.0, 0.0};
+  int want_norm = 0;           // RowsFwdEpilogue: accumulate |out|^2 partials
+};
+
+// Number of blocks (tiles) per batch entry used by a line stage; partial buffers are sized from it.
+int line_tiles(int N, bool cols, bool fp64);
+
+template <typename T, int N>
+void launch_lines(LineOp op, const LineArgs& a, hipStream_t s);
+
+template <typename T>
+void launch_lines_any(int N, LineOp op, const LineArgs& a, hipStream_t s);
+
+#define DBAR_FOR_EACH_N(X) X(8) X(16) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096)
+#define DBAR_EXTERN_N(NN)                                                              \
+  extern template void launch_lines<double, NN>(LineOp, const LineArgs&, hipStream_t); \
+  extern template void launch_lines<float, NN>(LineOp, const LineArgs&, hipStream_t);
+DBAR_FOR_EACH_N(DBAR_EXTERN_N)
+#undef DBAR_EXTERN_N
+
+// ------------------------------------------------------------------------------------------------------------
+// Vector (Krylov) kernels on the real 2n view of complex arrays; all accumulation in FP64.
+// ------------------------------------------------------------------------------------------------------------
+constexpr int kVecBlock = 256;
+constexpr int kVecEPT = 4;                          // complex elements per thread per chunk
+constexpr int kVecChunk = kVecBlock * kVecEPT;      // complex elements per block
+
+struct VecArgs {
+  int B = 1;
+  const int* act = nullptr;
+  size_t n = 0;                // complex elements per vector
+  const void* V = nullptr;     size_t V_bs = 0;   // basis: vector i of entry b at V + b*V_bs + i*n
+  int nv = 0;                  // number of basis vectors used
+  void* w = nullptr;           size_t w_bs = 0;   // target vector
+  const double* coef = nullptr; int coef_bs = 0;  // [b][i] coefficients
+  double* part = nullptr;      // [b][value][block] partials
+  int want_self = 0;           // dots: also |w|^2 as value nv; update: |w_new|^2 as value 0
+};
+
+template <typename T> void launch_dots(const VecArgs& a, hipStream_t s);          // part = <V_i, w>
+template <typename T> void launch_update(const VecArgs& a, hipStream_t s);        // w -= sum coef_i V_i
+template <typename TX, typename TV> void launch_axpy_multi(const VecArgs& a, hipStream_t s);  // w += sum coef_i V_i
+template <typename TO, typename TI> void launch_convert(const void* in, size_t in_bs, void* out, size_t out_bs,
+                                                       size_t n, int B, const int* act, double scale, hipStream_t s);
+int vec_blocks(size_t n);
+
+// Deterministic reduction of partial sums: out[b][v] = scale * sum_blk part[b][v][blk]
+void launch_reduce(const double* part, int nval, int nblk, double* out, int B, const int* act, hipStream_t s);
+
+// ------------------------------------------------------------------------------------------------------------
+// Optional measurement: HIP events around every launch, grouped by stage, with the number of active batch entries
+// of each launch logged on the device (so algorithmic bytes are exact without host synchronisation).
+// ------------------------------------------------------------------------------------------------------------
+enum Stage : int {
+  kStageLines = 0,                 // + 2 * LineOp + (float ? 1 : 0)
+  kStageDots = 32,                 // + (float ? 1 : 0)
+  kStageUpdate = 34,
+  kStageAxpy = 36,                 // f64 += f64 / f64 += f32 / f32 += f32: 36, 37, 38
+  kStageReduce = 39,
+  kStageConvert = 40,
+  kStageMoments = 41,
+  kStageControl = 42,
+  kNumStages = 43,
+};
+const char* stage_name(int stage);
+bool timer_on();
+int timer_begin(int stage, double bytes_per_entry, int B, const int* act, hipStream_t s);
+void timer_end(int handle, hipStream_t s);
+
+struct TimerScope {
+  int h = -1;
+  hipStream_t s;
+  TimerScope(int stage, double bytes_per_entry, int B, const int* act, hipStream_t st) : s(st) {
+    if (timer_on()) h = timer_begin(stage, bytes_per_entry, B, act, st);
+  }
+  ~TimerScope() {
+    if (h >= 0) timer_end(h, s);
+  }
+};
+
+}  // namespace dbar

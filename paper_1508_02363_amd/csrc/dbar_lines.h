@@ -1,0 +1,383 @@
+// Fused line-transform kernels of the D-bar operator (included only by the per-N translation units).
+//
+// One application of A(S) = S + i F(q_k conj(h(S))) (paper Section 4, algorithm step 4, with Q -> q_k of Section 5.1)
+// runs as six launches:
+//   RowsInvScaled   F^{-1} S, first pass
+//   ColsInvMoments  F^{-1} S, second pass, fused with the Taylor moments d_n = F(z^n s)(0)   (equation fourreeg4)
+//   (moment reduction: d_n, c_n = (-i/2)^n d_n / n!, R(0) = (-i/2) F(conj(z) s)(0))
+//   RowsInvRegular  R = (S - G)/xi with G of equation Gchoice, first pass of F^{-1} R
+//   ColsInvTailFwd  second pass of F^{-1} R, h = F^{-1} R + sum c_n W_n (equation S0Taylor), u = q_k conj(h),
+//                   first pass of F u  -- all in registers between the two column transforms
+//   RowsFwdEpilogue second pass of F u and A(S) = S + i F(u)
+#pragma once
+
+#include "dbar_fft.h"
+#include "dbar_launch.h"
+
+namespace dbar {
+
+static __constant__ double kInvFact[40] = {
+    1.0, 1.0, 5.0e-1, 1.6666666666666666e-1, 4.1666666666666664e-2, 8.3333333333333332e-3,
+    1.3888888888888889e-3, 1.9841269841269841e-4, 2.4801587301587302e-5, 2.7557319223985893e-6,
+    2.7557319223985888e-7, 2.5052108385441720e-8, 2.0876756987868100e-9, 1.6059043836821613e-10,
+    1.1470745597729725e-11, 7.6471637318198164e-13, 4.7794773323873853e-14, 2.8114572543455206e-15,
+    1.5619206968586225e-16, 8.2206352466243295e-18, 4.1103176233121648e-19, 1.9572941063391263e-20,
+    8.8967913924505741e-22, 3.8681701706306835e-23, 1.6117375710961184e-24, 6.4469502843844736e-26,
+    2.4795962632247972e-27, 9.1836898637955460e-29, 3.2798892370698378e-30, 1.1309962886447717e-31,
+    3.7699876288159054e-33, 1.2161250415535179e-34, 3.8003907548547434e-36, 1.1516335620771951e-37,
+    3.3871575355211620e-39, 9.6775929586318906e-41, 2.6882202662866363e-42, 7.2654601791530714e-44,
+    1.9119632050402819e-45, 4.9024697565135435e-47};
+
+// x_j = L(-pi + 2 pi j / N)
+template <int N>
+DBAR_D double xgrid(int j, double L) {
+  return L * (-kPi + (2.0 * kPi / N) * j);
+}
+
+// sum_{n=0}^{M} d_n omega_n(z),  omega_n = i P(n+1, u) / z^{n+1},  u = |z|^2/4  (c_n W_n = d_n omega_n).
+// u <  M+1: omega_n = i E_n (conj(z)/4)^{n+1} with E_n = e^{-u} sum_k u^k/(n+1+k)!  (equation fourreg5a with the
+//           factor e^{-u}); E_M by its series, E_n = u E_{n+1} + e^{-u}/(n+1)! downwards (positive terms only).
+// u >= M+1: omega_n = i (1 - e^{-u} sum_{k<=n} u^k/k!) / z^{n+1}  (equation fourreg5); no cancellation there.
+DBAR_D c64 tail_sum(double x, double y, const c64* __restrict__ d, int M) {
+  const double u = 0.25 * (x * x + y * y);
+  const double eu = exp(-u);
+  c64 acc{0.0, 0.0};
+  if (u < M + 1) {
+    double term = kInvFact[M + 1], sum = term;
+    for (int k = 1; k < 200; ++k) {
+      term *= u / (M + 1 + k);
+      sum += term;
+      if (term < 1e-17 * sum) break;
+    }
+    double E = eu * sum;
+    const c64 zeta{0.25 * x, -0.25 * y};
+    acc = E * d[M];
+    for (int n = M - 1; n >= 0; --n) {
+      E = u * E + eu * kInvFact[n + 1];
+      acc = E * d[n] + zeta * acc;
+    }
+    acc = zeta * acc;
+  } else {
+    double P[kMaxM + 1];
+    double t = eu, S = eu;
+#pragma unroll
+    for (int n = 0; n <= kMaxM; ++n) {
+      P[n] = 1.0 - S;
+      t *= u / (n + 1);
+      S += t;
+    }
+    const double r2 = x * x + y * y;
+    const c64 w{x / r2, -y / r2};  // 1/z
+#pragma unroll
+    for (int n = kMaxM; n >= 0; --n) {
+      if (n < M) acc = P[n] * d[n] + w * acc;
+      else if (n == M) acc = P[n] * d[n];
+    }
+    acc = w * acc;
+  }
+  return mul_i(acc);
+}
+
+// ------------------------------------------------------------------------------------------------------------
+// Block reduction of per-thread FP64 values into global partials dst[v * stride]
+// ------------------------------------------------------------------------------------------------------------
+template <int NT, int NV>
+DBAR_D void block_reduce_store(const double (&vals)[NV], double* __restrict__ dst, size_t stride, double* scratch) {
+  __syncthreads();  // scratch aliases the transform's LDS
+  if constexpr (NT >= 64) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      double x = vals[v];
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+      if (lane == 0) scratch[wave * NV + v] = x;
+    }
+    __syncthreads();
+    for (int v = threadIdx.x; v < NV; v += NT) {
+      double s = 0.0;
+      for (int w = 0; w < NT / 64; ++w) s += scratch[w * NV + v];
+      dst[v * stride] = s;
+    }
+  } else {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) scratch[threadIdx.x * NV + v] = vals[v];
+    __syncthreads();
+    for (int v = threadIdx.x; v < NV; v += NT) {  // fewer threads than values in tiny blocks
+      double s = 0.0;
+      for (int t = 0; t < NT; ++t) s += scratch[t * NV + v];
+      dst[v * stride] = s;
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------------------------------
+// Tiling
+// ------------------------------------------------------------------------------------------------------------
+template <typename T, int N>
+struct Tiling {
+  using G = LineGeom<N>;
+  static constexpr int cmin(int a, int b) { return a < b ? a : b; }
+  static constexpr int cmax(int a, int b) { return a > b ? a : b; }
+  static constexpr int kLdsBudget = 150 * 1024;
+  static constexpr int fit(int lines) {
+    while (lines > 1 && lines * G::LDS_LINE * (int)sizeof(cx<T>) > kLdsBudget) lines /= 2;
+    return lines;
+  }
+  static constexpr int ROWS = fit(cmin(N, cmax(1, 128 / G::TPL)));
+  static constexpr int COLS = fit(cmin(N, cmax(64 / (int)sizeof(cx<T>), cmax(1, 64 / G::TPL))));
+  // a column tile also needs enough scratch for the block reduction (NT/64 waves x 34 doubles)
+};
+
+// ------------------------------------------------------------------------------------------------------------
+// Operations
+// ------------------------------------------------------------------------------------------------------------
+struct NoAcc {};
+
+template <typename T, int N>
+struct OpBase {
+  LineArgs a;
+  DBAR_D bool active(int b) const { return a.act == nullptr || a.act[b] != 0; }
+  DBAR_D const cx<T>* inp(int b) const { return static_cast<const cx<T>*>(a.in) + (size_t)b * a.in_bs; }
+  DBAR_D cx<T>* outp(int b) const { return static_cast<cx<T>*>(a.out) + (size_t)b * a.out_bs; }
+  template <class Acc> DBAR_D void mid(int, int, int, cx<T>&) const {}
+  template <int NT, class Acc> DBAR_D void finish(Acc&, int, int, int, double*) const {}
+};
+
+// out = IFFT_rows(phase * ci * in)
+template <typename T, int N>
+struct OpRowsInvScaled : OpBase<T, N> {
+  static constexpr int DIR1 = +1;
+  static constexpr bool TWO = false;
+  using Acc = NoAcc;
+  DBAR_D cx<T> load(int b, int row, int pos) const {
+    const T f = static_cast<T>(((row + pos) & 1) ? -this->a.ci : this->a.ci);
+    return f * this->inp(b)[(size_t)row * N + pos];
+  }
+  DBAR_D void store(Acc&, int b, int row, int pos, cx<T> v) const { this->outp(b)[(size_t)row * N + pos] = v; }
+};
+
+// IFFT_cols(in) and accumulate sum z^n s (n <= M) and sum conj(z) s in FP64
+template <typename T, int N>
+struct OpColsInvMoments : OpBase<T, N> {
+  static constexpr int DIR1 = +1;
+  static constexpr bool TWO = false;
+  static constexpr int NV = 2 * kNMom;
+  struct Acc {
+    double v[2 * kNMom];
+  };
+  DBAR_D cx<T> load(int b, int col, int pos) const { return this->inp(b)[(size_t)pos * N + col]; }
+  DBAR_D void store(Acc& acc, int, int col, int pos, cx<T> v) const {
+    const c64 z{xgrid<N>(col, this->a.L), xgrid<N>(pos, this->a.L)};
+    const c64 s = cvt<double>(v);
+    c64 p = s;
+#pragma unroll
+    for (int n = 0; n <= kMaxM; ++n) {
+      if (n <= this->a.M) {
+        acc.v[2 * n] += p.re;
+        acc.v[2 * n + 1] += p.im;
+        p = p * z;
+      }
+    }
+    const c64 t = conj(z) * s;
+    acc.v[2 * (kMaxM + 1)] += t.re;
+    acc.v[2 * (kMaxM + 1) + 1] += t.im;
+  }
+  template <int NT>
+  DBAR_D void finish(Acc& acc, int b, int tile, int ntiles, double* scratch) const {
+    double* dst = this->a.part + (size_t)b * NV * ntiles + tile;
+    block_reduce_store<NT, NV>(acc.v, dst, ntiles, scratch);
+  }
+};
+
+// R = (S - G)/xi (R(0) from coefG slot kMaxM+1), then out = IFFT_rows(phase * ci * R)
+template <typename T, int N>
+struct OpRowsInvRegular : OpBase<T, N> {
+  static constexpr int DIR1 = +1;
+  static constexpr bool TWO = false;
+  using Acc = NoAcc;
+  DBAR_D cx<T> load(int b, int row, int pos) const {
+    const c64* __restrict__ c = this->a.coefG + (size_t)b * kNMom;
+    const double invL = 1.0 / this->a.L;
+    const double xi1 = wavenum(pos, N) * invL, xi2 = wavenum(row, N) * invL;
+    const double r2 = xi1 * xi1 + xi2 * xi2;
+    c64 R;
+    if (r2 == 0.0) {
+      R = c[kMaxM + 1];
+    } else {
+      c64 s = cvt<double>(this->inp(b)[(size_t)row * N + pos]);
+      if (r2 < 740.0) {  // e^{-|xi|^2} underflows beyond this
+        const c64 xib{xi1, -xi2};
+        const int M = this->a.M;
+        c64 g = c[M];
+        for (int n = M - 1; n >= 0; --n) g = c[n] + xib * g;
+        s = s - exp(-r2) * g;
+      }
+      const double ir2 = 1.0 / r2;
+      R = c64{(s.re * xi1 + s.im * xi2) * ir2, (s.im * xi1 - s.re * xi2) * ir2};  // s / xi
+    }
+    const double f = ((row + pos) & 1) ? -this->a.ci : this->a.ci;
+    return cvt<T>(f * R);
+  }
+  DBAR_D void store(Acc&, int b, int row, int pos, cx<T> v) const { this->outp(b)[(size_t)row * N + pos] = v; }
+};
+
+// r = IFFT_cols(in); h = r + tail; [hout = h]; u = q_k conj(h); out = FFT_cols(u)   (TAILONLY: stop after hout)
+template <typename T, int N, bool TAILONLY>
+struct OpColsInvTail : OpBase<T, N> {
+  static constexpr int DIR1 = +1;
+  static constexpr bool TWO = !TAILONLY;
+  using Acc = NoAcc;
+  DBAR_D cx<T> load(int b, int col, int pos) const { return this->inp(b)[(size_t)pos * N + col]; }
+  DBAR_D c64 h_at(int b, int col, int pos, cx<T> v) const {
+    const double x = xgrid<N>(col, this->a.L), y = xgrid<N>(pos, this->a.L);
+    return cvt<double>(v) + tail_sum(x, y, this->a.dmom + (size_t)b * kNMom, this->a.M);
+  }
+  template <class A>
+  DBAR_D void mid(int b, int col, int pos, cx<T>& v) const {
+    const c64 h = h_at(b, col, pos, v);
+    if (this->a.hout) (static_cast<cx<T>*>(this->a.hout) + (size_t)b * this->a.hout_bs)[(size_t)pos * N + col] = cvt<T>(h);
+    const c64 q = cvt<double>((static_cast<const cx<T>*>(this->a.Q) + (size_t)b * this->a.Q_bs)[(size_t)pos * N + col]);
+    const c64 e = this->a.ex[(size_t)b * N + col] * this->a.ey[(size_t)b * N + pos];
+    v = cvt<T>((q * e) * conj(h));
+  }
+  DBAR_D void store(Acc&, int b, int col, int pos, cx<T> v) const {
+    if constexpr (TAILONLY) {
+      const c64 h = h_at(b, col, pos, v);
+      (static_cast<cx<T>*>(this->a.hout) + (size_t)b * this->a.hout_bs)[(size_t)pos * N + col] = cvt<T>(h);
+    } else {
+      this->outp(b)[(size_t)pos * N + col] = v;
+    }
+  }
+};
+
+// X = FFT_rows(in); out = alpha S + beta cf phase X + gamma Y; optional |out|^2 partials
+template <typename T, int N>
+struct OpRowsFwdEpilogue : OpBase<T, N> {
+  static constexpr int DIR1 = -1;
+  static constexpr bool TWO = false;
+  struct Acc {
+    double v[1];
+  };
+  DBAR_D cx<T> load(int b, int row, int pos) const { return this->inp(b)[(size_t)row * N + pos]; }
+  DBAR_D void store(Acc& acc, int b, int row, int pos, cx<T> X) const {
+    const LineArgs& a = this->a;
+    const size_t idx = (size_t)row * N + pos;
+    const double f = ((row + pos) & 1) ? -a.cf : a.cf;
+    c64 o = a.beta * (f * cvt<double>(X));
+    if (a.alpha != 0.0) o = o + a.alpha * cvt<double>((static_cast<const cx<T>*>(a.S) + (size_t)b * a.S_bs)[idx]);
+    if (a.gamma != 0.0) o = o + a.gamma * cvt<double>((static_cast<const cx<T>*>(a.Y) + (size_t)b * a.Y_bs)[idx]);
+    const cx<T> ot = cvt<T>(o);
+    this->outp(b)[idx] = ot;
+    const c64 od = cvt<double>(ot);
+    acc.v[0] += norm2(od);
+  }
+  template <int NT>
+  DBAR_D void finish(Acc& acc, int b, int tile, int ntiles, double* scratch) const {
+    if (!this->a.want_norm) return;
+    block_reduce_store<NT, 1>(acc.v, this->a.part + (size_t)b * ntiles + tile, 0, scratch);
+  }
+};
+
+// out = FFT_cols(Q e_k)
+template <typename T, int N>
+struct OpColsFwdPotential : OpBase<T, N> {
+  static constexpr int DIR1 = -1;
+  static constexpr bool TWO = false;
+  using Acc = NoAcc;
+  DBAR_D cx<T> load(int b, int col, int pos) const {
+    const c64 q = cvt<double>((static_cast<const cx<T>*>(this->a.Q) + (size_t)b * this->a.Q_bs)[(size_t)pos * N + col]);
+    const c64 e = this->a.ex[(size_t)b * N + col] * this->a.ey[(size_t)b * N + pos];
+    return cvt<T>(q * e);
+  }
+  DBAR_D void store(Acc&, int b, int col, int pos, cx<T> v) const { this->outp(b)[(size_t)pos * N + col] = v; }
+};
+
+// out = FFT_cols(in) (DIR -1) or IFFT_cols(in) (DIR +1)
+template <typename T, int N, int DIR>
+struct OpColsPlain : OpBase<T, N> {
+  static constexpr int DIR1 = DIR;
+  static constexpr bool TWO = false;
+  using Acc = NoAcc;
+  DBAR_D cx<T> load(int b, int col, int pos) const { return this->inp(b)[(size_t)pos * N + col]; }
+  DBAR_D void store(Acc&, int b, int col, int pos, cx<T> v) const { this->outp(b)[(size_t)pos * N + col] = v; }
+};
+
+// ------------------------------------------------------------------------------------------------------------
+// The generic line kernel
+// ------------------------------------------------------------------------------------------------------------
+DBAR_D int xcd_swizzle(int bid, int nblk) {
+  // blocks are dispatched round-robin over the 8 XCDs; give each XCD a contiguous range of tiles so that tiles
+  // sharing cache lines (narrow column tiles) meet in the same L2
+  if ((nblk & 7) != 0) return bid;
+  return (bid & 7) * (nblk >> 3) + (bid >> 3);
+}
+
+template <typename T, int N, int LINES>
+struct LdsSize {
+  static constexpr int NT = LINES * LineGeom<N>::TPL;
+  static constexpr int kData = LINES * LineGeom<N>::LDS_LINE * (int)sizeof(cx<T>);
+  static constexpr int kScratch = (NT >= 64 ? NT / 64 : NT) * 2 * kNMom * (int)sizeof(double);
+  static constexpr int kElems = ((kData > kScratch ? kData : kScratch) + (int)sizeof(cx<T>) - 1) / (int)sizeof(cx<T>);
+};
+
+template <typename T, int N, int LINES, bool COLS, class Op>
+__global__ void __launch_bounds__(LINES * LineGeom<N>::TPL) k_lines(Op op) {
+  using G = LineGeom<N>;
+  constexpr int NT = LINES * G::TPL;
+  __shared__ cx<T> lds[LdsSize<T, N, LINES>::kElems];
+  const int b = blockIdx.y;
+  if (!op.active(b)) return;
+  const int tid = threadIdx.x;
+  const int ln = COLS ? (tid % LINES) : (tid / G::TPL);
+  const int jt = COLS ? (tid / LINES) : (tid % G::TPL);
+  const int tile = xcd_swizzle(blockIdx.x, gridDim.x);
+  const int line = tile * LINES + ln;
+  const cx<T>* tw = static_cast<const cx<T>*>(op.a.tw);
+
+  cx<T> v[G::RMAX];
+#pragma unroll
+  for (int s = 0; s < G::RMAX; ++s) v[s] = op.load(b, line, jt + s * G::TPL);
+  cx<T>* my = lds + ln * G::LDS_LINE;
+  line_fft<T, N, Op::DIR1>(v, jt, my, tw);
+  if constexpr (Op::TWO) {
+#pragma unroll
+    for (int s = 0; s < G::RMAX; ++s) op.template mid<typename Op::Acc>(b, line, jt + s * G::TPL, v[s]);
+    line_fft<T, N, -Op::DIR1>(v, jt, my, tw);
+  }
+  typename Op::Acc acc{};
+#pragma unroll
+  for (int s = 0; s < G::RMAX; ++s) op.store(acc, b, line, jt + s * G::TPL, v[s]);
+  op.template finish<NT>(acc, b, tile, gridDim.x, reinterpret_cast<double*>(lds));
+}
+
+template <typename T, int N, bool COLS, class Op>
+void launch_op(const LineArgs& a, hipStream_t s) {
+  constexpr int LINES = COLS ? Tiling<T, N>::COLS : Tiling<T, N>::ROWS;
+  constexpr int NT = LINES * LineGeom<N>::TPL;
+  Op op;
+  op.a = a;
+  dim3 grid(N / LINES, a.B);
+  hipLaunchKernelGGL((k_lines<T, N, LINES, COLS, Op>), grid, dim3(NT), 0, s, op);
+}
+
+template <typename T, int N>
+void launch_lines(LineOp op, const LineArgs& a, hipStream_t s) {
+  switch (op) {
+    case LineOp::RowsInvScaled: launch_op<T, N, false, OpRowsInvScaled<T, N>>(a, s); break;
+    case LineOp::ColsInvMoments: launch_op<T, N, true, OpColsInvMoments<T, N>>(a, s); break;
+    case LineOp::RowsInvRegular: launch_op<T, N, false, OpRowsInvRegular<T, N>>(a, s); break;
+    case LineOp::ColsInvTailFwd: launch_op<T, N, true, OpColsInvTail<T, N, false>>(a, s); break;
+    case LineOp::ColsInvTail: launch_op<T, N, true, OpColsInvTail<T, N, true>>(a, s); break;
+    case LineOp::RowsFwdEpilogue: launch_op<T, N, false, OpRowsFwdEpilogue<T, N>>(a, s); break;
+    case LineOp::ColsFwdPotential: launch_op<T, N, true, OpColsFwdPotential<T, N>>(a, s); break;
+    case LineOp::ColsFwdPlain: launch_op<T, N, true, OpColsPlain<T, N, -1>>(a, s); break;
+    case LineOp::ColsInvPlain: launch_op<T, N, true, OpColsPlain<T, N, +1>>(a, s); break;
+  }
+}
+
+#define DBAR_INSTANTIATE_N(NN)                                                  \
+  template void launch_lines<double, NN>(LineOp, const LineArgs&, hipStream_t); \
+  template void launch_lines<float, NN>(LineOp, const LineArgs&, hipStream_t);
+
+}  // namespace dbar

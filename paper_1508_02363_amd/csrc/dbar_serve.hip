@@ -1,0 +1,420 @@
+// Serving: a request queue with continuous batching for CGO solves (one k, one Q, one grid per request).
+//
+// Requests are grouped in classes by grid (N, L, M).  Each class owns a device workspace with `cap` slots, a HIP
+// stream and a worker thread, so classes of different N run concurrently as different kernel shapes.  A worker
+// repeats: admit queued requests into free slots (right-hand side, x = 0, first residual), run one lockstep Krylov
+// cycle over every slot in flight, update the solutions and recompute the FP64 residuals, then finish the requests
+// that converged (m = h(S), copy out) and free their slots.  New requests therefore join at the next cycle
+// boundary while others are mid-solve.  Admission is by device-memory footprint against the session budget.
+//
+// The paper motivates this by the need for solutions at many k (Section 1, and the outlook's parallelisation over
+// k); each slot is an independent solve of the Section 4 system with Q -> q_k.
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <tuple>
+#include <unordered_map>
+#include <vector>
+
+#include "dbar.h"
+#include "dbar_launch.h"
+#include "dbar_solver.h"
+
+namespace dbar {
+
+using Clock = std::chrono::steady_clock;
+
+struct SReq {
+  uint64_t ticket = 0;
+  dbar_grid grid{};
+  double k[2] = {0, 0};
+  double tol = 1e-10;
+  std::vector<c64> Q, S, m;
+  dbar_info info{};
+  int state = 0;  // 0 queued, 1 in flight, 2 done
+  int iters = 0;
+  size_t footprint = 0;
+  Clock::time_point t_submit, t_done;
+};
+
+struct SClass {
+  int N = 0, M = 11;
+  double L = 1.0;
+  int cap = 0;
+  int prec = DBAR_MIXED;
+  int restart = 20;
+  size_t footprint = 0;
+  Work w;
+  Pipeline P;
+  hipStream_t stream = nullptr;
+  std::vector<std::shared_ptr<SReq>> slots;
+  std::deque<std::shared_ptr<SReq>> queue;
+  std::thread th;
+  DevBuf newmask, finmask, tolv;
+  std::vector<int> h_new, h_fin, h_live;
+  std::vector<double> h_tol;
+  std::vector<std::vector<c64>> h_ex, h_ey;  // per-slot phase tables (kept alive until the copies complete)
+  bool ready = false;
+  int error = 0;
+};
+
+}  // namespace dbar
+
+struct dbar_session {
+  dbar_session_opts o{};
+  size_t budget = 0, allocated = 0;
+  int device = 0;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::map<std::tuple<int, int, double>, std::unique_ptr<dbar::SClass>> classes;
+  std::unordered_map<uint64_t, std::shared_ptr<dbar::SReq>> reqs;
+  uint64_t next_ticket = 1;
+  dbar_session_stats st{};
+  std::atomic<bool> stop{false};
+};
+
+namespace dbar {
+
+static size_t footprint_of(int N, int prec, int restart, int cap_hint) {
+  const size_t n = (size_t)N * N;
+  const bool mixed = prec == DBAR_MIXED;
+  size_t per = n * ((size_t)(restart + 1) * (mixed ? sizeof(c32) : sizeof(c64)));  // Krylov basis
+  per += n * sizeof(c64) * (mixed ? 5 : 4);                                       // x, b, T64, Q64 (+ r64)
+  per += mixed ? n * sizeof(c32) * 2 : 0;                                          // T32, Q32
+  per += 2 * (size_t)N * sizeof(c64) + sizeof(Ctl) + 2 * kNMom * sizeof(c64);
+  per += (size_t)2 * kNMom * 1024 * sizeof(double) + (size_t)(kMaxRestart + 2) * vec_blocks(n) * sizeof(double);
+  (void)cap_hint;
+  return per;
+}
+
+// Set up the class workspace (in the worker thread).
+static int class_init(SClass& c) {
+  int rc = c.w.setup(c.N, c.cap, c.restart, c.prec, false);
+  if (rc) return rc;
+  dbar_grid g{c.N, c.M, c.L};
+  if ((rc = make_pipeline(&g, c.w, &c.P))) return rc;
+  if ((rc = c.newmask.ensure(c.cap * sizeof(int)))) return rc;
+  if ((rc = c.finmask.ensure(c.cap * sizeof(int)))) return rc;
+  if ((rc = c.tolv.ensure(c.cap * sizeof(double)))) return rc;
+  if (hipStreamCreateWithFlags(&c.stream, hipStreamNonBlocking) != hipSuccess)
+    return fail(DBAR_EDEVICE, "stream creation failed");
+  c.slots.assign(c.cap, nullptr);
+  c.h_new.assign(c.cap, 0);
+  c.h_fin.assign(c.cap, 0);
+  c.h_live.assign(c.cap, 0);
+  c.h_tol.assign(c.cap, 1e-10);
+  c.h_ex.assign(c.cap, std::vector<c64>(c.N));
+  c.h_ey.assign(c.cap, std::vector<c64>(c.N));
+  c.w.B = c.cap;
+  if (hipMemsetAsync(c.w.live.p, 0, c.cap * sizeof(int), c.stream) != hipSuccess ||
+      hipMemsetAsync(c.w.act.p, 0, c.cap * sizeof(int), c.stream) != hipSuccess)
+    return fail(DBAR_EDEVICE, "memset failed");
+  return hipStreamSynchronize(c.stream) == hipSuccess ? DBAR_OK : fail(DBAR_EDEVICE, "sync failed");
+}
+
+static void worker(dbar_session* s, SClass* cp) {
+  SClass& c = *cp;
+  (void)hipSetDevice(s->device);
+  int rc = class_init(c);
+  {
+    std::lock_guard<std::mutex> lock(s->mu);
+    c.ready = rc == DBAR_OK;
+    c.error = rc;
+  }
+  if (rc) return;
+  Work& w = c.w;
+  const size_t n = w.n;
+  const bool mixed = c.prec == DBAR_MIXED;
+  const size_t V_bs = n * (w.m + 1);
+  BatchCfg cfg;
+  cfg.tol = 1e-10;
+  cfg.max_iter = 1000;
+  cfg.reorth = 2;
+  cfg.check_every = 4;
+  cfg.inner_tol = 1e-5;
+  while (!s->stop.load()) {
+    // ---- admission at the cycle boundary
+    std::vector<int> admitted;
+    bool any_live = false;
+    {
+      std::unique_lock<std::mutex> lock(s->mu);
+      for (int b = 0; b < c.cap; ++b) any_live |= c.slots[b] != nullptr;
+      if (!any_live && c.queue.empty()) {
+        s->cv_work.wait_for(lock, std::chrono::milliseconds(2));
+        continue;
+      }
+      for (int b = 0; b < c.cap && !c.queue.empty(); ++b) {
+        if (c.slots[b]) continue;
+        auto r = c.queue.front();
+        c.queue.pop_front();
+        r->state = 1;
+        c.slots[b] = r;
+        admitted.push_back(b);
+        s->st.queued -= 1;
+        s->st.in_flight += 1;
+        s->st.bytes_in_use += r->footprint;
+      }
+    }
+    if (!admitted.empty()) {
+      std::fill(c.h_new.begin(), c.h_new.end(), 0);
+      for (int b : admitted) {
+        SReq& r = *c.slots[b];
+        c.h_new[b] = 1;
+        c.h_live[b] = 1;
+        c.h_tol[b] = r.tol;
+        (void)hipMemcpyAsync(static_cast<c64*>(w.Q64.p) + (size_t)b * n, r.Q.data(), n * sizeof(c64),
+                             hipMemcpyHostToDevice, c.stream);
+        phase_tables(c.N, c.L, r.k[0], r.k[1], c.h_ex[b].data(), c.h_ey[b].data());
+        (void)hipMemcpyAsync(static_cast<c64*>(w.ex.p) + (size_t)b * c.N, c.h_ex[b].data(), c.N * sizeof(c64),
+                             hipMemcpyHostToDevice, c.stream);
+        (void)hipMemcpyAsync(static_cast<c64*>(w.ey.p) + (size_t)b * c.N, c.h_ey[b].data(), c.N * sizeof(c64),
+                             hipMemcpyHostToDevice, c.stream);
+        (void)hipMemsetAsync(static_cast<c64*>(w.x.p) + (size_t)b * n, 0, n * sizeof(c64), c.stream);
+        // host sources (request Q, per-slot tables, masks) stay untouched until the stream synchronises below
+      }
+      const int* nm = static_cast<const int*>(c.newmask.p);
+      (void)hipMemcpyAsync(c.newmask.p, c.h_new.data(), c.cap * sizeof(int), hipMemcpyHostToDevice, c.stream);
+      (void)hipMemcpyAsync(w.live.p, c.h_live.data(), c.cap * sizeof(int), hipMemcpyHostToDevice, c.stream);
+      (void)hipMemcpyAsync(c.tolv.p, c.h_tol.data(), c.cap * sizeof(double), hipMemcpyHostToDevice, c.stream);
+      if (mixed) launch_convert<float, double>(w.Q64.p, n, w.Q32.p, n, n, c.cap, nm, 1.0, c.stream);
+      c.P.rhs(w.Q64.p, n, w.T64.p, static_cast<c64*>(w.bvec.p), c.cap, nm, c.stream);
+      launch_reduce(static_cast<double*>(w.part_vec.p), 1, line_tiles(c.N, false, true),
+                    static_cast<double*>(w.nred.p), c.cap, nm, c.stream);
+      launch_ctl_check(w, 0.0, 1, nm, static_cast<const double*>(c.tolv.p), c.stream);
+      if (mixed)
+        launch_convert<float, double>(w.bvec.p, n, w.V.p, V_bs, n, c.cap, nm, 1.0, c.stream);
+      else
+        launch_convert<double, double>(w.bvec.p, n, w.V.p, V_bs, n, c.cap, nm, 1.0, c.stream);
+    }
+    // ---- one Krylov cycle for everything in flight
+    launch_ctl_start(w, mixed ? 0.3 : 0.5, mixed ? cfg.inner_tol : 0.0, static_cast<const double*>(c.tolv.p),
+                     c.stream);
+    int ran;
+    if (mixed) {
+      ran = krylov_cycle<float>(c.P, w, cfg, c.restart, c.stream);
+      end_cycle<float>(c.P, w, ran, w.r64.p, c.stream);
+    } else {
+      ran = krylov_cycle<double>(c.P, w, cfg, c.restart, c.stream);
+      end_cycle<double>(c.P, w, ran, w.V.p, c.stream);
+    }
+    launch_ctl_check(w, 0.0, 0, nullptr, static_cast<const double*>(c.tolv.p), c.stream);
+    if (mixed)
+      launch_convert<float, double>(w.r64.p, n, w.V.p, V_bs, n, c.cap, static_cast<const int*>(w.live.p), 1.0,
+                                    c.stream);
+    std::vector<int> live_now(c.cap);
+    (void)hipMemcpyAsync(live_now.data(), w.live.p, c.cap * sizeof(int), hipMemcpyDeviceToHost, c.stream);
+    if (hipStreamSynchronize(c.stream) != hipSuccess) {
+      std::lock_guard<std::mutex> lock(s->mu);
+      c.error = DBAR_EDEVICE;
+      for (auto& r : c.slots)
+        if (r) {
+          r->state = 2;
+          r->info.status = DBAR_EDEVICE;
+          r->t_done = Clock::now();
+        }
+      s->cv_done.notify_all();
+      return;
+    }
+    // ---- finish converged (or exhausted) requests
+    std::fill(c.h_fin.begin(), c.h_fin.end(), 0);
+    std::vector<int> fin;
+    for (int b = 0; b < c.cap; ++b) {
+      if (!c.slots[b] || !c.h_live[b]) continue;
+      c.slots[b]->iters += ran;
+      const bool done = live_now[b] == 0;
+      const bool exhausted = !done && c.slots[b]->iters >= cfg.max_iter;
+      if (done || exhausted || ran == 0) {
+        c.h_fin[b] = 1;
+        c.h_live[b] = 0;
+        fin.push_back(b);
+        c.slots[b]->info.status = done ? DBAR_OK : DBAR_ENOCONV;
+      }
+    }
+    if (fin.empty()) continue;
+    (void)hipMemcpyAsync(c.finmask.p, c.h_fin.data(), c.cap * sizeof(int), hipMemcpyHostToDevice, c.stream);
+    (void)hipMemcpyAsync(w.live.p, c.h_live.data(), c.cap * sizeof(int), hipMemcpyHostToDevice, c.stream);
+    c.P.h_of<double>(w.x.p, n, w.T64.p, n, w.bvec.p, c.cap, static_cast<const int*>(c.finmask.p), c.stream);
+    std::vector<Ctl> ctl_out(fin.size());
+    for (size_t i = 0; i < fin.size(); ++i) {
+      const int b = fin[i];
+      SReq& r = *c.slots[b];
+      r.S.resize(n);
+      r.m.resize(n);
+      (void)hipMemcpyAsync(r.S.data(), static_cast<c64*>(w.x.p) + (size_t)b * n, n * sizeof(c64),
+                           hipMemcpyDeviceToHost, c.stream);
+      (void)hipMemcpyAsync(r.m.data(), static_cast<c64*>(w.T64.p) + (size_t)b * n, n * sizeof(c64),
+                           hipMemcpyDeviceToHost, c.stream);
+      (void)hipMemcpyAsync(&ctl_out[i], static_cast<Ctl*>(w.ctl.p) + b, sizeof(Ctl), hipMemcpyDeviceToHost,
+                           c.stream);
+    }
+    const bool ok = hipStreamSynchronize(c.stream) == hipSuccess;
+    {
+      std::lock_guard<std::mutex> lock(s->mu);
+      for (size_t i = 0; i < fin.size(); ++i) {
+        const int b = fin[i];
+        auto r = c.slots[b];
+        const Ctl& cc = ctl_out[i];
+        r->info.iters = cc.iters;
+        r->info.outer = cc.cycles;
+        r->info.rel_residual = cc.bnorm > 0.0 ? cc.rnorm / cc.bnorm : 0.0;
+        r->info.m1_re = ok ? -r->S[0].im : 0.0;
+        r->info.m1_im = ok ? r->S[0].re : 0.0;
+        if (!ok) r->info.status = DBAR_EDEVICE;
+        r->state = 2;
+        r->t_done = Clock::now();
+        c.slots[b] = nullptr;
+        s->st.in_flight -= 1;
+        s->st.completed += 1;
+        s->st.bytes_in_use -= r->footprint;
+      }
+    }
+    s->cv_done.notify_all();
+  }
+}
+
+}  // namespace dbar
+
+using namespace dbar;
+
+extern "C" {
+
+size_t dbar_request_footprint(const dbar_grid* grid, int32_t precision, int32_t restart) {
+  if (validate_grid(grid)) return 0;
+  if (restart <= 0) restart = precision == DBAR_FP64 ? 40 : 20;
+  return footprint_of(grid->n, precision, restart, 1);
+}
+
+int dbar_session_create(const dbar_session_opts* opts, dbar_session** out) {
+  if (!out) return fail(DBAR_EINVAL, "out is NULL");
+  int cnt = 0;
+  if (hipGetDeviceCount(&cnt) != hipSuccess || cnt < 1) {
+    (void)hipGetLastError();
+    return fail(DBAR_EDEVICE, "no HIP device available");
+  }
+  auto* s = new dbar_session();
+  if (opts) s->o = *opts;
+  if (s->o.max_slots <= 0) s->o.max_slots = 64;
+  if (s->o.precision != DBAR_FP64) s->o.precision = DBAR_MIXED;
+  if (s->o.restart <= 0) s->o.restart = s->o.precision == DBAR_MIXED ? 20 : 40;
+  if (s->o.restart > kMaxRestart) s->o.restart = kMaxRestart;
+  (void)hipGetDevice(&s->device);
+  size_t fr = 0, tot = 0;
+  (void)hipMemGetInfo(&fr, &tot);
+  s->budget = s->o.hbm_budget_bytes ? s->o.hbm_budget_bytes : (size_t)(0.8 * (double)fr);
+  *out = s;
+  return DBAR_OK;
+}
+
+int dbar_submit(dbar_session* s, const dbar_grid* grid, const double* Q, const double* k, double tol,
+                uint64_t* ticket) {
+  if (!s || !ticket || !Q || !k) return fail(DBAR_EINVAL, "NULL argument");
+  int rc = validate_grid(grid);
+  if (rc) return rc;
+  if (!(tol > 0.0) || !std::isfinite(tol)) return fail(DBAR_EINVAL, "tol must be finite and > 0");
+  const size_t n = (size_t)grid->n * grid->n;
+  for (size_t i = 0; i < 2 * n; ++i)
+    if (!std::isfinite(Q[i])) return fail(DBAR_EINVAL, "Q contains NaN or Inf");
+  if (!std::isfinite(k[0]) || !std::isfinite(k[1])) return fail(DBAR_EINVAL, "k contains NaN or Inf");
+  auto r = std::make_shared<SReq>();
+  r->grid = *grid;
+  r->k[0] = k[0];
+  r->k[1] = k[1];
+  r->tol = tol;
+  r->Q.resize(n);
+  std::memcpy(r->Q.data(), Q, n * sizeof(c64));
+  r->footprint = footprint_of(grid->n, s->o.precision, s->o.restart, 1);
+  r->t_submit = Clock::now();
+  std::lock_guard<std::mutex> lock(s->mu);
+  auto key = std::make_tuple(grid->n, grid->M, grid->L);
+  auto it = s->classes.find(key);
+  if (it == s->classes.end()) {
+    const size_t fp = r->footprint;
+    const size_t left = s->budget > s->allocated ? s->budget - s->allocated : 0;
+    const int cap = (int)std::min<size_t>((size_t)s->o.max_slots, left / fp);
+    if (cap < 1) {
+      s->st.rejected += 1;
+      return fail(DBAR_ENOMEM, "request footprint exceeds the remaining HBM budget of the session");
+    }
+    auto c = std::make_unique<SClass>();
+    c->N = grid->n;
+    c->M = grid->M;
+    c->L = grid->L;
+    c->cap = cap;
+    c->prec = s->o.precision;
+    c->restart = s->o.restart;
+    c->footprint = fp;
+    s->allocated += (size_t)cap * fp;
+    SClass* cp = c.get();
+    it = s->classes.emplace(key, std::move(c)).first;
+    cp->th = std::thread(worker, s, cp);
+  }
+  SClass& c = *it->second;
+  if (c.error) return fail(c.error, "the worker for this grid failed to start");
+  r->ticket = s->next_ticket++;
+  c.queue.push_back(r);
+  s->reqs[r->ticket] = r;
+  s->st.submitted += 1;
+  s->st.queued += 1;
+  *ticket = r->ticket;
+  s->cv_work.notify_all();
+  return DBAR_OK;
+}
+
+static int take_result(dbar_session* s, std::unordered_map<uint64_t, std::shared_ptr<SReq>>::iterator it,
+                       double* S_out, double* m_out, dbar_info* info, double* latency_s) {
+  auto r = it->second;
+  const size_t n = r->S.size();
+  if (S_out && n) std::memcpy(S_out, r->S.data(), n * sizeof(c64));
+  if (m_out && n) std::memcpy(m_out, r->m.data(), n * sizeof(c64));
+  if (info) *info = r->info;
+  if (latency_s) *latency_s = std::chrono::duration<double>(r->t_done - r->t_submit).count();
+  s->reqs.erase(it);
+  return r->info.status == DBAR_EDEVICE ? fail(DBAR_EDEVICE, "device failure in the serving worker")
+                                        : (r->info.status == DBAR_ENOCONV ? DBAR_ENOCONV : DBAR_OK);
+}
+
+int dbar_poll(dbar_session* s, uint64_t ticket, double* S_out, double* m_out, dbar_info* info, double* latency_s) {
+  if (!s) return fail(DBAR_EINVAL, "session is NULL");
+  std::lock_guard<std::mutex> lock(s->mu);
+  auto it = s->reqs.find(ticket);
+  if (it == s->reqs.end()) return fail(DBAR_ENOTFOUND, "unknown ticket");
+  if (it->second->state != 2) return DBAR_EAGAIN;
+  return take_result(s, it, S_out, m_out, info, latency_s);
+}
+
+int dbar_wait(dbar_session* s, uint64_t ticket, double* S_out, double* m_out, dbar_info* info, double* latency_s) {
+  if (!s) return fail(DBAR_EINVAL, "session is NULL");
+  std::unique_lock<std::mutex> lock(s->mu);
+  while (true) {
+    auto it = s->reqs.find(ticket);
+    if (it == s->reqs.end()) return fail(DBAR_ENOTFOUND, "unknown ticket");
+    if (it->second->state == 2) return take_result(s, it, S_out, m_out, info, latency_s);
+    s->cv_done.wait_for(lock, std::chrono::milliseconds(50));
+  }
+}
+
+int dbar_session_get_stats(dbar_session* s, dbar_session_stats* st) {
+  if (!s || !st) return fail(DBAR_EINVAL, "NULL argument");
+  std::lock_guard<std::mutex> lock(s->mu);
+  *st = s->st;
+  return DBAR_OK;
+}
+
+void dbar_session_destroy(dbar_session* s) {
+  if (!s) return;
+  s->stop.store(true);
+  s->cv_work.notify_all();
+  for (auto& kv : s->classes)
+    if (kv.second->th.joinable()) kv.second->th.join();
+  for (auto& kv : s->classes)
+    if (kv.second->stream) (void)hipStreamDestroy(kv.second->stream);
+  delete s;
+}
+
+}  // extern "C"

@@ -1,0 +1,119 @@
+// Internal host structures of the D-bar solver (workspace, operator pipeline, per-entry GMRES record).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "dbar.h"
+#include "dbar_launch.h"
+
+namespace dbar {
+
+constexpr int kMaxRestart = 64;
+
+int fail(int code, const std::string& msg);
+
+// Owning device allocation that only grows.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+  DevBuf& operator=(DevBuf&& o) noexcept {
+    if (this != &o) {
+      if (p) (void)hipFree(p);
+      p = o.p;
+      bytes = o.bytes;
+      o.p = nullptr;
+      o.bytes = 0;
+    }
+    return *this;
+  }
+  ~DevBuf();
+  int ensure(size_t nbytes);
+};
+
+struct Twiddles {
+  DevBuf d64, d32;  // exp(-2 pi i j / N), j < N
+};
+
+// Per batch entry GMRES record (FP64).  H is column-major: H[j * (kMaxRestart + 1) + i].
+struct Ctl {
+  double sigma[kMaxRestart + 1];   // 1 / ||v_i|| of the unnormalised basis vectors
+  double hsum[kMaxRestart + 1];    // sigma_i <v_i, A v_j> summed over Gram-Schmidt passes
+  double coef[kMaxRestart + 1];    // update coefficients (Gram-Schmidt, then the solution update)
+  double H[kMaxRestart * (kMaxRestart + 1)];
+  double cs[kMaxRestart], sn[kMaxRestart], g[kMaxRestart + 1];
+  double bnorm, rnorm, thresh, resid;
+  int jn, iters, cycles, pad;
+};
+
+struct BatchCfg {
+  double tol = 1e-12;
+  int max_iter = 1000;
+  int reorth = 2;
+  int check_every = 4;
+  double inner_tol = 1e-5;
+};
+
+// Device workspace for a batch of B entries on an N x N grid with restart m.
+struct Work {
+  int N = 0, B = 0, m = 0, prec = 0;
+  size_t n = 0;
+  size_t Q_bs = 0;
+  DevBuf x, bvec, T64, r64, T32, V, Q64, Q32, ex, ey, coefG, dmom, part_mom, part_vec, dred, nred, ctl, act, live;
+  std::vector<int> host_act, host_live;
+  int setup(int N_, int B_, int m_, int prec_, bool shared_q);
+  size_t vec_bytes(int prec) const;
+};
+
+// The operator pipeline for one grid (pointers into a Work).
+struct Pipeline {
+  int N = 0, M = 11;
+  double L = 1.0;
+  size_t n = 0;
+  const Twiddles* tw = nullptr;
+  const c64* ex = nullptr;
+  const c64* ey = nullptr;
+  c64* coefG = nullptr;
+  c64* dmom = nullptr;
+  double* part_mom = nullptr;
+  double* part_vec = nullptr;
+
+  LineArgs base(int B, const int* act) const;
+  template <typename T>
+  void moments(const void* in, size_t in_bs, void* Tbuf, int B, const int* act, hipStream_t s) const;
+  template <typename T>
+  void apply(const void* in, size_t in_bs, void* out, size_t out_bs, const void* Qp, size_t Q_bs, void* Tbuf, int B,
+             const int* act, double alpha, double beta, const void* Y, size_t Y_bs, bool want_norm,
+             hipStream_t s) const;
+  void rhs(const void* Q64p, size_t Q_bs, void* T64, c64* bout, int B, const int* act, hipStream_t s) const;
+  template <typename T>
+  void h_of(const void* in, size_t in_bs, void* hout, size_t hout_bs, void* Tbuf, int B, const int* act,
+            hipStream_t s) const;
+  template <typename T>
+  void transform(bool inverse, const void* in, void* out, void* Tbuf, hipStream_t s) const;
+};
+
+int validate_grid(const dbar_grid* g);
+int get_twiddles(int N, const Twiddles** out);
+int make_pipeline(const dbar_grid* g, Work& w, Pipeline* p);
+void phase_tables(int N, double L, double k1, double k2, c64* ex, c64* ey);
+int run_batch(const Pipeline& P, Work& w, const BatchCfg& cfg, hipStream_t s, std::vector<int>& iters_out);
+int ctl_blocks(int B);
+// one lockstep Krylov cycle over the entries flagged in w.act; returns the iterations run
+template <typename T>
+int krylov_cycle(const Pipeline& P, Work& w, const BatchCfg& cfg, int it_budget, hipStream_t s);
+// solution update from the cycle and the FP64 residual r = b - A(x) into r_out (norms into w.nred)
+template <typename T>
+void end_cycle(const Pipeline& P, Work& w, int nv, void* r_out, hipStream_t s);
+// residual check (first = 1: record ||b|| and reset the counters of the entries in mask); tolv: per-entry tol
+void launch_ctl_check(Work& w, double tol, int first, const int* mask, const double* tolv, hipStream_t s);
+// start a cycle for every live entry from its residual norm
+void launch_ctl_start(Work& w, double abs_tol, double rel_tol, const double* tolv, hipStream_t s);
+
+}  // namespace dbar

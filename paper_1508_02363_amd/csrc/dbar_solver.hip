@@ -1,0 +1,877 @@
+// Host side of the D-bar solver: plans, workspace, the operator pipeline, device-resident GMRES and the C ABI.
+//
+// GMRES (Saad & Schultz) on the real 2N^2 form, restarted, x0 = 0, classical Gram-Schmidt (optionally twice),
+// Givens rotations.  The Krylov basis is kept unnormalised: v_{j+1} is the orthogonalised A v_j written in place and
+// q_j = sigma_j v_j with sigma_j = 1/||v_j|| (so no separate normalisation pass over memory).  All bookkeeping
+// (Hessenberg, rotations, residual estimate, convergence flags) lives on the device, one record per batch entry;
+// entries advance in lockstep and converged ones are masked out of every kernel.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "dbar.h"
+#include "dbar_launch.h"
+#include "dbar_solver.h"
+
+namespace dbar {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+// ------------------------------------------------------------------------------------------------------------
+// Control kernels (one thread per batch entry)
+// ------------------------------------------------------------------------------------------------------------
+static __constant__ double kInvFactC[kMaxM + 2] = {
+    1.0, 1.0, 5.0e-1, 1.6666666666666666e-1, 4.1666666666666664e-2, 8.3333333333333332e-3,
+    1.3888888888888889e-3, 1.9841269841269841e-4, 2.4801587301587302e-5, 2.7557319223985893e-6,
+    2.7557319223985888e-7, 2.5052108385441720e-8, 2.0876756987868100e-9, 1.6059043836821613e-10,
+    1.1470745597729725e-11, 7.6471637318198164e-13, 4.7794773323873853e-14};
+
+DBAR_D double wsum(double x) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+  return x;
+}
+
+// d_n = w sum_tiles part, c_n = (-i/2)^n d_n / n! (equation fourreeg4 with Gchoice), R(0) = (-i/2) dt
+__global__ void __launch_bounds__(256) k_moments(const double* part, int ntiles, const int* act, double wscale, int M,
+                                                 c64* coefG, c64* dmom) {
+  constexpr int NV = 2 * kNMom;
+  const int b = blockIdx.x;
+  if (act && !act[b]) return;
+  __shared__ double red[4][NV];
+  __shared__ double tot[NV];
+  for (int v = 0; v < NV; ++v) {
+    const double* p = part + ((size_t)b * NV + v) * ntiles;
+    double s = 0.0;
+    for (int i = threadIdx.x; i < ntiles; i += 256) s += p[i];
+    s = wsum(s);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6][v] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < NV) tot[threadIdx.x] = (red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] +
+                                            red[3][threadIdx.x]) * wscale;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    c64* cg = coefG + (size_t)b * kNMom;
+    c64* dm = dmom + (size_t)b * kNMom;
+    c64 p{1.0, 0.0};
+    const c64 mh{0.0, -0.5};
+    for (int n = 0; n <= kMaxM; ++n) {
+      const c64 d{tot[2 * n], tot[2 * n + 1]};
+      dm[n] = n <= M ? d : c64{0.0, 0.0};
+      cg[n] = n <= M ? kInvFactC[n] * (p * d) : c64{0.0, 0.0};
+      p = p * mh;
+    }
+    const c64 dt{tot[2 * (kMaxM + 1)], tot[2 * (kMaxM + 1) + 1]};
+    cg[kMaxM + 1] = mh * dt;
+    dm[kMaxM + 1] = dt;
+  }
+}
+
+__global__ void k_ctl_coef(Ctl* ctl, const double* dred, int nval, const int* act, int j, int pass, int B) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B || !act[b]) return;
+  Ctl& c = ctl[b];
+  for (int i = 0; i <= j; ++i) {
+    const double h = dred[(size_t)b * nval + i];
+    c.coef[i] = c.sigma[i] * c.sigma[i] * h;
+    c.hsum[i] = (pass ? c.hsum[i] : 0.0) + c.sigma[i] * h;
+  }
+}
+
+__global__ void k_ctl_givens(Ctl* ctl, const double* nred, int* act, int j, int m, int B) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B || !act[b]) return;
+  Ctl& c = ctl[b];
+  const double beta = sqrt(fmax(nred[b], 0.0));
+  const double sj = c.sigma[j];
+  double* col = c.H + (size_t)j * (kMaxRestart + 1);
+  for (int i = 0; i <= j; ++i) col[i] = sj * c.hsum[i];
+  col[j + 1] = sj * beta;
+  c.sigma[j + 1] = beta > 0.0 ? 1.0 / beta : 0.0;
+  for (int i = 0; i < j; ++i) {
+    const double t = c.cs[i] * col[i] + c.sn[i] * col[i + 1];
+    col[i + 1] = -c.sn[i] * col[i] + c.cs[i] * col[i + 1];
+    col[i] = t;
+  }
+  const double den = hypot(col[j], col[j + 1]);
+  c.cs[j] = den > 0.0 ? col[j] / den : 1.0;
+  c.sn[j] = den > 0.0 ? col[j + 1] / den : 0.0;
+  col[j] = den;
+  col[j + 1] = 0.0;
+  c.g[j + 1] = -c.sn[j] * c.g[j];
+  c.g[j] = c.cs[j] * c.g[j];
+  c.resid = fabs(c.g[j + 1]);
+  c.jn = j + 1;
+  c.iters += 1;
+  if (c.resid <= c.thresh || j + 1 >= m || beta == 0.0) act[b] = 0;
+}
+
+// y = H^{-1} g (upper triangular jn x jn), coef_i = y_i sigma_i, zero beyond jn
+__global__ void k_ctl_trisolve(Ctl* ctl, const int* live, int B) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B || !live[b]) return;
+  Ctl& c = ctl[b];
+  const int n = c.jn;
+  for (int i = n - 1; i >= 0; --i) {
+    double s = c.g[i];
+    for (int l = i + 1; l < n; ++l) s -= c.H[(size_t)l * (kMaxRestart + 1) + i] * c.coef[l];
+    const double d = c.H[(size_t)i * (kMaxRestart + 1) + i];
+    c.coef[i] = d != 0.0 ? s / d : 0.0;
+  }
+  for (int i = 0; i < n; ++i) c.coef[i] *= c.sigma[i];
+  for (int i = n; i <= kMaxRestart; ++i) c.coef[i] = 0.0;
+}
+
+// start a Krylov cycle from the residual whose squared norm is nred[b] (already stored as v_0)
+__global__ void k_ctl_start(Ctl* ctl, const double* nred, const int* live, int* act, double abs_tol, double rel_tol,
+                            const double* tolv, int B) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  Ctl& c = ctl[b];
+  if (!live[b]) {
+    act[b] = 0;
+    return;
+  }
+  const double rn = sqrt(fmax(nred[b], 0.0));
+  // abs_tol is a fraction of the entry's tolerance (tolv[b], or 1 when tolv is NULL and abs_tol carries it)
+  const double at = tolv ? abs_tol * tolv[b] : abs_tol;
+  c.rnorm = rn;
+  c.sigma[0] = rn > 0.0 ? 1.0 / rn : 0.0;
+  c.g[0] = rn;
+  c.thresh = fmax(at * c.bnorm, rel_tol * rn);
+  c.jn = 0;
+  act[b] = rn > c.thresh ? 1 : 0;
+}
+
+// after a recomputed residual: done when ||r|| <= tol ||b||
+__global__ void k_ctl_check(Ctl* ctl, const double* nred, int* live, double tol, int first, const int* mask,
+                            const double* tolv, int B) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B || (!first && !live[b]) || (mask && !mask[b])) return;
+  Ctl& c = ctl[b];
+  const double rn = sqrt(fmax(nred[b], 0.0));
+  if (first) {
+    c.bnorm = rn;
+    c.iters = 0;
+    c.cycles = 0;
+    c.jn = 0;
+  }
+  c.rnorm = rn;
+  c.cycles += 1;
+  const double t = tolv ? tolv[b] : tol;
+  if (rn <= t * c.bnorm) live[b] = 0;
+}
+
+// ------------------------------------------------------------------------------------------------------------
+// Plans and workspace
+// ------------------------------------------------------------------------------------------------------------
+DevBuf::~DevBuf() {
+  if (p) (void)hipFree(p);
+}
+int DevBuf::ensure(size_t nbytes) {
+  if (nbytes <= bytes) return DBAR_OK;
+  if (p) (void)hipFree(p);
+  p = nullptr;
+  bytes = 0;
+  if (nbytes == 0) return DBAR_OK;
+  hipError_t e = hipMalloc(&p, nbytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    p = nullptr;
+    return fail(DBAR_ENOMEM, "hipMalloc(" + std::to_string(nbytes) + " bytes) failed: " + hipGetErrorString(e));
+  }
+  bytes = nbytes;
+  return DBAR_OK;
+}
+
+static std::mutex g_mutex;      // serialises the one-shot C-ABI calls (shared workspace)
+static std::mutex g_tw_mutex;   // twiddle cache (also used by the serving workers)
+static std::map<int, std::unique_ptr<Twiddles>> g_twiddles;
+
+// exp(-2 pi i j / N) in long double, rounded once
+int get_twiddles(int N, const Twiddles** out) {
+  std::lock_guard<std::mutex> lock(g_tw_mutex);
+  auto it = g_twiddles.find(N);
+  if (it == g_twiddles.end()) {
+    auto t = std::make_unique<Twiddles>();
+    std::vector<c64> h64(N);
+    std::vector<c32> h32(N);
+    for (int j = 0; j < N; ++j) {
+      const long double a = -2.0L * 3.14159265358979323846264338327950288L * j / N;
+      h64[j] = c64{(double)cosl(a), (double)sinl(a)};
+      h32[j] = c32{(float)cosl(a), (float)sinl(a)};
+    }
+    int rc = t->d64.ensure(N * sizeof(c64));
+    if (rc) return rc;
+    rc = t->d32.ensure(N * sizeof(c32));
+    if (rc) return rc;
+    if (hipMemcpy(t->d64.p, h64.data(), N * sizeof(c64), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(t->d32.p, h32.data(), N * sizeof(c32), hipMemcpyHostToDevice) != hipSuccess)
+      return fail(DBAR_EDEVICE, "twiddle upload failed");
+    it = g_twiddles.emplace(N, std::move(t)).first;
+  }
+  *out = it->second.get();
+  return DBAR_OK;
+}
+
+int validate_grid(const dbar_grid* g) {
+  if (!g) return fail(DBAR_EINVAL, "grid is NULL");
+  const int N = g->n;
+  if (N < 8 || N > 4096 || (N & (N - 1)) != 0)
+    return fail(DBAR_EINVAL, "grid n must be a power of two in [8, 4096], got " + std::to_string(N));
+  if (!(g->L > 0.0) || !std::isfinite(g->L)) return fail(DBAR_EINVAL, "grid L must be finite and > 0");
+  if (g->M < 0 || g->M > kMaxM) return fail(DBAR_EINVAL, "grid M must be in [0, 15]");
+  return DBAR_OK;
+}
+
+// separable phase e^{conj(kz) - kz} = e^{-2i k2 x} e^{-2i k1 y} (eq:039)
+void phase_tables(int N, double L, double k1, double k2, c64* ex, c64* ey) {
+  for (int j = 0; j < N; ++j) {
+    const long double x = (long double)L * (-3.14159265358979323846264338327950288L +
+                                            2.0L * 3.14159265358979323846264338327950288L * j / N);
+    const long double ax = -2.0L * k2 * x, ay = -2.0L * k1 * x;
+    ex[j] = c64{(double)cosl(ax), (double)sinl(ax)};
+    ey[j] = c64{(double)cosl(ay), (double)sinl(ay)};
+  }
+}
+
+size_t Work::vec_bytes(int prec) const { return (size_t)n * (prec == DBAR_FP64 ? sizeof(c64) : sizeof(c32)); }
+
+int Work::setup(int N_, int B_, int m_, int prec_, bool shared_q) {
+  N = N_;
+  B = B_;
+  m = m_;
+  prec = prec_;
+  n = (size_t)N * N;
+  const size_t nb = (size_t)B * n;
+  const bool mixed = prec == DBAR_MIXED;
+  int rc;
+  if ((rc = x.ensure(nb * sizeof(c64)))) return rc;
+  if ((rc = bvec.ensure(nb * sizeof(c64)))) return rc;
+  if ((rc = T64.ensure(nb * sizeof(c64)))) return rc;
+  if ((rc = r64.ensure(mixed ? nb * sizeof(c64) : 0))) return rc;
+  if ((rc = T32.ensure(mixed ? nb * sizeof(c32) : 0))) return rc;
+  if ((rc = V.ensure(nb * (m + 1) * (mixed ? sizeof(c32) : sizeof(c64))))) return rc;
+  const size_t nq = shared_q ? n : nb;
+  if ((rc = Q64.ensure(nq * sizeof(c64)))) return rc;
+  if ((rc = Q32.ensure(mixed ? nq * sizeof(c32) : 0))) return rc;
+  Q_bs = shared_q ? 0 : n;
+  if ((rc = ex.ensure((size_t)B * N * sizeof(c64)))) return rc;
+  if ((rc = ey.ensure((size_t)B * N * sizeof(c64)))) return rc;
+  if ((rc = coefG.ensure((size_t)B * kNMom * sizeof(c64)))) return rc;
+  if ((rc = dmom.ensure((size_t)B * kNMom * sizeof(c64)))) return rc;
+  const int tiles = std::max(line_tiles(N, true, true), line_tiles(N, true, false));
+  const int rtiles = std::max(line_tiles(N, false, true), line_tiles(N, false, false));
+  if ((rc = part_mom.ensure((size_t)B * 2 * kNMom * std::max(tiles, rtiles) * sizeof(double)))) return rc;
+  if ((rc = part_vec.ensure((size_t)B * (kMaxRestart + 2) * std::max(vec_blocks(n), rtiles) * sizeof(double))))
+    return rc;
+  if ((rc = dred.ensure((size_t)B * (kMaxRestart + 2) * sizeof(double)))) return rc;
+  if ((rc = nred.ensure((size_t)B * sizeof(double)))) return rc;
+  if ((rc = ctl.ensure((size_t)B * sizeof(Ctl)))) return rc;
+  if ((rc = act.ensure((size_t)B * sizeof(int)))) return rc;
+  if ((rc = live.ensure((size_t)B * sizeof(int)))) return rc;
+  host_act.resize(B);
+  host_live.resize(B);
+  return DBAR_OK;
+}
+
+static Work g_work;
+
+// ------------------------------------------------------------------------------------------------------------
+// Operator pipeline
+// ------------------------------------------------------------------------------------------------------------
+LineArgs Pipeline::base(int B, const int* act) const {
+  LineArgs a;
+  a.B = B;
+  a.act = act;
+  a.L = L;
+  a.M = M;
+  a.ci = 1.0 / (2.0 * kPi * L * L);
+  const double dx = 2.0 * kPi * L / N;
+  a.cf = dx * dx / (2.0 * kPi);
+  a.ex = ex;
+  a.ey = ey;
+  a.coefG = coefG;
+  a.dmom = dmom;
+  return a;
+}
+
+template <typename T>
+static const void* tw_of(const Twiddles* t) {
+  return sizeof(T) == sizeof(double) ? t->d64.p : t->d32.p;
+}
+
+// h-moments of `in` (xi-space vector): F^{-1} in, d_n, c_n, R(0)
+template <typename T>
+void Pipeline::moments(const void* in, size_t in_bs, void* Tbuf, int B, const int* act, hipStream_t s) const {
+  LineArgs a = base(B, act);
+  a.tw = tw_of<T>(tw);
+  a.in = in;
+  a.in_bs = in_bs;
+  a.out = Tbuf;
+  a.out_bs = n;
+  launch_lines_any<T>(N, LineOp::RowsInvScaled, a, s);
+  a.in = Tbuf;
+  a.in_bs = n;
+  a.part = part_mom;
+  launch_lines_any<T>(N, LineOp::ColsInvMoments, a, s);
+  const double dx = 2.0 * kPi * L / N;
+  TimerScope ts(kStageMoments, 0.0, B, act, s);
+  hipLaunchKernelGGL(k_moments, dim3(B), dim3(256), 0, s, part_mom, line_tiles(N, true, sizeof(T) == 8), act,
+                     dx * dx / (2.0 * kPi), M, coefG, dmom);
+}
+
+// out = alpha in + beta i F(q_k conj(h(in))) + gamma Y; optional |out|^2 partials into part_vec
+template <typename T>
+void Pipeline::apply(const void* in, size_t in_bs, void* out, size_t out_bs, const void* Qp, size_t Q_bs, void* Tbuf,
+                     int B, const int* act, double alpha, double beta, const void* Y, size_t Y_bs, bool want_norm,
+                     hipStream_t s) const {
+  moments<T>(in, in_bs, Tbuf, B, act, s);
+  LineArgs a = base(B, act);
+  a.tw = tw_of<T>(tw);
+  a.in = in;
+  a.in_bs = in_bs;
+  a.out = Tbuf;
+  a.out_bs = n;
+  launch_lines_any<T>(N, LineOp::RowsInvRegular, a, s);
+  a.in = Tbuf;
+  a.in_bs = n;
+  a.Q = Qp;
+  a.Q_bs = Q_bs;
+  launch_lines_any<T>(N, LineOp::ColsInvTailFwd, a, s);
+  a.out = out;
+  a.out_bs = out_bs;
+  a.S = in;
+  a.S_bs = in_bs;
+  a.alpha = alpha;
+  a.beta = c64{0.0, beta};
+  a.Y = Y;
+  a.Y_bs = Y_bs;
+  a.gamma = Y ? 1.0 : 0.0;
+  a.want_norm = want_norm ? 1 : 0;
+  a.part = part_vec;
+  launch_lines_any<T>(N, LineOp::RowsFwdEpilogue, a, s);
+}
+
+// b = -i F(Q e_k) (FP64), with |b|^2 partials
+void Pipeline::rhs(const void* Q64p, size_t Q_bs, void* T64, c64* bout, int B, const int* act, hipStream_t s) const {
+  LineArgs a = base(B, act);
+  a.tw = tw_of<double>(tw);
+  a.Q = Q64p;
+  a.Q_bs = Q_bs;
+  a.out = T64;
+  a.out_bs = n;
+  launch_lines_any<double>(N, LineOp::ColsFwdPotential, a, s);
+  a.in = T64;
+  a.in_bs = n;
+  a.out = bout;
+  a.out_bs = n;
+  a.alpha = 0.0;
+  a.beta = c64{0.0, -1.0};
+  a.gamma = 0.0;
+  a.want_norm = 1;
+  a.part = part_vec;
+  launch_lines_any<double>(N, LineOp::RowsFwdEpilogue, a, s);
+}
+
+// h(in) -> hout (type T)
+template <typename T>
+void Pipeline::h_of(const void* in, size_t in_bs, void* hout, size_t hout_bs, void* Tbuf, int B, const int* act,
+                    hipStream_t s) const {
+  moments<T>(in, in_bs, Tbuf, B, act, s);
+  LineArgs a = base(B, act);
+  a.tw = tw_of<T>(tw);
+  a.in = in;
+  a.in_bs = in_bs;
+  a.out = Tbuf;
+  a.out_bs = n;
+  launch_lines_any<T>(N, LineOp::RowsInvRegular, a, s);
+  a.in = Tbuf;
+  a.in_bs = n;
+  a.hout = hout;
+  a.hout_bs = hout_bs;
+  launch_lines_any<T>(N, LineOp::ColsInvTail, a, s);
+}
+
+template <typename T>
+void Pipeline::transform(bool inverse, const void* in, void* out, void* Tbuf, hipStream_t s) const {
+  LineArgs a = base(1, nullptr);
+  a.tw = tw_of<T>(tw);
+  if (inverse) {
+    a.in = in;
+    a.out = Tbuf;
+    launch_lines_any<T>(N, LineOp::RowsInvScaled, a, s);
+    a.in = Tbuf;
+    a.out = out;
+    launch_lines_any<T>(N, LineOp::ColsInvPlain, a, s);
+  } else {
+    a.in = in;
+    a.out = Tbuf;
+    launch_lines_any<T>(N, LineOp::ColsFwdPlain, a, s);
+    a.in = Tbuf;
+    a.out = out;
+    a.alpha = 0.0;
+    a.beta = c64{1.0, 0.0};
+    launch_lines_any<T>(N, LineOp::RowsFwdEpilogue, a, s);
+  }
+}
+
+template void Pipeline::apply<double>(const void*, size_t, void*, size_t, const void*, size_t, void*, int, const int*,
+                                      double, double, const void*, size_t, bool, hipStream_t) const;
+template void Pipeline::apply<float>(const void*, size_t, void*, size_t, const void*, size_t, void*, int, const int*,
+                                     double, double, const void*, size_t, bool, hipStream_t) const;
+template void Pipeline::h_of<double>(const void*, size_t, void*, size_t, void*, int, const int*, hipStream_t) const;
+template void Pipeline::h_of<float>(const void*, size_t, void*, size_t, void*, int, const int*, hipStream_t) const;
+template void Pipeline::transform<double>(bool, const void*, void*, void*, hipStream_t) const;
+template void Pipeline::transform<float>(bool, const void*, void*, void*, hipStream_t) const;
+
+int make_pipeline(const dbar_grid* g, Work& w, Pipeline* p) {
+  int rc = get_twiddles(g->n, &p->tw);
+  if (rc) return rc;
+  p->N = g->n;
+  p->M = g->M;
+  p->L = g->L;
+  p->n = (size_t)g->n * g->n;
+  p->ex = static_cast<const c64*>(w.ex.p);
+  p->ey = static_cast<const c64*>(w.ey.p);
+  p->coefG = static_cast<c64*>(w.coefG.p);
+  p->dmom = static_cast<c64*>(w.dmom.p);
+  p->part_mom = static_cast<double*>(w.part_mom.p);
+  p->part_vec = static_cast<double*>(w.part_vec.p);
+  return DBAR_OK;
+}
+
+// ------------------------------------------------------------------------------------------------------------
+// GMRES driver for one batch of entries
+// ------------------------------------------------------------------------------------------------------------
+int ctl_blocks(int B) { return (B + 63) / 64; }
+
+// One Krylov cycle in lockstep; returns the number of iterations run (max over entries).
+template <typename T>
+int krylov_cycle(const Pipeline& P, Work& w, const BatchCfg& cfg, int it_budget, hipStream_t s) {
+  const int B = w.B;
+  const size_t n = w.n;
+  const size_t V_bs = n * (w.m + 1);
+  Ctl* ctl = static_cast<Ctl*>(w.ctl.p);
+  int* act = static_cast<int*>(w.act.p);
+  double* dred = static_cast<double*>(w.dred.p);
+  double* nred = static_cast<double*>(w.nred.p);
+  double* part = static_cast<double*>(w.part_vec.p);
+  const int nvb = vec_blocks(n);
+  const void* Qp = sizeof(T) == 8 ? w.Q64.p : w.Q32.p;
+  void* Tbuf = sizeof(T) == 8 ? w.T64.p : w.T32.p;
+  char* V = static_cast<char*>(w.V.p);
+  const int mlim = std::min(w.m, it_budget);
+  int j = 0;
+  for (; j < mlim; ++j) {
+    void* vj = V + (size_t)j * n * sizeof(cx<T>);
+    void* vj1 = V + (size_t)(j + 1) * n * sizeof(cx<T>);
+    P.apply<T>(vj, V_bs, vj1, V_bs, Qp, w.Q_bs, Tbuf, B, act, 1.0, 1.0, nullptr, 0, false, s);
+    for (int pass = 0; pass < cfg.reorth; ++pass) {
+      VecArgs va;
+      va.B = B;
+      va.act = act;
+      va.n = n;
+      va.V = V;
+      va.V_bs = V_bs;
+      va.nv = j + 1;
+      va.w = vj1;
+      va.w_bs = V_bs;
+      va.part = part;
+      va.want_self = 0;
+      launch_dots<T>(va, s);
+      launch_reduce(part, j + 1, nvb, dred, B, act, s);
+      hipLaunchKernelGGL(k_ctl_coef, dim3(ctl_blocks(B)), dim3(64), 0, s, ctl, dred, j + 1, act, j, pass, B);
+      va.coef = &ctl[0].coef[0];
+      va.coef_bs = sizeof(Ctl) / sizeof(double);
+      va.want_self = pass + 1 == cfg.reorth ? 1 : 0;
+      launch_update<T>(va, s);
+    }
+    launch_reduce(part, 1, nvb, nred, B, act, s);
+    hipLaunchKernelGGL(k_ctl_givens, dim3(ctl_blocks(B)), dim3(64), 0, s, ctl, nred, act, j, mlim, B);
+    if ((j + 1) % cfg.check_every == 0 || j + 1 == mlim) {
+      (void)hipMemcpyAsync(w.host_act.data(), act, B * sizeof(int), hipMemcpyDeviceToHost, s);
+      (void)hipStreamSynchronize(s);
+      bool any = false;
+      for (int b = 0; b < B; ++b) any |= w.host_act[b] != 0;
+      if (!any) return j + 1;
+    }
+  }
+  return j;
+}
+
+// x += sum coef_i V_i and the FP64 residual r = b - A(x) (into r_out), with squared norms in nred
+template <typename T>
+void end_cycle(const Pipeline& P, Work& w, int nv, void* r_out, hipStream_t s) {
+  const int B = w.B;
+  const size_t n = w.n;
+  Ctl* ctl = static_cast<Ctl*>(w.ctl.p);
+  int* live = static_cast<int*>(w.live.p);
+  hipLaunchKernelGGL(k_ctl_trisolve, dim3(ctl_blocks(B)), dim3(64), 0, s, ctl, live, B);
+  VecArgs va;
+  va.B = B;
+  va.act = live;
+  va.n = n;
+  va.V = w.V.p;
+  va.V_bs = n * (w.m + 1);
+  va.nv = nv;
+  va.w = w.x.p;
+  va.w_bs = n;
+  va.coef = &ctl[0].coef[0];
+  va.coef_bs = sizeof(Ctl) / sizeof(double);
+  launch_axpy_multi<double, T>(va, s);
+  P.apply<double>(w.x.p, n, r_out, sizeof(T) == 8 ? n * (w.m + 1) : n, w.Q64.p, w.Q_bs, w.T64.p, B, live, -1.0,
+                  -1.0, w.bvec.p, n, true, s);
+  launch_reduce(static_cast<double*>(w.part_vec.p), 1, line_tiles(w.N, false, true), static_cast<double*>(w.nred.p),
+                B, live, s);
+}
+
+template int krylov_cycle<float>(const Pipeline&, Work&, const BatchCfg&, int, hipStream_t);
+template int krylov_cycle<double>(const Pipeline&, Work&, const BatchCfg&, int, hipStream_t);
+template void end_cycle<float>(const Pipeline&, Work&, int, void*, hipStream_t);
+template void end_cycle<double>(const Pipeline&, Work&, int, void*, hipStream_t);
+
+void launch_ctl_check(Work& w, double tol, int first, const int* mask, const double* tolv, hipStream_t s) {
+  TimerScope ts(kStageControl, 0.0, w.B, nullptr, s);
+  hipLaunchKernelGGL(k_ctl_check, dim3(ctl_blocks(w.B)), dim3(64), 0, s, static_cast<Ctl*>(w.ctl.p),
+                     static_cast<const double*>(w.nred.p), static_cast<int*>(w.live.p), tol, first, mask, tolv, w.B);
+}
+void launch_ctl_start(Work& w, double abs_tol, double rel_tol, const double* tolv, hipStream_t s) {
+  TimerScope ts(kStageControl, 0.0, w.B, nullptr, s);
+  hipLaunchKernelGGL(k_ctl_start, dim3(ctl_blocks(w.B)), dim3(64), 0, s, static_cast<Ctl*>(w.ctl.p),
+                     static_cast<const double*>(w.nred.p), static_cast<const int*>(w.live.p),
+                     static_cast<int*>(w.act.p), abs_tol, rel_tol, tolv, w.B);
+}
+
+int run_batch(const Pipeline& P, Work& w, const BatchCfg& cfg, hipStream_t s, std::vector<int>& iters_out) {
+  const int B = w.B;
+  const size_t n = w.n;
+  const bool mixed = w.prec == DBAR_MIXED;
+  Ctl* ctl = static_cast<Ctl*>(w.ctl.p);
+  int* act = static_cast<int*>(w.act.p);
+  int* live = static_cast<int*>(w.live.p);
+  double* nred = static_cast<double*>(w.nred.p);
+  // b = -i F(q_k), |b|
+  P.rhs(w.Q64.p, w.Q_bs, w.T64.p, static_cast<c64*>(w.bvec.p), B, nullptr, s);
+  launch_reduce(static_cast<double*>(w.part_vec.p), 1, line_tiles(w.N, false, true), nred, B, nullptr, s);
+  if (hipMemsetAsync(w.x.p, 0, (size_t)B * n * sizeof(c64), s) != hipSuccess)
+    return fail(DBAR_EDEVICE, "hipMemsetAsync failed");
+  for (int b = 0; b < B; ++b) w.host_live[b] = 1;
+  if (hipMemcpyAsync(live, w.host_live.data(), B * sizeof(int), hipMemcpyHostToDevice, s) != hipSuccess)
+    return fail(DBAR_EDEVICE, "hipMemcpyAsync failed");
+  // r0 = b (x0 = 0); entries with b = 0 are done at once
+  hipLaunchKernelGGL(k_ctl_check, dim3(ctl_blocks(B)), dim3(64), 0, s, ctl, nred, live, 0.0, 1, nullptr, nullptr, B);
+  if (mixed) {
+    launch_convert<float, double>(w.bvec.p, n, w.V.p, n * (w.m + 1), n, B, nullptr, 1.0, s);
+  } else {
+    launch_convert<double, double>(w.bvec.p, n, w.V.p, n * (w.m + 1), n, B, nullptr, 1.0, s);
+  }
+  int first = 1;
+  int total = 0;
+  iters_out.assign(B, 0);
+  while (true) {
+    (void)hipMemcpyAsync(w.host_live.data(), live, B * sizeof(int), hipMemcpyDeviceToHost, s);
+    if (hipStreamSynchronize(s) != hipSuccess) return fail(DBAR_EDEVICE, "stream synchronize failed");
+    bool any = false;
+    for (int b = 0; b < B; ++b) any |= w.host_live[b] != 0;
+    if (!any || total >= cfg.max_iter) break;
+    const double rel = mixed ? cfg.inner_tol : 0.0;
+    const double abs_tol = mixed ? 0.3 * cfg.tol : 0.5 * cfg.tol;
+    hipLaunchKernelGGL(k_ctl_start, dim3(ctl_blocks(B)), dim3(64), 0, s, ctl, nred, live, act, abs_tol, rel, nullptr, B);
+    first = 0;
+    int ran;
+    if (mixed) {
+      ran = krylov_cycle<float>(P, w, cfg, cfg.max_iter - total, s);
+      end_cycle<float>(P, w, ran, w.r64.p, s);
+    } else {
+      ran = krylov_cycle<double>(P, w, cfg, cfg.max_iter - total, s);
+      end_cycle<double>(P, w, ran, w.V.p, s);
+    }
+    total += ran;
+    hipLaunchKernelGGL(k_ctl_check, dim3(ctl_blocks(B)), dim3(64), 0, s, ctl, nred, live, cfg.tol, 0, nullptr, nullptr, B);
+    if (mixed) launch_convert<float, double>(w.r64.p, n, w.V.p, n * (w.m + 1), n, B, live, 1.0, s);
+    if (ran == 0) break;
+  }
+  if (hipStreamSynchronize(s) != hipSuccess) return fail(DBAR_EDEVICE, "stream synchronize failed");
+  return DBAR_OK;
+}
+
+// ------------------------------------------------------------------------------------------------------------
+// C ABI helpers
+// ------------------------------------------------------------------------------------------------------------
+static bool all_finite(const double* p, size_t cnt) {
+  for (size_t i = 0; i < cnt; ++i)
+    if (!std::isfinite(p[i])) return false;
+  return true;
+}
+
+static int check_device() {
+  int cnt = 0;
+  hipError_t e = hipGetDeviceCount(&cnt);
+  if (e != hipSuccess || cnt < 1) {
+    (void)hipGetLastError();
+    return fail(DBAR_EDEVICE, "no HIP device available");
+  }
+  return DBAR_OK;
+}
+
+int solve_impl(const dbar_grid* grid, const void* Q, bool q_on_device, int64_t nk, const double* k, double tol,
+               const dbar_opts* opts_in, void* S, void* m, bool out_on_device, dbar_info* info, hipStream_t s) {
+  int rc = validate_grid(grid);
+  if (rc) return rc;
+  if (nk < 1) return fail(DBAR_EINVAL, "nk must be >= 1");
+  if (!k || !Q) return fail(DBAR_EINVAL, "Q and k must not be NULL");
+  if (!(tol > 0.0) || !std::isfinite(tol)) return fail(DBAR_EINVAL, "tol must be finite and > 0");
+  if (!all_finite(k, 2 * (size_t)nk)) return fail(DBAR_EINVAL, "k contains NaN or Inf");
+  dbar_opts o;
+  dbar_default_opts(&o);
+  if (opts_in) o = *opts_in;
+  if (o.precision != DBAR_FP64 && o.precision != DBAR_MIXED)
+    return fail(DBAR_EINVAL, "precision must be DBAR_FP64 or DBAR_MIXED for a solve");
+  if (o.restart <= 0) o.restart = o.precision == DBAR_MIXED ? 20 : 40;
+  if (o.restart > kMaxRestart) return fail(DBAR_EINVAL, "restart must be <= 64");
+  if (o.max_iter <= 0) o.max_iter = 1000;
+  if (o.reorth < 1 || o.reorth > 2) o.reorth = 2;
+  if (o.check_every <= 0) o.check_every = 4;
+  if (!(o.inner_tol > 0.0) || o.inner_tol >= 1.0) o.inner_tol = 1e-5;
+  if ((rc = check_device())) return rc;
+  const int N = grid->n;
+  const size_t n = (size_t)N * N;
+  std::lock_guard<std::mutex> lock(g_mutex);
+  // Q on the host: check finiteness
+  std::vector<double> hQ;
+  if (!q_on_device) {
+    if (!all_finite(static_cast<const double*>(Q), 2 * n)) return fail(DBAR_EINVAL, "Q contains NaN or Inf");
+  }
+  int B = o.mode == DBAR_MODE_PLAIN ? 1 : (o.batch > 0 ? o.batch : (int)std::min<int64_t>(nk, 64));
+  B = (int)std::min<int64_t>(B, nk);
+  if (o.mode != DBAR_MODE_PLAIN && o.batch <= 0) {
+    // fit the batch to free memory: basis + 6 vectors per entry
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) == hipSuccess) {
+      const size_t per = n * ((o.restart + 1) * (o.precision == DBAR_MIXED ? 8 : 16) + 6 * 16) + 65536;
+      const size_t cap = (size_t)(0.7 * (double)fr) / per;
+      if (cap >= 1 && (size_t)B > cap) B = (int)cap;
+    }
+  }
+  Work& w = g_work;
+  if ((rc = w.setup(N, B, o.restart, o.precision, true))) return rc;
+  Pipeline P;
+  if ((rc = make_pipeline(grid, w, &P))) return rc;
+  if (q_on_device) {
+    if (hipMemcpyAsync(w.Q64.p, Q, n * sizeof(c64), hipMemcpyDeviceToDevice, s) != hipSuccess)
+      return fail(DBAR_EDEVICE, "Q copy failed");
+  } else {
+    if (hipMemcpyAsync(w.Q64.p, Q, n * sizeof(c64), hipMemcpyHostToDevice, s) != hipSuccess)
+      return fail(DBAR_EDEVICE, "Q upload failed");
+  }
+  if (o.precision == DBAR_MIXED) launch_convert<float, double>(w.Q64.p, 0, w.Q32.p, 0, n, 1, nullptr, 1.0, s);
+  BatchCfg cfg;
+  cfg.tol = tol;
+  cfg.max_iter = o.max_iter;
+  cfg.reorth = o.reorth;
+  cfg.check_every = o.mode == DBAR_MODE_PLAIN ? 1 : o.check_every;
+  cfg.inner_tol = o.inner_tol;
+  std::vector<c64> hex((size_t)B * N), hey((size_t)B * N);
+  std::vector<Ctl> hctl(B);
+  std::vector<c64> s00(B);
+  int result = DBAR_OK;
+  for (int64_t k0 = 0; k0 < nk; k0 += B) {
+    const int nb = (int)std::min<int64_t>(B, nk - k0);
+    w.B = nb;
+    for (int b = 0; b < nb; ++b)
+      phase_tables(N, grid->L, k[2 * (k0 + b)], k[2 * (k0 + b) + 1], &hex[(size_t)b * N], &hey[(size_t)b * N]);
+    if (hipMemcpyAsync(w.ex.p, hex.data(), (size_t)nb * N * sizeof(c64), hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(w.ey.p, hey.data(), (size_t)nb * N * sizeof(c64), hipMemcpyHostToDevice, s) != hipSuccess)
+      return fail(DBAR_EDEVICE, "phase table upload failed");
+    std::vector<int> its;
+    if ((rc = run_batch(P, w, cfg, s, its))) return rc;
+    // outputs: S = x, m = h(x)
+    if (S) {
+      char* dst = static_cast<char*>(S) + (size_t)k0 * n * sizeof(c64);
+      if (hipMemcpyAsync(dst, w.x.p, (size_t)nb * n * sizeof(c64),
+                         out_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s) != hipSuccess)
+        return fail(DBAR_EDEVICE, "S copy failed");
+    }
+    if (m) {
+      P.h_of<double>(w.x.p, n, w.T64.p, n, w.bvec.p, nb, nullptr, s);  // bvec reused as scratch
+      char* dst = static_cast<char*>(m) + (size_t)k0 * n * sizeof(c64);
+      if (hipMemcpyAsync(dst, w.T64.p, (size_t)nb * n * sizeof(c64),
+                         out_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s) != hipSuccess)
+        return fail(DBAR_EDEVICE, "m copy failed");
+    }
+    (void)hipMemcpy2DAsync(s00.data(), sizeof(c64), w.x.p, n * sizeof(c64), sizeof(c64), nb, hipMemcpyDeviceToHost,
+                           s);
+    (void)hipMemcpyAsync(hctl.data(), w.ctl.p, (size_t)nb * sizeof(Ctl), hipMemcpyDeviceToHost, s);
+    (void)hipMemcpyAsync(w.host_live.data(), w.live.p, nb * sizeof(int), hipMemcpyDeviceToHost, s);
+    if (hipStreamSynchronize(s) != hipSuccess) return fail(DBAR_EDEVICE, "stream synchronize failed");
+    for (int b = 0; b < nb; ++b) {
+      const Ctl& c = hctl[b];
+      const bool ok = w.host_live[b] == 0;
+      if (!ok) result = DBAR_ENOCONV;
+      if (info) {
+        dbar_info& I = info[k0 + b];
+        I.status = ok ? DBAR_OK : DBAR_ENOCONV;
+        I.iters = c.iters;
+        I.outer = c.cycles;
+        I.reserved = 0;
+        I.rel_residual = c.bnorm > 0.0 ? c.rnorm / c.bnorm : 0.0;
+        I.m1_re = -s00[b].im;  // m1 = i S(0)
+        I.m1_im = s00[b].re;
+      }
+    }
+  }
+  if (result == DBAR_ENOCONV) fail(DBAR_ENOCONV, "GMRES reached max_iter before tol for some k");
+  return result;
+}
+
+}  // namespace dbar
+
+// ------------------------------------------------------------------------------------------------------------
+// C ABI
+// ------------------------------------------------------------------------------------------------------------
+using namespace dbar;
+
+extern "C" {
+
+void dbar_default_opts(dbar_opts* o) {
+  if (!o) return;
+  o->restart = 0;
+  o->max_iter = 1000;
+  o->precision = DBAR_FP64;
+  o->mode = DBAR_MODE_BATCHED;
+  o->batch = 0;
+  o->use_graph = 1;
+  o->reorth = 2;
+  o->check_every = 4;
+  o->inner_tol = 1e-5;
+}
+
+const char* dbar_last_error(void) { return g_last_error.c_str(); }
+
+int dbar_version(void) { return 100; }
+
+void dbar_release(void) {
+  std::lock_guard<std::mutex> lock(g_mutex);
+  g_work = Work();
+  g_twiddles.clear();
+}
+
+int dbar_solve(const dbar_grid* grid, const double* Q, int64_t nk, const double* k, double tol, const dbar_opts* opts,
+               double* S_out, double* m_out, dbar_info* info) {
+  return solve_impl(grid, Q, false, nk, k, tol, opts, S_out, m_out, false, info, nullptr);
+}
+
+int dbar_solve_device(const dbar_grid* grid, const void* Q_dev, int64_t nk, const double* k, double tol,
+                      const dbar_opts* opts, void* S_dev, void* m_dev, dbar_info* info, void* stream) {
+  return solve_impl(grid, Q_dev, true, nk, k, tol, opts, S_dev, m_dev, true, info,
+                    static_cast<hipStream_t>(stream));
+}
+
+static int single_prep(const dbar_grid* grid, int precision, Work*& w, Pipeline& P) {
+  int rc = validate_grid(grid);
+  if (rc) return rc;
+  if (precision != DBAR_FP64 && precision != DBAR_FP32) return fail(DBAR_EINVAL, "precision must be FP64 or FP32");
+  if ((rc = check_device())) return rc;
+  w = &g_work;
+  if ((rc = w->setup(grid->n, 1, 1, precision == DBAR_FP32 ? DBAR_MIXED : DBAR_FP64, true))) return rc;
+  w->B = 1;
+  return make_pipeline(grid, *w, &P);
+}
+
+int dbar_apply(const dbar_grid* grid, const double* Q, const double* k, const double* S_in, double* AS_out,
+               int32_t precision) {
+  if (!Q || !k || !S_in || !AS_out) return fail(DBAR_EINVAL, "NULL buffer");
+  std::lock_guard<std::mutex> lock(g_mutex);
+  Work* w;
+  Pipeline P;
+  int rc = single_prep(grid, precision, w, P);
+  if (rc) return rc;
+  const int N = grid->n;
+  const size_t n = (size_t)N * N;
+  if (!all_finite(Q, 2 * n) || !all_finite(k, 2) || !all_finite(S_in, 2 * n))
+    return fail(DBAR_EINVAL, "NaN or Inf in the inputs");
+  std::vector<c64> hex(N), hey(N);
+  phase_tables(N, grid->L, k[0], k[1], hex.data(), hey.data());
+  hipStream_t s = nullptr;
+  (void)hipMemcpy(w->ex.p, hex.data(), N * sizeof(c64), hipMemcpyHostToDevice);
+  (void)hipMemcpy(w->ey.p, hey.data(), N * sizeof(c64), hipMemcpyHostToDevice);
+  (void)hipMemcpy(w->Q64.p, Q, n * sizeof(c64), hipMemcpyHostToDevice);
+  (void)hipMemcpy(w->x.p, S_in, n * sizeof(c64), hipMemcpyHostToDevice);
+  if (precision == DBAR_FP64) {
+    P.apply<double>(w->x.p, n, w->bvec.p, n, w->Q64.p, 0, w->T64.p, 1, nullptr, 1.0, 1.0, nullptr, 0, false, s);
+    if (hipMemcpy(AS_out, w->bvec.p, n * sizeof(c64), hipMemcpyDeviceToHost) != hipSuccess)
+      return fail(DBAR_EDEVICE, "copy back failed");
+  } else {
+    launch_convert<float, double>(w->Q64.p, 0, w->Q32.p, 0, n, 1, nullptr, 1.0, s);
+    launch_convert<float, double>(w->x.p, 0, w->V.p, 0, n, 1, nullptr, 1.0, s);
+    char* V1 = static_cast<char*>(w->V.p) + n * sizeof(c32);
+    P.apply<float>(w->V.p, n, V1, n, w->Q32.p, 0, w->T32.p, 1, nullptr, 1.0, 1.0, nullptr, 0, false, s);
+    launch_convert<double, float>(V1, 0, w->bvec.p, 0, n, 1, nullptr, 1.0, s);
+    if (hipMemcpy(AS_out, w->bvec.p, n * sizeof(c64), hipMemcpyDeviceToHost) != hipSuccess)
+      return fail(DBAR_EDEVICE, "copy back failed");
+  }
+  if (hipDeviceSynchronize() != hipSuccess) return fail(DBAR_EDEVICE, "kernel failure");
+  return DBAR_OK;
+}
+
+int dbar_transform(const dbar_grid* grid, int32_t inverse, const double* in, double* out, int32_t precision) {
+  if (!in || !out) return fail(DBAR_EINVAL, "NULL buffer");
+  std::lock_guard<std::mutex> lock(g_mutex);
+  Work* w;
+  Pipeline P;
+  int rc = single_prep(grid, precision, w, P);
+  if (rc) return rc;
+  const size_t n = (size_t)grid->n * grid->n;
+  if (!all_finite(in, 2 * n)) return fail(DBAR_EINVAL, "NaN or Inf in the input");
+  (void)hipMemcpy(w->x.p, in, n * sizeof(c64), hipMemcpyHostToDevice);
+  if (precision == DBAR_FP64) {
+    P.transform<double>(inverse != 0, w->x.p, w->bvec.p, w->T64.p, nullptr);
+  } else {
+    launch_convert<float, double>(w->x.p, 0, w->V.p, 0, n, 1, nullptr, 1.0, nullptr);
+    char* V1 = static_cast<char*>(w->V.p) + n * sizeof(c32);
+    P.transform<float>(inverse != 0, w->V.p, V1, w->T32.p, nullptr);
+    launch_convert<double, float>(V1, 0, w->bvec.p, 0, n, 1, nullptr, 1.0, nullptr);
+  }
+  if (hipMemcpy(out, w->bvec.p, n * sizeof(c64), hipMemcpyDeviceToHost) != hipSuccess)
+    return fail(DBAR_EDEVICE, "copy back failed");
+  return DBAR_OK;
+}
+
+int dbar_dbar_inverse(const dbar_grid* grid, const double* S_in, double* h_out, int32_t precision) {
+  if (!S_in || !h_out) return fail(DBAR_EINVAL, "NULL buffer");
+  std::lock_guard<std::mutex> lock(g_mutex);
+  Work* w;
+  Pipeline P;
+  int rc = single_prep(grid, precision, w, P);
+  if (rc) return rc;
+  const size_t n = (size_t)grid->n * grid->n;
+  if (!all_finite(S_in, 2 * n)) return fail(DBAR_EINVAL, "NaN or Inf in the input");
+  (void)hipMemcpy(w->x.p, S_in, n * sizeof(c64), hipMemcpyHostToDevice);
+  if (precision == DBAR_FP64) {
+    P.h_of<double>(w->x.p, n, w->bvec.p, n, w->T64.p, 1, nullptr, nullptr);
+  } else {
+    launch_convert<float, double>(w->x.p, 0, w->V.p, 0, n, 1, nullptr, 1.0, nullptr);
+    char* V1 = static_cast<char*>(w->V.p) + n * sizeof(c32);
+    P.h_of<float>(w->V.p, n, V1, n, w->T32.p, 1, nullptr, nullptr);
+    launch_convert<double, float>(V1, 0, w->bvec.p, 0, n, 1, nullptr, 1.0, nullptr);
+  }
+  if (hipMemcpy(h_out, w->bvec.p, n * sizeof(c64), hipMemcpyDeviceToHost) != hipSuccess)
+    return fail(DBAR_EDEVICE, "copy back failed");
+  return DBAR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,162 @@
+"""Python binding of the D-bar GPU library: argument marshalling only (every step runs in the HIP library).
+
+Host functions take numpy complex128 arrays; the ``*_device`` variant takes torch tensors on the GPU (complex128)
+and runs on the current torch stream.  Array layouts are those of include/dbar.h: x-space a[iy, ix], xi-space
+A[p2, p1] in FFT order (wave number m = p for p <= N/2, p - N otherwise, xi = m / L).
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import _lib
+from ._lib import (DBAR_EAGAIN, DBAR_ENOCONV, DBAR_FP32, DBAR_FP64, DBAR_MIXED, DBAR_MODE_BATCHED,  # noqa: F401
+                   DBAR_MODE_PLAIN, DBAR_OK, DbarError, check)
+
+_D = ctypes.POINTER(ctypes.c_double)
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(_D)
+
+
+def _c128(a, shape=None) -> np.ndarray:
+    a = np.ascontiguousarray(a, dtype=np.complex128)
+    if shape is not None and a.shape != shape:
+        raise ValueError(f"expected shape {shape}, got {a.shape}")
+    return a
+
+
+def _grid(N: int, L: float, M: int) -> _lib.Grid:
+    return _lib.Grid(int(N), int(M), float(L))
+
+
+@dataclass
+class SolveInfo:
+    status: int
+    iters: int
+    outer: int
+    rel_residual: float
+    m1: complex
+
+
+def default_opts() -> _lib.Opts:
+    o = _lib.Opts()
+    _lib.load().dbar_default_opts(ctypes.byref(o))
+    return o
+
+
+def make_opts(precision=DBAR_FP64, mode=DBAR_MODE_BATCHED, restart=0, max_iter=1000, batch=0, use_graph=1,
+              reorth=2, check_every=4, inner_tol=1e-5) -> _lib.Opts:
+    o = default_opts()
+    o.precision, o.mode, o.restart, o.max_iter, o.batch = precision, mode, restart, max_iter, batch
+    o.use_graph, o.reorth, o.check_every, o.inner_tol = use_graph, reorth, check_every, inner_tol
+    return o
+
+
+def _infos(arr) -> list[SolveInfo]:
+    return [SolveInfo(i.status, i.iters, i.outer, i.rel_residual, complex(i.m1_re, i.m1_im)) for i in arr]
+
+
+def solve(Q: np.ndarray, ks, L: float, tol: float = 1e-12, M: int = 11, want_m: bool = True, **opt_kw):
+    """Solve A(S) = b for every k in ``ks`` (host arrays).  Returns (S [nk,N,N], m [nk,N,N] or None, infos)."""
+    Q = _c128(Q)
+    N = Q.shape[0]
+    ks = np.ascontiguousarray(np.atleast_1d(np.asarray(ks, dtype=np.complex128)))
+    nk = ks.size
+    S = np.empty((nk, N, N), np.complex128)
+    m = np.empty((nk, N, N), np.complex128) if want_m else None
+    info = (_lib.Info * nk)()
+    g = _grid(N, L, M)
+    o = make_opts(**opt_kw)
+    rc = _lib.load().dbar_solve(ctypes.byref(g), _dptr(Q), nk, _dptr(ks.view(np.float64)), float(tol),
+                                ctypes.byref(o), _dptr(S), _dptr(m) if m is not None else None, info)
+    check(rc, allow=(DBAR_OK, DBAR_ENOCONV))
+    return S, m, _infos(info)
+
+
+def solve_device(Q, ks, L: float, tol: float = 1e-12, M: int = 11, want_m: bool = True, **opt_kw):
+    """As solve, with torch complex128 tensors on the GPU (Q [N,N]); returns device tensors S, m and infos."""
+    import torch
+    if not (isinstance(Q, torch.Tensor) and Q.is_cuda and Q.dtype == torch.complex128):
+        raise TypeError("Q must be a complex128 torch tensor on the GPU")
+    Q = Q.contiguous()
+    N = Q.shape[0]
+    ks = np.ascontiguousarray(np.atleast_1d(np.asarray(ks, dtype=np.complex128)))
+    nk = ks.size
+    S = torch.empty((nk, N, N), dtype=torch.complex128, device=Q.device)
+    m = torch.empty((nk, N, N), dtype=torch.complex128, device=Q.device) if want_m else None
+    info = (_lib.Info * nk)()
+    g = _grid(N, L, M)
+    o = make_opts(**opt_kw)
+    stream = torch.cuda.current_stream(Q.device).cuda_stream
+    rc = _lib.load().dbar_solve_device(ctypes.byref(g), ctypes.c_void_p(Q.data_ptr()), nk,
+                                       _dptr(ks.view(np.float64)), float(tol), ctypes.byref(o),
+                                       ctypes.c_void_p(S.data_ptr()),
+                                       ctypes.c_void_p(m.data_ptr()) if m is not None else None, info,
+                                       ctypes.c_void_p(stream))
+    check(rc, allow=(DBAR_OK, DBAR_ENOCONV))
+    return S, m, _infos(info)
+
+
+def apply(Q: np.ndarray, k: complex, S: np.ndarray, L: float, M: int = 11, precision: int = DBAR_FP64):
+    """One application A(S) = S + i F(q_k conj(h(S)))."""
+    Q = _c128(Q)
+    N = Q.shape[0]
+    S = _c128(S, (N, N))
+    out = np.empty((N, N), np.complex128)
+    kk = np.array([complex(k)], np.complex128)
+    g = _grid(N, L, M)
+    check(_lib.load().dbar_apply(ctypes.byref(g), _dptr(Q), _dptr(kk.view(np.float64)), _dptr(S), _dptr(out),
+                                 int(precision)))
+    return out
+
+
+def transform(f: np.ndarray, L: float, inverse: bool = False, precision: int = DBAR_FP64):
+    """The grid transform consistent with the continuous F (inverse=False) or its inverse."""
+    f = _c128(f)
+    N = f.shape[0]
+    out = np.empty((N, N), np.complex128)
+    g = _grid(N, L, 11)
+    check(_lib.load().dbar_transform(ctypes.byref(g), 1 if inverse else 0, _dptr(f), _dptr(out), int(precision)))
+    return out
+
+
+def dbar_inverse(S: np.ndarray, L: float, M: int = 11, precision: int = DBAR_FP64):
+    """The regularised h(S) = F^{-1}(S / xi) of Section 4.2."""
+    S = _c128(S)
+    N = S.shape[0]
+    out = np.empty((N, N), np.complex128)
+    g = _grid(N, L, M)
+    check(_lib.load().dbar_dbar_inverse(ctypes.byref(g), _dptr(S), _dptr(out), int(precision)))
+    return out
+
+
+def timer_enable(on: bool = True):
+    """Start (clear) or stop the per-stage launch timer."""
+    check(_lib.load().dbar_timer_enable(1 if on else 0))
+
+
+def timer_stages() -> list[dict]:
+    """Per-stage totals recorded by the launch timer: name, total_ms, launches, bytes (algorithmic)."""
+    lib = _lib.load()
+    out = []
+    for st in range(lib.dbar_timer_num_stages()):
+        name = ctypes.create_string_buffer(64)
+        ms, nb = ctypes.c_double(), ctypes.c_double()
+        cnt = ctypes.c_int64()
+        check(lib.dbar_timer_stage(st, name, 64, ctypes.byref(ms), ctypes.byref(cnt), ctypes.byref(nb)))
+        if cnt.value:
+            out.append(dict(stage=st, name=name.value.decode(), total_ms=ms.value, launches=cnt.value,
+                            bytes=nb.value))
+    return out
+
+
+def release():
+    _lib.load().dbar_release()
+
+
+def version() -> int:
+    return _lib.load().dbar_version()

@@ -1,0 +1,83 @@
+"""CPU tests of the C ABI boundary: the library loads, exports every function include/*.h declares, and rejects bad
+arguments before touching a device (no compute calls here)."""
+import ctypes
+import glob
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_1508_02363_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        text = open(h).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for m in re.finditer(r"^\s*(?:const\s+)?[A-Za-z_][\w\s\*]*?\b(dbar_\w+)\s*\(", text, flags=re.M):
+            names.add(m.group(1))
+    return names
+
+
+def test_header_declares_the_binding_list():
+    assert declared_functions() == set(_lib.EXPORTED)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _lib.load()
+    out = subprocess.run(["nm", "-D", "--defined-only", _lib.LIB_PATH], capture_output=True, text=True).stdout
+    exported = {ln.split()[-1] for ln in out.splitlines() if ln.strip()}
+    missing = declared_functions() - exported
+    assert not missing, missing
+    for name in declared_functions():
+        assert hasattr(lib, name)
+    assert lib.dbar_version() >= 100
+
+
+def _solve_rc(N=16, M=11, L=2.0, nk=1, tol=1e-12, k=(0.5, 0.25), Q=None):
+    lib = _lib.load()
+    g = _lib.Grid(N, M, L)
+    n = max(N, 1) ** 2
+    Qa = np.zeros(2 * n) if Q is None else Q
+    ka = np.array(k, dtype=np.float64)
+    S = np.zeros(2 * n * max(nk, 1))
+    D = ctypes.POINTER(ctypes.c_double)
+    return lib.dbar_solve(ctypes.byref(g), Qa.ctypes.data_as(D), nk, ka.ctypes.data_as(D), tol, None,
+                          S.ctypes.data_as(D), None, None)
+
+
+@pytest.mark.parametrize("kw", [dict(N=100), dict(N=4), dict(N=8192), dict(L=-1.0), dict(L=float("nan")),
+                                dict(M=16), dict(M=-1), dict(nk=0), dict(tol=0.0), dict(tol=float("inf")),
+                                dict(k=(float("nan"), 0.0))])
+def test_invalid_arguments_are_rejected(kw):
+    assert _solve_rc(**kw) == _lib.DBAR_EINVAL
+    assert _lib.load().dbar_last_error().decode()
+
+
+def test_nan_in_potential_is_rejected():
+    Q = np.zeros(2 * 16 * 16)
+    Q[7] = np.nan
+    rc = _solve_rc(Q=Q)
+    assert rc in (_lib.DBAR_EINVAL, _lib.DBAR_EDEVICE)  # device check may come first on a CPU-only host
+
+
+def test_request_footprint_is_monotone_in_grid_and_restart():
+    lib = _lib.load()
+    f = lambda N, r, p=_lib.DBAR_MIXED: lib.dbar_request_footprint(ctypes.byref(_lib.Grid(N, 11, 5.0)), p, r)
+    assert f(256, 20) < f(512, 20) < f(1024, 20) < f(2048, 20)
+    assert f(1024, 10) < f(1024, 20)
+    assert f(1024, 20, _lib.DBAR_MIXED) < f(1024, 20, _lib.DBAR_FP64)
+    # mixed precision at N=1024, restart 20: 21 FP32 basis vectors + 5 FP64 + 2 FP32 arrays of 2^20 elements
+    assert f(1024, 20) >= (21 * 8 + 5 * 16 + 2 * 8) * 2 ** 20
+    assert lib.dbar_request_footprint(ctypes.byref(_lib.Grid(100, 11, 5.0)), _lib.DBAR_MIXED, 20) == 0
+
+
+def test_default_opts():
+    o = _lib.Opts()
+    _lib.load().dbar_default_opts(ctypes.byref(o))
+    assert o.max_iter == 1000 and o.reorth == 2 and o.precision == _lib.DBAR_FP64 and o.inner_tol == 1e-5

@@ -1,0 +1,156 @@
+"""GPU parity: the HIP library (through its C ABI) against the oracle, element by element on seeded inputs.
+
+Tolerances (relative to the largest magnitude of the reference):
+* FP64 transforms: 1e-13 (a length-N FFT accumulates O(eps log N) relative error, eps = 1.1e-16);
+* FP64 operator / regularised inverse: 1e-12 (adds z^n-weighted moment sums, whose rounding grows with |z|^n, and
+  the closed-form tail evaluated by a different but equally accurate recurrence);
+* FP32 transforms and operator: 2e-5 (eps_32 = 6e-8 times the same growth factors);
+* FP64 solves: 1e-10 relative L-infinity error of S and m (GMRES stops at a relative residual of 1e-12; the dense
+  LU pins show condition numbers below 50, so the error bound kappa * tol is far below 1e-10).
+"""
+import numpy as np
+import pytest
+
+import dbar_workloads as W
+from oracle import dbar_oracle as O
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1508_02363_amd import dbar as D  # noqa: E402
+
+
+def relerr(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def rand_c(rng, shape):
+    return rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+
+
+def smooth_xi(g, rng, width=3.0):
+    """A random smooth, rapidly decaying xi-space function (as the Krylov vectors are)."""
+    base = rand_c(rng, (g.N, g.N))
+    return O.Fd(g, np.exp(-np.abs(g.z) ** 2 / width) * O.Fd_inv(g, base * np.exp(-np.abs(g.xi) ** 2 / 8)))
+
+
+SIZES = [8, 16, 32, 64, 128, 256, 512]
+
+
+@pytest.mark.parametrize("N", SIZES + [1024])
+def test_transform_fp64(N):
+    rng = np.random.default_rng(N)
+    L = 0.25 * N / 8 + 1.0
+    g = O.make_grid(N, L)
+    f = rand_c(rng, (N, N))
+    assert relerr(D.transform(f, L), O.Fd(g, f)) < 1e-13
+    assert relerr(D.transform(f, L, inverse=True), O.Fd_inv(g, f)) < 1e-13
+
+
+@pytest.mark.parametrize("N", [16, 128, 1024])
+def test_transform_fp32(N):
+    rng = np.random.default_rng(N + 1)
+    L = 3.0
+    g = O.make_grid(N, L)
+    f = rand_c(rng, (N, N))
+    assert relerr(D.transform(f, L, precision=D.DBAR_FP32), O.Fd(g, f)) < 2e-5
+    assert relerr(D.transform(f, L, inverse=True, precision=D.DBAR_FP32), O.Fd_inv(g, f)) < 2e-5
+
+
+@pytest.mark.parametrize("N", SIZES)
+def test_regularised_inverse_random(N):
+    rng = np.random.default_rng(100 + N)
+    L = max(1.0, N / 32.0)
+    g = O.make_grid(N, L)
+    S = smooth_xi(g, rng)
+    want, _, _ = O.regularised_h(g, S, 11)
+    assert relerr(D.dbar_inverse(S, L), want) < 1e-12
+
+
+def test_regularised_inverse_dbartest_fig1():
+    """The paper's inversion test (a = 1/2, b = 1, c = i, L = 4, N = 128, M = 11): GPU equals the exact inverse to
+    machine precision, as the oracle does."""
+    g = O.make_grid(128, 4.0)
+    f = np.exp(-0.5 * (g.z - 1.0) * (np.conj(g.z) - 1j))
+    exact = 0.5j * (1 - f) / (0.5 * (g.z - 1.0))
+    h = D.dbar_inverse(O.Fd(g, f), 4.0)
+    assert np.max(np.abs(h - exact)) < 1e-13
+
+
+@pytest.mark.parametrize("N,k", [(8, 0.3 + 0.1j), (16, 1 + 0.5j), (32, -0.7 + 0.2j), (64, 1.5 - 1.0j),
+                                 (128, 1 + 0.5j), (256, -2.0 + 2.0j), (512, 3.0 - 1.0j)])
+def test_apply_fp64(N, k):
+    rng = np.random.default_rng(200 + N)
+    L = max(1.0, N / 32.0)
+    g = O.make_grid(N, L)
+    Q = (0.8 + 0.6j) * np.exp(-np.abs(g.z) ** 2)
+    S = smooth_xi(g, rng)
+    assert relerr(D.apply(Q, k, S, L), O.apply_A(g, Q, k, S)) < 1e-12
+
+
+@pytest.mark.parametrize("N", [16, 128, 512])
+def test_apply_fp32(N):
+    rng = np.random.default_rng(300 + N)
+    L = max(1.0, N / 32.0)
+    g = O.make_grid(N, L)
+    Q = W.potential_gaussian_sum(N, L, seed=N)
+    S = smooth_xi(g, rng)
+    k = 0.5 - 0.25j
+    assert relerr(D.apply(Q, k, S, L, precision=D.DBAR_FP32), O.apply_A(g, Q, k, S)) < 2e-5
+
+
+def test_apply_born_closed_form():
+    """K(S0) on the GPU equals the corrected closed-form first Born term (Section 5.1)."""
+    from test_oracle_operator import born_S1
+    g = O.make_grid(128, 4.0)
+    A, k = 0.8 + 0.6j, 1 + 0.5j
+    Q = A * np.exp(-np.abs(g.z) ** 2)
+    S0 = O.rhs(g, Q, k)
+    K_S0 = S0 - D.apply(Q, k, S0, 4.0)
+    assert np.max(np.abs(K_S0 - born_S1(g, A, k))) < 1e-13
+
+
+@pytest.mark.parametrize("mode", [D.DBAR_MODE_PLAIN, D.DBAR_MODE_BATCHED])
+def test_solve_plain_n128(mode):
+    w = W.workload("plain_n128")
+    g = O.make_grid(w.N, w.L)
+    ref = O.solve(g, w.Q, w.ks[0], tol=1e-13)
+    S, m, info = D.solve(w.Q, w.ks, w.L, tol=w.tol, mode=mode)
+    assert info[0].status == 0 and info[0].rel_residual <= w.tol
+    assert relerr(S[0], ref.S) < 1e-10
+    assert relerr(m[0], ref.m) < 1e-10
+    assert abs(info[0].m1 - ref.m1) < 1e-10 * abs(ref.m1)
+
+
+def test_solve_batched_small_grid_many_k():
+    """Eight k values in one batch on N = 64 against the oracle, with different iteration counts per k."""
+    N, L = 64, 3.0
+    g = O.make_grid(N, L)
+    Q = W.potential_gaussian_sum(N, L, seed=7)
+    ks = W.k_disk(8, 2.0, seed=8)
+    S, m, info = D.solve(Q, ks, L, tol=1e-12, batch=8)
+    for j, k in enumerate(ks):
+        ref = O.solve(g, Q, k, tol=1e-13)
+        assert info[j].status == 0
+        assert relerr(S[j], ref.S) < 1e-10, j
+        assert relerr(m[j], ref.m) < 1e-10, j
+
+
+def test_solve_zero_potential():
+    N, L = 32, 3.0
+    S, m, info = D.solve(np.zeros((N, N)), [1 + 1j, 0.5], L, tol=1e-12)
+    assert np.all(S == 0) and np.all(m == 0)
+    assert info[0].iters == 0 and info[0].status == 0
+
+
+def test_solve_mixed_precision_n128():
+    w = W.workload("plain_n128")
+    g = O.make_grid(w.N, w.L)
+    ref = O.solve(g, w.Q, w.ks[0], tol=1e-13)
+    S, m, info = D.solve(w.Q, w.ks, w.L, tol=1e-12, precision=D.DBAR_MIXED)
+    assert info[0].status == 0 and info[0].rel_residual <= 1e-12
+    assert relerr(S[0], ref.S) < 1e-10
+    assert relerr(m[0], ref.m) < 1e-10
