@@ -37,11 +37,80 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-context", action="store_true", help="skip the FP64 batched / plain path timings")
     ap.add_argument("--headline", choices=["auto", "mixed", "fp64"], default="auto")
+    ap.add_argument("--no-serving", action="store_true", help="skip the request-stream (p50/p99 latency) leg")
+    ap.add_argument("--serving-requests", type=int, default=48)
+    ap.add_argument("--probe", choices=["mixed", "fp64"], default=None,
+                    help="counter-collection mode: one warm step of the given path plus a 256 MiB device copy of "
+                         "known size (the calibration kernel for FETCH_SIZE / WRITE_SIZE); prints one JSON line")
     return ap.parse_args()
 
 
 def rel_linf(a, b):
     return float(np.max(np.abs(a - b)) / max(float(np.max(np.abs(b))), 1e-300))
+
+
+def serving_leg(D, W, n_req: int) -> dict:
+    """Poisson request stream over grids N in {256, 512, 1024, 2048} (k uniform in |k| <= 6, Gaussian-sum or sech^2
+    potentials with |A| <= 2, mixed precision to 1e-10).  The saturated capacity is measured first with a burst of
+    requests; the stream then arrives at 0.8 x that rate.  Latency = submit -> result on the host."""
+    import threading
+
+    burst = W.serving_stream(32, rate=1.0, seed=50)
+    stream = W.serving_stream(n_req, rate=1.0, seed=5)
+    with D.Session(max_slots=64) as s:
+        t0 = time.perf_counter()
+        tk = [s.submit(r.Q, r.k, r.L, tol=r.tol) for r in burst]
+        for t in tk:
+            s.wait(t)
+        capacity = len(burst) / (time.perf_counter() - t0)
+        rate = 0.8 * capacity
+        # rescale the unit-rate arrival times to the target rate
+        arrivals = [r.t_arrival / rate for r in stream]
+        lat, infos, done_at = {}, {}, {}
+        lock = threading.Lock()
+        pending = []
+        stop = [False]
+
+        def poller():
+            while True:
+                with lock:
+                    todo = list(pending)
+                for t in todo:
+                    res = s.poll(t)
+                    if res is not None:
+                        with lock:
+                            pending.remove(t)
+                        lat[t], infos[t], done_at[t] = res[3], res[2], time.perf_counter()
+                if stop[0] and not todo:
+                    return
+                time.sleep(0.0005)
+
+        th = threading.Thread(target=poller)
+        th.start()
+        t_start = time.perf_counter()
+        for r, ta in zip(stream, arrivals):
+            dt = t_start + ta - time.perf_counter()
+            if dt > 0:
+                time.sleep(dt)
+            t = s.submit(r.Q, r.k, r.L, tol=r.tol)
+            with lock:
+                pending.append(t)
+        stop[0] = True
+        th.join()
+        t_end = max(done_at.values())
+    L_ms = np.array([v * 1e3 for v in lat.values()])
+    by_n = {}
+    for r, t in zip(stream, sorted(lat)):
+        by_n.setdefault(r.N, []).append(lat[t] * 1e3)
+    return {
+        "requests": n_req, "grid_sizes": [256, 512, 1024, 2048], "precision": "mixed", "tol": 1e-10,
+        "saturated_capacity_solves_per_s": capacity, "arrival_rate_per_s": rate,
+        "solves_per_s": n_req / (t_end - t_start),
+        "p50_latency_ms": float(np.percentile(L_ms, 50)), "p99_latency_ms": float(np.percentile(L_ms, 99)),
+        "p50_latency_ms_by_N": {int(k): float(np.percentile(v, 50)) for k, v in sorted(by_n.items())},
+        "max_rel_residual": max(i.rel_residual for i in infos.values()),
+        "all_converged": all(i.status == 0 for i in infos.values()),
+    }
 
 
 def main():
@@ -72,6 +141,20 @@ def main():
         "fp64": dict(precision=D.DBAR_FP64),
         "plain": dict(precision=D.DBAR_FP64, mode=D.DBAR_MODE_PLAIN),
     }
+
+    if args.probe:
+        kw = paths[args.probe]
+        step(**kw)
+        torch.cuda.synchronize()
+        step(**kw)
+        src = torch.ones(16 * 2 ** 20, dtype=torch.complex128, device=dev)  # 256 MiB
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"probe": args.probe, "copy_bytes_read": src.numel() * 16, "copy_bytes_written":
+                          dst.numel() * 16}))
+        return
 
     def timed(kw, steps, warmup):
         out = None
@@ -155,6 +238,9 @@ def main():
         "stage_time_share_of_step": total_stage_ms / (sec * 1e3),
         "context": context,
     }
+
+    if not args.no_serving:
+        result["serving"] = serving_leg(D, W, args.serving_requests)
 
     if not args.no_cpu_baseline:
         from threadpoolctl import threadpool_limits

@@ -201,21 +201,24 @@ DBAR_D void fft_pass_regs(cx<T>* v, int jt, const cx<T>* __restrict__ tw) {
 #pragma unroll
     for (int r = 0; r < R; ++r) b[r] = v[q + r * NB];
     if constexpr (NS > 1) {
+      // W^r from the table entries for the powers of two in r (at most 3 products: r < 16), formed per element so
+      // that only log2(R) twiddles are live at a time
       const int k = j % NS;
-      cx<T> w[R];
-      w[0] = cx<T>{T(1), T(0)};
+      constexpr int LR = R == 16 ? 4 : R == 8 ? 3 : R == 4 ? 2 : 1;
+      cx<T> wp[LR];
 #pragma unroll
-      for (int r = 1; r < R; ++r) {
-        if ((r & (r - 1)) == 0) {
-          cx<T> t = tw[r * k * TS];  // table holds exp(-2 pi i m / N)
-          w[r] = DIR < 0 ? t : conj(t);
-        } else {
-          const int hb = 1 << (31 - __builtin_clz(r));
-          w[r] = w[hb] * w[r - hb];
-        }
+      for (int q2 = 0; q2 < LR; ++q2) {
+        const cx<T> t = tw[(1 << q2) * k * TS];  // table holds exp(-2 pi i m / N)
+        wp[q2] = DIR < 0 ? t : conj(t);
       }
 #pragma unroll
-      for (int r = 1; r < R; ++r) b[r] = b[r] * w[r];
+      for (int r = 1; r < R; ++r) {
+        cx<T> wr = wp[__builtin_ctz(r)];
+#pragma unroll
+        for (int q2 = __builtin_ctz(r) + 1; q2 < LR; ++q2)
+          if (r & (1 << q2)) wr = wr * wp[q2];
+        b[r] = b[r] * wr;
+      }
     }
     dft<R, DIR>(b);
 #pragma unroll

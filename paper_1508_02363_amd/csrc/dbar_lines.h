@@ -38,40 +38,43 @@ DBAR_D double xgrid(int j, double L) {
 // u <  M+1: omega_n = i E_n (conj(z)/4)^{n+1} with E_n = e^{-u} sum_k u^k/(n+1+k)!  (equation fourreg5a with the
 //           factor e^{-u}); E_M by its series, E_n = u E_{n+1} + e^{-u}/(n+1)! downwards (positive terms only).
 // u >= M+1: omega_n = i (1 - e^{-u} sum_{k<=n} u^k/k!) / z^{n+1}  (equation fourreg5); no cancellation there.
-DBAR_D c64 tail_sum(double x, double y, const c64* __restrict__ d, int M) {
-  const double u = 0.25 * (x * x + y * y);
-  const double eu = exp(-u);
-  c64 acc{0.0, 0.0};
-  if (u < M + 1) {
-    double term = kInvFact[M + 1], sum = term;
+// TT is the arithmetic type: double in the FP64 operator, float in the FP32 one (whose data carry 24-bit mantissas).
+template <typename TT>
+DBAR_D cx<TT> tail_sum(TT x, TT y, const c64* __restrict__ d, int M) {
+  const TT u = TT(0.25) * (x * x + y * y);
+  const TT eu = exp(-u);
+  const TT eps = sizeof(TT) == 8 ? TT(1e-17) : TT(3e-8);
+  cx<TT> acc{TT(0), TT(0)};
+  if (u < TT(M + 1)) {
+    TT term = TT(kInvFact[M + 1]), sum = term;
     for (int k = 1; k < 200; ++k) {
-      term *= u / (M + 1 + k);
+      term *= u / TT(M + 1 + k);
       sum += term;
-      if (term < 1e-17 * sum) break;
+      if (term < eps * sum) break;
     }
-    double E = eu * sum;
-    const c64 zeta{0.25 * x, -0.25 * y};
-    acc = E * d[M];
+    TT E = eu * sum;
+    const cx<TT> zeta{TT(0.25) * x, TT(-0.25) * y};
+    acc = E * cvt<TT>(d[M]);
     for (int n = M - 1; n >= 0; --n) {
-      E = u * E + eu * kInvFact[n + 1];
-      acc = E * d[n] + zeta * acc;
+      E = u * E + eu * TT(kInvFact[n + 1]);
+      acc = E * cvt<TT>(d[n]) + zeta * acc;
     }
     acc = zeta * acc;
   } else {
-    double P[kMaxM + 1];
-    double t = eu, S = eu;
+    TT P[kMaxM + 1];
+    TT t = eu, S = eu;
 #pragma unroll
     for (int n = 0; n <= kMaxM; ++n) {
-      P[n] = 1.0 - S;
-      t *= u / (n + 1);
+      P[n] = TT(1) - S;
+      t *= u / TT(n + 1);
       S += t;
     }
-    const double r2 = x * x + y * y;
-    const c64 w{x / r2, -y / r2};  // 1/z
+    const TT r2 = x * x + y * y;
+    const cx<TT> w{x / r2, -y / r2};  // 1/z
 #pragma unroll
     for (int n = kMaxM; n >= 0; --n) {
-      if (n < M) acc = P[n] * d[n] + w * acc;
-      else if (n == M) acc = P[n] * d[n];
+      if (n < M) acc = P[n] * cvt<TT>(d[n]) + w * acc;
+      else if (n == M) acc = P[n] * cvt<TT>(d[n]);
     }
     acc = w * acc;
   }
@@ -136,6 +139,7 @@ struct NoAcc {};
 
 template <typename T, int N>
 struct OpBase {
+  static constexpr bool ROLLED = false;  // heavy per-element epilogue: process through LDS in a rolled loop
   LineArgs a;
   DBAR_D bool active(int b) const { return a.act == nullptr || a.act[b] != 0; }
   DBAR_D const cx<T>* inp(int b) const { return static_cast<const cx<T>*>(a.in) + (size_t)b * a.in_bs; }
@@ -157,36 +161,72 @@ struct OpRowsInvScaled : OpBase<T, N> {
   DBAR_D void store(Acc&, int b, int row, int pos, cx<T> v) const { this->outp(b)[(size_t)row * N + pos] = v; }
 };
 
-// IFFT_cols(in) and accumulate sum z^n s (n <= M) and sum conj(z) s in FP64
+// IFFT_cols(in) and accumulate sum z^n s (n <= M) and sum conj(z) s in FP64.  Along a column x is fixed, so each
+// thread accumulates mu_k = sum_y y^k s (real weights, k <= M) and forms its share of
+// d_n = sum_k C(n,k) x^{n-k} i^k mu_k and conj-moment x mu_0 - i mu_1 once at the end (the binomial terms exceed
+// |z|^n by at most 2^{n/2}, i.e. < 50x at n = 11: a few ulps of FP64).
 template <typename T, int N>
 struct OpColsInvMoments : OpBase<T, N> {
   static constexpr int DIR1 = +1;
   static constexpr bool TWO = false;
+  static constexpr bool ROLLED = true;
   static constexpr int NV = 2 * kNMom;
   struct Acc {
-    double v[2 * kNMom];
+    double v[2 * kNMom];  // first mu_k (k <= M), replaced by d_n and the conj moment in finish()
+    double x;
   };
   DBAR_D cx<T> load(int b, int col, int pos) const { return this->inp(b)[(size_t)pos * N + col]; }
   DBAR_D void store(Acc& acc, int, int col, int pos, cx<T> v) const {
-    const c64 z{xgrid<N>(col, this->a.L), xgrid<N>(pos, this->a.L)};
+    const double y = xgrid<N>(pos, this->a.L);
+    acc.x = xgrid<N>(col, this->a.L);
     const c64 s = cvt<double>(v);
-    c64 p = s;
+    const int K = this->a.M < 1 ? 1 : this->a.M;  // mu_1 is always needed (conj moment)
+    double yp = 1.0;
 #pragma unroll
-    for (int n = 0; n <= kMaxM; ++n) {
-      if (n <= this->a.M) {
-        acc.v[2 * n] += p.re;
-        acc.v[2 * n + 1] += p.im;
-        p = p * z;
+    for (int k = 0; k <= kMaxM; ++k) {
+      if (k <= K) {
+        acc.v[2 * k] += yp * s.re;
+        acc.v[2 * k + 1] += yp * s.im;
+        yp *= y;
       }
     }
-    const c64 t = conj(z) * s;
-    acc.v[2 * (kMaxM + 1)] += t.re;
-    acc.v[2 * (kMaxM + 1) + 1] += t.im;
   }
   template <int NT>
   DBAR_D void finish(Acc& acc, int b, int tile, int ntiles, double* scratch) const {
+    const int M = this->a.M;
+    const double x = acc.x;
+    double out[NV];
+    double xp[kMaxM + 1];
+    xp[0] = 1.0;
+#pragma unroll
+    for (int k = 1; k <= kMaxM; ++k) xp[k] = xp[k - 1] * x;
+#pragma unroll
+    for (int n = 0; n <= kMaxM; ++n) {
+      double re = 0.0, im = 0.0;
+      if (n <= M) {
+        double binom = 1.0;
+#pragma unroll
+        for (int k = 0; k <= n; ++k) {
+          const double c = binom * xp[n - k];
+          const double mr = acc.v[2 * k], mi = acc.v[2 * k + 1];
+          switch (k & 3) {  // i^k mu_k
+            case 0: re += c * mr; im += c * mi; break;
+            case 1: re -= c * mi; im += c * mr; break;
+            case 2: re -= c * mr; im -= c * mi; break;
+            default: re += c * mi; im -= c * mr; break;
+          }
+          binom = binom * (n - k) / (k + 1);
+        }
+      }
+      out[2 * n] = re;
+      out[2 * n + 1] = im;
+    }
+    // conj(z) = x - i y: sum conj(z) s = x mu_0 - i mu_1
+    const double m1r = acc.v[2], m1i = acc.v[3];
+    out[2 * (kMaxM + 1)] = x * acc.v[0] + m1i;
+    out[2 * (kMaxM + 1) + 1] = x * acc.v[1] - m1r;
     double* dst = this->a.part + (size_t)b * NV * ntiles + tile;
-    block_reduce_store<NT, NV>(acc.v, dst, ntiles, scratch);
+    block_reduce_store<NT, NV>(out, dst, ntiles, scratch);
   }
 };
 
@@ -227,24 +267,26 @@ template <typename T, int N, bool TAILONLY>
 struct OpColsInvTail : OpBase<T, N> {
   static constexpr int DIR1 = +1;
   static constexpr bool TWO = !TAILONLY;
+  static constexpr bool ROLLED = true;
   using Acc = NoAcc;
   DBAR_D cx<T> load(int b, int col, int pos) const { return this->inp(b)[(size_t)pos * N + col]; }
-  DBAR_D c64 h_at(int b, int col, int pos, cx<T> v) const {
-    const double x = xgrid<N>(col, this->a.L), y = xgrid<N>(pos, this->a.L);
-    return cvt<double>(v) + tail_sum(x, y, this->a.dmom + (size_t)b * kNMom, this->a.M);
+  DBAR_D cx<T> h_at(int b, int col, int pos, cx<T> v) const {
+    const T x = static_cast<T>(xgrid<N>(col, this->a.L)), y = static_cast<T>(xgrid<N>(pos, this->a.L));
+    return v + tail_sum<T>(x, y, this->a.dmom + (size_t)b * kNMom, this->a.M);
   }
   template <class A>
   DBAR_D void mid(int b, int col, int pos, cx<T>& v) const {
-    const c64 h = h_at(b, col, pos, v);
-    if (this->a.hout) (static_cast<cx<T>*>(this->a.hout) + (size_t)b * this->a.hout_bs)[(size_t)pos * N + col] = cvt<T>(h);
-    const c64 q = cvt<double>((static_cast<const cx<T>*>(this->a.Q) + (size_t)b * this->a.Q_bs)[(size_t)pos * N + col]);
-    const c64 e = this->a.ex[(size_t)b * N + col] * this->a.ey[(size_t)b * N + pos];
-    v = cvt<T>((q * e) * conj(h));
+    const cx<T> h = h_at(b, col, pos, v);
+    if (this->a.hout) (static_cast<cx<T>*>(this->a.hout) + (size_t)b * this->a.hout_bs)[(size_t)pos * N + col] = h;
+    const cx<T> q = (static_cast<const cx<T>*>(this->a.Q) + (size_t)b * this->a.Q_bs)[(size_t)pos * N + col];
+    // the phase is tabulated in FP64 (arguments up to hundreds of radians); the product is formed in T
+    const cx<T> e = cvt<T>(this->a.ex[(size_t)b * N + col] * this->a.ey[(size_t)b * N + pos]);
+    v = (q * e) * conj(h);
   }
   DBAR_D void store(Acc&, int b, int col, int pos, cx<T> v) const {
     if constexpr (TAILONLY) {
-      const c64 h = h_at(b, col, pos, v);
-      (static_cast<cx<T>*>(this->a.hout) + (size_t)b * this->a.hout_bs)[(size_t)pos * N + col] = cvt<T>(h);
+      const cx<T> h = h_at(b, col, pos, v);
+      (static_cast<cx<T>*>(this->a.hout) + (size_t)b * this->a.hout_bs)[(size_t)pos * N + col] = h;
     } else {
       this->outp(b)[(size_t)pos * N + col] = v;
     }
@@ -340,14 +382,41 @@ __global__ void __launch_bounds__(LINES * LineGeom<N>::TPL) k_lines(Op op) {
   for (int s = 0; s < G::RMAX; ++s) v[s] = op.load(b, line, jt + s * G::TPL);
   cx<T>* my = lds + ln * G::LDS_LINE;
   line_fft<T, N, Op::DIR1>(v, jt, my, tw);
+  // Heavy per-element work (FP64 moments, the closed-form tail) runs in a rolled loop over values parked in LDS at
+  // the thread's own positions: registers stay low (occupancy) and no barrier is needed until the next exchange.
   if constexpr (Op::TWO) {
+    if constexpr (Op::ROLLED) {
 #pragma unroll
-    for (int s = 0; s < G::RMAX; ++s) op.template mid<typename Op::Acc>(b, line, jt + s * G::TPL, v[s]);
+      for (int s = 0; s < G::RMAX; ++s) my[G::padded(jt + s * G::TPL)] = v[s];
+#pragma unroll 1
+      for (int s = 0; s < G::RMAX; ++s) {
+        const int pos = jt + s * G::TPL;
+        cx<T> t = my[G::padded(pos)];
+        op.template mid<typename Op::Acc>(b, line, pos, t);
+        my[G::padded(pos)] = t;
+      }
+#pragma unroll
+      for (int s = 0; s < G::RMAX; ++s) v[s] = my[G::padded(jt + s * G::TPL)];
+      __syncthreads();  // the forward transform's first exchange writes other threads' positions
+    } else {
+#pragma unroll
+      for (int s = 0; s < G::RMAX; ++s) op.template mid<typename Op::Acc>(b, line, jt + s * G::TPL, v[s]);
+    }
     line_fft<T, N, -Op::DIR1>(v, jt, my, tw);
   }
   typename Op::Acc acc{};
+  if constexpr (Op::ROLLED && !Op::TWO) {
 #pragma unroll
-  for (int s = 0; s < G::RMAX; ++s) op.store(acc, b, line, jt + s * G::TPL, v[s]);
+    for (int s = 0; s < G::RMAX; ++s) my[G::padded(jt + s * G::TPL)] = v[s];
+#pragma unroll 1
+    for (int s = 0; s < G::RMAX; ++s) {
+      const int pos = jt + s * G::TPL;
+      op.store(acc, b, line, pos, my[G::padded(pos)]);
+    }
+  } else {
+#pragma unroll
+    for (int s = 0; s < G::RMAX; ++s) op.store(acc, b, line, jt + s * G::TPL, v[s]);
+  }
   op.template finish<NT>(acc, b, tile, gridDim.x, reinterpret_cast<double*>(lds));
 }
 

@@ -88,7 +88,7 @@ static size_t footprint_of(int N, int prec, int restart, int cap_hint) {
   per += n * sizeof(c64) * (mixed ? 5 : 4);                                       // x, b, T64, Q64 (+ r64)
   per += mixed ? n * sizeof(c32) * 2 : 0;                                          // T32, Q32
   per += 2 * (size_t)N * sizeof(c64) + sizeof(Ctl) + 2 * kNMom * sizeof(c64);
-  per += (size_t)2 * kNMom * 1024 * sizeof(double) + (size_t)(kMaxRestart + 2) * vec_blocks(n) * sizeof(double);
+  per += (size_t)2 * kNMom * 1024 * sizeof(double) + (size_t)(kMaxRestart + 3) * vec_blocks(n) * sizeof(double);
   (void)cap_hint;
   return per;
 }
@@ -135,7 +135,7 @@ static void worker(dbar_session* s, SClass* cp) {
   BatchCfg cfg;
   cfg.tol = 1e-10;
   cfg.max_iter = 1000;
-  cfg.reorth = 2;
+  cfg.reorth = 1;
   cfg.check_every = 4;
   cfg.inner_tol = 1e-5;
   while (!s->stop.load()) {

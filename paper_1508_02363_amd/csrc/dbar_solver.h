@@ -3,7 +3,10 @@
 
 #include <hip/hip_runtime.h>
 
+#include <map>
 #include <string>
+#include <tuple>
+#include <utility>
 #include <vector>
 
 #include "dbar.h"
@@ -37,6 +40,25 @@ struct DevBuf {
   int ensure(size_t nbytes);
 };
 
+// Pinned host allocation (device-to-host flag reads are DMA transfers, not staging kernels).
+struct PinnedInts {
+  int* p = nullptr;
+  size_t count = 0;
+  PinnedInts() = default;
+  PinnedInts(const PinnedInts&) = delete;
+  PinnedInts& operator=(const PinnedInts&) = delete;
+  PinnedInts(PinnedInts&& o) noexcept : p(o.p), count(o.count) { o.p = nullptr; o.count = 0; }
+  PinnedInts& operator=(PinnedInts&& o) noexcept {
+    std::swap(p, o.p);
+    std::swap(count, o.count);
+    return *this;
+  }
+  ~PinnedInts();
+  int ensure(size_t n);
+  int& operator[](size_t i) { return p[i]; }
+  int* data() { return p; }
+};
+
 struct Twiddles {
   DevBuf d64, d32;  // exp(-2 pi i j / N), j < N
 };
@@ -53,20 +75,28 @@ struct Ctl {
 };
 
 struct BatchCfg {
+  int use_graph = 0;
   double tol = 1e-12;
   int max_iter = 1000;
-  int reorth = 2;
+  int reorth = 1;
   int check_every = 4;
   double inner_tol = 1e-5;
 };
 
 // Device workspace for a batch of B entries on an N x N grid with restart m.
 struct Work {
+  ~Work();
+  Work() = default;
+  Work& operator=(Work&& o) noexcept;
   int N = 0, B = 0, m = 0, prec = 0;
+  // captured Krylov iterations: key (element bytes, j, reorth, B) -> executable graph; dropped on reallocation
+  std::map<std::tuple<int, int, int, int>, hipGraphExec_t> graphs;
+  void drop_graphs();
   size_t n = 0;
   size_t Q_bs = 0;
-  DevBuf x, bvec, T64, r64, T32, V, Q64, Q32, ex, ey, coefG, dmom, part_mom, part_vec, dred, nred, ctl, act, live;
-  std::vector<int> host_act, host_live;
+  DevBuf x, bvec, T64, r64, T32, V, Q64, Q32, ex, ey, coefG, dmom, part_mom, part_vec, part_norm, dred, nred, ctl,
+      act, live;
+  PinnedInts host_act, host_live;
   int setup(int N_, int B_, int m_, int prec_, bool shared_q);
   size_t vec_bytes(int prec) const;
 };

@@ -197,6 +197,23 @@ int DevBuf::ensure(size_t nbytes) {
   return DBAR_OK;
 }
 
+PinnedInts::~PinnedInts() {
+  if (p) (void)hipHostFree(p);
+}
+int PinnedInts::ensure(size_t n) {
+  if (n <= count) return DBAR_OK;
+  if (p) (void)hipHostFree(p);
+  p = nullptr;
+  count = 0;
+  if (hipHostMalloc(reinterpret_cast<void**>(&p), n * sizeof(int), hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    p = nullptr;
+    return fail(DBAR_ENOMEM, "hipHostMalloc failed");
+  }
+  count = n;
+  return DBAR_OK;
+}
+
 static std::mutex g_mutex;      // serialises the one-shot C-ABI calls (shared workspace)
 static std::mutex g_tw_mutex;   // twiddle cache (also used by the serving workers)
 static std::map<int, std::unique_ptr<Twiddles>> g_twiddles;
@@ -248,9 +265,31 @@ void phase_tables(int N, double L, double k1, double k2, c64* ex, c64* ey) {
   }
 }
 
+void Work::drop_graphs() {
+  for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
+  graphs.clear();
+}
+Work::~Work() { drop_graphs(); }
+Work& Work::operator=(Work&& o) noexcept {
+  drop_graphs();
+  N = o.N; B = o.B; m = o.m; prec = o.prec; n = o.n; Q_bs = o.Q_bs;
+  x = std::move(o.x); bvec = std::move(o.bvec); T64 = std::move(o.T64); r64 = std::move(o.r64);
+  T32 = std::move(o.T32); V = std::move(o.V); Q64 = std::move(o.Q64); Q32 = std::move(o.Q32);
+  ex = std::move(o.ex); ey = std::move(o.ey); coefG = std::move(o.coefG); dmom = std::move(o.dmom);
+  part_mom = std::move(o.part_mom); part_vec = std::move(o.part_vec); part_norm = std::move(o.part_norm);
+  dred = std::move(o.dred); nred = std::move(o.nred); ctl = std::move(o.ctl); act = std::move(o.act);
+  live = std::move(o.live); host_act = std::move(o.host_act); host_live = std::move(o.host_live);
+  graphs = std::move(o.graphs);
+  return *this;
+}
+
 size_t Work::vec_bytes(int prec) const { return (size_t)n * (prec == DBAR_FP64 ? sizeof(c64) : sizeof(c32)); }
 
 int Work::setup(int N_, int B_, int m_, int prec_, bool shared_q) {
+  // captured graphs hold raw pointers and sizes of this workspace: drop them if anything can change
+  if (N_ != N || B_ != B || m_ != m || prec_ != prec || (shared_q ? 0 : (size_t)N_ * N_) != Q_bs) drop_graphs();
+  const void* before[] = {x.p, V.p, T64.p, T32.p, ctl.p, act.p, part_vec.p, part_norm.p, part_mom.p, dred.p,
+                          nred.p, Q32.p, Q64.p, ex.p, ey.p, coefG.p, dmom.p};
   N = N_;
   B = B_;
   m = m_;
@@ -278,13 +317,17 @@ int Work::setup(int N_, int B_, int m_, int prec_, bool shared_q) {
   if ((rc = part_mom.ensure((size_t)B * 2 * kNMom * std::max(tiles, rtiles) * sizeof(double)))) return rc;
   if ((rc = part_vec.ensure((size_t)B * (kMaxRestart + 2) * std::max(vec_blocks(n), rtiles) * sizeof(double))))
     return rc;
+  if ((rc = part_norm.ensure((size_t)B * std::max(vec_blocks(n), rtiles) * sizeof(double)))) return rc;
   if ((rc = dred.ensure((size_t)B * (kMaxRestart + 2) * sizeof(double)))) return rc;
   if ((rc = nred.ensure((size_t)B * sizeof(double)))) return rc;
   if ((rc = ctl.ensure((size_t)B * sizeof(Ctl)))) return rc;
   if ((rc = act.ensure((size_t)B * sizeof(int)))) return rc;
   if ((rc = live.ensure((size_t)B * sizeof(int)))) return rc;
-  host_act.resize(B);
-  host_live.resize(B);
+  if ((rc = host_act.ensure(B))) return rc;
+  if ((rc = host_live.ensure(B))) return rc;
+  const void* after[] = {x.p, V.p, T64.p, T32.p, ctl.p, act.p, part_vec.p, part_norm.p, part_mom.p, dred.p,
+                         nred.p, Q32.p, Q64.p, ex.p, ey.p, coefG.p, dmom.p};
+  if (std::memcmp(before, after, sizeof(before)) != 0) drop_graphs();
   return DBAR_OK;
 }
 
@@ -460,6 +503,8 @@ int make_pipeline(const dbar_grid* g, Work& w, Pipeline* p) {
 int ctl_blocks(int B) { return (B + 63) / 64; }
 
 // One Krylov cycle in lockstep; returns the number of iterations run (max over entries).
+// With cfg.use_graph each iteration j is captured once into a HIP graph (per element size, j, passes and batch) and
+// replayed on later cycles and calls; nothing in a captured iteration is a memset or a host transfer.
 template <typename T>
 int krylov_cycle(const Pipeline& P, Work& w, const BatchCfg& cfg, int it_budget, hipStream_t s) {
   const int B = w.B;
@@ -470,13 +515,14 @@ int krylov_cycle(const Pipeline& P, Work& w, const BatchCfg& cfg, int it_budget,
   double* dred = static_cast<double*>(w.dred.p);
   double* nred = static_cast<double*>(w.nred.p);
   double* part = static_cast<double*>(w.part_vec.p);
+  double* pnorm = static_cast<double*>(w.part_norm.p);
   const int nvb = vec_blocks(n);
   const void* Qp = sizeof(T) == 8 ? w.Q64.p : w.Q32.p;
   void* Tbuf = sizeof(T) == 8 ? w.T64.p : w.T32.p;
   char* V = static_cast<char*>(w.V.p);
   const int mlim = std::min(w.m, it_budget);
-  int j = 0;
-  for (; j < mlim; ++j) {
+
+  auto enqueue = [&](int j) {
     void* vj = V + (size_t)j * n * sizeof(cx<T>);
     void* vj1 = V + (size_t)(j + 1) * n * sizeof(cx<T>);
     P.apply<T>(vj, V_bs, vj1, V_bs, Qp, w.Q_bs, Tbuf, B, act, 1.0, 1.0, nullptr, 0, false, s);
@@ -494,14 +540,49 @@ int krylov_cycle(const Pipeline& P, Work& w, const BatchCfg& cfg, int it_budget,
       va.want_self = 0;
       launch_dots<T>(va, s);
       launch_reduce(part, j + 1, nvb, dred, B, act, s);
-      hipLaunchKernelGGL(k_ctl_coef, dim3(ctl_blocks(B)), dim3(64), 0, s, ctl, dred, j + 1, act, j, pass, B);
+      {
+        TimerScope ts(kStageControl, 0.0, B, nullptr, s);
+        hipLaunchKernelGGL(k_ctl_coef, dim3(ctl_blocks(B)), dim3(64), 0, s, ctl, dred, j + 1, act, j, pass, B);
+      }
       va.coef = &ctl[0].coef[0];
       va.coef_bs = sizeof(Ctl) / sizeof(double);
       va.want_self = pass + 1 == cfg.reorth ? 1 : 0;
+      va.part = pnorm;
       launch_update<T>(va, s);
     }
-    launch_reduce(part, 1, nvb, nred, B, act, s);
-    hipLaunchKernelGGL(k_ctl_givens, dim3(ctl_blocks(B)), dim3(64), 0, s, ctl, nred, act, j, mlim, B);
+    launch_reduce(pnorm, 1, nvb, nred, B, act, s);
+    TimerScope ts(kStageControl, 0.0, B, nullptr, s);
+    hipLaunchKernelGGL(k_ctl_givens, dim3(ctl_blocks(B)), dim3(64), 0, s, ctl, nred, act, j, w.m, B);
+  };
+
+  bool graphs = cfg.use_graph && !timer_on();
+  int j = 0;
+  for (; j < mlim; ++j) {
+    bool done = false;
+    if (graphs) {
+      const auto key = std::make_tuple((int)sizeof(T), j, cfg.reorth, B);
+      auto it = w.graphs.find(key);
+      if (it != w.graphs.end()) {
+        done = hipGraphLaunch(it->second, s) == hipSuccess;
+      } else if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+        enqueue(j);
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t ge = nullptr;
+        if (hipStreamEndCapture(s, &graph) == hipSuccess && graph &&
+            hipGraphInstantiate(&ge, graph, nullptr, nullptr, 0) == hipSuccess) {
+          w.graphs[key] = ge;
+          done = hipGraphLaunch(ge, s) == hipSuccess;
+        } else if (ge) {
+          (void)hipGraphExecDestroy(ge);
+        }
+        if (graph) (void)hipGraphDestroy(graph);
+      }
+      if (!done) {
+        (void)hipGetLastError();  // capture or replay unavailable: enqueue directly from now on
+        graphs = false;
+      }
+    }
+    if (!done) enqueue(j);
     if ((j + 1) % cfg.check_every == 0 || j + 1 == mlim) {
       (void)hipMemcpyAsync(w.host_act.data(), act, B * sizeof(int), hipMemcpyDeviceToHost, s);
       (void)hipStreamSynchronize(s);
@@ -628,8 +709,25 @@ static int check_device() {
   return DBAR_OK;
 }
 
+// The solver's own stream (default priority, non-blocking): graph capture needs a stream other than the legacy
+// default one, and the caller's stream is joined through events.
+static hipStream_t g_stream = nullptr;
+static hipEvent_t g_join = nullptr;
+
+static int solver_stream(hipStream_t caller, hipStream_t* out) {
+  if (!g_stream) {
+    if (hipStreamCreateWithFlags(&g_stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&g_join, hipEventDisableTiming) != hipSuccess)
+      return fail(DBAR_EDEVICE, "stream creation failed");
+  }
+  if (hipEventRecord(g_join, caller) != hipSuccess || hipStreamWaitEvent(g_stream, g_join, 0) != hipSuccess)
+    return fail(DBAR_EDEVICE, "stream join failed");
+  *out = g_stream;
+  return DBAR_OK;
+}
+
 int solve_impl(const dbar_grid* grid, const void* Q, bool q_on_device, int64_t nk, const double* k, double tol,
-               const dbar_opts* opts_in, void* S, void* m, bool out_on_device, dbar_info* info, hipStream_t s) {
+               const dbar_opts* opts_in, void* S, void* m, bool out_on_device, dbar_info* info, hipStream_t caller) {
   int rc = validate_grid(grid);
   if (rc) return rc;
   if (nk < 1) return fail(DBAR_EINVAL, "nk must be >= 1");
@@ -644,7 +742,7 @@ int solve_impl(const dbar_grid* grid, const void* Q, bool q_on_device, int64_t n
   if (o.restart <= 0) o.restart = o.precision == DBAR_MIXED ? 20 : 40;
   if (o.restart > kMaxRestart) return fail(DBAR_EINVAL, "restart must be <= 64");
   if (o.max_iter <= 0) o.max_iter = 1000;
-  if (o.reorth < 1 || o.reorth > 2) o.reorth = 2;
+  if (o.reorth < 1 || o.reorth > 2) o.reorth = 1;
   if (o.check_every <= 0) o.check_every = 4;
   if (!(o.inner_tol > 0.0) || o.inner_tol >= 1.0) o.inner_tol = 1e-5;
   if ((rc = check_device())) return rc;
@@ -667,6 +765,8 @@ int solve_impl(const dbar_grid* grid, const void* Q, bool q_on_device, int64_t n
       if (cap >= 1 && (size_t)B > cap) B = (int)cap;
     }
   }
+  hipStream_t s = nullptr;
+  if ((rc = solver_stream(caller, &s))) return rc;
   Work& w = g_work;
   if ((rc = w.setup(N, B, o.restart, o.precision, true))) return rc;
   Pipeline P;
@@ -683,6 +783,7 @@ int solve_impl(const dbar_grid* grid, const void* Q, bool q_on_device, int64_t n
   cfg.tol = tol;
   cfg.max_iter = o.max_iter;
   cfg.reorth = o.reorth;
+  cfg.use_graph = o.mode == DBAR_MODE_PLAIN ? 0 : o.use_graph;
   cfg.check_every = o.mode == DBAR_MODE_PLAIN ? 1 : o.check_every;
   cfg.inner_tol = o.inner_tol;
   std::vector<c64> hex((size_t)B * N), hey((size_t)B * N);
@@ -755,7 +856,7 @@ void dbar_default_opts(dbar_opts* o) {
   o->mode = DBAR_MODE_BATCHED;
   o->batch = 0;
   o->use_graph = 1;
-  o->reorth = 2;
+  o->reorth = 1;
   o->check_every = 4;
   o->inner_tol = 1e-5;
 }
@@ -767,7 +868,14 @@ int dbar_version(void) { return 100; }
 void dbar_release(void) {
   std::lock_guard<std::mutex> lock(g_mutex);
   g_work = Work();
-  g_twiddles.clear();
+  {
+    std::lock_guard<std::mutex> tl(g_tw_mutex);
+    g_twiddles.clear();
+  }
+  if (g_stream) (void)hipStreamDestroy(g_stream);
+  if (g_join) (void)hipEventDestroy(g_join);
+  g_stream = nullptr;
+  g_join = nullptr;
 }
 
 int dbar_solve(const dbar_grid* grid, const double* Q, int64_t nk, const double* k, double tol, const dbar_opts* opts,

@@ -90,6 +90,7 @@ __global__ void __launch_bounds__(kVecBlock) k_update(VecArgs a) {
   }
   for (int i = 0; i < a.nv; ++i) {
     const double c = coef[i];
+    if (c == 0.0) continue;  // also keeps never-written basis slots (any bit pattern) out of the sum
     const cx<T>* Vi = V + (size_t)i * a.n;
 #pragma unroll
     for (int e = 0; e < kVecEPT; ++e) {
@@ -137,6 +138,7 @@ __global__ void __launch_bounds__(kVecBlock) k_axpy_multi(VecArgs a) {
   }
   for (int i = 0; i < a.nv; ++i) {
     const double c = coef[i];
+    if (c == 0.0) continue;  // entries that stopped early have zero coefficients beyond their own iterations
     const cx<TV>* Vi = V + (size_t)i * a.n;
 #pragma unroll
     for (int e = 0; e < kVecEPT; ++e) {

@@ -49,7 +49,7 @@ def default_opts() -> _lib.Opts:
 
 
 def make_opts(precision=DBAR_FP64, mode=DBAR_MODE_BATCHED, restart=0, max_iter=1000, batch=0, use_graph=1,
-              reorth=2, check_every=4, inner_tol=1e-5) -> _lib.Opts:
+              reorth=1, check_every=4, inner_tol=1e-5) -> _lib.Opts:
     o = default_opts()
     o.precision, o.mode, o.restart, o.max_iter, o.batch = precision, mode, restart, max_iter, batch
     o.use_graph, o.reorth, o.check_every, o.inner_tol = use_graph, reorth, check_every, inner_tol
@@ -152,6 +152,69 @@ def timer_stages() -> list[dict]:
             out.append(dict(stage=st, name=name.value.decode(), total_ms=ms.value, launches=cnt.value,
                             bytes=nb.value))
     return out
+
+
+class Session:
+    """Serving session: continuous batching of single-k solves (see include/dbar.h)."""
+
+    def __init__(self, hbm_budget_bytes: int = 0, max_slots: int = 64, precision: int = DBAR_MIXED,
+                 restart: int = 20):
+        o = _lib.SessionOpts(int(hbm_budget_bytes), int(max_slots), int(precision), int(restart), 0)
+        h = ctypes.c_void_p()
+        check(_lib.load().dbar_session_create(ctypes.byref(o), ctypes.byref(h)))
+        self._h = h
+        self._shape = {}
+
+    def submit(self, Q: np.ndarray, k: complex, L: float, tol: float = 1e-10, M: int = 11) -> int:
+        Q = _c128(Q)
+        N = Q.shape[0]
+        kk = np.array([complex(k)], np.complex128)
+        t = ctypes.c_uint64()
+        g = _grid(N, L, M)
+        check(_lib.load().dbar_submit(self._h, ctypes.byref(g), _dptr(Q), _dptr(kk.view(np.float64)), float(tol),
+                                      ctypes.byref(t)))
+        self._shape[t.value] = N
+        return t.value
+
+    def _fetch(self, fn, ticket: int):
+        N = self._shape.get(ticket)
+        info = _lib.Info()
+        lat = ctypes.c_double()
+        if N is None:  # unknown here: let the library report it
+            rc = fn(self._h, ctypes.c_uint64(ticket), None, None, ctypes.byref(info), ctypes.byref(lat))
+            check(rc)
+            return None
+        S = np.empty((N, N), np.complex128)
+        m = np.empty((N, N), np.complex128)
+        rc = fn(self._h, ctypes.c_uint64(ticket), _dptr(S), _dptr(m), ctypes.byref(info), ctypes.byref(lat))
+        if rc == DBAR_EAGAIN:
+            return None
+        check(rc, allow=(DBAR_OK, DBAR_ENOCONV))
+        del self._shape[ticket]
+        return S, m, _infos([info])[0], lat.value
+
+    def poll(self, ticket: int):
+        """(S, m, info, latency_s) if finished, else None."""
+        return self._fetch(_lib.load().dbar_poll, ticket)
+
+    def wait(self, ticket: int):
+        return self._fetch(_lib.load().dbar_wait, ticket)
+
+    def stats(self) -> dict:
+        st = _lib.SessionStats()
+        check(_lib.load().dbar_session_get_stats(self._h, ctypes.byref(st)))
+        return {f: getattr(st, f) for f, _ in st._fields_}
+
+    def close(self):
+        if self._h:
+            _lib.load().dbar_session_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
 
 def release():

@@ -154,3 +154,34 @@ def test_solve_mixed_precision_n128():
     assert info[0].status == 0 and info[0].rel_residual <= 1e-12
     assert relerr(S[0], ref.S) < 1e-10
     assert relerr(m[0], ref.m) < 1e-10
+
+
+def test_graph_replay_equals_direct_launches():
+    """Krylov iterations replayed from captured HIP graphs give bit-identical results to direct launches, over two
+    consecutive calls (the second replays the graphs captured by the first)."""
+    N, L = 64, 3.0
+    Q = W.potential_gaussian_sum(N, L, seed=21)
+    ks = W.k_disk(6, 2.5, seed=22)
+    S0, m0, i0 = D.solve(Q, ks, L, tol=1e-12, batch=6, use_graph=0)
+    for _ in range(2):
+        S1, m1, i1 = D.solve(Q, ks, L, tol=1e-12, batch=6, use_graph=1)
+        assert np.array_equal(S0, S1) and np.array_equal(m0, m1)
+        assert [a.iters for a in i0] == [a.iters for a in i1]
+
+
+def test_solve_two_gram_schmidt_passes():
+    w = W.workload("plain_n128")
+    g = O.make_grid(w.N, w.L)
+    ref = O.solve(g, w.Q, w.ks[0], tol=1e-13)
+    S, m, info = D.solve(w.Q, w.ks, w.L, tol=1e-12, reorth=2)
+    assert info[0].status == 0 and relerr(S[0], ref.S) < 1e-10 and relerr(m[0], ref.m) < 1e-10
+
+
+def test_max_iter_reports_no_convergence():
+    """Forced from the host: two iterations cannot reach 1e-12; the call reports DBAR_ENOCONV per k and still
+    writes the best iterate (its residual is below the initial one)."""
+    w = W.workload("plain_n128")
+    S, m, info = D.solve(w.Q, w.ks, w.L, tol=1e-12, max_iter=2, restart=2)
+    assert info[0].status == D.DBAR_ENOCONV
+    assert 1e-12 < info[0].rel_residual < 1.0
+    assert np.all(np.isfinite(S)) and np.all(np.isfinite(m))
