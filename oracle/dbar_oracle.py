@@ -35,6 +35,7 @@ import numpy as np
 __all__ = [
     "Grid", "make_grid", "Fd", "Fd_inv", "omega", "omega_table", "moments", "G_coefficients", "regularised_h",
     "apply_A", "rhs", "gmres_real", "dense_matrix", "solve", "dense_solve", "SolveResult",
+    "shift_index", "shifted_inverse", "apply_B", "solve_iterated",
 ]
 
 
@@ -319,3 +320,94 @@ def dense_solve(g: Grid, Q: np.ndarray, k: complex, M: int = 11):
     b = _to_real(rhs(g, Q, k))
     x = np.linalg.solve(Amat, b)
     return _to_complex(x, (g.N, g.N)), Amat
+
+
+# ----------------------------------------------------------------------------------------------------------------
+# The iterated integral equation for large k (Section 5.2 equations Sform, eqh, eqh2; Section 5.3 algorithm) with
+# the shifted regularisation of Section 5.1 (equation dbarinvShift).  2k lies on the xi grid (Section 5.3), so the
+# shift by 2i conj(k) is an index roll.
+# ----------------------------------------------------------------------------------------------------------------
+
+def shift_index(g: Grid, k: complex):
+    """Grid offsets (m1, m2) of a = 2i conj(k) = 2 k2 + 2i k1 on the xi grid: m1 = 2 k2 L, m2 = 2 k1 L."""
+    k = complex(k)
+    m1, m2 = 2.0 * k.imag * g.L, 2.0 * k.real * g.L
+    r1, r2 = int(round(m1)), int(round(m2))
+    if abs(m1 - r1) > 1e-9 or abs(m2 - r2) > 1e-9:
+        raise ValueError("the iterated method needs 2k on the xi grid: 2 k1 L and 2 k2 L must be integers")
+    return r1, r2
+
+
+def shifted_inverse(g: Grid, h: np.ndarray, k: complex, M: int, om=None) -> np.ndarray:
+    """F^{-1}(h / (xi - a)), a = 2i conj(k), for h concentrated near xi = 0, regularised about the singular point
+    xi = a (equation dbarinvShift): with G_a = e^{-|xi - a|^2} sum_n c_n conj(xi - a)^n built from the Taylor
+    coefficients of h at a,
+
+        F^{-1}(h/(xi - a)) = F^{-1}((h - G_a)/(xi - a)) + F^{-1}(G_a/(xi - a)),
+
+    where xi - a is formed from the grid's own xi (not reduced modulo the period), so the quotient is smooth inside
+    the domain and only jumps at its edge, where h vanishes.  The Taylor coefficients are
+    d^n h / d conj(xi)^n (a) = (-i/2)^n F(z^n e^{-i a.x} F^{-1} h)(0) (equation fourreeg4 at xi = a), and by the shift
+    theorem F^{-1}(G_a/(xi - a)) = e^{i a.x} sum_n c_n W_n.  Note e^{-i a.x} = e^{conj(kz) - kz}.  The value of
+    (h - G_a)/(xi - a) at xi = a is the limit dh/dxi(a)."""
+    if om is None:
+        om = omega_table(g, M)
+    shift_index(g, k)  # a must be a grid point
+    a = 2j * np.conj(complex(k))
+    ek = e_k(g, k)
+    s = Fd_inv(g, h)
+    d, dt = moments(g, s * ek, M)
+    c = G_coefficients(d)
+    zeta = g.xi - a
+    Ga = np.zeros_like(h)
+    p = np.ones_like(h)
+    for n in range(M + 1):
+        Ga = Ga + c[n] * p
+        p = p * np.conj(zeta)
+    Ga = np.exp(-np.abs(zeta) ** 2) * Ga
+    R = np.empty_like(h)
+    nz = np.abs(zeta) > 1e-12
+    R[nz] = (h[nz] - Ga[nz]) / zeta[nz]
+    R[~nz] = (-0.5j) * dt
+    r = Fd_inv(g, R)
+    tail = np.zeros_like(r)
+    for n in range(M + 1):
+        tail = tail + d[n] * om[n]
+    return r + np.conj(ek) * tail
+
+
+def apply_B(g: Grid, Q: np.ndarray, k: complex, h: np.ndarray, M: int = 11, om=None) -> np.ndarray:
+    """Left-hand side of equation eqh2: h - K0(H),  H = -i F(Q conj(F^{-1}(h/(xi - 2i conj k)))),
+    K0(S) = -i F(Q conj(F^{-1}(S/xi))) (equation shift, with q = Q)."""
+    H = -1j * Fd(g, Q * np.conj(shifted_inverse(g, h, k, M, om)))
+    r, _, _ = regularised_h(g, H, M, om)
+    return h + 1j * Fd(g, Q * np.conj(r))
+
+
+def solve_iterated(g: Grid, Q: np.ndarray, k: complex, tol: float = 1e-13, M: int = 11, restart: int = 40,
+                   max_iter: int = 2000, om=None) -> SolveResult:
+    """Solve eqh2 for h with GMRES (right-hand side -i F(Q)).  Then f = H (the simplification after eqh2 shows
+    K0(h o (xi + a)) o (xi + a) = H), S = f + h o (xi + a) (equation Sform; the second term is an index roll and
+    is meaningful only while it stays inside the xi domain), m = F^{-1}(S/xi) = F^{-1}(f/xi) + e^{-i a.x} F^{-1}(h/(xi-a))
+    (shift theorem), and m^(1) = i S(0) = i (f(0) + h(a)) (equation m1def)."""
+    if om is None:
+        om = omega_table(g, M)
+    b = -1j * Fd(g, Q)
+    shape = b.shape
+
+    def mv(v):
+        return _to_real(apply_B(g, Q, k, _to_complex(v, shape), M, om))
+
+    xr, its, rel = gmres_real(mv, _to_real(b), tol, restart, max_iter)
+    h = _to_complex(xr, shape)
+    m1i, m2i = shift_index(g, k)
+    ha = np.roll(h, (-m2i, -m1i), axis=(0, 1))
+    si = shifted_inverse(g, h, k, M, om)
+    f = -1j * Fd(g, Q * np.conj(si))
+    S = f + ha
+    rf, _, _ = regularised_h(g, f, M, om)
+    m = rf + e_k(g, k) * si
+    res = SolveResult(S, m, 1j * (f[0, 0] + ha[0, 0]), its, rel)
+    res.h = h
+    res.f = f
+    return res
