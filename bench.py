@@ -39,10 +39,85 @@ def parse():
     ap.add_argument("--headline", choices=["auto", "mixed", "fp64"], default="auto")
     ap.add_argument("--no-serving", action="store_true", help="skip the request-stream (p50/p99 latency) leg")
     ap.add_argument("--serving-requests", type=int, default=48)
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"), default=None,
+                    help="no GPU: turn the FETCH_SIZE / WRITE_SIZE counter CSVs of two `--probe` runs into "
+                         "profiles/traffic.json (bytes per launch per stage, scaled by the calibration copy)")
     ap.add_argument("--probe", choices=["mixed", "fp64"], default=None,
                     help="counter-collection mode: one warm step of the given path plus a 256 MiB device copy of "
                          "known size (the calibration kernel for FETCH_SIZE / WRITE_SIZE); prints one JSON line")
     return ap.parse_args()
+
+
+def kernel_source_hash() -> str:
+    """sha256 over the HIP sources: a stored counter measurement is only valid for the kernels it was taken on."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(HERE, "paper_1508_02363_amd", "csrc", "*"))):
+        h.update(os.path.basename(f).encode())
+        h.update(open(f, "rb").read())
+    return h.hexdigest()
+
+
+def stored_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the PMC runs recorded in profiles/traffic.json, or None if none was
+    recorded for it or the kernels changed since."""
+    path = os.path.join(HERE, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("source_sha256") != kernel_source_hash():
+        return None
+    ent = rec.get("kernels", {}).get(kernel)
+    return None if ent is None else ent["bytes_per_launch"]
+
+
+def stage_of_kernel(name: str):
+    """Stage name (as reported by the library's launch timer) of a demangled kernel name from rocprofv3."""
+    ops = {"OpRowsInvScaled": "RowsInvScaled", "OpColsInvMoments": "ColsInvMoments", "OpRowsInvRegular":
+           "RowsInvRegular", "OpRowsFwdEpilogue": "RowsFwdEpilogue", "OpColsFwdPotential": "ColsFwdPotential"}
+    prec = "f32" if "<float" in name else "f64"
+    if "k_lines" in name:
+        if "OpColsInvTail" in name:
+            return f"lines.{'ColsInvTail' if 'true>' in name.split('OpColsInvTail')[1] else 'ColsInvTailFwd'}.{prec}"
+        for k, v in ops.items():
+            if k in name:
+                return f"lines.{v}.{prec}"
+    for k in ("dots", "update"):
+        if f"k_{k}<" in name:
+            return f"krylov.{k}.{prec}"
+    return None
+
+
+def traffic_from(fetch_dir: str, write_dir: str) -> dict:
+    import csv
+    import glob
+
+    def load(d):
+        out = {}
+        for f in glob.glob(os.path.join(d, "*counter_collection.csv")):
+            for r in csv.DictReader(open(f)):
+                out.setdefault(r["Kernel_Name"], []).append((float(r["Counter_Value"]), int(r["Grid_Size"])))
+        return out
+    F, Wt = load(fetch_dir), load(write_dir)
+    cal = "__amd_rocclr_copyBuffer"
+    big = max(g for _, g in F[cal])
+    kib = 256 * 1024  # the probe's calibration copy: 256 MiB read and written
+    ff = kib / [v for v, g in F[cal] if g == big][-1]
+    fw = kib / [v for v, g in Wt[cal] if g == big][-1]
+    kernels = {}
+    for name, vals in F.items():
+        st = stage_of_kernel(name)
+        if st is None or name not in Wt:
+            continue
+        f = sum(v for v, _ in vals) / len(vals) * ff * 1024
+        wv = sum(v for v, _ in Wt[name]) / len(Wt[name]) * fw * 1024
+        kernels[st] = {"bytes_per_launch": f + wv, "fetch_bytes_per_launch": f, "write_bytes_per_launch": wv,
+                       "launches": len(vals)}
+    rec = {"source_sha256": kernel_source_hash(), "fetch_scale": ff, "write_scale": fw, "kernels": kernels}
+    path = os.path.join(HERE, "profiles", "traffic.json")
+    json.dump(rec, open(path, "w"), indent=1)
+    return rec
 
 
 def rel_linf(a, b):
@@ -115,6 +190,11 @@ def serving_leg(D, W, n_req: int) -> dict:
 
 def main():
     args = parse()
+    if args.traffic_from:
+        rec = traffic_from(*args.traffic_from)
+        print(json.dumps({"traffic_stages": len(rec["kernels"]), "fetch_scale": rec["fetch_scale"],
+                          "write_scale": rec["write_scale"]}))
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 (multi-GPU k-sharding is "
                           "described in DESIGN.md but not built)"}))
@@ -228,7 +308,7 @@ def main():
         },
         "roofline": {
             "bound": "hbm", "kernel": dom["name"], "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "frac": achieved / HBM_PEAK_GBS, "traffic": stored_traffic(dom["name"]),
             "launches": dom["launches"], "avg_launch_us": dom["total_ms"] * 1e3 / dom["launches"],
             "bytes_per_launch": dom["bytes"] / dom["launches"],
         },

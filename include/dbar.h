@@ -76,14 +76,22 @@ typedef struct {
                           orthogonality to ~1e-3 on this operator but GMRES reaches the same residual in the same
                           number of iterations; the FP64 residual is recomputed at every cycle end regardless. */
   int32_t check_every; /* batched mode: host reads convergence flags every this many iterations (default 4) */
+  int32_t method;      /* DBAR_METHOD_PLAIN (Section 4, default) or DBAR_METHOD_ITERATED (Section 5.3: the once-iterated
+                          equation eqh2 for h with the regularisation about xi = 2i conj(k), for large |k|; needs
+                          2 L Re k and 2 L Im k to be integers, i.e. 2k on the xi grid, else DBAR_EINVAL) */
+  int32_t reserved;
   double inner_tol;    /* DBAR_MIXED: residual reduction asked of each FP32 inner solve (default 1e-5) */
 } dbar_opts;
+
+enum { DBAR_METHOD_PLAIN = 0, DBAR_METHOD_ITERATED = 1 };
 
 /* Per-k result. */
 typedef struct {
   int32_t status;       /* DBAR_OK or DBAR_ENOCONV */
   int32_t iters;        /* GMRES iterations (operator applications inside Krylov cycles) */
-  int32_t outer;        /* FP64 residual evaluations (refinement steps in DBAR_MIXED; restarts + 1 in FP64) */
+  int32_t outer;        /* FP64 residual evaluations (refinement steps in DBAR_MIXED; restarts + 1 in FP64)
+                           DBAR_METHOD_ITERATED: S = f + h o (xi + 2i conj k) (Sform) and m = F^{-1}(S/xi) evaluated
+                           through the shift theorem; iters/rel_residual refer to the equation for h */
   int32_t reserved;
   double rel_residual;  /* ||b - A(S)||_2 / ||b||_2, recomputed in FP64 with the FP64 operator at the end */
   double m1_re, m1_im;  /* m^(1) = i S(0), the 1/z coefficient of m (equation m1def) */

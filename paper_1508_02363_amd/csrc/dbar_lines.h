@@ -174,12 +174,16 @@ struct OpColsInvMoments : OpBase<T, N> {
   struct Acc {
     double v[2 * kNMom];  // first mu_k (k <= M), replaced by d_n and the conj moment in finish()
     double x;
+    int col;
   };
   DBAR_D cx<T> load(int b, int col, int pos) const { return this->inp(b)[(size_t)pos * N + col]; }
-  DBAR_D void store(Acc& acc, int, int col, int pos, cx<T> v) const {
+  DBAR_D void store(Acc& acc, int b, int col, int pos, cx<T> v) const {
     const double y = xgrid<N>(pos, this->a.L);
     acc.x = xgrid<N>(col, this->a.L);
-    const c64 s = cvt<double>(v);
+    acc.col = col;
+    c64 s = cvt<double>(v);
+    // shifted regularisation: Taylor coefficients at xi = a are moments of s e^{-i a.x} = s e_k (ey here, ex below)
+    if (this->a.shv) s = s * this->a.ey[(size_t)b * this->a.e_bs + pos];
     const int K = this->a.M < 1 ? 1 : this->a.M;  // mu_1 is always needed (conj moment)
     double yp = 1.0;
 #pragma unroll
@@ -195,19 +199,18 @@ struct OpColsInvMoments : OpBase<T, N> {
   DBAR_D void finish(Acc& acc, int b, int tile, int ntiles, double* scratch) const {
     const int M = this->a.M;
     const double x = acc.x;
-    double out[NV];
-    double xp[kMaxM + 1];
-    xp[0] = 1.0;
+    // conj moment first (needs mu_0, mu_1): sum (x - i y) s = x mu_0 - i mu_1
+    acc.v[2 * (kMaxM + 1)] = x * acc.v[0] + acc.v[3];
+    acc.v[2 * (kMaxM + 1) + 1] = x * acc.v[1] - acc.v[2];
+    // d_n = sum_{k<=n} C(n,k) x^{n-k} i^k mu_k, in place from n = M down (d_n only needs mu_k with k <= n)
 #pragma unroll
-    for (int k = 1; k <= kMaxM; ++k) xp[k] = xp[k - 1] * x;
-#pragma unroll
-    for (int n = 0; n <= kMaxM; ++n) {
+    for (int n = kMaxM; n >= 0; --n) {
       double re = 0.0, im = 0.0;
       if (n <= M) {
-        double binom = 1.0;
+        double binom = 1.0, xpow = 1.0;  // C(n,k) and x^{n-k} for k = n, n-1, ..., 0
 #pragma unroll
-        for (int k = 0; k <= n; ++k) {
-          const double c = binom * xp[n - k];
+        for (int k = n; k >= 0; --k) {
+          const double c = binom * xpow;
           const double mr = acc.v[2 * k], mi = acc.v[2 * k + 1];
           switch (k & 3) {  // i^k mu_k
             case 0: re += c * mr; im += c * mi; break;
@@ -215,18 +218,24 @@ struct OpColsInvMoments : OpBase<T, N> {
             case 2: re -= c * mr; im -= c * mi; break;
             default: re += c * mi; im -= c * mr; break;
           }
-          binom = binom * (n - k) / (k + 1);
+          binom = binom * k / (n - k + 1);
+          xpow *= x;
         }
       }
-      out[2 * n] = re;
-      out[2 * n + 1] = im;
+      acc.v[2 * n] = re;
+      acc.v[2 * n + 1] = im;
     }
-    // conj(z) = x - i y: sum conj(z) s = x mu_0 - i mu_1
-    const double m1r = acc.v[2], m1i = acc.v[3];
-    out[2 * (kMaxM + 1)] = x * acc.v[0] + m1i;
-    out[2 * (kMaxM + 1) + 1] = x * acc.v[1] - m1r;
+    if (this->a.shv) {  // the column's factor e^{-2i k2 x}
+      const c64 e = this->a.ex[(size_t)b * this->a.e_bs + acc.col];
+#pragma unroll
+      for (int v = 0; v < kNMom; ++v) {
+        const c64 t = e * c64{acc.v[2 * v], acc.v[2 * v + 1]};
+        acc.v[2 * v] = t.re;
+        acc.v[2 * v + 1] = t.im;
+      }
+    }
     double* dst = this->a.part + (size_t)b * NV * ntiles + tile;
-    block_reduce_store<NT, NV>(out, dst, ntiles, scratch);
+    block_reduce_store<NT, NV>(acc.v, dst, ntiles, scratch);
   }
 };
 
@@ -239,7 +248,9 @@ struct OpRowsInvRegular : OpBase<T, N> {
   DBAR_D cx<T> load(int b, int row, int pos) const {
     const c64* __restrict__ c = this->a.coefG + (size_t)b * kNMom;
     const double invL = 1.0 / this->a.L;
-    const double xi1 = wavenum(pos, N) * invL, xi2 = wavenum(row, N) * invL;
+    // xi - a with a = 2i conj(k) on the grid (not reduced modulo the period: the quotient only jumps at the edge)
+    const int o1 = this->a.shv ? this->a.shv[2 * b] : 0, o2 = this->a.shv ? this->a.shv[2 * b + 1] : 0;
+    const double xi1 = (wavenum(pos, N) - o1) * invL, xi2 = (wavenum(row, N) - o2) * invL;
     const double r2 = xi1 * xi1 + xi2 * xi2;
     c64 R;
     if (r2 == 0.0) {
@@ -270,23 +281,31 @@ struct OpColsInvTail : OpBase<T, N> {
   static constexpr bool ROLLED = true;
   using Acc = NoAcc;
   DBAR_D cx<T> load(int b, int col, int pos) const { return this->inp(b)[(size_t)pos * N + col]; }
+  DBAR_D cx<T> phase(int b, int col, int pos) const {
+    // tabulated in FP64 (arguments up to hundreds of radians); the product is formed in T
+    return cvt<T>(this->a.ex[(size_t)b * this->a.e_bs + col] * this->a.ey[(size_t)b * this->a.e_bs + pos]);
+  }
+  // h = F^{-1}R + sum d_n omega_n; with the shifted regularisation the closed-form part is e^{i a.x} sum d_n omega_n
   DBAR_D cx<T> h_at(int b, int col, int pos, cx<T> v) const {
     const T x = static_cast<T>(xgrid<N>(col, this->a.L)), y = static_cast<T>(xgrid<N>(pos, this->a.L));
-    return v + tail_sum<T>(x, y, this->a.dmom + (size_t)b * kNMom, this->a.M);
+    const cx<T> t = tail_sum<T>(x, y, this->a.dmom + (size_t)b * kNMom, this->a.M);
+    return this->a.shv ? v + conj(phase(b, col, pos)) * t : v + t;
   }
   template <class A>
   DBAR_D void mid(int b, int col, int pos, cx<T>& v) const {
     const cx<T> h = h_at(b, col, pos, v);
     if (this->a.hout) (static_cast<cx<T>*>(this->a.hout) + (size_t)b * this->a.hout_bs)[(size_t)pos * N + col] = h;
     const cx<T> q = (static_cast<const cx<T>*>(this->a.Q) + (size_t)b * this->a.Q_bs)[(size_t)pos * N + col];
-    // the phase is tabulated in FP64 (arguments up to hundreds of radians); the product is formed in T
-    const cx<T> e = cvt<T>(this->a.ex[(size_t)b * N + col] * this->a.ey[(size_t)b * N + pos]);
-    v = (q * e) * conj(h);
+    // plain: q_k = Q e_k; shifted (the operator H of equation eqh2): Q alone
+    v = (this->a.shv ? q : q * phase(b, col, pos)) * conj(h);
   }
   DBAR_D void store(Acc&, int b, int col, int pos, cx<T> v) const {
     if constexpr (TAILONLY) {
-      const cx<T> h = h_at(b, col, pos, v);
-      (static_cast<cx<T>*>(this->a.hout) + (size_t)b * this->a.hout_bs)[(size_t)pos * N + col] = h;
+      cx<T> h = h_at(b, col, pos, v);
+      if (this->a.tail_phase_out) h = phase(b, col, pos) * h;
+      cx<T>* dst = static_cast<cx<T>*>(this->a.hout) + (size_t)b * this->a.hout_bs + (size_t)pos * N + col;
+      if (this->a.accumulate) h = h + *dst;
+      *dst = h;
     } else {
       this->outp(b)[(size_t)pos * N + col] = v;
     }
@@ -329,7 +348,7 @@ struct OpColsFwdPotential : OpBase<T, N> {
   using Acc = NoAcc;
   DBAR_D cx<T> load(int b, int col, int pos) const {
     const c64 q = cvt<double>((static_cast<const cx<T>*>(this->a.Q) + (size_t)b * this->a.Q_bs)[(size_t)pos * N + col]);
-    const c64 e = this->a.ex[(size_t)b * N + col] * this->a.ey[(size_t)b * N + pos];
+    const c64 e = this->a.ex[(size_t)b * this->a.e_bs + col] * this->a.ey[(size_t)b * this->a.e_bs + pos];
     return cvt<T>(q * e);
   }
   DBAR_D void store(Acc&, int b, int col, int pos, cx<T> v) const { this->outp(b)[(size_t)pos * N + col] = v; }
@@ -363,8 +382,16 @@ struct LdsSize {
   static constexpr int kElems = ((kData > kScratch ? kData : kScratch) + (int)sizeof(cx<T>) - 1) / (int)sizeof(cx<T>);
 };
 
+// Occupancy floor: at least 4 waves per SIMD (<= 128 VGPRs) for the wide column tiles, whose LDS allows two
+// blocks per CU only if the registers do too.
+template <int NT>
+struct MinWaves {
+  static constexpr int value = NT >= 256 ? 4 : 1;
+};
+
 template <typename T, int N, int LINES, bool COLS, class Op>
-__global__ void __launch_bounds__(LINES * LineGeom<N>::TPL) k_lines(Op op) {
+__global__ void __launch_bounds__(LINES * LineGeom<N>::TPL, MinWaves<LINES * LineGeom<N>::TPL>::value)
+    k_lines(Op op) {
   using G = LineGeom<N>;
   constexpr int NT = LINES * G::TPL;
   __shared__ cx<T> lds[LdsSize<T, N, LINES>::kElems];

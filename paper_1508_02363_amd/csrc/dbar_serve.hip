@@ -59,7 +59,7 @@ struct SClass {
   DevBuf newmask, finmask, tolv;
   std::vector<int> h_new, h_fin, h_live;
   std::vector<double> h_tol;
-  std::vector<std::vector<c64>> h_ex, h_ey;  // per-slot phase tables (kept alive until the copies complete)
+  std::vector<c64> h_k;  // per-slot k (host source of the async upload; stable until the stream synchronises)
   bool ready = false;
   int error = 0;
 };
@@ -109,8 +109,7 @@ static int class_init(SClass& c) {
   c.h_fin.assign(c.cap, 0);
   c.h_live.assign(c.cap, 0);
   c.h_tol.assign(c.cap, 1e-10);
-  c.h_ex.assign(c.cap, std::vector<c64>(c.N));
-  c.h_ey.assign(c.cap, std::vector<c64>(c.N));
+  c.h_k.assign(c.cap, c64{0.0, 0.0});
   c.w.B = c.cap;
   if (hipMemsetAsync(c.w.live.p, 0, c.cap * sizeof(int), c.stream) != hipSuccess ||
       hipMemsetAsync(c.w.act.p, 0, c.cap * sizeof(int), c.stream) != hipSuccess)
@@ -170,11 +169,11 @@ static void worker(dbar_session* s, SClass* cp) {
         c.h_tol[b] = r.tol;
         (void)hipMemcpyAsync(static_cast<c64*>(w.Q64.p) + (size_t)b * n, r.Q.data(), n * sizeof(c64),
                              hipMemcpyHostToDevice, c.stream);
-        phase_tables(c.N, c.L, r.k[0], r.k[1], c.h_ex[b].data(), c.h_ey[b].data());
-        (void)hipMemcpyAsync(static_cast<c64*>(w.ex.p) + (size_t)b * c.N, c.h_ex[b].data(), c.N * sizeof(c64),
-                             hipMemcpyHostToDevice, c.stream);
-        (void)hipMemcpyAsync(static_cast<c64*>(w.ey.p) + (size_t)b * c.N, c.h_ey[b].data(), c.N * sizeof(c64),
-                             hipMemcpyHostToDevice, c.stream);
+        c.h_k[b] = c64{r.k[0], r.k[1]};
+        (void)hipMemcpyAsync(static_cast<c64*>(w.kvals.p) + b, &c.h_k[b], sizeof(c64), hipMemcpyHostToDevice,
+                             c.stream);
+        launch_phase_tables(static_cast<const c64*>(w.kvals.p) + b, c.N, c.L, static_cast<c64*>(w.ex.p) + (size_t)b * c.N,
+                            static_cast<c64*>(w.ey.p) + (size_t)b * c.N, 1, c.stream);
         (void)hipMemsetAsync(static_cast<c64*>(w.x.p) + (size_t)b * n, 0, n * sizeof(c64), c.stream);
         // host sources (request Q, per-slot tables, masks) stay untouched until the stream synchronises below
       }
@@ -183,7 +182,7 @@ static void worker(dbar_session* s, SClass* cp) {
       (void)hipMemcpyAsync(w.live.p, c.h_live.data(), c.cap * sizeof(int), hipMemcpyHostToDevice, c.stream);
       (void)hipMemcpyAsync(c.tolv.p, c.h_tol.data(), c.cap * sizeof(double), hipMemcpyHostToDevice, c.stream);
       if (mixed) launch_convert<float, double>(w.Q64.p, n, w.Q32.p, n, n, c.cap, nm, 1.0, c.stream);
-      c.P.rhs(w.Q64.p, n, w.T64.p, static_cast<c64*>(w.bvec.p), c.cap, nm, c.stream);
+      c.P.rhs(w.Q64.p, n, w.T64.p, static_cast<c64*>(w.bvec.p), c.cap, nm, 0u, c.stream);
       launch_reduce(static_cast<double*>(w.part_vec.p), 1, line_tiles(c.N, false, true),
                     static_cast<double*>(w.nred.p), c.cap, nm, c.stream);
       launch_ctl_check(w, 0.0, 1, nm, static_cast<const double*>(c.tolv.p), c.stream);

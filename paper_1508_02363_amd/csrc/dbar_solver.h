@@ -74,8 +74,15 @@ struct Ctl {
   int jn, iters, cycles, pad;
 };
 
+struct EntryResult {
+  int iters, cycles;
+  double bnorm, rnorm;
+  c64 s00;
+};
+
 struct BatchCfg {
   int use_graph = 0;
+  int method = 0;  // 0: plain (Section 4), 1: iterated (Section 5.3)
   double tol = 1e-12;
   int max_iter = 1000;
   int reorth = 1;
@@ -95,13 +102,16 @@ struct Work {
   size_t n = 0;
   size_t Q_bs = 0;
   DevBuf x, bvec, T64, r64, T32, V, Q64, Q32, ex, ey, coefG, dmom, part_mom, part_vec, part_norm, dred, nred, ctl,
-      act, live;
+      act, live, kvals, results, shv, unit, Hbuf;
   PinnedInts host_act, host_live;
   int setup(int N_, int B_, int m_, int prec_, bool shared_q);
   size_t vec_bytes(int prec) const;
 };
 
 // The operator pipeline for one grid (pointers into a Work).
+constexpr unsigned kShifted = 1u;    // regularise about xi = a = 2i conj(k) (Section 5.1, equation dbarinvShift)
+constexpr unsigned kUnitPhase = 2u;  // k = 0 phase (the operator K0 of equation shift)
+
 struct Pipeline {
   int N = 0, M = 11;
   double L = 1.0;
@@ -109,30 +119,49 @@ struct Pipeline {
   const Twiddles* tw = nullptr;
   const c64* ex = nullptr;
   const c64* ey = nullptr;
+  const c64* unit = nullptr;
+  const int* shv = nullptr;
   c64* coefG = nullptr;
   c64* dmom = nullptr;
   double* part_mom = nullptr;
   double* part_vec = nullptr;
 
-  LineArgs base(int B, const int* act) const;
+  LineArgs base(int B, const int* act, unsigned flags) const;
   template <typename T>
-  void moments(const void* in, size_t in_bs, void* Tbuf, int B, const int* act, hipStream_t s) const;
+  void moments(const void* in, size_t in_bs, void* Tbuf, int B, const int* act, unsigned flags, hipStream_t s) const;
+  template <typename T>
+  void apply_impl(const void* in, size_t in_bs, void* out, size_t out_bs, const void* Qp, size_t Q_bs, void* Tbuf,
+                  int B, const int* act, double alpha, double beta, const void* Y, size_t Y_bs, bool want_norm,
+                  unsigned flags, const void* S_ep, size_t S_ep_bs, hipStream_t s) const;
+  // A(S) of the plain method (Section 4), as alpha S + beta i F(q_k conj(h(S))) + gamma Y
   template <typename T>
   void apply(const void* in, size_t in_bs, void* out, size_t out_bs, const void* Qp, size_t Q_bs, void* Tbuf, int B,
              const int* act, double alpha, double beta, const void* Y, size_t Y_bs, bool want_norm,
              hipStream_t s) const;
-  void rhs(const void* Q64p, size_t Q_bs, void* T64, c64* bout, int B, const int* act, hipStream_t s) const;
+  // H(h) of equation eqh2
+  template <typename T>
+  void H_of(const void* in, size_t in_bs, void* Hout, size_t H_bs, const void* Qp, size_t Q_bs, void* Tbuf, int B,
+            const int* act, hipStream_t s) const;
+  // B(h) = h - K0(H(h)) of equation eqh2, as alpha h + beta i F(Q conj(F^{-1}(H/xi))) + gamma Y
+  template <typename T>
+  void apply_B(const void* in, size_t in_bs, void* out, size_t out_bs, const void* Qp, size_t Q_bs, void* Tbuf,
+               void* Hbuf, int B, const int* act, double alpha, double beta, const void* Y, size_t Y_bs,
+               bool want_norm, hipStream_t s) const;
+  void rhs(const void* Q64p, size_t Q_bs, void* T64, c64* bout, int B, const int* act, unsigned flags,
+           hipStream_t s) const;
   template <typename T>
   void h_of(const void* in, size_t in_bs, void* hout, size_t hout_bs, void* Tbuf, int B, const int* act,
-            hipStream_t s) const;
+            hipStream_t s, unsigned flags = 0u, bool phase_out = false, bool accumulate = false) const;
   template <typename T>
   void transform(bool inverse, const void* in, void* out, void* Tbuf, hipStream_t s) const;
 };
 
+void launch_roll_add(const c64* f, const c64* h, const int* shv, int N, c64* out, int B, hipStream_t s);
+
 int validate_grid(const dbar_grid* g);
 int get_twiddles(int N, const Twiddles** out);
 int make_pipeline(const dbar_grid* g, Work& w, Pipeline* p);
-void phase_tables(int N, double L, double k1, double k2, c64* ex, c64* ey);
+void launch_phase_tables(const c64* kv_dev, int N, double L, c64* ex, c64* ey, int B, hipStream_t s);
 int run_batch(const Pipeline& P, Work& w, const BatchCfg& cfg, hipStream_t s, std::vector<int>& iters_out);
 int ctl_blocks(int B);
 // one lockstep Krylov cycle over the entries flagged in w.act; returns the iterations run
@@ -140,7 +169,7 @@ template <typename T>
 int krylov_cycle(const Pipeline& P, Work& w, const BatchCfg& cfg, int it_budget, hipStream_t s);
 // solution update from the cycle and the FP64 residual r = b - A(x) into r_out (norms into w.nred)
 template <typename T>
-void end_cycle(const Pipeline& P, Work& w, int nv, void* r_out, hipStream_t s);
+void end_cycle(const Pipeline& P, Work& w, int nv, void* r_out, hipStream_t s, int method = 0);
 // residual check (first = 1: record ||b|| and reset the counters of the entries in mask); tolv: per-entry tol
 void launch_ctl_check(Work& w, double tol, int first, const int* mask, const double* tolv, hipStream_t s);
 // start a cycle for every live entry from its residual norm

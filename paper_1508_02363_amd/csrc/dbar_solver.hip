@@ -175,6 +175,34 @@ __global__ void k_ctl_check(Ctl* ctl, const double* nred, int* live, double tol,
   if (rn <= t * c.bnorm) live[b] = 0;
 }
 
+// e^{conj(kz) - kz} = e^{-2i k2 x} e^{-2i k1 y} (eq:039) as two FP64 tables per entry, x_j = L(-pi + 2 pi j / N)
+__global__ void k_phase_tables(const c64* kv, int N, double L, c64* ex, c64* ey, int B) {
+  const int b = blockIdx.y;
+  if (b >= B) return;
+  const c64 k = kv[b];
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < N; j += gridDim.x * blockDim.x) {
+    const double x = L * (-kPi + (2.0 * kPi / N) * j);
+    double s1, c1, s2, c2;
+    sincos(-2.0 * k.im * x, &s1, &c1);
+    sincos(-2.0 * k.re * x, &s2, &c2);
+    ex[(size_t)b * N + j] = c64{c1, s1};
+    ey[(size_t)b * N + j] = c64{c2, s2};
+  }
+}
+
+// compact per-entry results: iterations, residual evaluations, ||b||, ||r||, S(0)
+__global__ void k_gather_results(const Ctl* ctl, const c64* x, size_t n, EntryResult* out, int B) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  const Ctl& c = ctl[b];
+  out[b] = EntryResult{c.iters, c.cycles, c.bnorm, c.rnorm, x[(size_t)b * n]};
+}
+
+void launch_phase_tables(const c64* kv_dev, int N, double L, c64* ex, c64* ey, int B, hipStream_t s) {
+  TimerScope ts(kStageControl, 0.0, B, nullptr, s);
+  hipLaunchKernelGGL(k_phase_tables, dim3((N + 255) / 256, B), dim3(256), 0, s, kv_dev, N, L, ex, ey, B);
+}
+
 // ------------------------------------------------------------------------------------------------------------
 // Plans and workspace
 // ------------------------------------------------------------------------------------------------------------
@@ -254,16 +282,6 @@ int validate_grid(const dbar_grid* g) {
   return DBAR_OK;
 }
 
-// separable phase e^{conj(kz) - kz} = e^{-2i k2 x} e^{-2i k1 y} (eq:039)
-void phase_tables(int N, double L, double k1, double k2, c64* ex, c64* ey) {
-  for (int j = 0; j < N; ++j) {
-    const long double x = (long double)L * (-3.14159265358979323846264338327950288L +
-                                            2.0L * 3.14159265358979323846264338327950288L * j / N);
-    const long double ax = -2.0L * k2 * x, ay = -2.0L * k1 * x;
-    ex[j] = c64{(double)cosl(ax), (double)sinl(ax)};
-    ey[j] = c64{(double)cosl(ay), (double)sinl(ay)};
-  }
-}
 
 void Work::drop_graphs() {
   for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
@@ -278,7 +296,9 @@ Work& Work::operator=(Work&& o) noexcept {
   ex = std::move(o.ex); ey = std::move(o.ey); coefG = std::move(o.coefG); dmom = std::move(o.dmom);
   part_mom = std::move(o.part_mom); part_vec = std::move(o.part_vec); part_norm = std::move(o.part_norm);
   dred = std::move(o.dred); nred = std::move(o.nred); ctl = std::move(o.ctl); act = std::move(o.act);
-  live = std::move(o.live); host_act = std::move(o.host_act); host_live = std::move(o.host_live);
+  live = std::move(o.live); kvals = std::move(o.kvals); results = std::move(o.results);
+  shv = std::move(o.shv); unit = std::move(o.unit); Hbuf = std::move(o.Hbuf);
+  host_act = std::move(o.host_act); host_live = std::move(o.host_live);
   graphs = std::move(o.graphs);
   return *this;
 }
@@ -289,7 +309,7 @@ int Work::setup(int N_, int B_, int m_, int prec_, bool shared_q) {
   // captured graphs hold raw pointers and sizes of this workspace: drop them if anything can change
   if (N_ != N || B_ != B || m_ != m || prec_ != prec || (shared_q ? 0 : (size_t)N_ * N_) != Q_bs) drop_graphs();
   const void* before[] = {x.p, V.p, T64.p, T32.p, ctl.p, act.p, part_vec.p, part_norm.p, part_mom.p, dred.p,
-                          nred.p, Q32.p, Q64.p, ex.p, ey.p, coefG.p, dmom.p};
+                          nred.p, Q32.p, Q64.p, ex.p, ey.p, coefG.p, dmom.p, shv.p, unit.p, Hbuf.p};
   N = N_;
   B = B_;
   m = m_;
@@ -321,12 +341,21 @@ int Work::setup(int N_, int B_, int m_, int prec_, bool shared_q) {
   if ((rc = dred.ensure((size_t)B * (kMaxRestart + 2) * sizeof(double)))) return rc;
   if ((rc = nred.ensure((size_t)B * sizeof(double)))) return rc;
   if ((rc = ctl.ensure((size_t)B * sizeof(Ctl)))) return rc;
+  if ((rc = kvals.ensure((size_t)B * sizeof(c64)))) return rc;
+  if ((rc = shv.ensure((size_t)B * 2 * sizeof(int)))) return rc;
+  if (unit.bytes < (size_t)N * sizeof(c64)) {
+    if ((rc = unit.ensure((size_t)N * sizeof(c64)))) return rc;
+    std::vector<c64> ones(N, c64{1.0, 0.0});
+    if (hipMemcpy(unit.p, ones.data(), N * sizeof(c64), hipMemcpyHostToDevice) != hipSuccess)
+      return fail(DBAR_EDEVICE, "upload of the unit phase table failed");
+  }
+  if ((rc = results.ensure((size_t)B * sizeof(EntryResult)))) return rc;
   if ((rc = act.ensure((size_t)B * sizeof(int)))) return rc;
   if ((rc = live.ensure((size_t)B * sizeof(int)))) return rc;
   if ((rc = host_act.ensure(B))) return rc;
   if ((rc = host_live.ensure(B))) return rc;
   const void* after[] = {x.p, V.p, T64.p, T32.p, ctl.p, act.p, part_vec.p, part_norm.p, part_mom.p, dred.p,
-                         nred.p, Q32.p, Q64.p, ex.p, ey.p, coefG.p, dmom.p};
+                         nred.p, Q32.p, Q64.p, ex.p, ey.p, coefG.p, dmom.p, shv.p, unit.p, Hbuf.p};
   if (std::memcmp(before, after, sizeof(before)) != 0) drop_graphs();
   return DBAR_OK;
 }
@@ -336,7 +365,7 @@ static Work g_work;
 // ------------------------------------------------------------------------------------------------------------
 // Operator pipeline
 // ------------------------------------------------------------------------------------------------------------
-LineArgs Pipeline::base(int B, const int* act) const {
+LineArgs Pipeline::base(int B, const int* act, unsigned flags) const {
   LineArgs a;
   a.B = B;
   a.act = act;
@@ -345,8 +374,16 @@ LineArgs Pipeline::base(int B, const int* act) const {
   a.ci = 1.0 / (2.0 * kPi * L * L);
   const double dx = 2.0 * kPi * L / N;
   a.cf = dx * dx / (2.0 * kPi);
-  a.ex = ex;
-  a.ey = ey;
+  if (flags & kUnitPhase) {  // k = 0: one shared table of ones
+    a.ex = unit;
+    a.ey = unit;
+    a.e_bs = 0;
+  } else {
+    a.ex = ex;
+    a.ey = ey;
+    a.e_bs = (size_t)N;
+  }
+  a.shv = (flags & kShifted) ? shv : nullptr;
   a.coefG = coefG;
   a.dmom = dmom;
   return a;
@@ -357,10 +394,11 @@ static const void* tw_of(const Twiddles* t) {
   return sizeof(T) == sizeof(double) ? t->d64.p : t->d32.p;
 }
 
-// h-moments of `in` (xi-space vector): F^{-1} in, d_n, c_n, R(0)
+// Taylor data of `in` (xi-space): F^{-1} in, d_n, c_n, R(0) -- about xi = 0, or about xi = a with kShifted
 template <typename T>
-void Pipeline::moments(const void* in, size_t in_bs, void* Tbuf, int B, const int* act, hipStream_t s) const {
-  LineArgs a = base(B, act);
+void Pipeline::moments(const void* in, size_t in_bs, void* Tbuf, int B, const int* act, unsigned flags,
+                       hipStream_t s) const {
+  LineArgs a = base(B, act, flags);
   a.tw = tw_of<T>(tw);
   a.in = in;
   a.in_bs = in_bs;
@@ -377,13 +415,14 @@ void Pipeline::moments(const void* in, size_t in_bs, void* Tbuf, int B, const in
                      dx * dx / (2.0 * kPi), M, coefG, dmom);
 }
 
-// out = alpha in + beta i F(q_k conj(h(in))) + gamma Y; optional |out|^2 partials into part_vec
+// out = alpha S_ep + beta i F(q conj(hh(in))) + gamma Y, with hh the regularised inverse of in/xi (or of in/(xi - a)
+// with kShifted) and q = Q e_k (Q alone with kShifted or kUnitPhase); S_ep defaults to in
 template <typename T>
-void Pipeline::apply(const void* in, size_t in_bs, void* out, size_t out_bs, const void* Qp, size_t Q_bs, void* Tbuf,
-                     int B, const int* act, double alpha, double beta, const void* Y, size_t Y_bs, bool want_norm,
-                     hipStream_t s) const {
-  moments<T>(in, in_bs, Tbuf, B, act, s);
-  LineArgs a = base(B, act);
+void Pipeline::apply_impl(const void* in, size_t in_bs, void* out, size_t out_bs, const void* Qp, size_t Q_bs,
+                          void* Tbuf, int B, const int* act, double alpha, double beta, const void* Y, size_t Y_bs,
+                          bool want_norm, unsigned flags, const void* S_ep, size_t S_ep_bs, hipStream_t s) const {
+  moments<T>(in, in_bs, Tbuf, B, act, flags, s);
+  LineArgs a = base(B, act, flags);
   a.tw = tw_of<T>(tw);
   a.in = in;
   a.in_bs = in_bs;
@@ -397,8 +436,8 @@ void Pipeline::apply(const void* in, size_t in_bs, void* out, size_t out_bs, con
   launch_lines_any<T>(N, LineOp::ColsInvTailFwd, a, s);
   a.out = out;
   a.out_bs = out_bs;
-  a.S = in;
-  a.S_bs = in_bs;
+  a.S = S_ep ? S_ep : in;
+  a.S_bs = S_ep ? S_ep_bs : in_bs;
   a.alpha = alpha;
   a.beta = c64{0.0, beta};
   a.Y = Y;
@@ -409,9 +448,34 @@ void Pipeline::apply(const void* in, size_t in_bs, void* out, size_t out_bs, con
   launch_lines_any<T>(N, LineOp::RowsFwdEpilogue, a, s);
 }
 
-// b = -i F(Q e_k) (FP64), with |b|^2 partials
-void Pipeline::rhs(const void* Q64p, size_t Q_bs, void* T64, c64* bout, int B, const int* act, hipStream_t s) const {
-  LineArgs a = base(B, act);
+template <typename T>
+void Pipeline::apply(const void* in, size_t in_bs, void* out, size_t out_bs, const void* Qp, size_t Q_bs, void* Tbuf,
+                     int B, const int* act, double alpha, double beta, const void* Y, size_t Y_bs, bool want_norm,
+                     hipStream_t s) const {
+  apply_impl<T>(in, in_bs, out, out_bs, Qp, Q_bs, Tbuf, B, act, alpha, beta, Y, Y_bs, want_norm, 0u, nullptr, 0, s);
+}
+
+// H(h) = -i F(Q conj(F^{-1}(h/(xi - a)))) (equation eqh2), into Hout
+template <typename T>
+void Pipeline::H_of(const void* in, size_t in_bs, void* Hout, size_t H_bs, const void* Qp, size_t Q_bs, void* Tbuf,
+                    int B, const int* act, hipStream_t s) const {
+  apply_impl<T>(in, in_bs, Hout, H_bs, Qp, Q_bs, Tbuf, B, act, 0.0, -1.0, nullptr, 0, false, kShifted, nullptr, 0, s);
+}
+
+// B(h) = h - K0(H(h)) = h + i F(Q conj(F^{-1}(H/xi))), written as alpha h + beta i F(...) + gamma Y
+template <typename T>
+void Pipeline::apply_B(const void* in, size_t in_bs, void* out, size_t out_bs, const void* Qp, size_t Q_bs,
+                       void* Tbuf, void* Hbuf, int B, const int* act, double alpha, double beta, const void* Y,
+                       size_t Y_bs, bool want_norm, hipStream_t s) const {
+  H_of<T>(in, in_bs, Hbuf, n, Qp, Q_bs, Tbuf, B, act, s);
+  apply_impl<T>(Hbuf, n, out, out_bs, Qp, Q_bs, Tbuf, B, act, alpha, beta, Y, Y_bs, want_norm, kUnitPhase, in,
+                in_bs, s);
+}
+
+// b = -i F(Q e_k) (FP64; e_k = 1 with kUnitPhase), with |b|^2 partials
+void Pipeline::rhs(const void* Q64p, size_t Q_bs, void* T64, c64* bout, int B, const int* act, unsigned flags,
+                   hipStream_t s) const {
+  LineArgs a = base(B, act, flags & kUnitPhase);
   a.tw = tw_of<double>(tw);
   a.Q = Q64p;
   a.Q_bs = Q_bs;
@@ -430,12 +494,12 @@ void Pipeline::rhs(const void* Q64p, size_t Q_bs, void* T64, c64* bout, int B, c
   launch_lines_any<double>(N, LineOp::RowsFwdEpilogue, a, s);
 }
 
-// h(in) -> hout (type T)
+// hout (=|+=) h(in): the regularised inverse of in/xi; with kShifted that of in/(xi - a), times e_k if phase_out
 template <typename T>
 void Pipeline::h_of(const void* in, size_t in_bs, void* hout, size_t hout_bs, void* Tbuf, int B, const int* act,
-                    hipStream_t s) const {
-  moments<T>(in, in_bs, Tbuf, B, act, s);
-  LineArgs a = base(B, act);
+                    hipStream_t s, unsigned flags, bool phase_out, bool accumulate) const {
+  moments<T>(in, in_bs, Tbuf, B, act, flags, s);
+  LineArgs a = base(B, act, flags);
   a.tw = tw_of<T>(tw);
   a.in = in;
   a.in_bs = in_bs;
@@ -446,12 +510,14 @@ void Pipeline::h_of(const void* in, size_t in_bs, void* hout, size_t hout_bs, vo
   a.in_bs = n;
   a.hout = hout;
   a.hout_bs = hout_bs;
+  a.tail_phase_out = phase_out ? 1 : 0;
+  a.accumulate = accumulate ? 1 : 0;
   launch_lines_any<T>(N, LineOp::ColsInvTail, a, s);
 }
 
 template <typename T>
 void Pipeline::transform(bool inverse, const void* in, void* out, void* Tbuf, hipStream_t s) const {
-  LineArgs a = base(1, nullptr);
+  LineArgs a = base(1, nullptr, 0u);
   a.tw = tw_of<T>(tw);
   if (inverse) {
     a.in = in;
@@ -472,14 +538,37 @@ void Pipeline::transform(bool inverse, const void* in, void* out, void* Tbuf, hi
   }
 }
 
-template void Pipeline::apply<double>(const void*, size_t, void*, size_t, const void*, size_t, void*, int, const int*,
-                                      double, double, const void*, size_t, bool, hipStream_t) const;
-template void Pipeline::apply<float>(const void*, size_t, void*, size_t, const void*, size_t, void*, int, const int*,
-                                     double, double, const void*, size_t, bool, hipStream_t) const;
-template void Pipeline::h_of<double>(const void*, size_t, void*, size_t, void*, int, const int*, hipStream_t) const;
-template void Pipeline::h_of<float>(const void*, size_t, void*, size_t, void*, int, const int*, hipStream_t) const;
-template void Pipeline::transform<double>(bool, const void*, void*, void*, hipStream_t) const;
-template void Pipeline::transform<float>(bool, const void*, void*, void*, hipStream_t) const;
+#define DBAR_PIPE_INST(T)                                                                                        \
+  template void Pipeline::apply<T>(const void*, size_t, void*, size_t, const void*, size_t, void*, int,            \
+                                   const int*, double, double, const void*, size_t, bool, hipStream_t) const;     \
+  template void Pipeline::apply_B<T>(const void*, size_t, void*, size_t, const void*, size_t, void*, void*, int,   \
+                                     const int*, double, double, const void*, size_t, bool, hipStream_t) const;   \
+  template void Pipeline::H_of<T>(const void*, size_t, void*, size_t, const void*, size_t, void*, int, const int*, \
+                                  hipStream_t) const;                                                            \
+  template void Pipeline::h_of<T>(const void*, size_t, void*, size_t, void*, int, const int*, hipStream_t,         \
+                                  unsigned, bool, bool) const;                                                   \
+  template void Pipeline::transform<T>(bool, const void*, void*, void*, hipStream_t) const;
+DBAR_PIPE_INST(double)
+DBAR_PIPE_INST(float)
+#undef DBAR_PIPE_INST
+
+// S = f + h o (xi + a): out[p] = f[p] + h[p + (m1, m2)] (periodic index roll, equation Sform)
+__global__ void k_roll_add(const c64* f, const c64* h, const int* shv, int N, c64* out, int B) {
+  const int b = blockIdx.y;
+  if (b >= B) return;
+  const size_t n = (size_t)N * N;
+  const int o1 = shv[2 * b], o2 = shv[2 * b + 1];
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    const int p2 = (int)(i / N), p1 = (int)(i % N);
+    const size_t src = (size_t)((p2 + o2) & (N - 1)) * N + ((p1 + o1) & (N - 1));
+    out[(size_t)b * n + i] = f[(size_t)b * n + i] + h[(size_t)b * n + src];
+  }
+}
+
+void launch_roll_add(const c64* f, const c64* h, const int* shv, int N, c64* out, int B, hipStream_t s) {
+  TimerScope ts(kStageConvert, 3.0 * (double)N * N * sizeof(c64), B, nullptr, s);
+  hipLaunchKernelGGL(k_roll_add, dim3(std::min(4096, (N * N + 255) / 256), B), dim3(256), 0, s, f, h, shv, N, out, B);
+}
 
 int make_pipeline(const dbar_grid* g, Work& w, Pipeline* p) {
   int rc = get_twiddles(g->n, &p->tw);
@@ -494,6 +583,8 @@ int make_pipeline(const dbar_grid* g, Work& w, Pipeline* p) {
   p->dmom = static_cast<c64*>(w.dmom.p);
   p->part_mom = static_cast<double*>(w.part_mom.p);
   p->part_vec = static_cast<double*>(w.part_vec.p);
+  p->unit = static_cast<const c64*>(w.unit.p);
+  p->shv = static_cast<const int*>(w.shv.p);
   return DBAR_OK;
 }
 
@@ -525,7 +616,10 @@ int krylov_cycle(const Pipeline& P, Work& w, const BatchCfg& cfg, int it_budget,
   auto enqueue = [&](int j) {
     void* vj = V + (size_t)j * n * sizeof(cx<T>);
     void* vj1 = V + (size_t)(j + 1) * n * sizeof(cx<T>);
-    P.apply<T>(vj, V_bs, vj1, V_bs, Qp, w.Q_bs, Tbuf, B, act, 1.0, 1.0, nullptr, 0, false, s);
+    if (cfg.method == 1)
+      P.apply_B<T>(vj, V_bs, vj1, V_bs, Qp, w.Q_bs, Tbuf, w.Hbuf.p, B, act, 1.0, 1.0, nullptr, 0, false, s);
+    else
+      P.apply<T>(vj, V_bs, vj1, V_bs, Qp, w.Q_bs, Tbuf, B, act, 1.0, 1.0, nullptr, 0, false, s);
     for (int pass = 0; pass < cfg.reorth; ++pass) {
       VecArgs va;
       va.B = B;
@@ -560,7 +654,7 @@ int krylov_cycle(const Pipeline& P, Work& w, const BatchCfg& cfg, int it_budget,
   for (; j < mlim; ++j) {
     bool done = false;
     if (graphs) {
-      const auto key = std::make_tuple((int)sizeof(T), j, cfg.reorth, B);
+      const auto key = std::make_tuple((int)sizeof(T) + 16 * cfg.method, j, cfg.reorth, B);
       auto it = w.graphs.find(key);
       if (it != w.graphs.end()) {
         done = hipGraphLaunch(it->second, s) == hipSuccess;
@@ -596,7 +690,7 @@ int krylov_cycle(const Pipeline& P, Work& w, const BatchCfg& cfg, int it_budget,
 
 // x += sum coef_i V_i and the FP64 residual r = b - A(x) (into r_out), with squared norms in nred
 template <typename T>
-void end_cycle(const Pipeline& P, Work& w, int nv, void* r_out, hipStream_t s) {
+void end_cycle(const Pipeline& P, Work& w, int nv, void* r_out, hipStream_t s, int method) {
   const int B = w.B;
   const size_t n = w.n;
   Ctl* ctl = static_cast<Ctl*>(w.ctl.p);
@@ -614,16 +708,20 @@ void end_cycle(const Pipeline& P, Work& w, int nv, void* r_out, hipStream_t s) {
   va.coef = &ctl[0].coef[0];
   va.coef_bs = sizeof(Ctl) / sizeof(double);
   launch_axpy_multi<double, T>(va, s);
-  P.apply<double>(w.x.p, n, r_out, sizeof(T) == 8 ? n * (w.m + 1) : n, w.Q64.p, w.Q_bs, w.T64.p, B, live, -1.0,
-                  -1.0, w.bvec.p, n, true, s);
+  const size_t r_bs = sizeof(T) == 8 ? n * (w.m + 1) : n;
+  if (method == 1)
+    P.apply_B<double>(w.x.p, n, r_out, r_bs, w.Q64.p, w.Q_bs, w.T64.p, w.Hbuf.p, B, live, -1.0, -1.0, w.bvec.p, n,
+                      true, s);
+  else
+    P.apply<double>(w.x.p, n, r_out, r_bs, w.Q64.p, w.Q_bs, w.T64.p, B, live, -1.0, -1.0, w.bvec.p, n, true, s);
   launch_reduce(static_cast<double*>(w.part_vec.p), 1, line_tiles(w.N, false, true), static_cast<double*>(w.nred.p),
                 B, live, s);
 }
 
 template int krylov_cycle<float>(const Pipeline&, Work&, const BatchCfg&, int, hipStream_t);
 template int krylov_cycle<double>(const Pipeline&, Work&, const BatchCfg&, int, hipStream_t);
-template void end_cycle<float>(const Pipeline&, Work&, int, void*, hipStream_t);
-template void end_cycle<double>(const Pipeline&, Work&, int, void*, hipStream_t);
+template void end_cycle<float>(const Pipeline&, Work&, int, void*, hipStream_t, int);
+template void end_cycle<double>(const Pipeline&, Work&, int, void*, hipStream_t, int);
 
 void launch_ctl_check(Work& w, double tol, int first, const int* mask, const double* tolv, hipStream_t s) {
   TimerScope ts(kStageControl, 0.0, w.B, nullptr, s);
@@ -646,7 +744,8 @@ int run_batch(const Pipeline& P, Work& w, const BatchCfg& cfg, hipStream_t s, st
   int* live = static_cast<int*>(w.live.p);
   double* nred = static_cast<double*>(w.nred.p);
   // b = -i F(q_k), |b|
-  P.rhs(w.Q64.p, w.Q_bs, w.T64.p, static_cast<c64*>(w.bvec.p), B, nullptr, s);
+  // plain: b = -i F(Q e_k); iterated (equation eqh2): b = -i F(Q)
+  P.rhs(w.Q64.p, w.Q_bs, w.T64.p, static_cast<c64*>(w.bvec.p), B, nullptr, cfg.method == 1 ? kUnitPhase : 0u, s);
   launch_reduce(static_cast<double*>(w.part_vec.p), 1, line_tiles(w.N, false, true), nred, B, nullptr, s);
   if (hipMemsetAsync(w.x.p, 0, (size_t)B * n * sizeof(c64), s) != hipSuccess)
     return fail(DBAR_EDEVICE, "hipMemsetAsync failed");
@@ -676,10 +775,10 @@ int run_batch(const Pipeline& P, Work& w, const BatchCfg& cfg, hipStream_t s, st
     int ran;
     if (mixed) {
       ran = krylov_cycle<float>(P, w, cfg, cfg.max_iter - total, s);
-      end_cycle<float>(P, w, ran, w.r64.p, s);
+      end_cycle<float>(P, w, ran, w.r64.p, s, cfg.method);
     } else {
       ran = krylov_cycle<double>(P, w, cfg, cfg.max_iter - total, s);
-      end_cycle<double>(P, w, ran, w.V.p, s);
+      end_cycle<double>(P, w, ran, w.V.p, s, cfg.method);
     }
     total += ran;
     hipLaunchKernelGGL(k_ctl_check, dim3(ctl_blocks(B)), dim3(64), 0, s, ctl, nred, live, cfg.tol, 0, nullptr, nullptr, B);
@@ -726,6 +825,9 @@ static int solver_stream(hipStream_t caller, hipStream_t* out) {
   return DBAR_OK;
 }
 
+// grid offset of 2 k_c L (k_c a component of k), known to be an integer
+static int shift_of(double kc, double L) { return (int)std::nearbyint(2.0 * kc * L); }
+
 int solve_impl(const dbar_grid* grid, const void* Q, bool q_on_device, int64_t nk, const double* k, double tol,
                const dbar_opts* opts_in, void* S, void* m, bool out_on_device, dbar_info* info, hipStream_t caller) {
   int rc = validate_grid(grid);
@@ -745,6 +847,14 @@ int solve_impl(const dbar_grid* grid, const void* Q, bool q_on_device, int64_t n
   if (o.reorth < 1 || o.reorth > 2) o.reorth = 1;
   if (o.check_every <= 0) o.check_every = 4;
   if (!(o.inner_tol > 0.0) || o.inner_tol >= 1.0) o.inner_tol = 1e-5;
+  if (o.method != 0 && o.method != 1) return fail(DBAR_EINVAL, "method must be 0 (plain) or 1 (iterated)");
+  if (o.method == 1) {
+    for (int64_t j = 0; j < 2 * nk; ++j) {
+      const double m = 2.0 * k[j] * grid->L;
+      if (std::fabs(m - std::nearbyint(m)) > 1e-9 * std::max(1.0, std::fabs(m)))
+        return fail(DBAR_EINVAL, "the iterated method needs 2k on the xi grid: 2 L Re k and 2 L Im k integers");
+    }
+  }
   if ((rc = check_device())) return rc;
   const int N = grid->n;
   const size_t n = (size_t)N * N;
@@ -784,43 +894,65 @@ int solve_impl(const dbar_grid* grid, const void* Q, bool q_on_device, int64_t n
   cfg.max_iter = o.max_iter;
   cfg.reorth = o.reorth;
   cfg.use_graph = o.mode == DBAR_MODE_PLAIN ? 0 : o.use_graph;
+  cfg.method = o.method;
+  if (cfg.method == 1 && (rc = w.Hbuf.ensure((size_t)B * n * sizeof(c64)))) return rc;
   cfg.check_every = o.mode == DBAR_MODE_PLAIN ? 1 : o.check_every;
   cfg.inner_tol = o.inner_tol;
-  std::vector<c64> hex((size_t)B * N), hey((size_t)B * N);
-  std::vector<Ctl> hctl(B);
-  std::vector<c64> s00(B);
+  std::vector<EntryResult> hres(B);
+  std::vector<int> shifts(2 * (size_t)B);
   int result = DBAR_OK;
   for (int64_t k0 = 0; k0 < nk; k0 += B) {
     const int nb = (int)std::min<int64_t>(B, nk - k0);
     w.B = nb;
-    for (int b = 0; b < nb; ++b)
-      phase_tables(N, grid->L, k[2 * (k0 + b)], k[2 * (k0 + b) + 1], &hex[(size_t)b * N], &hey[(size_t)b * N]);
-    if (hipMemcpyAsync(w.ex.p, hex.data(), (size_t)nb * N * sizeof(c64), hipMemcpyHostToDevice, s) != hipSuccess ||
-        hipMemcpyAsync(w.ey.p, hey.data(), (size_t)nb * N * sizeof(c64), hipMemcpyHostToDevice, s) != hipSuccess)
-      return fail(DBAR_EDEVICE, "phase table upload failed");
+    if (hipMemcpyAsync(w.kvals.p, k + 2 * k0, (size_t)nb * sizeof(c64), hipMemcpyHostToDevice, s) != hipSuccess)
+      return fail(DBAR_EDEVICE, "k upload failed");
+    if (cfg.method == 1) {
+      for (int b = 0; b < nb; ++b) shifts[2 * b] = shift_of(k[2 * (k0 + b) + 1], grid->L), shifts[2 * b + 1] =
+                                                                                       shift_of(k[2 * (k0 + b)], grid->L);
+      if (hipMemcpyAsync(w.shv.p, shifts.data(), (size_t)nb * 2 * sizeof(int), hipMemcpyHostToDevice, s) != hipSuccess)
+        return fail(DBAR_EDEVICE, "shift upload failed");
+    }
+    launch_phase_tables(static_cast<const c64*>(w.kvals.p), N, grid->L, static_cast<c64*>(w.ex.p),
+                        static_cast<c64*>(w.ey.p), nb, s);
     std::vector<int> its;
     if ((rc = run_batch(P, w, cfg, s, its))) return rc;
-    // outputs: S = x, m = h(x)
-    if (S) {
+    // outputs: S = x, m = h(x) (plain); the iterated method forms S and m from h below
+    if (S && cfg.method == 0) {
       char* dst = static_cast<char*>(S) + (size_t)k0 * n * sizeof(c64);
       if (hipMemcpyAsync(dst, w.x.p, (size_t)nb * n * sizeof(c64),
                          out_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s) != hipSuccess)
         return fail(DBAR_EDEVICE, "S copy failed");
     }
-    if (m) {
+    if (cfg.method == 1) {
+      // f = H(h) (into Hbuf), S = f + h o (xi + a) (into bvec), m = h(f) + e_k F^{-1}(h/(xi - a)) (into T64)
+      c64* Hb = static_cast<c64*>(w.Hbuf.p);
+      c64* Sb = static_cast<c64*>(w.bvec.p);
+      P.H_of<double>(w.x.p, n, Hb, n, w.Q64.p, w.Q_bs, Sb, nb, nullptr, s);
+      P.h_of<double>(Hb, n, w.T64.p, n, Sb, nb, nullptr, s);
+      P.h_of<double>(w.x.p, n, w.T64.p, n, Sb, nb, nullptr, s, kShifted, true, true);
+      launch_roll_add(Hb, static_cast<const c64*>(w.x.p), static_cast<const int*>(w.shv.p), N, Sb, nb, s);
+      if (S && hipMemcpyAsync(static_cast<char*>(S) + (size_t)k0 * n * sizeof(c64), Sb, (size_t)nb * n * sizeof(c64),
+                              out_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s) != hipSuccess)
+        return fail(DBAR_EDEVICE, "S copy failed");
+      if (m && hipMemcpyAsync(static_cast<char*>(m) + (size_t)k0 * n * sizeof(c64), w.T64.p,
+                              (size_t)nb * n * sizeof(c64),
+                              out_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s) != hipSuccess)
+        return fail(DBAR_EDEVICE, "m copy failed");
+    } else if (m) {
       P.h_of<double>(w.x.p, n, w.T64.p, n, w.bvec.p, nb, nullptr, s);  // bvec reused as scratch
       char* dst = static_cast<char*>(m) + (size_t)k0 * n * sizeof(c64);
       if (hipMemcpyAsync(dst, w.T64.p, (size_t)nb * n * sizeof(c64),
                          out_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s) != hipSuccess)
         return fail(DBAR_EDEVICE, "m copy failed");
     }
-    (void)hipMemcpy2DAsync(s00.data(), sizeof(c64), w.x.p, n * sizeof(c64), sizeof(c64), nb, hipMemcpyDeviceToHost,
-                           s);
-    (void)hipMemcpyAsync(hctl.data(), w.ctl.p, (size_t)nb * sizeof(Ctl), hipMemcpyDeviceToHost, s);
+    hipLaunchKernelGGL(k_gather_results, dim3(ctl_blocks(nb)), dim3(64), 0, s, static_cast<const Ctl*>(w.ctl.p),
+                       static_cast<const c64*>(cfg.method == 1 ? w.bvec.p : w.x.p), n,
+                       static_cast<EntryResult*>(w.results.p), nb);
+    (void)hipMemcpyAsync(hres.data(), w.results.p, (size_t)nb * sizeof(EntryResult), hipMemcpyDeviceToHost, s);
     (void)hipMemcpyAsync(w.host_live.data(), w.live.p, nb * sizeof(int), hipMemcpyDeviceToHost, s);
     if (hipStreamSynchronize(s) != hipSuccess) return fail(DBAR_EDEVICE, "stream synchronize failed");
     for (int b = 0; b < nb; ++b) {
-      const Ctl& c = hctl[b];
+      const EntryResult& c = hres[b];
       const bool ok = w.host_live[b] == 0;
       if (!ok) result = DBAR_ENOCONV;
       if (info) {
@@ -830,8 +962,8 @@ int solve_impl(const dbar_grid* grid, const void* Q, bool q_on_device, int64_t n
         I.outer = c.cycles;
         I.reserved = 0;
         I.rel_residual = c.bnorm > 0.0 ? c.rnorm / c.bnorm : 0.0;
-        I.m1_re = -s00[b].im;  // m1 = i S(0)
-        I.m1_im = s00[b].re;
+        I.m1_re = -c.s00.im;  // m1 = i S(0)
+        I.m1_im = c.s00.re;
       }
     }
   }
@@ -858,6 +990,8 @@ void dbar_default_opts(dbar_opts* o) {
   o->use_graph = 1;
   o->reorth = 1;
   o->check_every = 4;
+  o->method = 0;
+  o->reserved = 0;
   o->inner_tol = 1e-5;
 }
 
@@ -912,11 +1046,10 @@ int dbar_apply(const dbar_grid* grid, const double* Q, const double* k, const do
   const size_t n = (size_t)N * N;
   if (!all_finite(Q, 2 * n) || !all_finite(k, 2) || !all_finite(S_in, 2 * n))
     return fail(DBAR_EINVAL, "NaN or Inf in the inputs");
-  std::vector<c64> hex(N), hey(N);
-  phase_tables(N, grid->L, k[0], k[1], hex.data(), hey.data());
   hipStream_t s = nullptr;
-  (void)hipMemcpy(w->ex.p, hex.data(), N * sizeof(c64), hipMemcpyHostToDevice);
-  (void)hipMemcpy(w->ey.p, hey.data(), N * sizeof(c64), hipMemcpyHostToDevice);
+  (void)hipMemcpy(w->kvals.p, k, sizeof(c64), hipMemcpyHostToDevice);
+  launch_phase_tables(static_cast<const c64*>(w->kvals.p), N, grid->L, static_cast<c64*>(w->ex.p),
+                      static_cast<c64*>(w->ey.p), 1, s);
   (void)hipMemcpy(w->Q64.p, Q, n * sizeof(c64), hipMemcpyHostToDevice);
   (void)hipMemcpy(w->x.p, S_in, n * sizeof(c64), hipMemcpyHostToDevice);
   if (precision == DBAR_FP64) {

@@ -185,3 +185,36 @@ def test_max_iter_reports_no_convergence():
     assert info[0].status == D.DBAR_ENOCONV
     assert 1e-12 < info[0].rel_residual < 1.0
     assert np.all(np.isfinite(S)) and np.all(np.isfinite(m))
+
+
+@pytest.mark.parametrize("prec", [D.DBAR_FP64, D.DBAR_MIXED])
+def test_iterated_method_fig2_case(prec):
+    """Section 5.3 solver on the GPU against the oracle's, at the Fig. 2 parameters (k = 8.5936 = 55/6.4, L = 3.2,
+    N = 128), where the plain method cannot represent the solution."""
+    L, k, N = 3.2, 55 / 6.4, 128
+    g = O.make_grid(N, L)
+    Q = W.potential_gaussian(N, L, 1.0)
+    ref = O.solve_iterated(g, Q, k, tol=1e-14)
+    S, m, info = D.solve(Q, [k], L, tol=1e-12, method=D.DBAR_METHOD_ITERATED, precision=prec)
+    assert info[0].status == 0 and info[0].rel_residual <= 1e-12
+    assert relerr(S[0], ref.S) < 1e-10
+    assert relerr(m[0], ref.m) < 1e-10
+    assert abs(info[0].m1 - ref.m1) < 1e-10 * abs(ref.m1)
+
+
+def test_iterated_method_batch():
+    N, L = 64, 3.2
+    g = O.make_grid(N, L)
+    Q = W.potential_gaussian_sum(N, L, seed=31, amp_max=1.0)
+    ks = [0.0, 2.5 + 2.5j, -5.0 + 1.25j, 3.75 - 6.25j]  # 2 k L on the grid (1/6.4 steps)
+    S, m, info = D.solve(Q, ks, L, tol=1e-12, batch=4, method=D.DBAR_METHOD_ITERATED)
+    for j, k in enumerate(ks):
+        ref = O.solve_iterated(g, Q, k, tol=1e-14)
+        assert info[j].status == 0, j
+        assert relerr(S[j], ref.S) < 1e-10 and relerr(m[j], ref.m) < 1e-10, j
+
+
+def test_iterated_method_rejects_k_off_the_grid():
+    with pytest.raises(D.DbarError) as e:
+        D.solve(np.zeros((32, 32)) + 0.1, [0.3 + 0.1j], 3.0, method=D.DBAR_METHOD_ITERATED)
+    assert e.value.code == D._lib.DBAR_EINVAL
