@@ -36,6 +36,7 @@ __all__ = [
     "Grid", "make_grid", "Fd", "Fd_inv", "omega", "omega_table", "moments", "G_coefficients", "regularised_h",
     "apply_A", "rhs", "gmres_real", "dense_matrix", "solve", "dense_solve", "SolveResult",
     "shift_index", "shifted_inverse", "apply_B", "solve_iterated",
+    "reflection_coefficient", "reflection_grid", "evolve_reflection", "dual_grid", "reconstruct_potential",
 ]
 
 
@@ -411,3 +412,55 @@ def solve_iterated(g: Grid, Q: np.ndarray, k: complex, tol: float = 1e-13, M: in
     res.h = h
     res.f = f
     return res
+
+
+# ----------------------------------------------------------------------------------------------------------------
+# DS II reflection coefficient (Section 6: equations MainEQDSpm, hpmdef, rviah, m1def, eq:023)
+# ----------------------------------------------------------------------------------------------------------------
+
+def reflection_coefficient(g: Grid, q: np.ndarray, k: complex, tol: float = 1e-13, M: int = 11, om=None) -> complex:
+    """r(k) = i h(i conj k) (equation rviah) in the convention of Section 6 (k replaced by k/2, so that k lies on the
+    xi grid): h solves the iterated equation for the potential q with spectral parameter k/2, whose shift is
+    2i conj(k/2) = i conj(k).  The value at xi = i conj(k) is read at grid offsets (k2 L, k1 L)."""
+    res = solve_iterated(g, q, complex(k) / 2.0, tol=tol, M=M, om=om)
+    k = complex(k)
+    p1, p2 = int(round(k.imag * g.L)) % g.N, int(round(k.real * g.L)) % g.N
+    return 1j * res.h[p2, p1]
+
+
+def reflection_grid(g: Grid, q: np.ndarray, tol: float = 1e-13, M: int = 11) -> np.ndarray:
+    """r(k) for every k on the xi grid of g (Section 6 convention), laid out like S: r[p2, p1] is r at
+    k = xi[p2, p1]."""
+    om = omega_table(g, M)
+    r = np.zeros((g.N, g.N), dtype=complex)
+    for p2 in range(g.N):
+        for p1 in range(g.N):
+            r[p2, p1] = reflection_coefficient(g, q, g.xi[p2, p1], tol=tol, M=M, om=om)
+    return r
+
+
+def evolve_reflection(g: Grid, r: np.ndarray, t: float) -> np.ndarray:
+    """r(k, t) = r(k, 0) exp(-i t (k^2 + conj(k)^2)/4) (equation rt), applied with k on the xi grid (the Section 6
+    convention, in which the Remark of Section 6 writes the same factor as exp(-i t Re(k^2)/2))."""
+    return r * np.exp(-0.5j * t * (g.xi ** 2).real)
+
+
+def dual_grid(g: Grid) -> Grid:
+    """The xi grid of g read as an x-space grid: spacing 1/L, points m/L for m = -N/2 .. N/2-1, i.e. half-length
+    L' = N/(2 pi L).  Its own xi grid has spacing 2 pi L / N and contains every point of g's x grid."""
+    return make_grid(g.N, g.N / (2.0 * math.pi * g.L))
+
+
+def reconstruct_potential(g: Grid, r: np.ndarray, tol: float = 1e-13, M: int = 11) -> np.ndarray:
+    """q on the x grid of g from r on its xi grid (equations dbarrecA, dbarrecB, qRec): the same D-bar problem with
+    z and k interchanged and q replaced by conj(r), so q(z) = i h(i conj z) where h solves the iterated equation on
+    the dual grid with potential conj(r) and spectral parameter z/2.  The FFT-ordered r is moved to the dual x
+    grid by an fftshift; its Nyquist row and column (k = +N/(2L)) land at -N/(2L), the periodic image."""
+    gp = dual_grid(g)
+    P = np.fft.fftshift(np.conj(r))
+    om = omega_table(gp, M)
+    q = np.zeros((g.N, g.N), dtype=complex)
+    for j2 in range(g.N):
+        for j1 in range(g.N):
+            q[j2, j1] = reflection_coefficient(gp, P, g.z[j2, j1], tol=tol, M=M, om=om)
+    return q
