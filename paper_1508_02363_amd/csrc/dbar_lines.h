@@ -28,6 +28,13 @@ static __constant__ double kInvFact[40] = {
     3.3871575355211620e-39, 9.6775929586318906e-41, 2.6882202662866363e-42, 7.2654601791530714e-44,
     1.9119632050402819e-45, 4.9024697565135435e-47};
 
+// Smallest u beyond which e^{-u} sum_{k<=M} u^k/k! (times a safety factor 10) is below the rounding unit, so that
+// P(n+1, u) = 1 exactly for every n <= M and omega_n = i / z^{n+1} (index M = 0..15).
+static __constant__ float kTailOneF32[16] = {19.0f,  22.75f, 26.0f,  28.75f, 31.25f, 33.5f,  36.0f,  38.0f,
+                                             40.25f, 42.25f, 44.25f, 46.25f, 48.0f,  50.0f,  51.75f, 53.75f};
+static __constant__ double kTailOneF64[16] = {39.25, 43.75, 47.25, 50.5, 53.5, 56.25, 59.0, 61.5,
+                                              64.0,  66.5,  68.75, 71.0, 73.25, 75.5, 77.5, 79.75};
+
 // x_j = L(-pi + 2 pi j / N)
 template <int N>
 DBAR_D double xgrid(int j, double L) {
@@ -42,6 +49,14 @@ DBAR_D double xgrid(int j, double L) {
 template <typename TT>
 DBAR_D cx<TT> tail_sum(TT x, TT y, const c64* __restrict__ d, int M) {
   const TT u = TT(0.25) * (x * x + y * y);
+  const TT one_from = sizeof(TT) == 8 ? TT(kTailOneF64[M]) : TT(kTailOneF32[M]);
+  if (u >= one_from) {  // all P(n+1, u) = 1: i sum_n d_n / z^{n+1}
+    const TT r2 = x * x + y * y;
+    const cx<TT> w{x / r2, -y / r2};
+    cx<TT> acc = cvt<TT>(d[M]);
+    for (int n = M - 1; n >= 0; --n) acc = cvt<TT>(d[n]) + w * acc;
+    return mul_i(w * acc);
+  }
   const TT eu = exp(-u);
   const TT eps = sizeof(TT) == 8 ? TT(1e-17) : TT(3e-8);
   cx<TT> acc{TT(0), TT(0)};
@@ -195,14 +210,11 @@ struct OpColsInvMoments : OpBase<T, N> {
       }
     }
   }
-  template <int NT>
-  DBAR_D void finish(Acc& acc, int b, int tile, int ntiles, double* scratch) const {
+  // d_n = sum_{k<=n} C(n,k) x^{n-k} i^k mu_k in place from n = M down (d_n only needs mu_k, k <= n), then the conj
+  // moment x mu_0 - i mu_1 (computed first) and, with the shifted regularisation, the column factor e^{-2i k2 x}
+  DBAR_D void combine(double* v, double x, int b, int col) const {
     const int M = this->a.M;
-    const double x = acc.x;
-    // conj moment first (needs mu_0, mu_1): sum (x - i y) s = x mu_0 - i mu_1
-    acc.v[2 * (kMaxM + 1)] = x * acc.v[0] + acc.v[3];
-    acc.v[2 * (kMaxM + 1) + 1] = x * acc.v[1] - acc.v[2];
-    // d_n = sum_{k<=n} C(n,k) x^{n-k} i^k mu_k, in place from n = M down (d_n only needs mu_k with k <= n)
+    const double cr = x * v[0] + v[3], ci = x * v[1] - v[2];
 #pragma unroll
     for (int n = kMaxM; n >= 0; --n) {
       double re = 0.0, im = 0.0;
@@ -211,7 +223,7 @@ struct OpColsInvMoments : OpBase<T, N> {
 #pragma unroll
         for (int k = n; k >= 0; --k) {
           const double c = binom * xpow;
-          const double mr = acc.v[2 * k], mi = acc.v[2 * k + 1];
+          const double mr = v[2 * k], mi = v[2 * k + 1];
           switch (k & 3) {  // i^k mu_k
             case 0: re += c * mr; im += c * mi; break;
             case 1: re -= c * mi; im += c * mr; break;
@@ -222,20 +234,74 @@ struct OpColsInvMoments : OpBase<T, N> {
           xpow *= x;
         }
       }
-      acc.v[2 * n] = re;
-      acc.v[2 * n + 1] = im;
+      v[2 * n] = re;
+      v[2 * n + 1] = im;
     }
-    if (this->a.shv) {  // the column's factor e^{-2i k2 x}
-      const c64 e = this->a.ex[(size_t)b * this->a.e_bs + acc.col];
+    v[2 * (kMaxM + 1)] = cr;
+    v[2 * (kMaxM + 1) + 1] = ci;
+    if (this->a.shv) {
+      const c64 e = this->a.ex[(size_t)b * this->a.e_bs + col];
 #pragma unroll
-      for (int v = 0; v < kNMom; ++v) {
-        const c64 t = e * c64{acc.v[2 * v], acc.v[2 * v + 1]};
-        acc.v[2 * v] = t.re;
-        acc.v[2 * v + 1] = t.im;
+      for (int q = 0; q < kNMom; ++q) {
+        const c64 t = e * c64{v[2 * q], v[2 * q + 1]};
+        v[2 * q] = t.re;
+        v[2 * q + 1] = t.im;
       }
     }
+  }
+
+  static constexpr int NMU = 2 * (kMaxM + 1);  // mu_0 .. mu_kMaxM (re, im)
+
+  template <int NT>
+  DBAR_D void finish(Acc& acc, int b, int tile, int ntiles, double* scratch) const {
     double* dst = this->a.part + (size_t)b * NV * ntiles + tile;
-    block_reduce_store<NT, NV>(acc.v, dst, ntiles, scratch);
+    constexpr int TPL = LineGeom<N>::TPL;
+    constexpr int LN = NT / TPL;  // columns per tile; thread tid serves column tid % LN
+    if constexpr (NT >= 64 && LN < 64) {
+      // 1) sum each column's mu_k over its threads: within a wave, lanes that differ by multiples of LN
+      __syncthreads();  // scratch aliases the transform's LDS
+      const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+      constexpr int NW = NT / 64;
+#pragma unroll
+      for (int q = 0; q < NMU; ++q) {
+        double x = acc.v[q];
+#pragma unroll
+        for (int off = 32; off >= LN; off >>= 1) x += __shfl_xor(x, off, 64);
+        acc.v[q] = x;
+      }
+      double* sc = scratch;                 // [NW][LN][NMU]
+      double* colv = scratch + NW * LN * NMU;  // [LN][NV]
+      if (lane < LN) {
+#pragma unroll
+        for (int q = 0; q < NMU; ++q) sc[(wave * LN + lane) * NMU + q] = acc.v[q];
+      }
+      __syncthreads();
+      // 2) one thread per column: sum over waves, binomial combination
+      if (threadIdx.x < LN) {
+        const int c = threadIdx.x;
+        double v[NV];
+#pragma unroll
+        for (int q = 0; q < NMU; ++q) {
+          double t = 0.0;
+          for (int w = 0; w < NW; ++w) t += sc[(w * LN + c) * NMU + q];
+          v[q] = t;
+        }
+        const int col = tile * LN + c;
+        combine(v, xgrid<N>(col, this->a.L), b, col);
+#pragma unroll
+        for (int q = 0; q < NV; ++q) colv[c * NV + q] = v[q];
+      }
+      __syncthreads();
+      // 3) the tile's partials: sum over its columns
+      for (int q = threadIdx.x; q < NV; q += NT) {
+        double t = 0.0;
+        for (int c = 0; c < LN; ++c) t += colv[c * NV + q];
+        dst[(size_t)q * ntiles] = t;
+      }
+    } else {
+      combine(acc.v, acc.x, b, acc.col);
+      block_reduce_store<NT, NV>(acc.v, dst, ntiles, scratch);
+    }
   }
 };
 
@@ -252,23 +318,19 @@ struct OpRowsInvRegular : OpBase<T, N> {
     const int o1 = this->a.shv ? this->a.shv[2 * b] : 0, o2 = this->a.shv ? this->a.shv[2 * b + 1] : 0;
     const double xi1 = (wavenum(pos, N) - o1) * invL, xi2 = (wavenum(row, N) - o2) * invL;
     const double r2 = xi1 * xi1 + xi2 * xi2;
-    c64 R;
-    if (r2 == 0.0) {
-      R = c[kMaxM + 1];
-    } else {
-      c64 s = cvt<double>(this->inp(b)[(size_t)row * N + pos]);
-      if (r2 < 740.0) {  // e^{-|xi|^2} underflows beyond this
-        const c64 xib{xi1, -xi2};
-        const int M = this->a.M;
-        c64 g = c[M];
-        for (int n = M - 1; n >= 0; --n) g = c[n] + xib * g;
-        s = s - exp(-r2) * g;
-      }
-      const double ir2 = 1.0 / r2;
-      R = c64{(s.re * xi1 + s.im * xi2) * ir2, (s.im * xi1 - s.re * xi2) * ir2};  // s / xi
-    }
     const double f = ((row + pos) & 1) ? -this->a.ci : this->a.ci;
-    return cvt<T>(f * R);
+    if (r2 == 0.0) return cvt<T>(f * c[kMaxM + 1]);
+    cx<T> sv = this->inp(b)[(size_t)row * N + pos];
+    if (r2 < 740.0) {  // G (FP64: conj(xi)^n overflows FP32 for |xi|^n > 3e38); e^{-|xi|^2} underflows beyond 740
+      const c64 xib{xi1, -xi2};
+      const int M = this->a.M;
+      c64 g = c[M];
+      for (int n = M - 1; n >= 0; --n) g = c[n] + xib * g;
+      sv = cvt<T>(cvt<double>(sv) - exp(-r2) * g);
+    }
+    // (S - G) / xi in the transform's precision
+    const T t1 = static_cast<T>(xi1), t2 = static_cast<T>(xi2), ir2 = static_cast<T>(f / r2);
+    return cx<T>{(sv.re * t1 + sv.im * t2) * ir2, (sv.im * t1 - sv.re * t2) * ir2};
   }
   DBAR_D void store(Acc&, int b, int row, int pos, cx<T> v) const { this->outp(b)[(size_t)row * N + pos] = v; }
 };
@@ -378,7 +440,10 @@ template <typename T, int N, int LINES>
 struct LdsSize {
   static constexpr int NT = LINES * LineGeom<N>::TPL;
   static constexpr int kData = LINES * LineGeom<N>::LDS_LINE * (int)sizeof(cx<T>);
-  static constexpr int kScratch = (NT >= 64 ? NT / 64 : NT) * 2 * kNMom * (int)sizeof(double);
+  static constexpr int LN = LINES;
+  static constexpr int kScratchReduce = (NT >= 64 ? NT / 64 : NT) * 2 * kNMom * (int)sizeof(double);
+  static constexpr int kScratchCols = ((NT >= 64 ? NT / 64 : 1) * LN * 2 * (kMaxM + 1) + LN * 2 * kNMom) * 8;
+  static constexpr int kScratch = kScratchReduce > kScratchCols ? kScratchReduce : kScratchCols;
   static constexpr int kElems = ((kData > kScratch ? kData : kScratch) + (int)sizeof(cx<T>) - 1) / (int)sizeof(cx<T>);
 };
 
