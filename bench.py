@@ -39,6 +39,8 @@ def parse():
     ap.add_argument("--headline", choices=["auto", "mixed", "fp64"], default="auto")
     ap.add_argument("--no-serving", action="store_true", help="skip the request-stream (p50/p99 latency) leg")
     ap.add_argument("--serving-requests", type=int, default=48)
+    ap.add_argument("--no-rows-f", action="store_true",
+                    help="skip the iterated-solver (Section 5.3) and DS II round-trip (Section 6) legs")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"), default=None,
                     help="no GPU: turn the FETCH_SIZE / WRITE_SIZE counter CSVs of two `--probe` runs into "
                          "profiles/traffic.json (bytes per launch per stage, scaled by the calibration copy)")
@@ -188,6 +190,50 @@ def serving_leg(D, W, n_req: int) -> dict:
     }
 
 
+def iterated_leg(D, Qd, L: float, M: int, tol: float) -> dict:
+    """The Section 5.3 iterated solver on the benchmark's potential and grid: 16 k with 2kL integer (a 4 x 4 grid over
+    {-2, -0.6, 0.6, 2}^2), batched; the mixed path's S is checked against the FP64 path's."""
+    import torch
+    ks = np.array([complex(a, b) for b in (-2.0, -0.6, 0.6, 2.0) for a in (-2.0, -0.6, 0.6, 2.0)])
+
+    def run(prec):
+        return D.solve_device(Qd, ks, L, tol=tol, M=M, batch=len(ks), method=D.DBAR_METHOD_ITERATED, precision=prec)
+
+    out = {"n_k": len(ks), "k_set": "{-2, -0.6, 0.6, 2}^2"}
+    res = {}
+    for name, prec in (("mixed", D.DBAR_MIXED), ("fp64", D.DBAR_FP64)):
+        run(prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res[name] = run(prec)
+        torch.cuda.synchronize()
+        out[f"{name}_solves_per_s"] = len(ks) / (time.perf_counter() - t0)
+        out[f"{name}_iters"] = [i.iters for i in res[name][2]]
+    S64 = res["fp64"][0].cpu().numpy()
+    out["mixed_err_S_vs_fp64"] = max(rel_linf(res["mixed"][0][j].cpu().numpy(), S64[j]) for j in range(len(ks)))
+    return out
+
+
+def ds2_leg(D, W, N: int = 128, L: float = 3.2) -> dict:
+    """DS II round trip of Section 6.2 (reconstruction table row N = 2^7, L = 3.2, M = 11; the paper's error is
+    2.40e-13): r(k) for q0 = e^{-x^2-y^2} at every k of the xi grid, then q from r at every z of the x grid, FP64."""
+    q0 = W.potential_gaussian(N, L, 1.0)
+    ks = W.k_xi_grid(N, L)
+    t0 = time.perf_counter()
+    r, info_r = D.reflection(q0, ks.ravel(), L, tol=1e-12)
+    t_r = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    q, info_q = D.reconstruct(r.reshape(N, N), L, tol=1e-12, want_info=True)
+    t_q = time.perf_counter() - t0
+    return {
+        "N": N, "L": L, "M": 11, "precision": "fp64", "solves": 2 * N * N,
+        "reflection_solves_per_s": N * N / t_r, "reconstruction_solves_per_s": N * N / t_q,
+        "round_trip_s": t_r + t_q, "err_q_vs_q0": float(np.max(np.abs(q - q0))), "paper_err": 2.40e-13,
+        "mean_iters": float(np.mean([i.iters for i in info_r] + [i.iters for i in info_q])),
+        "all_converged": all(i.status == 0 for i in info_r) and all(i.status == 0 for i in info_q),
+    }
+
+
 def main():
     args = parse()
     if args.traffic_from:
@@ -196,8 +242,8 @@ def main():
                           "write_scale": rec["write_scale"]}))
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 (multi-GPU k-sharding is "
-                          "described in DESIGN.md but not built)"}))
+        print(json.dumps({"error": "one GPU only: --gpus must be 1 (sharding the k values over several GPUs is "
+                          "not built)"}))
         sys.exit(2)
     import torch
 
@@ -321,6 +367,9 @@ def main():
 
     if not args.no_serving:
         result["serving"] = serving_leg(D, W, args.serving_requests)
+    if not args.no_rows_f:
+        result["iterated"] = iterated_leg(D, Qd, L, w.M, w.tol)
+        result["ds2"] = ds2_leg(D, W)
 
     if not args.no_cpu_baseline:
         from threadpoolctl import threadpool_limits

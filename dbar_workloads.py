@@ -74,6 +74,15 @@ def k_square_grid(lo: float, hi: float, n: int, exclude_zero: bool = True) -> np
     return ks.astype(np.complex128)
 
 
+def k_xi_grid(N: int, L: float) -> np.ndarray:
+    """Every point of the xi grid as a spectral parameter, laid out like an xi-space array in FFT order:
+    k[p2, p1] = (m(p1) + i m(p2)) / L with m(p) = p for p <= N/2, p - N otherwise (Section 4.1, equation
+    'xidomain'; Section 6 puts k on this grid)."""
+    m = np.arange(N)
+    m = np.where(m <= N // 2, m, m - N).astype(np.float64)
+    return (m[None, :] + 1j * m[:, None]) / L
+
+
 def k_disk(n: int, radius: float, seed: int) -> np.ndarray:
     """n values of k uniform in the disk |k| <= radius (seeded)."""
     rng = np.random.default_rng(seed)

@@ -89,13 +89,14 @@ enum { DBAR_METHOD_PLAIN = 0, DBAR_METHOD_ITERATED = 1 };
 typedef struct {
   int32_t status;       /* DBAR_OK or DBAR_ENOCONV */
   int32_t iters;        /* GMRES iterations (operator applications inside Krylov cycles) */
-  int32_t outer;        /* FP64 residual evaluations (refinement steps in DBAR_MIXED; restarts + 1 in FP64)
-                           DBAR_METHOD_ITERATED: S = f + h o (xi + 2i conj k) (Sform) and m = F^{-1}(S/xi) evaluated
-                           through the shift theorem; iters/rel_residual refer to the equation for h */
+  int32_t outer;        /* FP64 residual evaluations (refinement steps in DBAR_MIXED; restarts + 1 in FP64) */
   int32_t reserved;
   double rel_residual;  /* ||b - A(S)||_2 / ||b||_2, recomputed in FP64 with the FP64 operator at the end */
-  double m1_re, m1_im;  /* m^(1) = i S(0), the 1/z coefficient of m (equation m1def) */
+  double m1_re, m1_im;  /* m^(1) = i S(0), the 1/z coefficient of m (equation m1def); 0 from dbar_reflection and
+                           dbar_reconstruct, which do not form S */
 } dbar_info;
+/* With DBAR_METHOD_ITERATED, iters and rel_residual refer to the equation for h (eqh2); S = f + h o (xi + 2i conj k)
+ * (equation Sform) and m = F^{-1}(S/xi) is evaluated through the shift theorem. */
 
 /* Fill *opts with the defaults listed above. */
 void dbar_default_opts(dbar_opts* opts);
@@ -140,6 +141,36 @@ int dbar_transform(const dbar_grid* grid, int32_t inverse, const double* in, dou
  * F(dbar u) = (i/2) xi F(u), this is (i/2) dbar^{-1} F^{-1}(S).  Host buffers, N*N complex128 each.
  */
 int dbar_dbar_inverse(const dbar_grid* grid, const double* S_in, double* h_out, int32_t precision);
+
+/* ------------------------------------------------------------------------------------------------------------
+ * DS II scattering transforms (Section 6).  Both run the iterated solver (Section 5.3) in FP64 or DBAR_MIXED as
+ * opts->precision says (opts->method is ignored), batched over their many independent solves.
+ * ------------------------------------------------------------------------------------------------------------ */
+
+/*
+ * Reflection coefficient r(k) = i h(i conj k) (equation rviah) of the potential q, in the Section 6 convention
+ * (k replaced by k/2, so that k and xi are dual variables on the same grid): h solves the iterated equation for q
+ * with spectral parameter k/2, and h(i conj k) is its value at the shift offset (L Im k, L Re k).  Equivalently
+ * r = (M1^(1) - M2^(1))/2 for the CGO solutions M1, M2 of equations eq:021 and eq:022 (equation eq:023).
+ * q: host N*N complex128 (x-space).  k: nk (re, im) pairs, each on the xi grid (L Re k and L Im k integers, else
+ * DBAR_EINVAL).  r_out: nk complex128.  info: nk entries or NULL (iters and rel_residual of each solve for h).
+ * Returns DBAR_OK, DBAR_ENOCONV (r_out still written) or an error.
+ */
+int dbar_reflection(const dbar_grid* grid, const double* q, int64_t nk, const double* k, double tol,
+                    const dbar_opts* opts, double* r_out, dbar_info* info);
+
+/*
+ * Reconstruction of the potential q(x, y, t) from the reflection coefficient at t = 0 (equations dbarrecA,
+ * dbarrecB, qRec, with r(k, t) = r(k, 0) exp(-i t Re(k^2)/2), equation rt in the Section 6 convention): the D-bar
+ * problem of dbar_reflection with z and k interchanged and q replaced by conj(r(k, t)).  r: host N*N complex128 on
+ * the xi grid of `grid`, laid out like S (r[p2 * N + p1] = r(k), k = xi of that index; the row and column of the
+ * Nyquist wave number N/(2L) are taken as their periodic images at -N/(2L)).  q_out: host N*N complex128 on the x
+ * grid of `grid`.  The problem is solved on the dual grid (N, M, L' = N/(2 pi L)), whose xi grid holds the x grid
+ * of `grid`; it takes N*N solves (one per z).  info: N*N entries (row-major over z) or NULL.
+ * Returns DBAR_OK, DBAR_ENOCONV (q_out still written) or an error.
+ */
+int dbar_reconstruct(const dbar_grid* grid, const double* r, double t, double tol, const dbar_opts* opts,
+                     double* q_out, dbar_info* info);
 
 /* ------------------------------------------------------------------------------------------------------------
  * Serving: a request queue with continuous batching.  Requests (one k, one Q, one grid each) are admitted into

@@ -27,6 +27,7 @@ DBAR_METHOD_ITERATED = 1
 # every symbol include/dbar.h declares
 EXPORTED = [
     "dbar_default_opts", "dbar_solve", "dbar_solve_device", "dbar_apply", "dbar_transform", "dbar_dbar_inverse",
+    "dbar_reflection", "dbar_reconstruct",
     "dbar_session_create", "dbar_submit", "dbar_poll", "dbar_wait", "dbar_session_get_stats",
     "dbar_request_footprint", "dbar_session_destroy", "dbar_timer_enable", "dbar_timer_num_stages",
     "dbar_timer_stage", "dbar_last_error", "dbar_release", "dbar_version",
@@ -91,6 +92,10 @@ def load() -> ctypes.CDLL:
         lib.dbar_apply.argtypes = [G, D, D, D, D, ctypes.c_int32]
         lib.dbar_transform.argtypes = [G, ctypes.c_int32, D, D, ctypes.c_int32]
         lib.dbar_dbar_inverse.argtypes = [G, D, D, ctypes.c_int32]
+        lib.dbar_reflection.argtypes = [G, D, ctypes.c_int64, D, ctypes.c_double, ctypes.POINTER(Opts), D,
+                                        ctypes.POINTER(Info)]
+        lib.dbar_reconstruct.argtypes = [G, D, ctypes.c_double, ctypes.c_double, ctypes.POINTER(Opts), D,
+                                         ctypes.POINTER(Info)]
         if hasattr(lib, "dbar_session_create"):
             lib.dbar_session_create.argtypes = [ctypes.POINTER(SessionOpts), ctypes.POINTER(P)]
             lib.dbar_submit.argtypes = [P, G, D, D, ctypes.c_double, ctypes.POINTER(ctypes.c_uint64)]

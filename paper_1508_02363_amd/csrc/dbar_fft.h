@@ -226,8 +226,10 @@ DBAR_D void fft_pass_regs(cx<T>* v, int jt, const cx<T>* __restrict__ tw) {
   }
 }
 
-// Write the output of pass PASS to LDS (its Stockham destination positions) ...
-template <typename T, int N, int PASS>
+// Write the output of pass PASS to LDS (its Stockham destination positions) ...  Element p of a line lives at
+// line[padded(p) * LS]: LS = 1 for a line of its own, LS = lines per tile when the lines of a column tile are
+// interleaved element by element (the threads of one wave then touch consecutive addresses across the tile's lines)
+template <typename T, int N, int PASS, int LS>
 DBAR_D void lds_store_pass(cx<T>* __restrict__ line, const cx<T>* v, int jt) {
   using G = LineGeom<N>;
   constexpr int R = PassInfo<N, PASS>::R;
@@ -238,35 +240,36 @@ DBAR_D void lds_store_pass(cx<T>* __restrict__ line, const cx<T>* v, int jt) {
     const int j = jt + q * G::TPL;
     const int base = (j / NS) * NS * R + (j % NS);
 #pragma unroll
-    for (int r = 0; r < R; ++r) line[G::padded(base + r * NS)] = v[q + r * NB];
+    for (int r = 0; r < R; ++r) line[G::padded(base + r * NS) * LS] = v[q + r * NB];
   }
 }
 
 // ... and read the input pattern of the next pass.
-template <typename T, int N>
+template <typename T, int N, int LS>
 DBAR_D void lds_load_line(const cx<T>* __restrict__ line, cx<T>* v, int jt) {
   using G = LineGeom<N>;
 #pragma unroll
-  for (int s = 0; s < G::RMAX; ++s) v[s] = line[G::padded(jt + s * G::TPL)];
+  for (int s = 0; s < G::RMAX; ++s) v[s] = line[G::padded(jt + s * G::TPL) * LS];
 }
 
 // Full line transform: registers in (positions jt + s*TPL), registers out (same positions, transformed).
-// `line` is this line's LDS buffer (LDS_LINE elements).  Must be called by all threads of the block (barriers).
-template <typename T, int N, int DIR>
+// `line` is this line's LDS buffer (LDS_LINE elements at stride LS).  Must be called by all threads of the block
+// (barriers).
+template <typename T, int N, int DIR, int LS>
 DBAR_D void line_fft(cx<T>* v, int jt, cx<T>* __restrict__ line, const cx<T>* __restrict__ tw) {
   using G = LineGeom<N>;
   fft_pass_regs<T, N, 0, DIR>(v, jt, tw);
   if constexpr (G::NPASS > 1) {
-    lds_store_pass<T, N, 0>(line, v, jt);
+    lds_store_pass<T, N, 0, LS>(line, v, jt);
     __syncthreads();
-    lds_load_line<T, N>(line, v, jt);
+    lds_load_line<T, N, LS>(line, v, jt);
     __syncthreads();
     fft_pass_regs<T, N, 1, DIR>(v, jt, tw);
   }
   if constexpr (G::NPASS > 2) {
-    lds_store_pass<T, N, 1>(line, v, jt);
+    lds_store_pass<T, N, 1, LS>(line, v, jt);
     __syncthreads();
-    lds_load_line<T, N>(line, v, jt);
+    lds_load_line<T, N, LS>(line, v, jt);
     __syncthreads();
     fft_pass_regs<T, N, 2, DIR>(v, jt, tw);
   }

@@ -35,6 +35,36 @@ static __constant__ float kTailOneF32[16] = {19.0f,  22.75f, 26.0f,  28.75f, 31.
 static __constant__ double kTailOneF64[16] = {39.25, 43.75, 47.25, 50.5, 53.5, 56.25, 59.0, 61.5,
                                               64.0,  66.5,  68.75, 71.0, 73.25, 75.5, 77.5, 79.75};
 
+// Exact binomial coefficients C(n, k), n, k <= kMaxM (Pascal's rule at compile time), and reciprocals 1/j of the
+// integers (j < kNInv) for the tail recurrences, which would otherwise divide in every step.
+struct BinomTable {
+  double v[kMaxM + 1][kMaxM + 1];
+};
+constexpr BinomTable make_binom() {
+  BinomTable t{};
+  for (int n = 0; n <= kMaxM; ++n)
+    for (int k = 0; k <= n; ++k) t.v[n][k] = (k == 0 || k == n) ? 1.0 : t.v[n - 1][k - 1] + t.v[n - 1][k];
+  return t;
+}
+static __constant__ BinomTable kBinom = make_binom();
+
+constexpr int kNInv = 256;
+struct InvTable {
+  double d[kNInv];
+  float f[kNInv];
+};
+constexpr InvTable make_inv() {
+  InvTable t{};
+  for (int j = 1; j < kNInv; ++j) t.d[j] = 1.0 / j, t.f[j] = 1.0f / j;
+  return t;
+}
+static __constant__ InvTable kInv = make_inv();
+template <typename TT>
+DBAR_D TT inv_int(int j) {
+  if constexpr (sizeof(TT) == 8) return kInv.d[j];
+  else return kInv.f[j];
+}
+
 // x_j = L(-pi + 2 pi j / N)
 template <int N>
 DBAR_D double xgrid(int j, double L) {
@@ -51,8 +81,8 @@ DBAR_D cx<TT> tail_sum(TT x, TT y, const c64* __restrict__ d, int M) {
   const TT u = TT(0.25) * (x * x + y * y);
   const TT one_from = sizeof(TT) == 8 ? TT(kTailOneF64[M]) : TT(kTailOneF32[M]);
   if (u >= one_from) {  // all P(n+1, u) = 1: i sum_n d_n / z^{n+1}
-    const TT r2 = x * x + y * y;
-    const cx<TT> w{x / r2, -y / r2};
+    const TT ir2 = TT(1) / (x * x + y * y);
+    const cx<TT> w{x * ir2, -y * ir2};
     cx<TT> acc = cvt<TT>(d[M]);
     for (int n = M - 1; n >= 0; --n) acc = cvt<TT>(d[n]) + w * acc;
     return mul_i(w * acc);
@@ -62,8 +92,8 @@ DBAR_D cx<TT> tail_sum(TT x, TT y, const c64* __restrict__ d, int M) {
   cx<TT> acc{TT(0), TT(0)};
   if (u < TT(M + 1)) {
     TT term = TT(kInvFact[M + 1]), sum = term;
-    for (int k = 1; k < 200; ++k) {
-      term *= u / TT(M + 1 + k);
+    for (int k = 1; M + 1 + k < kNInv; ++k) {
+      term *= u * inv_int<TT>(M + 1 + k);
       sum += term;
       if (term < eps * sum) break;
     }
@@ -81,11 +111,11 @@ DBAR_D cx<TT> tail_sum(TT x, TT y, const c64* __restrict__ d, int M) {
 #pragma unroll
     for (int n = 0; n <= kMaxM; ++n) {
       P[n] = TT(1) - S;
-      t *= u / TT(n + 1);
+      t *= u * inv_int<TT>(n + 1);
       S += t;
     }
-    const TT r2 = x * x + y * y;
-    const cx<TT> w{x / r2, -y / r2};  // 1/z
+    const TT ir2 = TT(1) / (x * x + y * y);
+    const cx<TT> w{x * ir2, -y * ir2};  // 1/z
 #pragma unroll
     for (int n = kMaxM; n >= 0; --n) {
       if (n < M) acc = P[n] * cvt<TT>(d[n]) + w * acc;
@@ -210,43 +240,42 @@ struct OpColsInvMoments : OpBase<T, N> {
       }
     }
   }
-  // d_n = sum_{k<=n} C(n,k) x^{n-k} i^k mu_k in place from n = M down (d_n only needs mu_k, k <= n), then the conj
-  // moment x mu_0 - i mu_1 (computed first) and, with the shifted regularisation, the column factor e^{-2i k2 x}
-  DBAR_D void combine(double* v, double x, int b, int col) const {
-    const int M = this->a.M;
-    const double cr = x * v[0] + v[3], ci = x * v[1] - v[2];
-#pragma unroll
-    for (int n = kMaxM; n >= 0; --n) {
-      double re = 0.0, im = 0.0;
-      if (n <= M) {
-        double binom = 1.0, xpow = 1.0;  // C(n,k) and x^{n-k} for k = n, n-1, ..., 0
-#pragma unroll
-        for (int k = n; k >= 0; --k) {
-          const double c = binom * xpow;
-          const double mr = v[2 * k], mi = v[2 * k + 1];
-          switch (k & 3) {  // i^k mu_k
-            case 0: re += c * mr; im += c * mi; break;
-            case 1: re -= c * mi; im += c * mr; break;
-            case 2: re -= c * mr; im -= c * mi; break;
-            default: re += c * mi; im -= c * mr; break;
-          }
-          binom = binom * k / (n - k + 1);
-          xpow *= x;
+  // Moment q of one column from its mu_k: d_q = sum_{k<=q} C(q,k) x^{q-k} i^k mu_k for q <= M (0 for M < q <=
+  // kMaxM), and for q = kMaxM+1 the conj moment x mu_0 - i mu_1; with the shifted regularisation times the column
+  // factor e^{-2i k2 x}.  mu is (re, im) interleaved.
+  DBAR_D c64 combine_one(const double* mu, double x, int q, int b, int col) const {
+    double re = 0.0, im = 0.0;
+    if (q == kMaxM + 1) {
+      re = x * mu[0] + mu[3];
+      im = x * mu[1] - mu[2];
+    } else if (q <= this->a.M) {
+      double xpow = 1.0;  // x^{q-k} for k = q, q-1, ..., 0
+      for (int k = q; k >= 0; --k) {
+        const double c = kBinom.v[q][k] * xpow;
+        const double mr = mu[2 * k], mi = mu[2 * k + 1];
+        switch (k & 3) {  // i^k mu_k
+          case 0: re += c * mr; im += c * mi; break;
+          case 1: re -= c * mi; im += c * mr; break;
+          case 2: re -= c * mr; im -= c * mi; break;
+          default: re += c * mi; im -= c * mr; break;
         }
+        xpow *= x;
       }
-      v[2 * n] = re;
-      v[2 * n + 1] = im;
     }
-    v[2 * (kMaxM + 1)] = cr;
-    v[2 * (kMaxM + 1) + 1] = ci;
-    if (this->a.shv) {
-      const c64 e = this->a.ex[(size_t)b * this->a.e_bs + col];
+    c64 d{re, im};
+    if (this->a.shv) d = this->a.ex[(size_t)b * this->a.e_bs + col] * d;
+    return d;
+  }
+  // all moments of one thread's own partial sums (small tiles)
+  DBAR_D void combine(double* v, double x, int b, int col) const {
+    double mu[2 * (kMaxM + 1)];
 #pragma unroll
-      for (int q = 0; q < kNMom; ++q) {
-        const c64 t = e * c64{v[2 * q], v[2 * q + 1]};
-        v[2 * q] = t.re;
-        v[2 * q + 1] = t.im;
-      }
+    for (int q = 0; q < 2 * (kMaxM + 1); ++q) mu[q] = v[q];
+#pragma unroll 1
+    for (int q = 0; q < kNMom; ++q) {
+      const c64 d = combine_one(mu, x, q, b, col);
+      v[2 * q] = d.re;
+      v[2 * q + 1] = d.im;
     }
   }
 
@@ -276,20 +305,22 @@ struct OpColsInvMoments : OpBase<T, N> {
         for (int q = 0; q < NMU; ++q) sc[(wave * LN + lane) * NMU + q] = acc.v[q];
       }
       __syncthreads();
-      // 2) one thread per column: sum over waves, binomial combination
-      if (threadIdx.x < LN) {
-        const int c = threadIdx.x;
-        double v[NV];
-#pragma unroll
-        for (int q = 0; q < NMU; ++q) {
-          double t = 0.0;
-          for (int w = 0; w < NW; ++w) t += sc[(w * LN + c) * NMU + q];
-          v[q] = t;
-        }
+      // 2) each column's mu_k summed over its waves (one thread per column and value) ...
+      double* mus = colv + LN * NV;  // [LN][NMU]
+      for (int t = threadIdx.x; t < LN * NMU; t += NT) {
+        const int c = t / NMU, q = t % NMU;
+        double v = 0.0;
+        for (int w = 0; w < NW; ++w) v += sc[(w * LN + c) * NMU + q];
+        mus[c * NMU + q] = v;
+      }
+      __syncthreads();
+      // ... and combined into the moments (one thread per column and moment)
+      for (int t = threadIdx.x; t < LN * kNMom; t += NT) {
+        const int c = t / kNMom, q = t % kNMom;
         const int col = tile * LN + c;
-        combine(v, xgrid<N>(col, this->a.L), b, col);
-#pragma unroll
-        for (int q = 0; q < NV; ++q) colv[c * NV + q] = v[q];
+        const c64 d = combine_one(mus + c * NMU, xgrid<N>(col, this->a.L), q, b, col);
+        colv[c * NV + 2 * q] = d.re;
+        colv[c * NV + 2 * q + 1] = d.im;
       }
       __syncthreads();
       // 3) the tile's partials: sum over its columns
@@ -442,7 +473,8 @@ struct LdsSize {
   static constexpr int kData = LINES * LineGeom<N>::LDS_LINE * (int)sizeof(cx<T>);
   static constexpr int LN = LINES;
   static constexpr int kScratchReduce = (NT >= 64 ? NT / 64 : NT) * 2 * kNMom * (int)sizeof(double);
-  static constexpr int kScratchCols = ((NT >= 64 ? NT / 64 : 1) * LN * 2 * (kMaxM + 1) + LN * 2 * kNMom) * 8;
+  static constexpr int kScratchCols =
+      ((NT >= 64 ? NT / 64 : 1) * LN * 2 * (kMaxM + 1) + LN * 2 * kNMom + LN * 2 * (kMaxM + 1)) * 8;
   static constexpr int kScratch = kScratchReduce > kScratchCols ? kScratchReduce : kScratchCols;
   static constexpr int kElems = ((kData > kScratch ? kData : kScratch) + (int)sizeof(cx<T>) - 1) / (int)sizeof(cx<T>);
 };
@@ -472,38 +504,41 @@ __global__ void __launch_bounds__(LINES * LineGeom<N>::TPL, MinWaves<LINES * Lin
   cx<T> v[G::RMAX];
 #pragma unroll
   for (int s = 0; s < G::RMAX; ++s) v[s] = op.load(b, line, jt + s * G::TPL);
-  cx<T>* my = lds + ln * G::LDS_LINE;
-  line_fft<T, N, Op::DIR1>(v, jt, my, tw);
+  // LDS: a row tile keeps each line contiguous (one line per wave or less); a column tile interleaves its lines
+  // element by element, so that the lanes of a wave (consecutive columns) hit consecutive banks
+  constexpr int LS = COLS ? LINES : 1;
+  cx<T>* my = COLS ? lds + ln : lds + ln * G::LDS_LINE;
+  line_fft<T, N, Op::DIR1, LS>(v, jt, my, tw);
   // Heavy per-element work (FP64 moments, the closed-form tail) runs in a rolled loop over values parked in LDS at
   // the thread's own positions: registers stay low (occupancy) and no barrier is needed until the next exchange.
   if constexpr (Op::TWO) {
     if constexpr (Op::ROLLED) {
 #pragma unroll
-      for (int s = 0; s < G::RMAX; ++s) my[G::padded(jt + s * G::TPL)] = v[s];
+      for (int s = 0; s < G::RMAX; ++s) my[G::padded(jt + s * G::TPL) * LS] = v[s];
 #pragma unroll 1
       for (int s = 0; s < G::RMAX; ++s) {
         const int pos = jt + s * G::TPL;
-        cx<T> t = my[G::padded(pos)];
+        cx<T> t = my[G::padded(pos) * LS];
         op.template mid<typename Op::Acc>(b, line, pos, t);
-        my[G::padded(pos)] = t;
+        my[G::padded(pos) * LS] = t;
       }
 #pragma unroll
-      for (int s = 0; s < G::RMAX; ++s) v[s] = my[G::padded(jt + s * G::TPL)];
+      for (int s = 0; s < G::RMAX; ++s) v[s] = my[G::padded(jt + s * G::TPL) * LS];
       __syncthreads();  // the forward transform's first exchange writes other threads' positions
     } else {
 #pragma unroll
       for (int s = 0; s < G::RMAX; ++s) op.template mid<typename Op::Acc>(b, line, jt + s * G::TPL, v[s]);
     }
-    line_fft<T, N, -Op::DIR1>(v, jt, my, tw);
+    line_fft<T, N, -Op::DIR1, LS>(v, jt, my, tw);
   }
   typename Op::Acc acc{};
   if constexpr (Op::ROLLED && !Op::TWO) {
 #pragma unroll
-    for (int s = 0; s < G::RMAX; ++s) my[G::padded(jt + s * G::TPL)] = v[s];
+    for (int s = 0; s < G::RMAX; ++s) my[G::padded(jt + s * G::TPL) * LS] = v[s];
 #pragma unroll 1
     for (int s = 0; s < G::RMAX; ++s) {
       const int pos = jt + s * G::TPL;
-      op.store(acc, b, line, pos, my[G::padded(pos)]);
+      op.store(acc, b, line, pos, my[G::padded(pos) * LS]);
     }
   } else {
 #pragma unroll

@@ -78,6 +78,7 @@ struct EntryResult {
   int iters, cycles;
   double bnorm, rnorm;
   c64 s00;
+  c64 hsh;  // iterated method: h at the shift offset, h(2i conj k)
 };
 
 struct BatchCfg {
@@ -159,6 +160,11 @@ struct Pipeline {
 void launch_roll_add(const c64* f, const c64* h, const int* shv, int N, c64* out, int B, hipStream_t s);
 
 int validate_grid(const dbar_grid* g);
+// batched solve behind dbar_solve / dbar_solve_device; r_out (host, nk complex or NULL) receives i h(2i conj k) of
+// the iterated method, and with S = m = NULL only that is formed
+int solve_impl(const dbar_grid* grid, const void* Q, bool q_on_device, int64_t nk, const double* k, double tol,
+               const dbar_opts* opts_in, void* S, void* m, bool out_on_device, dbar_info* info, hipStream_t caller,
+               double* r_out);
 int get_twiddles(int N, const Twiddles** out);
 int make_pipeline(const dbar_grid* g, Work& w, Pipeline* p);
 void launch_phase_tables(const c64* kv_dev, int N, double L, c64* ex, c64* ey, int B, hipStream_t s);

@@ -50,18 +50,26 @@ __global__ void __launch_bounds__(256) k_moments(const double* part, int ntiles,
   constexpr int NV = 2 * kNMom;
   const int b = blockIdx.x;
   if (act && !act[b]) return;
-  __shared__ double red[4][NV];
   __shared__ double tot[NV];
-  for (int v = 0; v < NV; ++v) {
-    const double* p = part + ((size_t)b * NV + v) * ntiles;
-    double s = 0.0;
-    for (int i = threadIdx.x; i < ntiles; i += 256) s += p[i];
-    s = wsum(s);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6][v] = s;
+  // wave w sums values v = w, w + 4, ...; every lane issues all of its loads before the wave reductions
+  constexpr int PER = (NV + 3) / 4;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double acc[PER];
+#pragma unroll
+  for (int j = 0; j < PER; ++j) acc[j] = 0.0;
+  for (int i = lane; i < ntiles; i += 64) {
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      const int v = wave + 4 * j;
+      if (v < NV) acc[j] += part[((size_t)b * NV + v) * ntiles + i];
+    }
   }
-  __syncthreads();
-  if (threadIdx.x < NV) tot[threadIdx.x] = (red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] +
-                                            red[3][threadIdx.x]) * wscale;
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    const double t = wsum(acc[j]);
+    const int v = wave + 4 * j;
+    if (lane == 0 && v < NV) tot[v] = t * wscale;
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
     c64* cg = coefG + (size_t)b * kNMom;
@@ -190,12 +198,19 @@ __global__ void k_phase_tables(const c64* kv, int N, double L, c64* ex, c64* ey,
   }
 }
 
-// compact per-entry results: iterations, residual evaluations, ||b||, ||r||, S(0)
-__global__ void k_gather_results(const Ctl* ctl, const c64* x, size_t n, EntryResult* out, int B) {
+// compact per-entry results: iterations, residual evaluations, ||b||, ||r||, S(0), and with shifts (iterated
+// method) h at the shift offset (m1, m2) = (2 k2 L, 2 k1 L), i.e. h(xi = 2i conj k)
+__global__ void k_gather_results(const Ctl* ctl, const c64* x, size_t n, const c64* h, const int* shv, int N,
+                                 EntryResult* out, int B) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= B) return;
   const Ctl& c = ctl[b];
-  out[b] = EntryResult{c.iters, c.cycles, c.bnorm, c.rnorm, x[(size_t)b * n]};
+  c64 hs{0.0, 0.0};
+  if (shv) {
+    const int p1 = ((shv[2 * b] % N) + N) % N, p2 = ((shv[2 * b + 1] % N) + N) % N;
+    hs = h[(size_t)b * n + (size_t)p2 * N + p1];
+  }
+  out[b] = EntryResult{c.iters, c.cycles, c.bnorm, c.rnorm, x[(size_t)b * n], hs};
 }
 
 void launch_phase_tables(const c64* kv_dev, int N, double L, c64* ex, c64* ey, int B, hipStream_t s) {
@@ -828,8 +843,11 @@ static int solver_stream(hipStream_t caller, hipStream_t* out) {
 // grid offset of 2 k_c L (k_c a component of k), known to be an integer
 static int shift_of(double kc, double L) { return (int)std::nearbyint(2.0 * kc * L); }
 
+// r_out (host, nk complex, or NULL): with the iterated method, i h(2i conj k) per entry; when S and m are both NULL
+// the S and m post-processing is skipped (the reflection-coefficient path)
 int solve_impl(const dbar_grid* grid, const void* Q, bool q_on_device, int64_t nk, const double* k, double tol,
-               const dbar_opts* opts_in, void* S, void* m, bool out_on_device, dbar_info* info, hipStream_t caller) {
+               const dbar_opts* opts_in, void* S, void* m, bool out_on_device, dbar_info* info, hipStream_t caller,
+               double* r_out) {
   int rc = validate_grid(grid);
   if (rc) return rc;
   if (nk < 1) return fail(DBAR_EINVAL, "nk must be >= 1");
@@ -923,7 +941,8 @@ int solve_impl(const dbar_grid* grid, const void* Q, bool q_on_device, int64_t n
                          out_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s) != hipSuccess)
         return fail(DBAR_EDEVICE, "S copy failed");
     }
-    if (cfg.method == 1) {
+    const bool post = cfg.method == 1 && (S || m || !r_out);
+    if (post) {
       // f = H(h) (into Hbuf), S = f + h o (xi + a) (into bvec), m = h(f) + e_k F^{-1}(h/(xi - a)) (into T64)
       c64* Hb = static_cast<c64*>(w.Hbuf.p);
       c64* Sb = static_cast<c64*>(w.bvec.p);
@@ -938,7 +957,7 @@ int solve_impl(const dbar_grid* grid, const void* Q, bool q_on_device, int64_t n
                               (size_t)nb * n * sizeof(c64),
                               out_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s) != hipSuccess)
         return fail(DBAR_EDEVICE, "m copy failed");
-    } else if (m) {
+    } else if (m && cfg.method == 0) {
       P.h_of<double>(w.x.p, n, w.T64.p, n, w.bvec.p, nb, nullptr, s);  // bvec reused as scratch
       char* dst = static_cast<char*>(m) + (size_t)k0 * n * sizeof(c64);
       if (hipMemcpyAsync(dst, w.T64.p, (size_t)nb * n * sizeof(c64),
@@ -946,7 +965,8 @@ int solve_impl(const dbar_grid* grid, const void* Q, bool q_on_device, int64_t n
         return fail(DBAR_EDEVICE, "m copy failed");
     }
     hipLaunchKernelGGL(k_gather_results, dim3(ctl_blocks(nb)), dim3(64), 0, s, static_cast<const Ctl*>(w.ctl.p),
-                       static_cast<const c64*>(cfg.method == 1 ? w.bvec.p : w.x.p), n,
+                       static_cast<const c64*>(post ? w.bvec.p : w.x.p), n, static_cast<const c64*>(w.x.p),
+                       cfg.method == 1 ? static_cast<const int*>(w.shv.p) : nullptr, N,
                        static_cast<EntryResult*>(w.results.p), nb);
     (void)hipMemcpyAsync(hres.data(), w.results.p, (size_t)nb * sizeof(EntryResult), hipMemcpyDeviceToHost, s);
     (void)hipMemcpyAsync(w.host_live.data(), w.live.p, nb * sizeof(int), hipMemcpyDeviceToHost, s);
@@ -962,8 +982,12 @@ int solve_impl(const dbar_grid* grid, const void* Q, bool q_on_device, int64_t n
         I.outer = c.cycles;
         I.reserved = 0;
         I.rel_residual = c.bnorm > 0.0 ? c.rnorm / c.bnorm : 0.0;
-        I.m1_re = -c.s00.im;  // m1 = i S(0)
-        I.m1_im = c.s00.re;
+        I.m1_re = post || cfg.method == 0 ? -c.s00.im : 0.0;  // m1 = i S(0); not formed on the r-only path
+        I.m1_im = post || cfg.method == 0 ? c.s00.re : 0.0;
+      }
+      if (r_out) {  // r = i h(2i conj k)
+        r_out[2 * (k0 + b)] = -c.hsh.im;
+        r_out[2 * (k0 + b) + 1] = c.hsh.re;
       }
     }
   }
@@ -1014,13 +1038,13 @@ void dbar_release(void) {
 
 int dbar_solve(const dbar_grid* grid, const double* Q, int64_t nk, const double* k, double tol, const dbar_opts* opts,
                double* S_out, double* m_out, dbar_info* info) {
-  return solve_impl(grid, Q, false, nk, k, tol, opts, S_out, m_out, false, info, nullptr);
+  return solve_impl(grid, Q, false, nk, k, tol, opts, S_out, m_out, false, info, nullptr, nullptr);
 }
 
 int dbar_solve_device(const dbar_grid* grid, const void* Q_dev, int64_t nk, const double* k, double tol,
                       const dbar_opts* opts, void* S_dev, void* m_dev, dbar_info* info, void* stream) {
   return solve_impl(grid, Q_dev, true, nk, k, tol, opts, S_dev, m_dev, true, info,
-                    static_cast<hipStream_t>(stream));
+                    static_cast<hipStream_t>(stream), nullptr);
 }
 
 static int single_prep(const dbar_grid* grid, int precision, Work*& w, Pipeline& P) {

@@ -102,6 +102,38 @@ def solve_device(Q, ks, L: float, tol: float = 1e-12, M: int = 11, want_m: bool 
     return S, m, _infos(info)
 
 
+def reflection(q: np.ndarray, ks, L: float, tol: float = 1e-12, M: int = 11, **opt_kw):
+    """DS II reflection coefficient r(k) = i h(i conj k) (Section 6 convention, every k on the xi grid).
+    Returns (r [nk], infos)."""
+    q = _c128(q)
+    N = q.shape[0]
+    ks = np.ascontiguousarray(np.atleast_1d(np.asarray(ks, dtype=np.complex128)).ravel())
+    r = np.empty(ks.size, np.complex128)
+    info = (_lib.Info * ks.size)()
+    g = _grid(N, L, M)
+    o = make_opts(**opt_kw)
+    rc = _lib.load().dbar_reflection(ctypes.byref(g), _dptr(q), ks.size, _dptr(ks.view(np.float64)), float(tol),
+                                     ctypes.byref(o), _dptr(r.view(np.float64)), info)
+    check(rc, allow=(DBAR_OK, DBAR_ENOCONV))
+    return r, _infos(info)
+
+
+def reconstruct(r: np.ndarray, L: float, t: float = 0.0, tol: float = 1e-12, M: int = 11, want_info: bool = False,
+                **opt_kw):
+    """DS II potential q(x, y, t) on the x grid from r(k, 0) on the xi grid (laid out like S).  Returns q [N, N]
+    (and the N*N infos with want_info)."""
+    r = _c128(r)
+    N = r.shape[0]
+    q = np.empty((N, N), np.complex128)
+    info = (_lib.Info * (N * N))() if want_info else None
+    g = _grid(N, L, M)
+    o = make_opts(**opt_kw)
+    rc = _lib.load().dbar_reconstruct(ctypes.byref(g), _dptr(r), float(t), float(tol), ctypes.byref(o), _dptr(q),
+                                      info)
+    check(rc, allow=(DBAR_OK, DBAR_ENOCONV))
+    return (q, _infos(info)) if want_info else q
+
+
 def apply(Q: np.ndarray, k: complex, S: np.ndarray, L: float, M: int = 11, precision: int = DBAR_FP64):
     """One application A(S) = S + i F(q_k conj(h(S)))."""
     Q = _c128(Q)

@@ -81,3 +81,26 @@ def test_default_opts():
     o = _lib.Opts()
     _lib.load().dbar_default_opts(ctypes.byref(o))
     assert o.max_iter == 1000 and o.reorth == 1 and o.precision == _lib.DBAR_FP64 and o.inner_tol == 1e-5
+
+
+def test_reflection_and_reconstruction_reject_bad_arguments():
+    lib = _lib.load()
+    D = ctypes.POINTER(ctypes.c_double)
+    g = _lib.Grid(16, 11, 2.0)
+    q = np.zeros(2 * 256)
+    r = np.zeros(2)
+    off = np.array([0.1, 0.0])  # L Re k = 0.2: not on the xi grid
+    assert lib.dbar_reflection(ctypes.byref(g), q.ctypes.data_as(D), 1, off.ctypes.data_as(D), 1e-12, None,
+                               r.ctypes.data_as(D), None) == _lib.DBAR_EINVAL
+    on = np.array([0.5, -1.0])
+    assert lib.dbar_reflection(ctypes.byref(g), q.ctypes.data_as(D), 1, on.ctypes.data_as(D), 1e-12, None,
+                               None, None) == _lib.DBAR_EINVAL
+    rr = np.zeros(2 * 256)
+    rr[3] = np.inf
+    qo = np.zeros(2 * 256)
+    assert lib.dbar_reconstruct(ctypes.byref(g), rr.ctypes.data_as(D), 0.0, 1e-12, None, qo.ctypes.data_as(D),
+                                None) == _lib.DBAR_EINVAL
+    assert lib.dbar_reconstruct(ctypes.byref(g), qo.ctypes.data_as(D), float("nan"), 1e-12, None,
+                                qo.ctypes.data_as(D), None) == _lib.DBAR_EINVAL
+    assert lib.dbar_reconstruct(ctypes.byref(_lib.Grid(12, 11, 2.0)), qo.ctypes.data_as(D), 0.0, 1e-12, None,
+                                qo.ctypes.data_as(D), None) == _lib.DBAR_EINVAL

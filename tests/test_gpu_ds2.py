@@ -1,0 +1,109 @@
+"""GPU parity of the DS II scattering transforms (Section 6) through the C ABI: dbar_reflection and dbar_reconstruct
+against the oracle, and the Section 6.2 reconstruction table.
+
+Tolerances: r and q are O(1) or smaller and every solve stops at a relative residual of 1e-12 with condition
+numbers below 50 (the dense pins), so FP64 results agree with the oracle (which solves to 1e-13) to 1e-11 absolute.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import dbar_oracle as O
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1508_02363_amd import dbar as D  # noqa: E402
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def grid_ks(g, rng, n):
+    """n points of the xi grid (FFT order indices), including 0 and the corners."""
+    idx = [(0, 0), (g.N // 2, g.N // 2), (g.N - 1, 1)] + [tuple(rng.integers(0, g.N, 2)) for _ in range(n - 3)]
+    return idx, np.array([g.xi[a, b] for a, b in idx])
+
+
+@pytest.mark.parametrize("prec", [D.DBAR_FP64, D.DBAR_MIXED])
+def test_reflection_matches_oracle(prec):
+    N, L = 64, 3.2
+    g = O.make_grid(N, L)
+    q = (0.7 - 0.2j) * np.exp(-np.abs(g.z) ** 2)
+    _, ks = grid_ks(g, np.random.default_rng(11), 12)
+    r, info = D.reflection(q, ks, L, tol=1e-12, precision=prec)
+    om = O.omega_table(g, 11)
+    for j, k in enumerate(ks):
+        assert info[j].status == 0 and info[j].rel_residual <= 1e-12
+        assert abs(r[j] - O.reflection_coefficient(g, q, k, om=om)) < 1e-11, (j, k)
+
+
+def test_reflection_rejects_k_off_the_grid():
+    with pytest.raises(D.DbarError) as e:
+        D.reflection(np.ones((32, 32)) * 0.1, [0.1 + 0.0j], 3.0)
+    assert e.value.code == D._lib.DBAR_EINVAL
+
+
+def test_reconstruction_matches_oracle_n16():
+    """Full round trip q0 -> r -> q at N = 16 on the GPU against the oracle's, element by element."""
+    N, L = 16, 1.075
+    g = O.make_grid(N, L)
+    q0 = np.exp(-np.abs(g.z) ** 2)
+    r_ref = O.reflection_grid(g, q0)
+    q_ref = O.reconstruct_potential(g, r_ref)
+    r, _ = D.reflection(q0, g.xi.ravel(), L)
+    r = r.reshape(N, N)
+    assert np.max(np.abs(r - r_ref)) < 1e-11
+    q = D.reconstruct(r, L)
+    assert np.max(np.abs(q - q_ref)) < 1e-11
+    assert 0.5 * 3.1872e-4 < np.max(np.abs(q - q0)) < 1.25 * 3.1872e-4  # Section 6.2 table, N = 2^4
+
+
+def test_reconstruction_time_evolution_small_amplitude():
+    """q(t) for eps e^{-|z|^2}, eps = 1e-3, t = 0.3: the linear DS II solution up to O(eps^3), and the oracle."""
+    N, L, eps, t = 16, 1.3, 1e-3, 0.3
+    g = O.make_grid(N, L)
+    r, _ = D.reflection(eps * np.exp(-np.abs(g.z) ** 2), g.xi.ravel(), L)
+    r = r.reshape(N, N)
+    q = D.reconstruct(r, L, t=t)
+    x, y = g.z.real, g.z.imag
+    lin = eps * np.exp(-x ** 2 / (1 + 2j * t)) / np.sqrt(1 + 2j * t) * np.exp(-y ** 2 / (1 - 2j * t)) / np.sqrt(1 - 2j * t)
+    assert np.max(np.abs(q - lin)) < 1e-4 * eps
+    assert np.max(np.abs(q - O.reconstruct_potential(g, O.evolve_reflection(g, r, t)))) < 1e-13
+
+
+def test_reconstruction_table_n64():
+    """Section 6.2 table, N = 2^6, L = 2.1213: the GPU round trip has the oracle's error (paper: 1.736e-9) and
+    matches the oracle's r and q at sampled points (stored by tests/golden/make_reconstruction_golden.py)."""
+    gold = json.load(open(os.path.join(GOLDEN, "reconstruction_n64.json")))
+    N, L = gold["N"], gold["L"]
+    g = O.make_grid(N, L)
+    q0 = np.exp(-np.abs(g.z) ** 2)
+    r, info = D.reflection(q0, g.xi.ravel(), L)
+    assert all(i.status == 0 for i in info)
+    r = r.reshape(N, N)
+    q = D.reconstruct(r, L)
+    for s in gold["samples"]:
+        a, b = s["p2"], s["p1"]
+        assert abs(r[a, b] - complex(*s["r"])) < 1e-12, (a, b)
+        assert abs(q[a, b] - complex(*s["q"])) < 1e-12, (a, b)
+    err = np.max(np.abs(q - q0))
+    assert abs(err - gold["oracle_error"]) < 1e-12 + 0.05 * gold["oracle_error"]
+    assert err < 2 * gold["paper_error"]
+
+
+def test_reconstruction_table_n128():
+    """Section 6.2 table, N = 2^7, L = 3.2: the initial data come back to the paper's 2.40e-13 (16384 reflection
+    solves and 16384 reconstruction solves)."""
+    N, L = 128, 3.2
+    g = O.make_grid(N, L)
+    q0 = np.exp(-np.abs(g.z) ** 2)
+    r, _ = D.reflection(q0, g.xi.ravel(), L)
+    q = D.reconstruct(r.reshape(N, N), L)
+    err = np.max(np.abs(q - q0))
+    print(f"N=128 L=3.2 reconstruction error {err:.3e}")
+    assert err < 1e-12

@@ -50,3 +50,17 @@ def test_small_amplitude_time_evolution():
         assert np.max(np.abs(q - lin)) < 1e-4 * eps, t
     # the reflection coefficient keeps its modulus (Section 6.1)
     assert np.allclose(np.abs(O.evolve_reflection(g, r, 0.7)), np.abs(r), rtol=1e-15, atol=0)
+
+
+def test_stored_n64_round_trip_matches_the_table():
+    """tests/golden/reconstruction_n64.json holds the oracle's own N = 64 round trip (8192 solves, written by
+    make_reconstruction_golden.py); its error is the table's 1.736e-9 to within the same margin as the rows above."""
+    import json
+    import os
+    gold = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                                       "reconstruction_n64.json")))
+    assert 0.5 * gold["paper_error"] < gold["oracle_error"] < 1.25 * gold["paper_error"]
+    g = O.make_grid(gold["N"], gold["L"])
+    for s in gold["samples"][:3]:  # spot-check three stored reflection values against a fresh oracle solve
+        k = g.xi[s["p2"], s["p1"]]
+        assert abs(O.reflection_coefficient(g, np.exp(-np.abs(g.z) ** 2), k) - complex(*s["r"])) < 1e-13
