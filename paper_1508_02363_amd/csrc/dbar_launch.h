@@ -31,12 +31,14 @@ struct LineArgs {
   const void* Y = nullptr;     size_t Y_bs = 0;    // epilogue vector (gamma term)
   const void* Q = nullptr;     size_t Q_bs = 0;    // potential, same precision as the transform; stride 0 = shared
   const c64* ex = nullptr;     const c64* ey = nullptr;  // [b][N] tables e^{-2i k2 x_j}, e^{-2i k1 y_j}
+  const c32* ex32 = nullptr;   const c32* ey32 = nullptr;  // the same rounded to FP32 (FP32 operator)
   size_t e_bs = 0;             // per-entry stride of ex / ey (N; 0 = one table shared by all entries)
   const int* shv = nullptr;    // per-entry grid offsets (m1, m2) of a = 2i conj(k): regularise about xi = a
   int tail_phase_out = 0;      // ColsInvTail with shv: return e_k F^{-1}(h/(xi - a)) instead of F^{-1}(h/(xi - a))
   int accumulate = 0;          // ColsInvTail: hout += result
   const c64* coefG = nullptr;  // [b][kNMom]: c_0..c_M, slot kMaxM+1 = R(0) = (-i/2) dt
   const c64* dmom = nullptr;   // [b][kNMom]: d_0..d_M (tail weights)
+  const c32* dmom32 = nullptr; // the same rounded to FP32 (FP32 operator)
   void* hout = nullptr;        size_t hout_bs = 0;
   double* part = nullptr;      // per-block partial sums [b][tile][nval]
   const void* tw = nullptr;    // twiddle table exp(-2 pi i j / N), j < N, in the transform's precision

@@ -70,57 +70,73 @@ template <int N>
 DBAR_D double xgrid(int j, double L) {
   return L * (-kPi + (2.0 * kPi / N) * j);
 }
+// the same in the arithmetic type TT (the FP32 operator evaluates its tail in FP32)
+template <typename TT, int N>
+DBAR_D TT xgrid_t(int j, double L) {
+  if constexpr (sizeof(TT) == 8) return xgrid<N>(j, L);
+  else return static_cast<float>(L) * (static_cast<float>(-kPi) + static_cast<float>(2.0 * kPi / N) * j);
+}
+
+// 1/r: FP64 division, or the hardware reciprocal (1 ulp) in FP32
+template <typename TT>
+DBAR_D TT recip(TT r) {
+  if constexpr (sizeof(TT) == 8) return 1.0 / r;
+  else return __builtin_amdgcn_rcpf(r);
+}
 
 // sum_{n=0}^{M} d_n omega_n(z),  omega_n = i P(n+1, u) / z^{n+1},  u = |z|^2/4  (c_n W_n = d_n omega_n).
 // u <  M+1: omega_n = i E_n (conj(z)/4)^{n+1} with E_n = e^{-u} sum_k u^k/(n+1+k)!  (equation fourreg5a with the
 //           factor e^{-u}); E_M by its series, E_n = u E_{n+1} + e^{-u}/(n+1)! downwards (positive terms only).
 // u >= M+1: omega_n = i (1 - e^{-u} sum_{k<=n} u^k/k!) / z^{n+1}  (equation fourreg5); no cancellation there.
 // TT is the arithmetic type: double in the FP64 operator, float in the FP32 one (whose data carry 24-bit mantissas).
-template <typename TT>
-DBAR_D cx<TT> tail_sum(TT x, TT y, const c64* __restrict__ d, int M) {
-  const TT u = TT(0.25) * (x * x + y * y);
-  const TT one_from = sizeof(TT) == 8 ? TT(kTailOneF64[M]) : TT(kTailOneF32[M]);
+// MM is the Taylor order the loops are unrolled for: the order M itself (M = 11, the paper's choice), or kMaxM for any
+// M, which is exact too because d_n = 0 for M < n <= kMaxM.  d holds d_0..d_kMaxM in registers.
+template <typename TT, int MM>
+DBAR_D cx<TT> tail_sum(TT x, TT y, const cx<TT> (&d)[kMaxM + 1]) {
+  const TT r2 = x * x + y * y;
+  const TT u = TT(0.25) * r2;
+  const TT one_from = sizeof(TT) == 8 ? TT(kTailOneF64[MM]) : TT(kTailOneF32[MM]);
   if (u >= one_from) {  // all P(n+1, u) = 1: i sum_n d_n / z^{n+1}
-    const TT ir2 = TT(1) / (x * x + y * y);
+    const TT ir2 = recip(r2);
     const cx<TT> w{x * ir2, -y * ir2};
-    cx<TT> acc = cvt<TT>(d[M]);
-    for (int n = M - 1; n >= 0; --n) acc = cvt<TT>(d[n]) + w * acc;
+    cx<TT> acc = d[MM];
+#pragma unroll
+    for (int n = MM - 1; n >= 0; --n) acc = d[n] + w * acc;
     return mul_i(w * acc);
   }
   const TT eu = exp(-u);
   const TT eps = sizeof(TT) == 8 ? TT(1e-17) : TT(3e-8);
   cx<TT> acc{TT(0), TT(0)};
-  if (u < TT(M + 1)) {
-    TT term = TT(kInvFact[M + 1]), sum = term;
-    for (int k = 1; M + 1 + k < kNInv; ++k) {
-      term *= u * inv_int<TT>(M + 1 + k);
+  if (u < TT(MM + 1)) {
+    TT term = TT(kInvFact[MM + 1]), sum = term;
+    for (int k = 1; MM + 1 + k < kNInv; ++k) {
+      term *= u * inv_int<TT>(MM + 1 + k);
       sum += term;
       if (term < eps * sum) break;
     }
     TT E = eu * sum;
     const cx<TT> zeta{TT(0.25) * x, TT(-0.25) * y};
-    acc = E * cvt<TT>(d[M]);
-    for (int n = M - 1; n >= 0; --n) {
+    acc = E * d[MM];
+#pragma unroll
+    for (int n = MM - 1; n >= 0; --n) {
       E = u * E + eu * TT(kInvFact[n + 1]);
-      acc = E * cvt<TT>(d[n]) + zeta * acc;
+      acc = E * d[n] + zeta * acc;
     }
     acc = zeta * acc;
   } else {
-    TT P[kMaxM + 1];
+    TT P[MM + 1];
     TT t = eu, S = eu;
 #pragma unroll
-    for (int n = 0; n <= kMaxM; ++n) {
+    for (int n = 0; n <= MM; ++n) {
       P[n] = TT(1) - S;
       t *= u * inv_int<TT>(n + 1);
       S += t;
     }
-    const TT ir2 = TT(1) / (x * x + y * y);
+    const TT ir2 = recip(r2);
     const cx<TT> w{x * ir2, -y * ir2};  // 1/z
+    acc = P[MM] * d[MM];
 #pragma unroll
-    for (int n = kMaxM; n >= 0; --n) {
-      if (n < M) acc = P[n] * cvt<TT>(d[n]) + w * acc;
-      else if (n == M) acc = P[n] * cvt<TT>(d[n]);
-    }
+    for (int n = MM - 1; n >= 0; --n) acc = P[n] * d[n] + w * acc;
     acc = w * acc;
   }
   return mul_i(acc);
@@ -191,6 +207,10 @@ struct OpBase {
   DBAR_D cx<T>* outp(int b) const { return static_cast<cx<T>*>(a.out) + (size_t)b * a.out_bs; }
   template <class Acc> DBAR_D void mid(int, int, int, cx<T>&) const {}
   template <int NT, class Acc> DBAR_D void finish(Acc&, int, int, int, double*) const {}
+  // per-block data read once at kernel start, before any store (ops that need it define PRE and a Pre type)
+  static constexpr bool PRE = false;
+  struct Pre {};
+  DBAR_D void prologue(int, Pre&) const {}
 };
 
 // out = IFFT_rows(phase * ci * in)
@@ -360,7 +380,8 @@ struct OpRowsInvRegular : OpBase<T, N> {
       sv = cvt<T>(cvt<double>(sv) - exp(-r2) * g);
     }
     // (S - G) / xi in the transform's precision
-    const T t1 = static_cast<T>(xi1), t2 = static_cast<T>(xi2), ir2 = static_cast<T>(f / r2);
+    const T t1 = static_cast<T>(xi1), t2 = static_cast<T>(xi2);
+    const T ir2 = sizeof(T) == 8 ? static_cast<T>(f / r2) : static_cast<T>(f) * recip(static_cast<T>(r2));
     return cx<T>{(sv.re * t1 + sv.im * t2) * ir2, (sv.im * t1 - sv.re * t2) * ir2};
   }
   DBAR_D void store(Acc&, int b, int row, int pos, cx<T> v) const { this->outp(b)[(size_t)row * N + pos] = v; }
@@ -375,26 +396,41 @@ struct OpColsInvTail : OpBase<T, N> {
   using Acc = NoAcc;
   DBAR_D cx<T> load(int b, int col, int pos) const { return this->inp(b)[(size_t)pos * N + col]; }
   DBAR_D cx<T> phase(int b, int col, int pos) const {
-    // tabulated in FP64 (arguments up to hundreds of radians); the product is formed in T
-    return cvt<T>(this->a.ex[(size_t)b * this->a.e_bs + col] * this->a.ey[(size_t)b * this->a.e_bs + pos]);
+    // tabulated in FP64 (arguments up to hundreds of radians; the FP32 operator reads their FP32 roundings); the
+    // product is formed in T
+    const size_t o = (size_t)b * this->a.e_bs;
+    if constexpr (sizeof(T) == 8) return this->a.ex[o + col] * this->a.ey[o + pos];
+    else return this->a.ex32[o + col] * this->a.ey32[o + pos];
+  }
+  // the moments d_0..d_kMaxM of this entry (zero beyond M) in registers, in the transform's precision
+  static constexpr bool PRE = true;
+  struct Pre {
+    cx<T> d[kMaxM + 1];
+  };
+  DBAR_D void prologue(int b, Pre& p) const {
+    const cx<T>* d;
+    if constexpr (sizeof(T) == 8) d = this->a.dmom + (size_t)b * kNMom;
+    else d = this->a.dmom32 + (size_t)b * kNMom;
+#pragma unroll
+    for (int n = 0; n <= kMaxM; ++n) p.d[n] = d[n];
   }
   // h = F^{-1}R + sum d_n omega_n; with the shifted regularisation the closed-form part is e^{i a.x} sum d_n omega_n
-  DBAR_D cx<T> h_at(int b, int col, int pos, cx<T> v) const {
-    const T x = static_cast<T>(xgrid<N>(col, this->a.L)), y = static_cast<T>(xgrid<N>(pos, this->a.L));
-    const cx<T> t = tail_sum<T>(x, y, this->a.dmom + (size_t)b * kNMom, this->a.M);
+  DBAR_D cx<T> h_at(int b, int col, int pos, cx<T> v, const Pre& p) const {
+    const T x = xgrid_t<T, N>(col, this->a.L), y = xgrid_t<T, N>(pos, this->a.L);
+    const cx<T> t = this->a.M == 11 ? tail_sum<T, 11>(x, y, p.d) : tail_sum<T, kMaxM>(x, y, p.d);
     return this->a.shv ? v + conj(phase(b, col, pos)) * t : v + t;
   }
   template <class A>
-  DBAR_D void mid(int b, int col, int pos, cx<T>& v) const {
-    const cx<T> h = h_at(b, col, pos, v);
+  DBAR_D void mid(int b, int col, int pos, cx<T>& v, const Pre& p) const {
+    const cx<T> h = h_at(b, col, pos, v, p);
     if (this->a.hout) (static_cast<cx<T>*>(this->a.hout) + (size_t)b * this->a.hout_bs)[(size_t)pos * N + col] = h;
     const cx<T> q = (static_cast<const cx<T>*>(this->a.Q) + (size_t)b * this->a.Q_bs)[(size_t)pos * N + col];
     // plain: q_k = Q e_k; shifted (the operator H of equation eqh2): Q alone
     v = (this->a.shv ? q : q * phase(b, col, pos)) * conj(h);
   }
-  DBAR_D void store(Acc&, int b, int col, int pos, cx<T> v) const {
+  DBAR_D void store(Acc&, int b, int col, int pos, cx<T> v, const Pre& p) const {
     if constexpr (TAILONLY) {
-      cx<T> h = h_at(b, col, pos, v);
+      cx<T> h = h_at(b, col, pos, v, p);
       if (this->a.tail_phase_out) h = phase(b, col, pos) * h;
       cx<T>* dst = static_cast<cx<T>*>(this->a.hout) + (size_t)b * this->a.hout_bs + (size_t)pos * N + col;
       if (this->a.accumulate) h = h + *dst;
@@ -494,6 +530,8 @@ __global__ void __launch_bounds__(LINES * LineGeom<N>::TPL, MinWaves<LINES * Lin
   __shared__ cx<T> lds[LdsSize<T, N, LINES>::kElems];
   const int b = blockIdx.y;
   if (!op.active(b)) return;
+  typename Op::Pre pre;
+  op.prologue(b, pre);
   const int tid = threadIdx.x;
   const int ln = COLS ? (tid % LINES) : (tid / G::TPL);
   const int jt = COLS ? (tid / LINES) : (tid % G::TPL);
@@ -519,7 +557,8 @@ __global__ void __launch_bounds__(LINES * LineGeom<N>::TPL, MinWaves<LINES * Lin
       for (int s = 0; s < G::RMAX; ++s) {
         const int pos = jt + s * G::TPL;
         cx<T> t = my[G::padded(pos) * LS];
-        op.template mid<typename Op::Acc>(b, line, pos, t);
+        if constexpr (Op::PRE) op.template mid<typename Op::Acc>(b, line, pos, t, pre);
+        else op.template mid<typename Op::Acc>(b, line, pos, t);
         my[G::padded(pos) * LS] = t;
       }
 #pragma unroll
@@ -527,7 +566,10 @@ __global__ void __launch_bounds__(LINES * LineGeom<N>::TPL, MinWaves<LINES * Lin
       __syncthreads();  // the forward transform's first exchange writes other threads' positions
     } else {
 #pragma unroll
-      for (int s = 0; s < G::RMAX; ++s) op.template mid<typename Op::Acc>(b, line, jt + s * G::TPL, v[s]);
+      for (int s = 0; s < G::RMAX; ++s) {
+        if constexpr (Op::PRE) op.template mid<typename Op::Acc>(b, line, jt + s * G::TPL, v[s], pre);
+        else op.template mid<typename Op::Acc>(b, line, jt + s * G::TPL, v[s]);
+      }
     }
     line_fft<T, N, -Op::DIR1, LS>(v, jt, my, tw);
   }
@@ -538,11 +580,15 @@ __global__ void __launch_bounds__(LINES * LineGeom<N>::TPL, MinWaves<LINES * Lin
 #pragma unroll 1
     for (int s = 0; s < G::RMAX; ++s) {
       const int pos = jt + s * G::TPL;
-      op.store(acc, b, line, pos, my[G::padded(pos) * LS]);
+      if constexpr (Op::PRE) op.store(acc, b, line, pos, my[G::padded(pos) * LS], pre);
+      else op.store(acc, b, line, pos, my[G::padded(pos) * LS]);
     }
   } else {
 #pragma unroll
-    for (int s = 0; s < G::RMAX; ++s) op.store(acc, b, line, jt + s * G::TPL, v[s]);
+    for (int s = 0; s < G::RMAX; ++s) {
+      if constexpr (Op::PRE) op.store(acc, b, line, jt + s * G::TPL, v[s], pre);
+      else op.store(acc, b, line, jt + s * G::TPL, v[s]);
+    }
   }
   op.template finish<NT>(acc, b, tile, gridDim.x, reinterpret_cast<double*>(lds));
 }

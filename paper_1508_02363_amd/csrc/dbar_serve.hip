@@ -173,7 +173,8 @@ static void worker(dbar_session* s, SClass* cp) {
         (void)hipMemcpyAsync(static_cast<c64*>(w.kvals.p) + b, &c.h_k[b], sizeof(c64), hipMemcpyHostToDevice,
                              c.stream);
         launch_phase_tables(static_cast<const c64*>(w.kvals.p) + b, c.N, c.L, static_cast<c64*>(w.ex.p) + (size_t)b * c.N,
-                            static_cast<c64*>(w.ey.p) + (size_t)b * c.N, 1, c.stream);
+                            static_cast<c64*>(w.ey.p) + (size_t)b * c.N, static_cast<c32*>(w.ex32.p) + (size_t)b * c.N,
+                            static_cast<c32*>(w.ey32.p) + (size_t)b * c.N, 1, c.stream);
         (void)hipMemsetAsync(static_cast<c64*>(w.x.p) + (size_t)b * n, 0, n * sizeof(c64), c.stream);
         // host sources (request Q, per-slot tables, masks) stay untouched until the stream synchronises below
       }

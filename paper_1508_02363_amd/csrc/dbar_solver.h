@@ -102,8 +102,8 @@ struct Work {
   void drop_graphs();
   size_t n = 0;
   size_t Q_bs = 0;
-  DevBuf x, bvec, T64, r64, T32, V, Q64, Q32, ex, ey, coefG, dmom, part_mom, part_vec, part_norm, dred, nred, ctl,
-      act, live, kvals, results, shv, unit, Hbuf;
+  DevBuf x, bvec, T64, r64, T32, V, Q64, Q32, ex, ey, ex32, ey32, coefG, dmom, dmom32, part_mom, part_vec, part_norm,
+      dred, nred, ctl, act, live, kvals, results, shv, unit, unit32, Hbuf;
   PinnedInts host_act, host_live;
   int setup(int N_, int B_, int m_, int prec_, bool shared_q);
   size_t vec_bytes(int prec) const;
@@ -120,10 +120,14 @@ struct Pipeline {
   const Twiddles* tw = nullptr;
   const c64* ex = nullptr;
   const c64* ey = nullptr;
+  const c32* ex32 = nullptr;
+  const c32* ey32 = nullptr;
   const c64* unit = nullptr;
+  const c32* unit32 = nullptr;
   const int* shv = nullptr;
   c64* coefG = nullptr;
   c64* dmom = nullptr;
+  c32* dmom32 = nullptr;
   double* part_mom = nullptr;
   double* part_vec = nullptr;
 
@@ -167,7 +171,9 @@ int solve_impl(const dbar_grid* grid, const void* Q, bool q_on_device, int64_t n
                double* r_out);
 int get_twiddles(int N, const Twiddles** out);
 int make_pipeline(const dbar_grid* g, Work& w, Pipeline* p);
-void launch_phase_tables(const c64* kv_dev, int N, double L, c64* ex, c64* ey, int B, hipStream_t s);
+// e_k tables of B entries: FP64 ex/ey and their FP32 roundings ex32/ey32 (per-entry stride N)
+void launch_phase_tables(const c64* kv_dev, int N, double L, c64* ex, c64* ey, c32* ex32, c32* ey32, int B,
+                         hipStream_t s);
 int run_batch(const Pipeline& P, Work& w, const BatchCfg& cfg, hipStream_t s, std::vector<int>& iters_out);
 int ctl_blocks(int B);
 // one lockstep Krylov cycle over the entries flagged in w.act; returns the iterations run

@@ -46,7 +46,7 @@ DBAR_D double wsum(double x) {
 
 // d_n = w sum_tiles part, c_n = (-i/2)^n d_n / n! (equation fourreeg4 with Gchoice), R(0) = (-i/2) dt
 __global__ void __launch_bounds__(256) k_moments(const double* part, int ntiles, const int* act, double wscale, int M,
-                                                 c64* coefG, c64* dmom) {
+                                                 c64* coefG, c64* dmom, c32* dmom32) {
   constexpr int NV = 2 * kNMom;
   const int b = blockIdx.x;
   if (act && !act[b]) return;
@@ -74,17 +74,20 @@ __global__ void __launch_bounds__(256) k_moments(const double* part, int ntiles,
   if (threadIdx.x == 0) {
     c64* cg = coefG + (size_t)b * kNMom;
     c64* dm = dmom + (size_t)b * kNMom;
+    c32* dm32 = dmom32 + (size_t)b * kNMom;
     c64 p{1.0, 0.0};
     const c64 mh{0.0, -0.5};
     for (int n = 0; n <= kMaxM; ++n) {
       const c64 d{tot[2 * n], tot[2 * n + 1]};
       dm[n] = n <= M ? d : c64{0.0, 0.0};
+      dm32[n] = cvt<float>(dm[n]);
       cg[n] = n <= M ? kInvFactC[n] * (p * d) : c64{0.0, 0.0};
       p = p * mh;
     }
     const c64 dt{tot[2 * (kMaxM + 1)], tot[2 * (kMaxM + 1) + 1]};
     cg[kMaxM + 1] = mh * dt;
     dm[kMaxM + 1] = dt;
+    dm32[kMaxM + 1] = cvt<float>(dt);
   }
 }
 
@@ -184,7 +187,7 @@ __global__ void k_ctl_check(Ctl* ctl, const double* nred, int* live, double tol,
 }
 
 // e^{conj(kz) - kz} = e^{-2i k2 x} e^{-2i k1 y} (eq:039) as two FP64 tables per entry, x_j = L(-pi + 2 pi j / N)
-__global__ void k_phase_tables(const c64* kv, int N, double L, c64* ex, c64* ey, int B) {
+__global__ void k_phase_tables(const c64* kv, int N, double L, c64* ex, c64* ey, c32* ex32, c32* ey32, int B) {
   const int b = blockIdx.y;
   if (b >= B) return;
   const c64 k = kv[b];
@@ -195,6 +198,8 @@ __global__ void k_phase_tables(const c64* kv, int N, double L, c64* ex, c64* ey,
     sincos(-2.0 * k.re * x, &s2, &c2);
     ex[(size_t)b * N + j] = c64{c1, s1};
     ey[(size_t)b * N + j] = c64{c2, s2};
+    ex32[(size_t)b * N + j] = c32{(float)c1, (float)s1};
+    ey32[(size_t)b * N + j] = c32{(float)c2, (float)s2};
   }
 }
 
@@ -213,9 +218,10 @@ __global__ void k_gather_results(const Ctl* ctl, const c64* x, size_t n, const c
   out[b] = EntryResult{c.iters, c.cycles, c.bnorm, c.rnorm, x[(size_t)b * n], hs};
 }
 
-void launch_phase_tables(const c64* kv_dev, int N, double L, c64* ex, c64* ey, int B, hipStream_t s) {
+void launch_phase_tables(const c64* kv_dev, int N, double L, c64* ex, c64* ey, c32* ex32, c32* ey32, int B,
+                         hipStream_t s) {
   TimerScope ts(kStageControl, 0.0, B, nullptr, s);
-  hipLaunchKernelGGL(k_phase_tables, dim3((N + 255) / 256, B), dim3(256), 0, s, kv_dev, N, L, ex, ey, B);
+  hipLaunchKernelGGL(k_phase_tables, dim3((N + 255) / 256, B), dim3(256), 0, s, kv_dev, N, L, ex, ey, ex32, ey32, B);
 }
 
 // ------------------------------------------------------------------------------------------------------------
@@ -309,6 +315,7 @@ Work& Work::operator=(Work&& o) noexcept {
   x = std::move(o.x); bvec = std::move(o.bvec); T64 = std::move(o.T64); r64 = std::move(o.r64);
   T32 = std::move(o.T32); V = std::move(o.V); Q64 = std::move(o.Q64); Q32 = std::move(o.Q32);
   ex = std::move(o.ex); ey = std::move(o.ey); coefG = std::move(o.coefG); dmom = std::move(o.dmom);
+  ex32 = std::move(o.ex32); ey32 = std::move(o.ey32); dmom32 = std::move(o.dmom32); unit32 = std::move(o.unit32);
   part_mom = std::move(o.part_mom); part_vec = std::move(o.part_vec); part_norm = std::move(o.part_norm);
   dred = std::move(o.dred); nred = std::move(o.nred); ctl = std::move(o.ctl); act = std::move(o.act);
   live = std::move(o.live); kvals = std::move(o.kvals); results = std::move(o.results);
@@ -324,7 +331,8 @@ int Work::setup(int N_, int B_, int m_, int prec_, bool shared_q) {
   // captured graphs hold raw pointers and sizes of this workspace: drop them if anything can change
   if (N_ != N || B_ != B || m_ != m || prec_ != prec || (shared_q ? 0 : (size_t)N_ * N_) != Q_bs) drop_graphs();
   const void* before[] = {x.p, V.p, T64.p, T32.p, ctl.p, act.p, part_vec.p, part_norm.p, part_mom.p, dred.p,
-                          nred.p, Q32.p, Q64.p, ex.p, ey.p, coefG.p, dmom.p, shv.p, unit.p, Hbuf.p};
+                          nred.p, Q32.p, Q64.p, ex.p, ey.p, coefG.p, dmom.p, shv.p, unit.p, Hbuf.p, ex32.p, ey32.p,
+                          dmom32.p, unit32.p};
   N = N_;
   B = B_;
   m = m_;
@@ -347,6 +355,9 @@ int Work::setup(int N_, int B_, int m_, int prec_, bool shared_q) {
   if ((rc = ey.ensure((size_t)B * N * sizeof(c64)))) return rc;
   if ((rc = coefG.ensure((size_t)B * kNMom * sizeof(c64)))) return rc;
   if ((rc = dmom.ensure((size_t)B * kNMom * sizeof(c64)))) return rc;
+  if ((rc = dmom32.ensure((size_t)B * kNMom * sizeof(c32)))) return rc;
+  if ((rc = ex32.ensure((size_t)B * N * sizeof(c32)))) return rc;
+  if ((rc = ey32.ensure((size_t)B * N * sizeof(c32)))) return rc;
   const int tiles = std::max(line_tiles(N, true, true), line_tiles(N, true, false));
   const int rtiles = std::max(line_tiles(N, false, true), line_tiles(N, false, false));
   if ((rc = part_mom.ensure((size_t)B * 2 * kNMom * std::max(tiles, rtiles) * sizeof(double)))) return rc;
@@ -358,10 +369,13 @@ int Work::setup(int N_, int B_, int m_, int prec_, bool shared_q) {
   if ((rc = ctl.ensure((size_t)B * sizeof(Ctl)))) return rc;
   if ((rc = kvals.ensure((size_t)B * sizeof(c64)))) return rc;
   if ((rc = shv.ensure((size_t)B * 2 * sizeof(int)))) return rc;
-  if (unit.bytes < (size_t)N * sizeof(c64)) {
+  if (unit.bytes < (size_t)N * sizeof(c64) || unit32.bytes < (size_t)N * sizeof(c32)) {
     if ((rc = unit.ensure((size_t)N * sizeof(c64)))) return rc;
+    if ((rc = unit32.ensure((size_t)N * sizeof(c32)))) return rc;
     std::vector<c64> ones(N, c64{1.0, 0.0});
-    if (hipMemcpy(unit.p, ones.data(), N * sizeof(c64), hipMemcpyHostToDevice) != hipSuccess)
+    std::vector<c32> ones32(N, c32{1.0f, 0.0f});
+    if (hipMemcpy(unit.p, ones.data(), N * sizeof(c64), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(unit32.p, ones32.data(), N * sizeof(c32), hipMemcpyHostToDevice) != hipSuccess)
       return fail(DBAR_EDEVICE, "upload of the unit phase table failed");
   }
   if ((rc = results.ensure((size_t)B * sizeof(EntryResult)))) return rc;
@@ -370,7 +384,8 @@ int Work::setup(int N_, int B_, int m_, int prec_, bool shared_q) {
   if ((rc = host_act.ensure(B))) return rc;
   if ((rc = host_live.ensure(B))) return rc;
   const void* after[] = {x.p, V.p, T64.p, T32.p, ctl.p, act.p, part_vec.p, part_norm.p, part_mom.p, dred.p,
-                         nred.p, Q32.p, Q64.p, ex.p, ey.p, coefG.p, dmom.p, shv.p, unit.p, Hbuf.p};
+                         nred.p, Q32.p, Q64.p, ex.p, ey.p, coefG.p, dmom.p, shv.p, unit.p, Hbuf.p, ex32.p, ey32.p,
+                          dmom32.p, unit32.p};
   if (std::memcmp(before, after, sizeof(before)) != 0) drop_graphs();
   return DBAR_OK;
 }
@@ -392,15 +407,20 @@ LineArgs Pipeline::base(int B, const int* act, unsigned flags) const {
   if (flags & kUnitPhase) {  // k = 0: one shared table of ones
     a.ex = unit;
     a.ey = unit;
+    a.ex32 = unit32;
+    a.ey32 = unit32;
     a.e_bs = 0;
   } else {
     a.ex = ex;
     a.ey = ey;
+    a.ex32 = ex32;
+    a.ey32 = ey32;
     a.e_bs = (size_t)N;
   }
   a.shv = (flags & kShifted) ? shv : nullptr;
   a.coefG = coefG;
   a.dmom = dmom;
+  a.dmom32 = dmom32;
   return a;
 }
 
@@ -427,7 +447,7 @@ void Pipeline::moments(const void* in, size_t in_bs, void* Tbuf, int B, const in
   const double dx = 2.0 * kPi * L / N;
   TimerScope ts(kStageMoments, 0.0, B, act, s);
   hipLaunchKernelGGL(k_moments, dim3(B), dim3(256), 0, s, part_mom, line_tiles(N, true, sizeof(T) == 8), act,
-                     dx * dx / (2.0 * kPi), M, coefG, dmom);
+                     dx * dx / (2.0 * kPi), M, coefG, dmom, dmom32);
 }
 
 // out = alpha S_ep + beta i F(q conj(hh(in))) + gamma Y, with hh the regularised inverse of in/xi (or of in/(xi - a)
@@ -596,6 +616,10 @@ int make_pipeline(const dbar_grid* g, Work& w, Pipeline* p) {
   p->ey = static_cast<const c64*>(w.ey.p);
   p->coefG = static_cast<c64*>(w.coefG.p);
   p->dmom = static_cast<c64*>(w.dmom.p);
+  p->dmom32 = static_cast<c32*>(w.dmom32.p);
+  p->ex32 = static_cast<const c32*>(w.ex32.p);
+  p->ey32 = static_cast<const c32*>(w.ey32.p);
+  p->unit32 = static_cast<const c32*>(w.unit32.p);
   p->part_mom = static_cast<double*>(w.part_mom.p);
   p->part_vec = static_cast<double*>(w.part_vec.p);
   p->unit = static_cast<const c64*>(w.unit.p);
@@ -931,7 +955,7 @@ int solve_impl(const dbar_grid* grid, const void* Q, bool q_on_device, int64_t n
         return fail(DBAR_EDEVICE, "shift upload failed");
     }
     launch_phase_tables(static_cast<const c64*>(w.kvals.p), N, grid->L, static_cast<c64*>(w.ex.p),
-                        static_cast<c64*>(w.ey.p), nb, s);
+                        static_cast<c64*>(w.ey.p), static_cast<c32*>(w.ex32.p), static_cast<c32*>(w.ey32.p), nb, s);
     std::vector<int> its;
     if ((rc = run_batch(P, w, cfg, s, its))) return rc;
     // outputs: S = x, m = h(x) (plain); the iterated method forms S and m from h below
@@ -1073,7 +1097,7 @@ int dbar_apply(const dbar_grid* grid, const double* Q, const double* k, const do
   hipStream_t s = nullptr;
   (void)hipMemcpy(w->kvals.p, k, sizeof(c64), hipMemcpyHostToDevice);
   launch_phase_tables(static_cast<const c64*>(w->kvals.p), N, grid->L, static_cast<c64*>(w->ex.p),
-                      static_cast<c64*>(w->ey.p), 1, s);
+                      static_cast<c64*>(w->ey.p), static_cast<c32*>(w->ex32.p), static_cast<c32*>(w->ey32.p), 1, s);
   (void)hipMemcpy(w->Q64.p, Q, n * sizeof(c64), hipMemcpyHostToDevice);
   (void)hipMemcpy(w->x.p, S_in, n * sizeof(c64), hipMemcpyHostToDevice);
   if (precision == DBAR_FP64) {
