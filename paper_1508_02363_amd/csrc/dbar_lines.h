@@ -249,15 +249,19 @@ struct OpColsInvMoments : OpBase<T, N> {
     c64 s = cvt<double>(v);
     // shifted regularisation: Taylor coefficients at xi = a are moments of s e^{-i a.x} = s e_k (ey here, ex below)
     if (this->a.shv) s = s * this->a.ey[(size_t)b * this->a.e_bs + pos];
-    const int K = this->a.M < 1 ? 1 : this->a.M;  // mu_1 is always needed (conj moment)
+    // mu_0..mu_KK with KK fixed at compile time: the order M = 11 itself, else kMaxM (the extra mu_k are unused);
+    // mu_1 is always needed (conj moment)
+    if (this->a.M == 11) accumulate<11>(acc, y, s);
+    else accumulate<kMaxM>(acc, y, s);
+  }
+  template <int KK>
+  DBAR_D static void accumulate(Acc& acc, double y, c64 s) {
     double yp = 1.0;
 #pragma unroll
-    for (int k = 0; k <= kMaxM; ++k) {
-      if (k <= K) {
-        acc.v[2 * k] += yp * s.re;
-        acc.v[2 * k + 1] += yp * s.im;
-        yp *= y;
-      }
+    for (int k = 0; k <= KK; ++k) {
+      acc.v[2 * k] += yp * s.re;
+      acc.v[2 * k + 1] += yp * s.im;
+      yp *= y;
     }
   }
   // Moment q of one column from its mu_k: d_q = sum_{k<=q} C(q,k) x^{q-k} i^k mu_k for q <= M (0 for M < q <=
