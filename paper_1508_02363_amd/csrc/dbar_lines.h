@@ -236,27 +236,35 @@ struct OpColsInvMoments : OpBase<T, N> {
   static constexpr bool TWO = false;
   static constexpr bool ROLLED = true;
   static constexpr int NV = 2 * kNMom;
+  static constexpr int NMU = 2 * (kMaxM + 1);  // mu_0 .. mu_kMaxM (re, im)
+  // Per-thread column moments are accumulated in the transform's precision (16 elements per thread; the FP32
+  // operator's s carries FP32 rounding anyway, and the regularisation is exact for any G coefficients); every
+  // reduction beyond the thread and the binomial combination run in FP64.
   struct Acc {
-    double v[2 * kNMom];  // first mu_k (k <= M), replaced by d_n and the conj moment in finish()
+    T v[NMU];  // mu_k = sum_y y^k s over this thread's elements
     double x;
     int col;
   };
   DBAR_D cx<T> load(int b, int col, int pos) const { return this->inp(b)[(size_t)pos * N + col]; }
   DBAR_D void store(Acc& acc, int b, int col, int pos, cx<T> v) const {
-    const double y = xgrid<N>(pos, this->a.L);
+    const T y = xgrid_t<T, N>(pos, this->a.L);
     acc.x = xgrid<N>(col, this->a.L);
     acc.col = col;
-    c64 s = cvt<double>(v);
+    cx<T> s = v;
     // shifted regularisation: Taylor coefficients at xi = a are moments of s e^{-i a.x} = s e_k (ey here, ex below)
-    if (this->a.shv) s = s * this->a.ey[(size_t)b * this->a.e_bs + pos];
+    if (this->a.shv) {
+      const size_t o = (size_t)b * this->a.e_bs + pos;
+      if constexpr (sizeof(T) == 8) s = s * this->a.ey[o];
+      else s = s * this->a.ey32[o];
+    }
     // mu_0..mu_KK with KK fixed at compile time: the order M = 11 itself, else kMaxM (the extra mu_k are unused);
     // mu_1 is always needed (conj moment)
     if (this->a.M == 11) accumulate<11>(acc, y, s);
     else accumulate<kMaxM>(acc, y, s);
   }
   template <int KK>
-  DBAR_D static void accumulate(Acc& acc, double y, c64 s) {
-    double yp = 1.0;
+  DBAR_D static void accumulate(Acc& acc, T y, cx<T> s) {
+    T yp = T(1);
 #pragma unroll
     for (int k = 0; k <= KK; ++k) {
       acc.v[2 * k] += yp * s.re;
@@ -303,10 +311,14 @@ struct OpColsInvMoments : OpBase<T, N> {
     }
   }
 
-  static constexpr int NMU = 2 * (kMaxM + 1);  // mu_0 .. mu_kMaxM (re, im)
-
   template <int NT>
   DBAR_D void finish(Acc& acc, int b, int tile, int ntiles, double* scratch) const {
+    if (this->a.M == 11) finish_kk<NT, 11>(acc, b, tile, ntiles, scratch);
+    else finish_kk<NT, kMaxM>(acc, b, tile, ntiles, scratch);
+  }
+  template <int NT, int KK>
+  DBAR_D void finish_kk(Acc& acc, int b, int tile, int ntiles, double* scratch) const {
+    constexpr int NU = 2 * (KK + 1);  // mu values in use
     double* dst = this->a.part + (size_t)b * NV * ntiles + tile;
     constexpr int TPL = LineGeom<N>::TPL;
     constexpr int LN = NT / TPL;  // columns per tile; thread tid serves column tid % LN
@@ -316,17 +328,17 @@ struct OpColsInvMoments : OpBase<T, N> {
       const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
       constexpr int NW = NT / 64;
 #pragma unroll
-      for (int q = 0; q < NMU; ++q) {
-        double x = acc.v[q];
+      for (int q = 0; q < NU; ++q) {
+        T x = acc.v[q];
 #pragma unroll
         for (int off = 32; off >= LN; off >>= 1) x += __shfl_xor(x, off, 64);
         acc.v[q] = x;
       }
-      double* sc = scratch;                 // [NW][LN][NMU]
+      double* sc = scratch;                    // [NW][LN][NMU]
       double* colv = scratch + NW * LN * NMU;  // [LN][NV]
       if (lane < LN) {
 #pragma unroll
-        for (int q = 0; q < NMU; ++q) sc[(wave * LN + lane) * NMU + q] = acc.v[q];
+        for (int q = 0; q < NMU; ++q) sc[(wave * LN + lane) * NMU + q] = q < NU ? static_cast<double>(acc.v[q]) : 0.0;
       }
       __syncthreads();
       // 2) each column's mu_k summed over its waves (one thread per column and value) ...
@@ -354,8 +366,11 @@ struct OpColsInvMoments : OpBase<T, N> {
         dst[(size_t)q * ntiles] = t;
       }
     } else {
-      combine(acc.v, acc.x, b, acc.col);
-      block_reduce_store<NT, NV>(acc.v, dst, ntiles, scratch);
+      double v[NV];
+#pragma unroll
+      for (int q = 0; q < NV; ++q) v[q] = q < NU ? static_cast<double>(acc.v[q]) : 0.0;
+      combine(v, acc.x, b, acc.col);
+      block_reduce_store<NT, NV>(v, dst, ntiles, scratch);
     }
   }
 };
