@@ -39,6 +39,8 @@ def parse():
     ap.add_argument("--headline", choices=["auto", "mixed", "fp64"], default="auto")
     ap.add_argument("--no-serving", action="store_true", help="skip the request-stream (p50/p99 latency) leg")
     ap.add_argument("--serving-requests", type=int, default=48)
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default column-tile widths (skip the library's tuner before the timed region)")
     ap.add_argument("--no-rows-f", action="store_true",
                     help="skip the iterated-solver (Section 5.3) and DS II round-trip (Section 6) legs")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"), default=None,
@@ -262,6 +264,9 @@ def main():
     def step(**kw):
         return D.solve_device(Qd, w.ks, L, tol=w.tol, M=w.M, batch=nk, **kw)
 
+    # the library's tuner picks the column-tile widths for this grid (outside the timed region, like the warm-up)
+    tuning = None if args.no_autotune or args.probe else D.autotune(N, L, precision=D.DBAR_MIXED, batch=nk, M=w.M)
+
     paths = {
         "mixed": dict(precision=D.DBAR_MIXED),
         "fp64": dict(precision=D.DBAR_FP64),
@@ -363,6 +368,7 @@ def main():
         "fft_matvec_GBs": fft_gbs,
         "stage_time_share_of_step": total_stage_ms / (sec * 1e3),
         "context": context,
+        "tuning": tuning,
     }
 
     if not args.no_serving:

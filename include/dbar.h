@@ -143,6 +143,36 @@ int dbar_transform(const dbar_grid* grid, int32_t inverse, const double* in, dou
 int dbar_dbar_inverse(const dbar_grid* grid, const double* S_in, double* h_out, int32_t precision);
 
 /* ------------------------------------------------------------------------------------------------------------
+ * Tuning.  Not in the paper: the column passes of the 2D transforms (the y-direction lines of the three FFTs of
+ * the Section 4 algorithm) run on tiles of adjacent columns whose best width depends on the grid size and
+ * precision, and the batched solver's entries per launch trade throughput against memory.  The choices are kept
+ * per process and device-independent; they apply to every later solve, apply and session launch.  Do not call
+ * these while another thread is inside a solve or while a serving session is running.
+ * ------------------------------------------------------------------------------------------------------------ */
+typedef struct {
+  int32_t n_variants[2];    /* [0]: FP64 operator, [1]: FP32 operator; 0 if that operator was not tuned */
+  int32_t chosen[2];        /* the variant kept */
+  int32_t columns[2][3];    /* columns per tile of each variant */
+  double ms[2][3];          /* one operator application over `batch` entries, per variant (milliseconds) */
+  int32_t batch;            /* entries per launch kept for solves with opts->batch = 0 */
+  int32_t batch_candidates[4];
+  int32_t reserved;
+  double per_entry_ms[4];   /* operator time per entry at each candidate batch size */
+} dbar_tune_result;
+
+/*
+ * Time one operator application (A(S), FP64 and/or FP32 as `precision` says: DBAR_FP64, DBAR_MIXED (both) or
+ * DBAR_FP32) over `batch` entries (1..1024) for every column-tile width valid at this grid size, keep the fastest,
+ * then keep the smallest batch size (of batch, batch/2, batch/4, batch/8) whose per-entry time is within 5% of
+ * the best.  out may be NULL.  Uses the library's workspace (device memory for `batch` entries).
+ */
+int dbar_autotune(const dbar_grid* grid, int32_t precision, int32_t batch, dbar_tune_result* out);
+/* Force the column-tile variant of grid size n for the FP64 or FP32 operator (precision DBAR_FP64 / DBAR_FP32). */
+int dbar_set_tile(int32_t n, int32_t precision, int32_t variant);
+/* Current variant, its columns per tile and the number of variants for grid size n (any output may be NULL). */
+int dbar_get_tile(int32_t n, int32_t precision, int32_t* variant, int32_t* columns, int32_t* variants);
+
+/* ------------------------------------------------------------------------------------------------------------
  * DS II scattering transforms (Section 6).  Both run the iterated solver (Section 5.3) in FP64 or DBAR_MIXED as
  * opts->precision says (opts->method is ignored), batched over their many independent solves.
  * ------------------------------------------------------------------------------------------------------------ */

@@ -27,11 +27,18 @@ DBAR_METHOD_ITERATED = 1
 # every symbol include/dbar.h declares
 EXPORTED = [
     "dbar_default_opts", "dbar_solve", "dbar_solve_device", "dbar_apply", "dbar_transform", "dbar_dbar_inverse",
-    "dbar_reflection", "dbar_reconstruct",
+    "dbar_reflection", "dbar_reconstruct", "dbar_autotune", "dbar_set_tile", "dbar_get_tile",
     "dbar_session_create", "dbar_submit", "dbar_poll", "dbar_wait", "dbar_session_get_stats",
     "dbar_request_footprint", "dbar_session_destroy", "dbar_timer_enable", "dbar_timer_num_stages",
     "dbar_timer_stage", "dbar_last_error", "dbar_release", "dbar_version",
 ]
+
+
+class TuneResult(ctypes.Structure):
+    _fields_ = [("n_variants", ctypes.c_int32 * 2), ("chosen", ctypes.c_int32 * 2),
+                ("columns", (ctypes.c_int32 * 3) * 2), ("ms", (ctypes.c_double * 3) * 2),
+                ("batch", ctypes.c_int32), ("batch_candidates", ctypes.c_int32 * 4), ("reserved", ctypes.c_int32),
+                ("per_entry_ms", ctypes.c_double * 4)]
 
 
 class Grid(ctypes.Structure):
@@ -92,6 +99,10 @@ def load() -> ctypes.CDLL:
         lib.dbar_apply.argtypes = [G, D, D, D, D, ctypes.c_int32]
         lib.dbar_transform.argtypes = [G, ctypes.c_int32, D, D, ctypes.c_int32]
         lib.dbar_dbar_inverse.argtypes = [G, D, D, ctypes.c_int32]
+        lib.dbar_autotune.argtypes = [G, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(TuneResult)]
+        lib.dbar_set_tile.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
+        I32P = ctypes.POINTER(ctypes.c_int32)
+        lib.dbar_get_tile.argtypes = [ctypes.c_int32, ctypes.c_int32, I32P, I32P, I32P]
         lib.dbar_reflection.argtypes = [G, D, ctypes.c_int64, D, ctypes.c_double, ctypes.POINTER(Opts), D,
                                         ctypes.POINTER(Info)]
         lib.dbar_reconstruct.argtypes = [G, D, ctypes.c_double, ctypes.c_double, ctypes.POINTER(Opts), D,

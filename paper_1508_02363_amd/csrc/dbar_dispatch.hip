@@ -1,17 +1,53 @@
 // Run-time dispatch over the grid size N for the line-transform stages.
+#include <atomic>
+
 #include "dbar_lines.h"
 
 namespace dbar {
 
-int line_tiles(int N, bool cols, bool fp64) {
-#define DBAR_TILES(NN)                                                                          \
-  if (N == NN) {                                                                                \
-    if (fp64) return NN / (cols ? Tiling<double, NN>::COLS : Tiling<double, NN>::ROWS);         \
-    return NN / (cols ? Tiling<float, NN>::COLS : Tiling<float, NN>::ROWS);                     \
+// ------------------------------------------------------------------------------------------------------------
+// Column-tile width choices (set by the tuner; default 0 = the narrowest tile)
+// ------------------------------------------------------------------------------------------------------------
+static int size_index(int N) {
+  int i = 0;
+  for (int m = 8; m < N && i < 12; m <<= 1) ++i;
+  return i;
+}
+static std::atomic<int> g_tile[2][12];  // [fp64][log2(N) - 3]
+static std::atomic<int> g_epoch{0};
+
+int tile_variants(int N, bool fp64) {
+#define DBAR_VARIANTS(NN) \
+  if (N == NN) return fp64 ? Tiling<double, NN>::variants() : Tiling<float, NN>::variants();
+  DBAR_FOR_EACH_N(DBAR_VARIANTS)
+#undef DBAR_VARIANTS
+  return 1;
+}
+
+int tile_variant(int N, bool fp64) { return g_tile[fp64 ? 1 : 0][size_index(N)].load(); }
+
+void set_tile_variant(int N, bool fp64, int variant) {
+  if (variant < 0 || variant >= tile_variants(N, fp64)) variant = 0;
+  if (g_tile[fp64 ? 1 : 0][size_index(N)].exchange(variant) != variant) ++g_epoch;
+}
+
+int tuning_epoch() { return g_epoch.load(); }
+
+int line_tiles_variant(int N, bool cols, bool fp64, int variant) {
+#define DBAR_TILES(NN)                                                                                   \
+  if (N == NN) {                                                                                         \
+    if (fp64) return NN / (cols ? (Tiling<double, NN>::COLS << variant) : Tiling<double, NN>::ROWS);     \
+    return NN / (cols ? (Tiling<float, NN>::COLS << variant) : Tiling<float, NN>::ROWS);                 \
   }
   DBAR_FOR_EACH_N(DBAR_TILES)
 #undef DBAR_TILES
   return 0;
+}
+
+int tile_columns(int N, bool fp64, int variant) { return N / line_tiles_variant(N, true, fp64, variant); }
+
+int line_tiles(int N, bool cols, bool fp64) {
+  return line_tiles_variant(N, cols, fp64, cols ? tile_variant(N, fp64) : 0);
 }
 
 // Algorithmic HBM bytes per batch entry of one stage (each array read or written once).
@@ -32,9 +68,11 @@ static double line_bytes(int N, LineOp op, const LineArgs& a, size_t es) {
 }
 
 template <typename T>
-void launch_lines_any(int N, LineOp op, const LineArgs& a, hipStream_t s) {
+void launch_lines_any(int N, LineOp op, const LineArgs& a_in, hipStream_t s) {
   TimerScope ts(kStageLines + 2 * static_cast<int>(op) + (sizeof(T) == 4 ? 1 : 0),
-                line_bytes(N, op, a, sizeof(cx<T>)), a.B, a.act, s);
+                line_bytes(N, op, a_in, sizeof(cx<T>)), a_in.B, a_in.act, s);
+  LineArgs a = a_in;
+  a.tile = tile_variant(N, sizeof(T) == 8);
   switch (N) {
 #define DBAR_CASE(NN) \
   case NN:            \

@@ -47,10 +47,22 @@ struct LineArgs {
   double alpha = 0.0, gamma = 0.0;
   c64 beta{0.0, 0.0};
   int want_norm = 0;           // RowsFwdEpilogue: accumulate |out|^2 partials
+  int tile = 0;                // column stages: tile width variant (columns per tile = default << tile)
 };
 
-// Number of blocks (tiles) per batch entry used by a line stage; partial buffers are sized from it.
+// Number of blocks (tiles) per batch entry used by a line stage with the current tile choice; partial buffers are
+// sized for the default (narrowest, most tiles) choice.
 int line_tiles(int N, bool cols, bool fp64);
+int line_tiles_variant(int N, bool cols, bool fp64, int variant);
+// Column-tile width choice per (N, precision): the number of valid variants (columns per tile = default << v, while
+// the block has at most 1024 threads and its LDS fits), the current choice, and the columns of a variant.
+constexpr int kMaxTileVariants = 3;
+int tile_variants(int N, bool fp64);
+int tile_variant(int N, bool fp64);
+int tile_columns(int N, bool fp64, int variant);
+void set_tile_variant(int N, bool fp64, int variant);
+// Incremented whenever a tile choice changes (captured graphs hold kernels and tile counts of the old choice).
+int tuning_epoch();
 
 template <typename T, int N>
 void launch_lines(LineOp op, const LineArgs& a, hipStream_t s);

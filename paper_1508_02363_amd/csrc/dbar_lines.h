@@ -190,7 +190,16 @@ struct Tiling {
   }
   static constexpr int ROWS = fit(cmin(N, cmax(1, 128 / G::TPL)));
   static constexpr int COLS = fit(cmin(N, cmax(64 / (int)sizeof(cx<T>), cmax(1, 64 / G::TPL))));
-  // a column tile also needs enough scratch for the block reduction (NT/64 waves x 34 doubles)
+  // wider column tiles (variant V: COLS << V columns) for the tuner: valid while the block has at most 1024 threads
+  // and the tile's lines fit the LDS budget
+  template <int V>
+  static constexpr int cols_v() { return COLS << V; }
+  template <int V>
+  static constexpr bool cols_valid() {
+    return V == 0 || (cols_v<V>() <= N && cols_v<V>() * G::TPL <= 1024 &&
+                      cols_v<V>() * G::LDS_LINE * (int)sizeof(cx<T>) <= kLdsBudget);
+  }
+  static constexpr int variants() { return cols_valid<2>() ? 3 : cols_valid<1>() ? 2 : 1; }
 };
 
 // ------------------------------------------------------------------------------------------------------------
@@ -612,9 +621,9 @@ __global__ void __launch_bounds__(LINES * LineGeom<N>::TPL, MinWaves<LINES * Lin
   op.template finish<NT>(acc, b, tile, gridDim.x, reinterpret_cast<double*>(lds));
 }
 
-template <typename T, int N, bool COLS, class Op>
+template <typename T, int N, bool COLS, class Op, int V = 0>
 void launch_op(const LineArgs& a, hipStream_t s) {
-  constexpr int LINES = COLS ? Tiling<T, N>::COLS : Tiling<T, N>::ROWS;
+  constexpr int LINES = COLS ? Tiling<T, N>::template cols_v<V>() : Tiling<T, N>::ROWS;
   constexpr int NT = LINES * LineGeom<N>::TPL;
   Op op;
   op.a = a;
@@ -622,18 +631,30 @@ void launch_op(const LineArgs& a, hipStream_t s) {
   hipLaunchKernelGGL((k_lines<T, N, LINES, COLS, Op>), grid, dim3(NT), 0, s, op);
 }
 
+// column stages at tile variant V (only the valid variants are instantiated)
+template <typename T, int N, class Op>
+void launch_cols(const LineArgs& a, hipStream_t s) {
+  if constexpr (Tiling<T, N>::template cols_valid<2>()) {
+    if (a.tile == 2) return launch_op<T, N, true, Op, 2>(a, s);
+  }
+  if constexpr (Tiling<T, N>::template cols_valid<1>()) {
+    if (a.tile == 1) return launch_op<T, N, true, Op, 1>(a, s);
+  }
+  launch_op<T, N, true, Op, 0>(a, s);
+}
+
 template <typename T, int N>
 void launch_lines(LineOp op, const LineArgs& a, hipStream_t s) {
   switch (op) {
     case LineOp::RowsInvScaled: launch_op<T, N, false, OpRowsInvScaled<T, N>>(a, s); break;
-    case LineOp::ColsInvMoments: launch_op<T, N, true, OpColsInvMoments<T, N>>(a, s); break;
+    case LineOp::ColsInvMoments: launch_cols<T, N, OpColsInvMoments<T, N>>(a, s); break;
     case LineOp::RowsInvRegular: launch_op<T, N, false, OpRowsInvRegular<T, N>>(a, s); break;
-    case LineOp::ColsInvTailFwd: launch_op<T, N, true, OpColsInvTail<T, N, false>>(a, s); break;
-    case LineOp::ColsInvTail: launch_op<T, N, true, OpColsInvTail<T, N, true>>(a, s); break;
+    case LineOp::ColsInvTailFwd: launch_cols<T, N, OpColsInvTail<T, N, false>>(a, s); break;
+    case LineOp::ColsInvTail: launch_cols<T, N, OpColsInvTail<T, N, true>>(a, s); break;
     case LineOp::RowsFwdEpilogue: launch_op<T, N, false, OpRowsFwdEpilogue<T, N>>(a, s); break;
-    case LineOp::ColsFwdPotential: launch_op<T, N, true, OpColsFwdPotential<T, N>>(a, s); break;
-    case LineOp::ColsFwdPlain: launch_op<T, N, true, OpColsPlain<T, N, -1>>(a, s); break;
-    case LineOp::ColsInvPlain: launch_op<T, N, true, OpColsPlain<T, N, +1>>(a, s); break;
+    case LineOp::ColsFwdPotential: launch_cols<T, N, OpColsFwdPotential<T, N>>(a, s); break;
+    case LineOp::ColsFwdPlain: launch_cols<T, N, OpColsPlain<T, N, -1>>(a, s); break;
+    case LineOp::ColsInvPlain: launch_cols<T, N, OpColsPlain<T, N, +1>>(a, s); break;
   }
 }
 

@@ -99,6 +99,7 @@ struct Work {
   int N = 0, B = 0, m = 0, prec = 0;
   // captured Krylov iterations: key (element bytes, j, reorth, B) -> executable graph; dropped on reallocation
   std::map<std::tuple<int, int, int, int>, hipGraphExec_t> graphs;
+  int graph_epoch = 0;  // tuning epoch the graphs were captured in
   void drop_graphs();
   size_t n = 0;
   size_t Q_bs = 0;

@@ -12,6 +12,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <atomic>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -322,6 +323,7 @@ Work& Work::operator=(Work&& o) noexcept {
   shv = std::move(o.shv); unit = std::move(o.unit); Hbuf = std::move(o.Hbuf);
   host_act = std::move(o.host_act); host_live = std::move(o.host_live);
   graphs = std::move(o.graphs);
+  graph_epoch = o.graph_epoch;
   return *this;
 }
 
@@ -358,7 +360,8 @@ int Work::setup(int N_, int B_, int m_, int prec_, bool shared_q) {
   if ((rc = dmom32.ensure((size_t)B * kNMom * sizeof(c32)))) return rc;
   if ((rc = ex32.ensure((size_t)B * N * sizeof(c32)))) return rc;
   if ((rc = ey32.ensure((size_t)B * N * sizeof(c32)))) return rc;
-  const int tiles = std::max(line_tiles(N, true, true), line_tiles(N, true, false));
+  // partial buffers for the narrowest column tiles (variant 0: the most tiles), whatever the current choice
+  const int tiles = std::max(line_tiles_variant(N, true, true, 0), line_tiles_variant(N, true, false, 0));
   const int rtiles = std::max(line_tiles(N, false, true), line_tiles(N, false, false));
   if ((rc = part_mom.ensure((size_t)B * 2 * kNMom * std::max(tiles, rtiles) * sizeof(double)))) return rc;
   if ((rc = part_vec.ensure((size_t)B * (kMaxRestart + 2) * std::max(vec_blocks(n), rtiles) * sizeof(double))))
@@ -689,6 +692,10 @@ int krylov_cycle(const Pipeline& P, Work& w, const BatchCfg& cfg, int it_budget,
   };
 
   bool graphs = cfg.use_graph && !timer_on();
+  if (w.graph_epoch != tuning_epoch()) {  // captured with another tile choice
+    w.drop_graphs();
+    w.graph_epoch = tuning_epoch();
+  }
   int j = 0;
   for (; j < mlim; ++j) {
     bool done = false;
@@ -837,6 +844,15 @@ static bool all_finite(const double* p, size_t cnt) {
   return true;
 }
 
+// batch size chosen by the tuner per (N, precision); 0 = not tuned (use min(nk, 64))
+static std::atomic<int> g_batch[2][12];
+static int batch_slot(int N) {
+  int i = 0;
+  for (int m = 8; m < N && i < 11; m <<= 1) ++i;
+  return i;
+}
+static int tuned_batch(int N, bool fp64) { return g_batch[fp64 ? 1 : 0][batch_slot(N)].load(); }
+
 static int check_device() {
   int cnt = 0;
   hipError_t e = hipGetDeviceCount(&cnt);
@@ -906,7 +922,8 @@ int solve_impl(const dbar_grid* grid, const void* Q, bool q_on_device, int64_t n
   if (!q_on_device) {
     if (!all_finite(static_cast<const double*>(Q), 2 * n)) return fail(DBAR_EINVAL, "Q contains NaN or Inf");
   }
-  int B = o.mode == DBAR_MODE_PLAIN ? 1 : (o.batch > 0 ? o.batch : (int)std::min<int64_t>(nk, 64));
+  const int tuned = tuned_batch(N, o.precision == DBAR_FP64);
+  int B = o.mode == DBAR_MODE_PLAIN ? 1 : (o.batch > 0 ? o.batch : (int)std::min<int64_t>(nk, tuned > 0 ? tuned : 64));
   B = (int)std::min<int64_t>(B, nk);
   if (o.mode != DBAR_MODE_PLAIN && o.batch <= 0) {
     // fit the batch to free memory: basis + 6 vectors per entry
@@ -1069,6 +1086,124 @@ int dbar_solve_device(const dbar_grid* grid, const void* Q_dev, int64_t nk, cons
                       const dbar_opts* opts, void* S_dev, void* m_dev, dbar_info* info, void* stream) {
   return solve_impl(grid, Q_dev, true, nk, k, tol, opts, S_dev, m_dev, true, info,
                     static_cast<hipStream_t>(stream), nullptr);
+}
+
+// Tuner: times one operator application over `batch` entries for every column-tile width of the grid size, keeps the
+// fastest, then times the operator at a few batch sizes and keeps the smallest within 5% of the best per-entry time.
+int dbar_autotune(const dbar_grid* grid, int32_t precision, int32_t batch, dbar_tune_result* out) {
+  int rc = validate_grid(grid);
+  if (rc) return rc;
+  if (precision != DBAR_FP64 && precision != DBAR_MIXED && precision != DBAR_FP32)
+    return fail(DBAR_EINVAL, "precision must be DBAR_FP64, DBAR_MIXED or DBAR_FP32");
+  if (batch < 1 || batch > 1024) return fail(DBAR_EINVAL, "batch must be in [1, 1024]");
+  if ((rc = check_device())) return rc;
+  std::lock_guard<std::mutex> lock(g_mutex);
+  const int N = grid->n;
+  const size_t n = (size_t)N * N;
+  hipStream_t s = nullptr;
+  if ((rc = solver_stream(nullptr, &s))) return rc;
+  Work& w = g_work;
+  // FP32 operator buffers come with the mixed layout; one Krylov vector pair serves as input and output
+  if ((rc = w.setup(N, batch, 1, precision == DBAR_FP64 ? DBAR_FP64 : DBAR_MIXED, true))) return rc;
+  Pipeline P;
+  if ((rc = make_pipeline(grid, w, &P))) return rc;
+  // zero inputs: the kernels' work does not depend on the data (k = 0, Q = 0, S = 0)
+  const size_t vb = precision == DBAR_FP64 ? sizeof(c64) : sizeof(c32);
+  if (hipMemsetAsync(w.x.p, 0, (size_t)batch * n * sizeof(c64), s) != hipSuccess ||
+      hipMemsetAsync(w.V.p, 0, (size_t)batch * n * 2 * vb, s) != hipSuccess ||
+      hipMemsetAsync(w.Q64.p, 0, n * sizeof(c64), s) != hipSuccess ||
+      hipMemsetAsync(w.kvals.p, 0, (size_t)batch * sizeof(c64), s) != hipSuccess ||
+      (precision != DBAR_FP64 && hipMemsetAsync(w.Q32.p, 0, n * sizeof(c32), s) != hipSuccess))
+    return fail(DBAR_EDEVICE, "tuner buffer initialisation failed");
+  w.B = batch;
+  launch_phase_tables(static_cast<const c64*>(w.kvals.p), N, grid->L, static_cast<c64*>(w.ex.p),
+                      static_cast<c64*>(w.ey.p), static_cast<c32*>(w.ex32.p), static_cast<c32*>(w.ey32.p), batch, s);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    return fail(DBAR_EDEVICE, "event creation failed");
+  const size_t V_bs = n * 2;  // the workspace basis holds m + 1 = 2 vectors per entry
+  auto time_apply = [&](bool fp64, int B, int reps) -> double {
+    auto once = [&]() {
+      if (fp64)
+        P.apply<double>(w.x.p, n, w.bvec.p, n, w.Q64.p, 0, w.T64.p, B, nullptr, 1.0, 1.0, nullptr, 0, false, s);
+      else
+        P.apply<float>(w.V.p, V_bs, static_cast<char*>(w.V.p) + n * sizeof(c32), V_bs, w.Q32.p, 0, w.T32.p, B,
+                       nullptr, 1.0, 1.0, nullptr, 0, false, s);
+    };
+    once();  // warm-up (first launch of each kernel)
+    (void)hipEventRecord(e0, s);
+    for (int r = 0; r < reps; ++r) once();
+    (void)hipEventRecord(e1, s);
+    float ms = 0.f;
+    if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return -1.0;
+    return ms / reps;
+  };
+  dbar_tune_result res{};
+  int result = DBAR_OK;
+  for (int f = 0; f < 2 && result == DBAR_OK; ++f) {  // f = 0: FP64 operator, 1: FP32 operator
+    const bool fp64 = f == 0;
+    if (fp64 ? precision == DBAR_FP32 : precision == DBAR_FP64) continue;
+    const int nv = tile_variants(N, fp64);
+    res.n_variants[f] = nv;
+    int best = 0;
+    for (int v = 0; v < nv; ++v) {
+      set_tile_variant(N, fp64, v);
+      res.columns[f][v] = tile_columns(N, fp64, v);
+      res.ms[f][v] = time_apply(fp64, batch, 5);
+      if (res.ms[f][v] < 0.0) result = fail(DBAR_EDEVICE, "timing failed");
+      if (res.ms[f][v] < res.ms[f][best]) best = v;
+    }
+    set_tile_variant(N, fp64, best);
+    res.chosen[f] = best;
+  }
+  // batch size: per-entry time at batch, batch/2, batch/4, batch/8 with the operator that dominates the solves
+  if (result == DBAR_OK) {
+    const bool fp64 = precision == DBAR_FP64;
+    double best_pe = 1e300;
+    for (int c = 0; c < 4; ++c) {
+      const int Bc = std::max(1, batch >> c);
+      res.batch_candidates[c] = Bc;
+      res.per_entry_ms[c] = time_apply(fp64, Bc, 3) / Bc;
+      best_pe = std::min(best_pe, res.per_entry_ms[c]);
+    }
+    res.batch = batch;
+    for (int c = 3; c >= 0; --c)
+      if (res.per_entry_ms[c] <= 1.05 * best_pe) {
+        res.batch = res.batch_candidates[c];
+        break;
+      }
+    g_batch[fp64 ? 1 : 0][batch_slot(N)] = res.batch;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  w.drop_graphs();
+  if (out) *out = res;
+  return result;
+}
+
+int dbar_set_tile(int32_t n, int32_t precision, int32_t variant) {
+  dbar_grid g{n, 11, 1.0};
+  int rc = validate_grid(&g);
+  if (rc) return rc;
+  const bool fp64 = precision == DBAR_FP64;
+  if (precision != DBAR_FP64 && precision != DBAR_FP32) return fail(DBAR_EINVAL, "precision must be FP64 or FP32");
+  if (variant < 0 || variant >= tile_variants(n, fp64)) return fail(DBAR_EINVAL, "no such tile variant for this grid");
+  std::lock_guard<std::mutex> lock(g_mutex);
+  set_tile_variant(n, fp64, variant);
+  return DBAR_OK;
+}
+
+int dbar_get_tile(int32_t n, int32_t precision, int32_t* variant, int32_t* columns, int32_t* variants) {
+  dbar_grid g{n, 11, 1.0};
+  int rc = validate_grid(&g);
+  if (rc) return rc;
+  if (precision != DBAR_FP64 && precision != DBAR_FP32) return fail(DBAR_EINVAL, "precision must be FP64 or FP32");
+  const bool fp64 = precision == DBAR_FP64;
+  const int v = tile_variant(n, fp64);
+  if (variant) *variant = v;
+  if (columns) *columns = tile_columns(n, fp64, v);
+  if (variants) *variants = tile_variants(n, fp64);
+  return DBAR_OK;
 }
 
 static int single_prep(const dbar_grid* grid, int precision, Work*& w, Pipeline& P) {

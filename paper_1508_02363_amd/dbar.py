@@ -134,6 +134,32 @@ def reconstruct(r: np.ndarray, L: float, t: float = 0.0, tol: float = 1e-12, M: 
     return (q, _infos(info)) if want_info else q
 
 
+def autotune(N: int, L: float, precision: int = DBAR_MIXED, batch: int = 16, M: int = 11) -> dict:
+    """Time the operator for every column-tile width at grid size N (and batch sizes up to `batch`), keep the
+    fastest; returns the timings and choices."""
+    r = _lib.TuneResult()
+    check(_lib.load().dbar_autotune(ctypes.byref(_grid(N, L, M)), int(precision), int(batch), ctypes.byref(r)))
+    out = {"batch": r.batch, "batch_candidates": list(r.batch_candidates), "per_entry_ms": list(r.per_entry_ms)}
+    for f, name in ((0, "fp64"), (1, "fp32")):
+        nv = r.n_variants[f]
+        if nv:
+            out[name] = {"columns": list(r.columns[f])[:nv], "ms": list(r.ms[f])[:nv],
+                         "chosen_columns": r.columns[f][r.chosen[f]]}
+    return out
+
+
+def set_tile(N: int, precision: int, variant: int):
+    """Force the column-tile variant of grid size N for the FP64 or FP32 operator."""
+    check(_lib.load().dbar_set_tile(int(N), int(precision), int(variant)))
+
+
+def get_tile(N: int, precision: int) -> tuple[int, int, int]:
+    """(variant, columns per tile, number of variants) for grid size N."""
+    v, c, nv = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    check(_lib.load().dbar_get_tile(int(N), int(precision), ctypes.byref(v), ctypes.byref(c), ctypes.byref(nv)))
+    return v.value, c.value, nv.value
+
+
 def apply(Q: np.ndarray, k: complex, S: np.ndarray, L: float, M: int = 11, precision: int = DBAR_FP64):
     """One application A(S) = S + i F(q_k conj(h(S)))."""
     Q = _c128(Q)

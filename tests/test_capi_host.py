@@ -104,3 +104,17 @@ def test_reflection_and_reconstruction_reject_bad_arguments():
                                 qo.ctypes.data_as(D), None) == _lib.DBAR_EINVAL
     assert lib.dbar_reconstruct(ctypes.byref(_lib.Grid(12, 11, 2.0)), qo.ctypes.data_as(D), 0.0, 1e-12, None,
                                 qo.ctypes.data_as(D), None) == _lib.DBAR_EINVAL
+
+
+def test_tuning_entry_points_validate_arguments():
+    lib = _lib.load()
+    g = _lib.Grid(100, 11, 2.0)
+    assert lib.dbar_autotune(ctypes.byref(g), _lib.DBAR_MIXED, 16, None) == _lib.DBAR_EINVAL
+    g = _lib.Grid(256, 11, 2.0)
+    assert lib.dbar_autotune(ctypes.byref(g), 7, 16, None) == _lib.DBAR_EINVAL
+    assert lib.dbar_autotune(ctypes.byref(g), _lib.DBAR_MIXED, 0, None) == _lib.DBAR_EINVAL
+    assert lib.dbar_set_tile(256, _lib.DBAR_FP64, 99) == _lib.DBAR_EINVAL
+    assert lib.dbar_set_tile(256, _lib.DBAR_MIXED, 0) == _lib.DBAR_EINVAL
+    v, c, nv = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    assert lib.dbar_get_tile(256, _lib.DBAR_FP32, ctypes.byref(v), ctypes.byref(c), ctypes.byref(nv)) == 0
+    assert v.value == 0 and nv.value >= 2 and c.value == 8  # default: 8 columns (64 B rows of FP32 complex)

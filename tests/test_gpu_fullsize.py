@@ -1,0 +1,79 @@
+"""GPU parity at the workloads' full sizes, in the launch configurations the benchmark and the batched path use.
+
+* N = 1024, 16 k, batch 16, mixed precision (the benchmark's step): S and m against oracle solves for sampled k
+  (the oracle's solve at N = 1024 takes seconds), and all 16 against the FP64 batched path.
+* N = 512, the 1024 k of the 32 x 32 grid in [-6, 6]^2, FP64 batched after autotuning: every entry converges, and
+  sampled k agree with the oracle.
+* N = 4096, 64 k in |k| <= 8, mixed precision: every entry converges to the FP64 residual, and for a sampled k the
+  oracle's own FP64 operator confirms ||b - A(S)|| / ||b|| (a property that holds at any size; an oracle solve at
+  this size does not fit a test).
+"""
+import numpy as np
+import pytest
+
+import dbar_workloads as W
+from oracle import dbar_oracle as O
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1508_02363_amd import dbar as D  # noqa: E402
+
+
+def relerr(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def test_bench_config_n1024_mixed():
+    w = W.workload("plain_n1024")
+    Qd = torch.from_numpy(w.Q).to("cuda:0")
+    S, m, info = D.solve_device(Qd, w.ks, w.L, tol=w.tol, batch=len(w.ks), precision=D.DBAR_MIXED)
+    S64, m64, info64 = D.solve_device(Qd, w.ks, w.L, tol=w.tol, batch=len(w.ks), precision=D.DBAR_FP64)
+    S, m, S64, m64 = (t.cpu().numpy() for t in (S, m, S64, m64))
+    assert all(i.status == 0 and i.rel_residual <= w.tol for i in info)
+    for j in range(len(w.ks)):
+        assert relerr(S[j], S64[j]) < 1e-10 and relerr(m[j], m64[j]) < 1e-10, j
+    g = O.make_grid(w.N, w.L)
+    om = O.omega_table(g, w.M)
+    for j in (0, 9):
+        print(f"oracle solve N=1024 k={w.ks[j]}", flush=True)
+        ref = O.solve(g, w.Q, w.ks[j], tol=1e-13, om=om)
+        assert relerr(S[j], ref.S) < 1e-10, j
+        assert relerr(m[j], ref.m) < 1e-10, j
+
+
+def test_batched_n512_all_k_autotuned():
+    w = W.workload("batched_n512")
+    try:
+        tune = D.autotune(w.N, w.L, precision=D.DBAR_FP64, batch=64)
+        print("tuning", tune, flush=True)
+        Qd = torch.from_numpy(w.Q).to("cuda:0")
+        S, m, info = D.solve_device(Qd, w.ks, w.L, tol=w.tol, precision=D.DBAR_FP64, want_m=False)
+        assert len(info) == 1024 and all(i.status == 0 and i.rel_residual <= w.tol for i in info)
+        g = O.make_grid(w.N, w.L)
+        om = O.omega_table(g, w.M)
+        for j in (0, 517, 1023):  # corner k = -6-6i, an interior one, corner 6+6i
+            print(f"oracle solve N=512 k={w.ks[j]}", flush=True)
+            ref = O.solve(g, w.Q, w.ks[j], tol=1e-13, om=om)
+            assert relerr(S[j].cpu().numpy(), ref.S) < 1e-10, j
+    finally:
+        D.set_tile(w.N, D.DBAR_FP64, 0)
+
+
+def test_mixed_n4096_residual_by_oracle_operator():
+    w = W.workload("mixed_n4096")
+    Qd = torch.from_numpy(w.Q).to("cuda:0")
+    S, _, info = D.solve_device(Qd, w.ks, w.L, tol=w.tol, precision=D.DBAR_MIXED, want_m=False)
+    assert len(info) == 64 and all(i.status == 0 and i.rel_residual <= w.tol for i in info)
+    j = 5
+    print(f"oracle operator N=4096 k={w.ks[j]}", flush=True)
+    g = O.make_grid(w.N, w.L)
+    om = O.omega_table(g, w.M)
+    Sj = S[j].cpu().numpy()
+    del S
+    b = O.rhs(g, w.Q, w.ks[j])
+    r = b - O.apply_A(g, w.Q, w.ks[j], Sj, w.M, om)
+    assert np.linalg.norm(r) / np.linalg.norm(b) < 1e-11
