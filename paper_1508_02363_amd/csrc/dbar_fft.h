@@ -186,9 +186,32 @@ struct PassInfo {
   }();
 };
 
-// One Stockham pass in registers (twiddle + DFT).  v[s] holds position jt + s*TPL.
-template <typename T, int N, int PASS, int DIR>
-DBAR_D void fft_pass_regs(cx<T>* v, int jt, const cx<T>* __restrict__ tw) {
+// Twiddles of pass 1 (NS = 16, radix R1): W_N^{r k N/(16 R1)} = W_{16 R1}^{r k} for r < R1, k < 16, whatever N is.
+// Kept in LDS as t1[(r - 1) * 16 + k] (r-major: the lanes of a wave, consecutive k, read consecutive banks).
+template <int N>
+struct Pass1Table {
+  static constexpr bool USED = LineGeom<N>::NPASS > 1;
+  static constexpr int R1 = USED ? PassInfo<N, 1>::R : 2;
+  static constexpr int SIZE = (R1 - 1) * 16;
+};
+
+// Fill the pass-1 table from the global twiddle table exp(-2 pi i m / N) (all threads of the block; ordered before
+// its first use by the barriers of pass 0's exchange).
+template <typename T, int N>
+DBAR_D void fill_pass1_table(cx<T>* __restrict__ t1, const cx<T>* __restrict__ tw, int tid, int nt) {
+  using P1 = Pass1Table<N>;
+  if constexpr (P1::USED) {
+    for (int t = tid; t < P1::SIZE; t += nt) {
+      const int r = t / 16 + 1, k = t % 16;
+      t1[t] = tw[r * k * (N / (16 * P1::R1))];
+    }
+  }
+}
+
+// One Stockham pass in registers (twiddle + DFT).  v[s] holds position jt + s*TPL.  T1: pass 1 reads its twiddles
+// from the LDS table t1 (kernels bound by arithmetic) instead of forming them from tw (kernels bound by memory).
+template <typename T, int N, int PASS, int DIR, bool T1>
+DBAR_D void fft_pass_regs(cx<T>* v, int jt, const cx<T>* __restrict__ tw, const cx<T>* __restrict__ t1) {
   using G = LineGeom<N>;
   constexpr int R = PassInfo<N, PASS>::R;
   constexpr int NS = PassInfo<N, PASS>::NS;
@@ -200,7 +223,14 @@ DBAR_D void fft_pass_regs(cx<T>* v, int jt, const cx<T>* __restrict__ tw) {
     cx<T> b[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) b[r] = v[q + r * NB];
-    if constexpr (NS > 1) {
+    if constexpr (T1 && PASS == 1 && NS == 16) {
+      const int k = j % 16;
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        const cx<T> t = t1[(r - 1) * 16 + k];
+        b[r] = b[r] * (DIR < 0 ? t : conj(t));
+      }
+    } else if constexpr (NS > 1) {
       // W^r from the table entries for the powers of two in r (at most 3 products: r < 16), formed per element so
       // that only log2(R) twiddles are live at a time
       const int k = j % NS;
@@ -255,23 +285,24 @@ DBAR_D void lds_load_line(const cx<T>* __restrict__ line, cx<T>* v, int jt) {
 // Full line transform: registers in (positions jt + s*TPL), registers out (same positions, transformed).
 // `line` is this line's LDS buffer (LDS_LINE elements at stride LS).  Must be called by all threads of the block
 // (barriers).
-template <typename T, int N, int DIR, int LS>
-DBAR_D void line_fft(cx<T>* v, int jt, cx<T>* __restrict__ line, const cx<T>* __restrict__ tw) {
+template <typename T, int N, int DIR, int LS, bool T1>
+DBAR_D void line_fft(cx<T>* v, int jt, cx<T>* __restrict__ line, const cx<T>* __restrict__ tw,
+                     const cx<T>* __restrict__ t1) {
   using G = LineGeom<N>;
-  fft_pass_regs<T, N, 0, DIR>(v, jt, tw);
+  fft_pass_regs<T, N, 0, DIR, T1>(v, jt, tw, t1);
   if constexpr (G::NPASS > 1) {
     lds_store_pass<T, N, 0, LS>(line, v, jt);
     __syncthreads();
     lds_load_line<T, N, LS>(line, v, jt);
     __syncthreads();
-    fft_pass_regs<T, N, 1, DIR>(v, jt, tw);
+    fft_pass_regs<T, N, 1, DIR, T1>(v, jt, tw, t1);
   }
   if constexpr (G::NPASS > 2) {
     lds_store_pass<T, N, 1, LS>(line, v, jt);
     __syncthreads();
     lds_load_line<T, N, LS>(line, v, jt);
     __syncthreads();
-    fft_pass_regs<T, N, 2, DIR>(v, jt, tw);
+    fft_pass_regs<T, N, 2, DIR, T1>(v, jt, tw, t1);
   }
   static_assert(G::NPASS <= 3, "N <= 4096 needs at most three passes");
 }

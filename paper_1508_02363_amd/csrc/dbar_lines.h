@@ -556,6 +556,8 @@ __global__ void __launch_bounds__(LINES * LineGeom<N>::TPL, MinWaves<LINES * Lin
   using G = LineGeom<N>;
   constexpr int NT = LINES * G::TPL;
   __shared__ cx<T> lds[LdsSize<T, N, LINES>::kElems];
+  // pass-1 twiddle table: column stages only (their element work makes them arithmetic-bound)
+  __shared__ cx<T> lds_t1[COLS ? Pass1Table<N>::SIZE : 1];
   const int b = blockIdx.y;
   if (!op.active(b)) return;
   typename Op::Pre pre;
@@ -566,6 +568,7 @@ __global__ void __launch_bounds__(LINES * LineGeom<N>::TPL, MinWaves<LINES * Lin
   const int tile = xcd_swizzle(blockIdx.x, gridDim.x);
   const int line = tile * LINES + ln;
   const cx<T>* tw = static_cast<const cx<T>*>(op.a.tw);
+  if constexpr (COLS) fill_pass1_table<T, N>(lds_t1, tw, tid, NT);
 
   cx<T> v[G::RMAX];
 #pragma unroll
@@ -574,7 +577,7 @@ __global__ void __launch_bounds__(LINES * LineGeom<N>::TPL, MinWaves<LINES * Lin
   // element by element, so that the lanes of a wave (consecutive columns) hit consecutive banks
   constexpr int LS = COLS ? LINES : 1;
   cx<T>* my = COLS ? lds + ln : lds + ln * G::LDS_LINE;
-  line_fft<T, N, Op::DIR1, LS>(v, jt, my, tw);
+  line_fft<T, N, Op::DIR1, LS, COLS>(v, jt, my, tw, lds_t1);
   // Heavy per-element work (FP64 moments, the closed-form tail) runs in a rolled loop over values parked in LDS at
   // the thread's own positions: registers stay low (occupancy) and no barrier is needed until the next exchange.
   if constexpr (Op::TWO) {
@@ -599,7 +602,7 @@ __global__ void __launch_bounds__(LINES * LineGeom<N>::TPL, MinWaves<LINES * Lin
         else op.template mid<typename Op::Acc>(b, line, jt + s * G::TPL, v[s]);
       }
     }
-    line_fft<T, N, -Op::DIR1, LS>(v, jt, my, tw);
+    line_fft<T, N, -Op::DIR1, LS, COLS>(v, jt, my, tw, lds_t1);
   }
   typename Op::Acc acc{};
   if constexpr (Op::ROLLED && !Op::TWO) {
