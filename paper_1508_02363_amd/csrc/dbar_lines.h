@@ -392,25 +392,34 @@ struct OpRowsInvRegular : OpBase<T, N> {
   using Acc = NoAcc;
   DBAR_D cx<T> load(int b, int row, int pos) const {
     const c64* __restrict__ c = this->a.coefG + (size_t)b * kNMom;
-    const double invL = 1.0 / this->a.L;
-    // xi - a with a = 2i conj(k) on the grid (not reduced modulo the period: the quotient only jumps at the edge)
+    // xi - a with a = 2i conj(k) on the grid (not reduced modulo the period: the quotient only jumps at the edge),
+    // as integer wave numbers: L^2 |xi - a|^2 = m1^2 + m2^2 exactly
     const int o1 = this->a.shv ? this->a.shv[2 * b] : 0, o2 = this->a.shv ? this->a.shv[2 * b + 1] : 0;
-    const double xi1 = (wavenum(pos, N) - o1) * invL, xi2 = (wavenum(row, N) - o2) * invL;
-    const double r2 = xi1 * xi1 + xi2 * xi2;
+    const int m1 = wavenum(pos, N) - o1, m2 = wavenum(row, N) - o2;
+    const int q = m1 * m1 + m2 * m2;
     const double f = ((row + pos) & 1) ? -this->a.ci : this->a.ci;
-    if (r2 == 0.0) return cvt<T>(f * c[kMaxM + 1]);
+    if (q == 0) return cvt<T>(f * c[kMaxM + 1]);
     cx<T> sv = this->inp(b)[(size_t)row * N + pos];
-    if (r2 < 740.0) {  // G (FP64: conj(xi)^n overflows FP32 for |xi|^n > 3e38); e^{-|xi|^2} underflows beyond 740
+    const double invL = 1.0 / this->a.L;
+    // G in FP64 (conj(xi)^n overflows FP32 for |xi|^n > 3e38), only where e^{-|xi|^2} has not underflowed
+    if (static_cast<float>(q) < static_cast<float>(740.0 * this->a.L * this->a.L)) {
+      const double xi1 = m1 * invL, xi2 = m2 * invL;
       const c64 xib{xi1, -xi2};
       const int M = this->a.M;
       c64 g = c[M];
       for (int n = M - 1; n >= 0; --n) g = c[n] + xib * g;
-      sv = cvt<T>(cvt<double>(sv) - exp(-r2) * g);
+      sv = cvt<T>(cvt<double>(sv) - exp(-(xi1 * xi1 + xi2 * xi2)) * g);
     }
     // (S - G) / xi in the transform's precision
-    const T t1 = static_cast<T>(xi1), t2 = static_cast<T>(xi2);
-    const T ir2 = sizeof(T) == 8 ? static_cast<T>(f / r2) : static_cast<T>(f) * recip(static_cast<T>(r2));
-    return cx<T>{(sv.re * t1 + sv.im * t2) * ir2, (sv.im * t1 - sv.re * t2) * ir2};
+    if constexpr (sizeof(T) == 8) {
+      const double t1 = m1 * invL, t2 = m2 * invL, ir2 = f / (t1 * t1 + t2 * t2);
+      return cx<T>{(sv.re * t1 + sv.im * t2) * ir2, (sv.im * t1 - sv.re * t2) * ir2};
+    } else {
+      const float il = static_cast<float>(invL);
+      const float t1 = static_cast<float>(m1) * il, t2 = static_cast<float>(m2) * il;
+      const float ir2 = static_cast<float>(f) * recip(t1 * t1 + t2 * t2);
+      return cx<T>{(sv.re * t1 + sv.im * t2) * ir2, (sv.im * t1 - sv.re * t2) * ir2};
+    }
   }
   DBAR_D void store(Acc&, int b, int row, int pos, cx<T> v) const { this->outp(b)[(size_t)row * N + pos] = v; }
 };

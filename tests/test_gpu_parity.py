@@ -218,3 +218,46 @@ def test_iterated_method_rejects_k_off_the_grid():
     with pytest.raises(D.DbarError) as e:
         D.solve(np.zeros((32, 32)) + 0.1, [0.3 + 0.1j], 3.0, method=D.DBAR_METHOD_ITERATED)
     assert e.value.code == D._lib.DBAR_EINVAL
+
+
+def test_ragged_batches_equal_single_solves():
+    """nk = 7 in batches of 3 (3 + 3 + 1) gives the same S as one k per launch."""
+    N, L = 64, 3.0
+    Q = W.potential_gaussian_sum(N, L, seed=41)
+    ks = W.k_disk(7, 2.0, seed=42)
+    S3, m3, i3 = D.solve(Q, ks, L, tol=1e-12, batch=3)
+    S1, m1, i1 = D.solve(Q, ks, L, tol=1e-12, mode=D.DBAR_MODE_PLAIN)
+    assert all(a.status == 0 for a in i3 + i1)
+    for j in range(7):
+        assert relerr(S3[j], S1[j]) < 1e-10 and relerr(m3[j], m1[j]) < 1e-10, j
+
+
+@pytest.mark.parametrize("M", [0, 5, 15])
+def test_taylor_order_extremes(M):
+    """M = 0 (G = c_0 e^{-|xi|^2}) and M = 15 (the largest order the kernels carry) against the oracle; any M other
+    than 11 runs the generic unrolled paths of the moment and tail kernels."""
+    N, L = 128, 4.0
+    rng = np.random.default_rng(M)
+    g = O.make_grid(N, L)
+    Q = (0.8 + 0.6j) * np.exp(-np.abs(g.z) ** 2)
+    S = smooth_xi(g, rng)
+    k = 0.75 - 0.5j
+    assert relerr(D.dbar_inverse(S, L, M=M), O.regularised_h(g, S, M)[0]) < 1e-12
+    assert relerr(D.apply(Q, k, S, L, M=M), O.apply_A(g, Q, k, S, M)) < 1e-12
+    assert relerr(D.apply(Q, k, S, L, M=M, precision=D.DBAR_FP32), O.apply_A(g, Q, k, S, M)) < 2e-5
+    ref = O.solve(g, Q, k, tol=1e-13, M=M)
+    Sg, mg, info = D.solve(Q, [k], L, tol=1e-12, M=M, precision=D.DBAR_MIXED)
+    assert info[0].status == 0 and relerr(Sg[0], ref.S) < 1e-10 and relerr(mg[0], ref.m) < 1e-10
+
+
+def test_default_batch_with_many_k():
+    """batch = 0 lets the library choose entries per launch (tuned or min(nk, 64), capped by memory)."""
+    N, L = 32, 2.0
+    g = O.make_grid(N, L)
+    Q = W.potential_gaussian(N, L, 0.5 + 0.2j)
+    ks = W.k_square_grid(-1.5, 1.5, 9)  # 80 k
+    S, m, info = D.solve(Q, ks, L, tol=1e-12)
+    assert len(info) == len(ks) and all(i.status == 0 for i in info)
+    for j in (0, 41, 79):
+        ref = O.solve(g, Q, ks[j], tol=1e-13)
+        assert relerr(S[j], ref.S) < 1e-10, j
