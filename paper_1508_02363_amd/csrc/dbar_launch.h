@@ -48,6 +48,11 @@ struct LineArgs {
   c64 beta{0.0, 0.0};
   int want_norm = 0;           // RowsFwdEpilogue: accumulate |out|^2 partials
   int tile = 0;                // column stages: tile width variant (columns per tile = default << tile)
+  // RowsFwdEpilogue: Gram-Schmidt products Re<V_i, out> for i < dot_nv written as per-tile partials
+  // dot_part[b][i][tile] (V_i of entry b at dotV + b * dotV_bs + i * N * N, the transform's precision)
+  const void* dotV = nullptr;  size_t dotV_bs = 0;
+  int dot_nv = 0;
+  double* dot_part = nullptr;
 };
 
 // Number of blocks (tiles) per batch entry used by a line stage with the current tile choice; partial buffers are

@@ -216,6 +216,8 @@ struct OpBase {
   DBAR_D cx<T>* outp(int b) const { return static_cast<cx<T>*>(a.out) + (size_t)b * a.out_bs; }
   template <class Acc> DBAR_D void mid(int, int, int, cx<T>&) const {}
   template <int NT, class Acc> DBAR_D void finish(Acc&, int, int, int, double*) const {}
+  // after the stores: dots over the values the stores left in the thread's registers (ops that define DOTS)
+  static constexpr bool DOTS = false;
   // per-block data read once at kernel start, before any store (ops that need it define PRE and a Pre type)
   static constexpr bool PRE = false;
   struct Pre {};
@@ -483,11 +485,13 @@ template <typename T, int N>
 struct OpRowsFwdEpilogue : OpBase<T, N> {
   static constexpr int DIR1 = -1;
   static constexpr bool TWO = false;
+  static constexpr bool DOTS = true;
   struct Acc {
     double v[1];
   };
   DBAR_D cx<T> load(int b, int row, int pos) const { return this->inp(b)[(size_t)row * N + pos]; }
-  DBAR_D void store(Acc& acc, int b, int row, int pos, cx<T> X) const {
+  // X (the row transform's output) is replaced by the stored value, for the Gram-Schmidt products below
+  DBAR_D void store(Acc& acc, int b, int row, int pos, cx<T>& X) const {
     const LineArgs& a = this->a;
     const size_t idx = (size_t)row * N + pos;
     const double f = ((row + pos) & 1) ? -a.cf : a.cf;
@@ -496,6 +500,7 @@ struct OpRowsFwdEpilogue : OpBase<T, N> {
     if (a.gamma != 0.0) o = o + a.gamma * cvt<double>((static_cast<const cx<T>*>(a.Y) + (size_t)b * a.Y_bs)[idx]);
     const cx<T> ot = cvt<T>(o);
     this->outp(b)[idx] = ot;
+    X = ot;
     const c64 od = cvt<double>(ot);
     acc.v[0] += norm2(od);
   }
@@ -503,6 +508,29 @@ struct OpRowsFwdEpilogue : OpBase<T, N> {
   DBAR_D void finish(Acc& acc, int b, int tile, int ntiles, double* scratch) const {
     if (!this->a.want_norm) return;
     block_reduce_store<NT, 1>(acc.v, this->a.part + (size_t)b * ntiles + tile, 0, scratch);
+  }
+  // Re<V_i, out> over this tile for i < dot_nv, from the output values in registers (FP64 accumulation, the order
+  // fixed): the multi-dot of the first classical Gram-Schmidt pass without reading the new vector back
+  template <int NT>
+  DBAR_D void dots(const cx<T>* v, int b, int row, int jt, int tile, int ntiles, double* scratch) const {
+    using G = LineGeom<N>;
+    const LineArgs& a = this->a;
+    if (a.dot_nv <= 0) return;
+    const cx<T>* V = static_cast<const cx<T>*>(a.dotV) + (size_t)b * a.dotV_bs + (size_t)row * N;
+    double* dst = a.dot_part + (size_t)b * a.dot_nv * ntiles + tile;
+#pragma unroll 1
+    for (int i = 0; i < a.dot_nv; ++i) {
+      const cx<T>* Vi = V + (size_t)i * N * N;
+      double p4[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int s = 0; s < G::RMAX; ++s) {
+        const c64 x = cvt<double>(Vi[jt + s * G::TPL]);
+        const c64 w = cvt<double>(v[s]);
+        p4[s & 3] += x.re * w.re + x.im * w.im;
+      }
+      const double val[1] = {(p4[0] + p4[1]) + (p4[2] + p4[3])};
+      block_reduce_store<NT, 1>(val, dst + (size_t)i * ntiles, 0, scratch);
+    }
   }
 };
 
@@ -631,6 +659,7 @@ __global__ void __launch_bounds__(LINES * LineGeom<N>::TPL, MinWaves<LINES * Lin
     }
   }
   op.template finish<NT>(acc, b, tile, gridDim.x, reinterpret_cast<double*>(lds));
+  if constexpr (Op::DOTS && !COLS) op.template dots<NT>(v, b, line, jt, tile, gridDim.x, reinterpret_cast<double*>(lds));
 }
 
 template <typename T, int N, bool COLS, class Op, int V = 0>

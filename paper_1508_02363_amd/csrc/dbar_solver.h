@@ -114,6 +114,14 @@ struct Work {
 constexpr unsigned kShifted = 1u;    // regularise about xi = a = 2i conj(k) (Section 5.1, equation dbarinvShift)
 constexpr unsigned kUnitPhase = 2u;  // k = 0 phase (the operator K0 of equation shift)
 
+// Gram-Schmidt products fused into the operator's last kernel: Re<V_i, out> for i < nv as per-tile partials
+struct DotReq {
+  const void* V = nullptr;
+  size_t V_bs = 0;
+  int nv = 0;
+  double* part = nullptr;
+};
+
 struct Pipeline {
   int N = 0, M = 11;
   double L = 1.0;
@@ -138,12 +146,12 @@ struct Pipeline {
   template <typename T>
   void apply_impl(const void* in, size_t in_bs, void* out, size_t out_bs, const void* Qp, size_t Q_bs, void* Tbuf,
                   int B, const int* act, double alpha, double beta, const void* Y, size_t Y_bs, bool want_norm,
-                  unsigned flags, const void* S_ep, size_t S_ep_bs, hipStream_t s) const;
+                  unsigned flags, const void* S_ep, size_t S_ep_bs, hipStream_t s, const DotReq* dr = nullptr) const;
   // A(S) of the plain method (Section 4), as alpha S + beta i F(q_k conj(h(S))) + gamma Y
   template <typename T>
   void apply(const void* in, size_t in_bs, void* out, size_t out_bs, const void* Qp, size_t Q_bs, void* Tbuf, int B,
              const int* act, double alpha, double beta, const void* Y, size_t Y_bs, bool want_norm,
-             hipStream_t s) const;
+             hipStream_t s, const DotReq* dr = nullptr) const;
   // H(h) of equation eqh2
   template <typename T>
   void H_of(const void* in, size_t in_bs, void* Hout, size_t H_bs, const void* Qp, size_t Q_bs, void* Tbuf, int B,
@@ -152,7 +160,7 @@ struct Pipeline {
   template <typename T>
   void apply_B(const void* in, size_t in_bs, void* out, size_t out_bs, const void* Qp, size_t Q_bs, void* Tbuf,
                void* Hbuf, int B, const int* act, double alpha, double beta, const void* Y, size_t Y_bs,
-               bool want_norm, hipStream_t s) const;
+               bool want_norm, hipStream_t s, const DotReq* dr = nullptr) const;
   void rhs(const void* Q64p, size_t Q_bs, void* T64, c64* bout, int B, const int* act, unsigned flags,
            hipStream_t s) const;
   template <typename T>

@@ -458,7 +458,7 @@ void Pipeline::moments(const void* in, size_t in_bs, void* Tbuf, int B, const in
 template <typename T>
 void Pipeline::apply_impl(const void* in, size_t in_bs, void* out, size_t out_bs, const void* Qp, size_t Q_bs,
                           void* Tbuf, int B, const int* act, double alpha, double beta, const void* Y, size_t Y_bs,
-                          bool want_norm, unsigned flags, const void* S_ep, size_t S_ep_bs, hipStream_t s) const {
+                          bool want_norm, unsigned flags, const void* S_ep, size_t S_ep_bs, hipStream_t s, const DotReq* dr) const {
   moments<T>(in, in_bs, Tbuf, B, act, flags, s);
   LineArgs a = base(B, act, flags);
   a.tw = tw_of<T>(tw);
@@ -483,14 +483,21 @@ void Pipeline::apply_impl(const void* in, size_t in_bs, void* out, size_t out_bs
   a.gamma = Y ? 1.0 : 0.0;
   a.want_norm = want_norm ? 1 : 0;
   a.part = part_vec;
+  if (dr) {
+    a.dotV = dr->V;
+    a.dotV_bs = dr->V_bs;
+    a.dot_nv = dr->nv;
+    a.dot_part = dr->part;
+  }
   launch_lines_any<T>(N, LineOp::RowsFwdEpilogue, a, s);
 }
 
 template <typename T>
 void Pipeline::apply(const void* in, size_t in_bs, void* out, size_t out_bs, const void* Qp, size_t Q_bs, void* Tbuf,
                      int B, const int* act, double alpha, double beta, const void* Y, size_t Y_bs, bool want_norm,
-                     hipStream_t s) const {
-  apply_impl<T>(in, in_bs, out, out_bs, Qp, Q_bs, Tbuf, B, act, alpha, beta, Y, Y_bs, want_norm, 0u, nullptr, 0, s);
+                     hipStream_t s, const DotReq* dr) const {
+  apply_impl<T>(in, in_bs, out, out_bs, Qp, Q_bs, Tbuf, B, act, alpha, beta, Y, Y_bs, want_norm, 0u, nullptr, 0, s,
+                dr);
 }
 
 // H(h) = -i F(Q conj(F^{-1}(h/(xi - a)))) (equation eqh2), into Hout
@@ -504,10 +511,10 @@ void Pipeline::H_of(const void* in, size_t in_bs, void* Hout, size_t H_bs, const
 template <typename T>
 void Pipeline::apply_B(const void* in, size_t in_bs, void* out, size_t out_bs, const void* Qp, size_t Q_bs,
                        void* Tbuf, void* Hbuf, int B, const int* act, double alpha, double beta, const void* Y,
-                       size_t Y_bs, bool want_norm, hipStream_t s) const {
+                       size_t Y_bs, bool want_norm, hipStream_t s, const DotReq* dr) const {
   H_of<T>(in, in_bs, Hbuf, n, Qp, Q_bs, Tbuf, B, act, s);
   apply_impl<T>(Hbuf, n, out, out_bs, Qp, Q_bs, Tbuf, B, act, alpha, beta, Y, Y_bs, want_norm, kUnitPhase, in,
-                in_bs, s);
+                in_bs, s, dr);
 }
 
 // b = -i F(Q e_k) (FP64; e_k = 1 with kUnitPhase), with |b|^2 partials
@@ -578,9 +585,11 @@ void Pipeline::transform(bool inverse, const void* in, void* out, void* Tbuf, hi
 
 #define DBAR_PIPE_INST(T)                                                                                        \
   template void Pipeline::apply<T>(const void*, size_t, void*, size_t, const void*, size_t, void*, int,            \
-                                   const int*, double, double, const void*, size_t, bool, hipStream_t) const;     \
+                                   const int*, double, double, const void*, size_t, bool, hipStream_t,            \
+                                   const DotReq*) const;                                                          \
   template void Pipeline::apply_B<T>(const void*, size_t, void*, size_t, const void*, size_t, void*, void*, int,   \
-                                     const int*, double, double, const void*, size_t, bool, hipStream_t) const;   \
+                                     const int*, double, double, const void*, size_t, bool, hipStream_t,          \
+                                     const DotReq*) const;                                                        \
   template void Pipeline::H_of<T>(const void*, size_t, void*, size_t, const void*, size_t, void*, int, const int*, \
                                   hipStream_t) const;                                                            \
   template void Pipeline::h_of<T>(const void*, size_t, void*, size_t, void*, int, const int*, hipStream_t,         \
@@ -658,10 +667,16 @@ int krylov_cycle(const Pipeline& P, Work& w, const BatchCfg& cfg, int it_budget,
   auto enqueue = [&](int j) {
     void* vj = V + (size_t)j * n * sizeof(cx<T>);
     void* vj1 = V + (size_t)(j + 1) * n * sizeof(cx<T>);
+    // the first Gram-Schmidt pass's products Re<V_i, w>, i <= j, come out of the operator's last kernel
+    DotReq dr;
+    dr.V = V;
+    dr.V_bs = V_bs;
+    dr.nv = j + 1;
+    dr.part = part;
     if (cfg.method == 1)
-      P.apply_B<T>(vj, V_bs, vj1, V_bs, Qp, w.Q_bs, Tbuf, w.Hbuf.p, B, act, 1.0, 1.0, nullptr, 0, false, s);
+      P.apply_B<T>(vj, V_bs, vj1, V_bs, Qp, w.Q_bs, Tbuf, w.Hbuf.p, B, act, 1.0, 1.0, nullptr, 0, false, s, &dr);
     else
-      P.apply<T>(vj, V_bs, vj1, V_bs, Qp, w.Q_bs, Tbuf, B, act, 1.0, 1.0, nullptr, 0, false, s);
+      P.apply<T>(vj, V_bs, vj1, V_bs, Qp, w.Q_bs, Tbuf, B, act, 1.0, 1.0, nullptr, 0, false, s, &dr);
     for (int pass = 0; pass < cfg.reorth; ++pass) {
       VecArgs va;
       va.B = B;
@@ -674,8 +689,12 @@ int krylov_cycle(const Pipeline& P, Work& w, const BatchCfg& cfg, int it_budget,
       va.w_bs = V_bs;
       va.part = part;
       va.want_self = 0;
-      launch_dots<T>(va, s);
-      launch_reduce(part, j + 1, nvb, dred, B, act, s);
+      if (pass == 0) {
+        launch_reduce(part, j + 1, line_tiles(w.N, false, sizeof(T) == 8), dred, B, act, s);
+      } else {
+        launch_dots<T>(va, s);
+        launch_reduce(part, j + 1, nvb, dred, B, act, s);
+      }
       {
         TimerScope ts(kStageControl, 0.0, B, nullptr, s);
         hipLaunchKernelGGL(k_ctl_coef, dim3(ctl_blocks(B)), dim3(64), 0, s, ctl, dred, j + 1, act, j, pass, B);
