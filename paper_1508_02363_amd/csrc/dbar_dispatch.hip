@@ -59,7 +59,7 @@ static double line_bytes(int N, LineOp op, const LineArgs& a, size_t es) {
     case LineOp::RowsInvRegular: return 2 * P;
     case LineOp::ColsInvTailFwd: return 3 * P + (a.hout ? P : 0.0);
     case LineOp::ColsInvTail: return 2 * P;
-    case LineOp::RowsFwdEpilogue:  // fused dots read V_i, i < dot_nv, besides S (= V_{dot_nv - 1} in GMRES)
+    case LineOp::RowsFwdEpilogue:  // fused dots read V_i, i < dot_nv - 1, besides S (= V_{dot_nv - 1})
       return 2 * P + (a.alpha != 0.0 ? P : 0.0) + (a.gamma != 0.0 ? P : 0.0) +
              (a.dot_nv > 0 ? (a.dot_nv - (a.alpha != 0.0 ? 1 : 0)) * P : 0.0);
     case LineOp::ColsFwdPotential: return 2 * P;

@@ -49,7 +49,8 @@ struct LineArgs {
   int want_norm = 0;           // RowsFwdEpilogue: accumulate |out|^2 partials
   int tile = 0;                // column stages: tile width variant (columns per tile = default << tile)
   // RowsFwdEpilogue: Gram-Schmidt products Re<V_i, out> for i < dot_nv written as per-tile partials
-  // dot_part[b][i][tile] (V_i of entry b at dotV + b * dotV_bs + i * N * N, the transform's precision)
+  // dot_part[b][i][tile] (V_i of entry b at dotV + b * dotV_bs + i * N * N, the transform's precision); the last one,
+  // V_{dot_nv - 1}, must be the epilogue's S (alpha != 0)
   const void* dotV = nullptr;  size_t dotV_bs = 0;
   int dot_nv = 0;
   double* dot_part = nullptr;

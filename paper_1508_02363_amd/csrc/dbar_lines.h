@@ -488,6 +488,7 @@ struct OpRowsFwdEpilogue : OpBase<T, N> {
   static constexpr bool DOTS = true;
   struct Acc {
     double v[1];
+    double sdot;  // Re<S, out> over this thread's elements (S is the last vector of the fused products)
   };
   DBAR_D cx<T> load(int b, int row, int pos) const { return this->inp(b)[(size_t)row * N + pos]; }
   // X (the row transform's output) is replaced by the stored value, for the Gram-Schmidt products below
@@ -496,13 +497,18 @@ struct OpRowsFwdEpilogue : OpBase<T, N> {
     const size_t idx = (size_t)row * N + pos;
     const double f = ((row + pos) & 1) ? -a.cf : a.cf;
     c64 o = a.beta * (f * cvt<double>(X));
-    if (a.alpha != 0.0) o = o + a.alpha * cvt<double>((static_cast<const cx<T>*>(a.S) + (size_t)b * a.S_bs)[idx]);
+    c64 sv{0.0, 0.0};
+    if (a.alpha != 0.0) {
+      sv = cvt<double>((static_cast<const cx<T>*>(a.S) + (size_t)b * a.S_bs)[idx]);
+      o = o + a.alpha * sv;
+    }
     if (a.gamma != 0.0) o = o + a.gamma * cvt<double>((static_cast<const cx<T>*>(a.Y) + (size_t)b * a.Y_bs)[idx]);
     const cx<T> ot = cvt<T>(o);
     this->outp(b)[idx] = ot;
     X = ot;
     const c64 od = cvt<double>(ot);
     acc.v[0] += norm2(od);
+    acc.sdot += sv.re * od.re + sv.im * od.im;
   }
   template <int NT>
   DBAR_D void finish(Acc& acc, int b, int tile, int ntiles, double* scratch) const {
@@ -510,16 +516,20 @@ struct OpRowsFwdEpilogue : OpBase<T, N> {
     block_reduce_store<NT, 1>(acc.v, this->a.part + (size_t)b * ntiles + tile, 0, scratch);
   }
   // Re<V_i, out> over this tile for i < dot_nv, from the output values in registers (FP64 accumulation, the order
-  // fixed): the multi-dot of the first classical Gram-Schmidt pass without reading the new vector back
+  // fixed): the multi-dot of the first classical Gram-Schmidt pass without reading the new vector back.  The last
+  // vector, V_{dot_nv - 1}, is the epilogue's S (the operator's input) and was accumulated by the stores.
   template <int NT>
-  DBAR_D void dots(const cx<T>* v, int b, int row, int jt, int tile, int ntiles, double* scratch) const {
+  DBAR_D void dots(const Acc& acc, const cx<T>* v, int b, int row, int jt, int tile, int ntiles,
+                   double* scratch) const {
     using G = LineGeom<N>;
     const LineArgs& a = this->a;
     if (a.dot_nv <= 0) return;
     const cx<T>* V = static_cast<const cx<T>*>(a.dotV) + (size_t)b * a.dotV_bs + (size_t)row * N;
     double* dst = a.dot_part + (size_t)b * a.dot_nv * ntiles + tile;
+    const double last[1] = {acc.sdot};
+    block_reduce_store<NT, 1>(last, dst + (size_t)(a.dot_nv - 1) * ntiles, 0, scratch);
 #pragma unroll 1
-    for (int i = 0; i < a.dot_nv; ++i) {
+    for (int i = 0; i < a.dot_nv - 1; ++i) {
       const cx<T>* Vi = V + (size_t)i * N * N;
       double p4[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
@@ -659,7 +669,8 @@ __global__ void __launch_bounds__(LINES * LineGeom<N>::TPL, MinWaves<LINES * Lin
     }
   }
   op.template finish<NT>(acc, b, tile, gridDim.x, reinterpret_cast<double*>(lds));
-  if constexpr (Op::DOTS && !COLS) op.template dots<NT>(v, b, line, jt, tile, gridDim.x, reinterpret_cast<double*>(lds));
+  if constexpr (Op::DOTS && !COLS)
+    op.template dots<NT>(acc, v, b, line, jt, tile, gridDim.x, reinterpret_cast<double*>(lds));
 }
 
 template <typename T, int N, bool COLS, class Op, int V = 0>
