@@ -92,22 +92,51 @@ __global__ void __launch_bounds__(256) k_moments(const double* part, int ntiles,
   }
 }
 
-__global__ void k_ctl_coef(Ctl* ctl, const double* dred, int nval, const int* act, int j, int pass, int B) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= B || !act[b]) return;
-  Ctl& c = ctl[b];
-  for (int i = 0; i <= j; ++i) {
-    const double h = dred[(size_t)b * nval + i];
-    c.coef[i] = c.sigma[i] * c.sigma[i] * h;
-    c.hsum[i] = (pass ? c.hsum[i] : 0.0) + c.sigma[i] * h;
+// Deterministic block reduction of one entry's partials: red[v] = sum_blk part[v * nblk + blk] for v < nval
+// (wave w sums the values v = w, w + NW, ...; lanes stride over the partials).  1024 threads.
+constexpr int kCtlThreads = 1024;
+DBAR_D void reduce_entry(const double* __restrict__ part, int nval, int nblk, double* red) {
+  constexpr int NW = kCtlThreads / 64;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int v = wave; v < nval; v += NW) {
+    const double* p = part + (size_t)v * nblk;
+    double acc = 0.0;
+    for (int i = lane; i < nblk; i += 64) acc += p[i];
+    acc = wsum(acc);
+    if (lane == 0) red[v] = acc;
+  }
+  __syncthreads();
+}
+
+// Gram-Schmidt pass `pass` of step j: h_i = <v_i, w> from the partials, coef_i = sigma_i^2 h_i (the basis is kept
+// unnormalised, v_i / ||v_i|| = sigma_i v_i), hsum_i accumulates sigma_i h_i over the passes.  One block per entry.
+__global__ void __launch_bounds__(kCtlThreads) k_ctl_coef(Ctl* ctl, const double* part, int nval, int nblk,
+                                                          const int* act, int j, int pass) {
+  const int b = blockIdx.x;
+  if (!act[b]) return;
+  __shared__ double red[kMaxRestart + 2];
+  reduce_entry(part + (size_t)b * nval * nblk, nval, nblk, red);
+  if (threadIdx.x == 0) {
+    Ctl& c = ctl[b];
+    for (int i = 0; i <= j; ++i) {
+      const double h = red[i];
+      c.coef[i] = c.sigma[i] * c.sigma[i] * h;
+      c.hsum[i] = (pass ? c.hsum[i] : 0.0) + c.sigma[i] * h;
+    }
   }
 }
 
-__global__ void k_ctl_givens(Ctl* ctl, const double* nred, int* act, int j, int m, int B) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= B || !act[b]) return;
+// Column j of the Hessenberg matrix from hsum and beta = ||w_new|| (reduced from the update's partials), Givens
+// rotation, residual estimate; the entry leaves the cycle when the estimate meets its threshold.  One block per entry.
+__global__ void __launch_bounds__(kCtlThreads) k_ctl_givens(Ctl* ctl, const double* pnorm, int nblk, int* act, int j,
+                                                            int m) {
+  const int b = blockIdx.x;
+  if (!act[b]) return;
+  __shared__ double red[1];
+  reduce_entry(pnorm + (size_t)b * nblk, 1, nblk, red);
+  if (threadIdx.x != 0) return;
   Ctl& c = ctl[b];
-  const double beta = sqrt(fmax(nred[b], 0.0));
+  const double beta = sqrt(fmax(red[0], 0.0));
   const double sj = c.sigma[j];
   double* col = c.H + (size_t)j * (kMaxRestart + 1);
   for (int i = 0; i <= j; ++i) col[i] = sj * c.hsum[i];
@@ -654,8 +683,6 @@ int krylov_cycle(const Pipeline& P, Work& w, const BatchCfg& cfg, int it_budget,
   const size_t V_bs = n * (w.m + 1);
   Ctl* ctl = static_cast<Ctl*>(w.ctl.p);
   int* act = static_cast<int*>(w.act.p);
-  double* dred = static_cast<double*>(w.dred.p);
-  double* nred = static_cast<double*>(w.nred.p);
   double* part = static_cast<double*>(w.part_vec.p);
   double* pnorm = static_cast<double*>(w.part_norm.p);
   const int nvb = vec_blocks(n);
@@ -689,15 +716,14 @@ int krylov_cycle(const Pipeline& P, Work& w, const BatchCfg& cfg, int it_budget,
       va.w_bs = V_bs;
       va.part = part;
       va.want_self = 0;
-      if (pass == 0) {
-        launch_reduce(part, j + 1, line_tiles(w.N, false, sizeof(T) == 8), dred, B, act, s);
-      } else {
+      int nblk = line_tiles(w.N, false, sizeof(T) == 8);  // pass 0: partials of the operator's last kernel
+      if (pass > 0) {
         launch_dots<T>(va, s);
-        launch_reduce(part, j + 1, nvb, dred, B, act, s);
+        nblk = nvb;
       }
       {
         TimerScope ts(kStageControl, 0.0, B, nullptr, s);
-        hipLaunchKernelGGL(k_ctl_coef, dim3(ctl_blocks(B)), dim3(64), 0, s, ctl, dred, j + 1, act, j, pass, B);
+        hipLaunchKernelGGL(k_ctl_coef, dim3(B), dim3(kCtlThreads), 0, s, ctl, part, j + 1, nblk, act, j, pass);
       }
       va.coef = &ctl[0].coef[0];
       va.coef_bs = sizeof(Ctl) / sizeof(double);
@@ -705,9 +731,8 @@ int krylov_cycle(const Pipeline& P, Work& w, const BatchCfg& cfg, int it_budget,
       va.part = pnorm;
       launch_update<T>(va, s);
     }
-    launch_reduce(pnorm, 1, nvb, nred, B, act, s);
     TimerScope ts(kStageControl, 0.0, B, nullptr, s);
-    hipLaunchKernelGGL(k_ctl_givens, dim3(ctl_blocks(B)), dim3(64), 0, s, ctl, nred, act, j, w.m, B);
+    hipLaunchKernelGGL(k_ctl_givens, dim3(B), dim3(kCtlThreads), 0, s, ctl, pnorm, nvb, act, j, w.m);
   };
 
   bool graphs = cfg.use_graph && !timer_on();
@@ -824,7 +849,6 @@ int run_batch(const Pipeline& P, Work& w, const BatchCfg& cfg, hipStream_t s, st
   } else {
     launch_convert<double, double>(w.bvec.p, n, w.V.p, n * (w.m + 1), n, B, nullptr, 1.0, s);
   }
-  int first = 1;
   int total = 0;
   iters_out.assign(B, 0);
   while (true) {
@@ -836,7 +860,6 @@ int run_batch(const Pipeline& P, Work& w, const BatchCfg& cfg, hipStream_t s, st
     const double rel = mixed ? cfg.inner_tol : 0.0;
     const double abs_tol = mixed ? 0.3 * cfg.tol : 0.5 * cfg.tol;
     hipLaunchKernelGGL(k_ctl_start, dim3(ctl_blocks(B)), dim3(64), 0, s, ctl, nred, live, act, abs_tol, rel, nullptr, B);
-    first = 0;
     int ran;
     if (mixed) {
       ran = krylov_cycle<float>(P, w, cfg, cfg.max_iter - total, s);
