@@ -39,6 +39,8 @@ def parse():
     ap.add_argument("--headline", choices=["auto", "mixed", "fp64"], default="auto")
     ap.add_argument("--no-serving", action="store_true", help="skip the request-stream (p50/p99 latency) leg")
     ap.add_argument("--serving-requests", type=int, default=48)
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the N = 512 batched and N = 4096 mixed-precision context legs")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default column-tile widths (skip the library's tuner before the timed region)")
     ap.add_argument("--no-rows-f", action="store_true",
@@ -216,6 +218,44 @@ def iterated_leg(D, Qd, L: float, M: int, tol: float) -> dict:
     return out
 
 
+def configs_leg(D, W) -> dict:
+    """The other full-size workloads, one timed pass each after a warm-up: the batched N = 512 workload (all 1024 k
+    of the 32 x 32 grid, FP64, column tiles and batch tuned first) and the N = 4096 mixed-precision workload (64 k),
+    whose S is checked against the FP64 path for four sampled k."""
+    import torch
+    out = {}
+    w = W.workload("batched_n512")
+    tune = D.autotune(w.N, w.L, precision=D.DBAR_FP64, batch=64, M=w.M)
+    Qd = torch.from_numpy(w.Q).to("cuda:0")
+    D.solve_device(Qd, w.ks[:64], w.L, tol=w.tol, M=w.M, precision=D.DBAR_FP64, want_m=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, _, info = D.solve_device(Qd, w.ks, w.L, tol=w.tol, M=w.M, precision=D.DBAR_FP64)
+    torch.cuda.synchronize()
+    out["batched_n512"] = {"n_k": len(w.ks), "precision": "fp64", "solves_per_s": len(w.ks) / (time.perf_counter() - t0),
+                           "batch": tune["batch"], "fp64_tile_columns": tune["fp64"]["chosen_columns"],
+                           "all_converged": all(i.status == 0 for i in info),
+                           "mean_iters": float(np.mean([i.iters for i in info]))}
+    D.set_tile(w.N, D.DBAR_FP64, 0)
+    del Qd
+    w = W.workload("mixed_n4096")
+    Qd = torch.from_numpy(w.Q).to("cuda:0")
+    D.solve_device(Qd, w.ks[:4], w.L, tol=w.tol, M=w.M, precision=D.DBAR_MIXED, want_m=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    S, _, info = D.solve_device(Qd, w.ks, w.L, tol=w.tol, M=w.M, precision=D.DBAR_MIXED, want_m=False)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    sample = [0, 21, 42, 63]
+    S64, _, _ = D.solve_device(Qd, w.ks[sample], w.L, tol=w.tol, M=w.M, precision=D.DBAR_FP64, want_m=False)
+    err = max(rel_linf(S[j].cpu().numpy(), S64[i].cpu().numpy()) for i, j in enumerate(sample))
+    out["mixed_n4096"] = {"n_k": len(w.ks), "precision": "mixed", "solves_per_s": len(w.ks) / dt,
+                          "all_converged": all(i.status == 0 for i in info),
+                          "max_rel_residual": max(i.rel_residual for i in info),
+                          "err_S_vs_fp64_sampled": err, "sampled_k": sample}
+    return out
+
+
 def ds2_leg(D, W, N: int = 128, L: float = 3.2) -> dict:
     """DS II round trip of Section 6.2 (reconstruction table row N = 2^7, L = 3.2, M = 11; the paper's error is
     2.40e-13): r(k) for q0 = e^{-x^2-y^2} at every k of the xi grid, then q from r at every z of the x grid, FP64."""
@@ -376,6 +416,8 @@ def main():
     if not args.no_rows_f:
         result["iterated"] = iterated_leg(D, Qd, L, w.M, w.tol)
         result["ds2"] = ds2_leg(D, W)
+    if not args.no_configs:
+        result["other_configs"] = configs_leg(D, W)
 
     if not args.no_cpu_baseline:
         from threadpoolctl import threadpool_limits
