@@ -261,3 +261,17 @@ def test_default_batch_with_many_k():
     for j in (0, 41, 79):
         ref = O.solve(g, Q, ks[j], tol=1e-13)
         assert relerr(S[j], ref.S) < 1e-10, j
+
+
+@pytest.mark.parametrize("prec", [D.DBAR_FP64, D.DBAR_MIXED])
+def test_plain_method_at_k_zero(prec):
+    """k = 0 (e_k = 1: the operator K0 of Section 5.1) in a batch with nonzero k."""
+    N, L = 64, 3.0
+    g = O.make_grid(N, L)
+    Q = W.potential_gaussian_sum(N, L, seed=51)
+    ks = [0.0, 0.5 - 1.0j, 0.0 + 0.0j]
+    S, m, info = D.solve(Q, ks, L, tol=1e-12, batch=3, precision=prec)
+    for j, k in enumerate(ks):
+        ref = O.solve(g, Q, k, tol=1e-13)
+        assert info[j].status == 0 and relerr(S[j], ref.S) < 1e-10 and relerr(m[j], ref.m) < 1e-10, j
+    assert np.array_equal(S[0], S[2])
