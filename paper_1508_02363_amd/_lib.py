@@ -23,6 +23,8 @@ DBAR_MODE_BATCHED = 0
 DBAR_MODE_PLAIN = 1
 DBAR_METHOD_PLAIN = 0
 DBAR_METHOD_ITERATED = 1
+DBAR_SPACE_X = 0
+DBAR_SPACE_XI = 1
 
 # every symbol include/dbar.h declares
 EXPORTED = [
@@ -49,7 +51,7 @@ class Opts(ctypes.Structure):
     _fields_ = [("restart", ctypes.c_int32), ("max_iter", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("mode", ctypes.c_int32), ("batch", ctypes.c_int32), ("use_graph", ctypes.c_int32),
                 ("reorth", ctypes.c_int32), ("check_every", ctypes.c_int32), ("method", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("inner_tol", ctypes.c_double)]
+                ("space", ctypes.c_int32), ("inner_tol", ctypes.c_double)]
 
 
 class Info(ctypes.Structure):

@@ -20,6 +20,12 @@ enum class LineOp : int {
   ColsFwdPotential = 6,// out = FFT_cols(Q e_k)                                      (first pass of F(q_k))
   ColsFwdPlain = 7,   // out = FFT_cols(in)
   ColsInvPlain = 8,   // out = IFFT_cols(in)
+  // The operator on s = F^{-1} S (x-space form, three launches):
+  RowsFwdMoments = 9, // moments sum z^n s, sum conj(z) s of the input (x-space) -> part; out = FFT_rows(in)
+  ColsFwdRegularInv = 10, // S = cf phase FFT_cols(in); R = (S - G)/xi, R(0) = (-i/2) dt; out = IFFT_cols(phase ci R)
+  RowsInvTailEpilogue = 11, // r = IFFT_rows(in); h = r + sum d_n omega_n; out = alpha S + beta q_k conj(h) + gamma Y;
+                            // optional |out|^2 -> part and Gram-Schmidt products -> dot_part
+  RowsInvTail = 12,   // r = IFFT_rows(in); hout = r + sum d_n omega_n
 };
 
 struct LineArgs {
@@ -46,9 +52,9 @@ struct LineArgs {
   int M = 11;
   double alpha = 0.0, gamma = 0.0;
   c64 beta{0.0, 0.0};
-  int want_norm = 0;           // RowsFwdEpilogue: accumulate |out|^2 partials
+  int want_norm = 0;           // RowsFwdEpilogue, RowsInvTailEpilogue: accumulate |out|^2 partials
   int tile = 0;                // column stages: tile width variant (columns per tile = default << tile)
-  // RowsFwdEpilogue: Gram-Schmidt products Re<V_i, out> for i < dot_nv written as per-tile partials
+  // RowsFwdEpilogue, RowsInvTailEpilogue: Gram-Schmidt products Re<V_i, out> for i < dot_nv written as per-tile partials
   // dot_part[b][i][tile] (V_i of entry b at dotV + b * dotV_bs + i * N * N, the transform's precision); the last one,
   // V_{dot_nv - 1}, must be the epilogue's S (alpha != 0)
   const void* dotV = nullptr;  size_t dotV_bs = 0;

@@ -9,6 +9,13 @@
 //   ColsInvTailFwd  second pass of F^{-1} R, h = F^{-1} R + sum c_n W_n (equation S0Taylor), u = q_k conj(h),
 //                   first pass of F u  -- all in registers between the two column transforms
 //   RowsFwdEpilogue second pass of F u and A(S) = S + i F(u)
+//
+// The same operator on s = F^{-1} S (the form the Krylov solver iterates on: F is unitary up to a constant, so GMRES
+// takes the same steps, and the moments are sums over the x grid that need no transform) runs as three launches plus
+// the moment reduction:
+//   RowsFwdMoments      moments d_n = F(z^n s)(0), dt = F(conj(z) s)(0) of the input, first pass of F s
+//   ColsFwdRegularInv   second pass of F s (= S), R = (S - G)/xi, first pass of F^{-1} R
+//   RowsInvTailEpilogue second pass of F^{-1} R, h, and F^{-1} A(S) = s + i q_k conj(h)
 #pragma once
 
 #include "dbar_fft.h"
@@ -84,9 +91,34 @@ DBAR_D TT recip(TT r) {
   else return __builtin_amdgcn_rcpf(r);
 }
 
+// Coefficients c_k = prod_{j=1..k} (M+1)/(M+1+j) of F(u) = (M+1)! sum_k u^k/(M+1+k)! in powers of v = u/(M+1), and
+// the number of terms after which the rest is below half a rounding unit of F for every v < 1 (FP32 or FP64), for
+// the orders the tail is instantiated with (M = 11 and kMaxM).  Read from constant memory in a rolled loop: unrolled,
+// the compiler keeps every coefficient in a register.
+constexpr int kSerK32[2] = {25, 28}, kSerK64[2] = {40, 45};
+struct SeriesTables {
+  double d[2][45];
+  float f[2][28];
+};
+constexpr SeriesTables make_series() {
+  SeriesTables t{};
+  for (int w = 0; w < 2; ++w) {
+    const int M1 = (w == 0 ? 11 : kMaxM) + 1;
+    double c = 1.0;
+    for (int k = 0; k < 45; ++k) {
+      if (k > 0) c = c * (double)M1 / (double)(M1 + k);
+      t.d[w][k] = c;
+      if (k < 28) t.f[w][k] = (float)c;
+    }
+  }
+  return t;
+}
+static __constant__ SeriesTables kSeries = make_series();
+
 // sum_{n=0}^{M} d_n omega_n(z),  omega_n = i P(n+1, u) / z^{n+1},  u = |z|^2/4  (c_n W_n = d_n omega_n).
 // u <  M+1: omega_n = i E_n (conj(z)/4)^{n+1} with E_n = e^{-u} sum_k u^k/(n+1+k)!  (equation fourreg5a with the
-//           factor e^{-u}); E_M by its series, E_n = u E_{n+1} + e^{-u}/(n+1)! downwards (positive terms only).
+//           factor e^{-u}); E_M by its series (a fixed-length polynomial), E_n = u E_{n+1} + e^{-u}/(n+1)! downwards
+//           (positive terms only).
 // u >= M+1: omega_n = i (1 - e^{-u} sum_{k<=n} u^k/k!) / z^{n+1}  (equation fourreg5); no cancellation there.
 // TT is the arithmetic type: double in the FP64 operator, float in the FP32 one (whose data carry 24-bit mantissas).
 // MM is the Taylor order the loops are unrolled for: the order M itself (M = 11, the paper's choice), or kMaxM for any
@@ -105,16 +137,21 @@ DBAR_D cx<TT> tail_sum(TT x, TT y, const cx<TT> (&d)[kMaxM + 1]) {
     return mul_i(w * acc);
   }
   const TT eu = exp(-u);
-  const TT eps = sizeof(TT) == 8 ? TT(1e-17) : TT(3e-8);
   cx<TT> acc{TT(0), TT(0)};
   if (u < TT(MM + 1)) {
-    TT term = TT(kInvFact[MM + 1]), sum = term;
-    for (int k = 1; MM + 1 + k < kNInv; ++k) {
-      term *= u * inv_int<TT>(MM + 1 + k);
-      sum += term;
-      if (term < eps * sum) break;
-    }
-    TT E = eu * sum;
+    // E_M = e^{-u} F(u) / (M+1)!, F(u) = sum_k c_k v^k with v = u/(M+1) < 1, c_k = prod_{j<=k} (M+1)/(M+1+j):
+    // a fixed number of Horner steps (positive terms; the first omitted one is below half a rounding unit of F)
+    static_assert(MM == 11 || MM == kMaxM, "series tables for M = 11 and kMaxM");
+    constexpr int W = MM == 11 ? 0 : 1;
+    constexpr int K = sizeof(TT) == 8 ? kSerK64[W] : kSerK32[W];
+    const TT* c;
+    if constexpr (sizeof(TT) == 8) c = kSeries.d[W];
+    else c = kSeries.f[W];
+    const TT v = u * TT(1.0 / (MM + 1));
+    TT F = c[K - 1];
+#pragma unroll 1
+    for (int k = K - 2; k >= 0; --k) F = F * v + c[k];
+    TT E = eu * F * TT(kInvFact[MM + 1]);
     const cx<TT> zeta{TT(0.25) * x, TT(-0.25) * y};
     acc = E * d[MM];
 #pragma unroll
@@ -145,6 +182,12 @@ DBAR_D cx<TT> tail_sum(TT x, TT y, const cx<TT> (&d)[kMaxM + 1]) {
 // ------------------------------------------------------------------------------------------------------------
 // Block reduction of per-thread FP64 values into global partials dst[v * stride]
 // ------------------------------------------------------------------------------------------------------------
+DBAR_D double wsum64(double x) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+  return x;
+}
+
 template <int NT, int NV>
 DBAR_D void block_reduce_store(const double (&vals)[NV], double* __restrict__ dst, size_t stride, double* scratch) {
   __syncthreads();  // scratch aliases the transform's LDS
@@ -218,6 +261,10 @@ struct OpBase {
   template <int NT, class Acc> DBAR_D void finish(Acc&, int, int, int, double*) const {}
   // after the stores: dots over the values the stores left in the thread's registers (ops that define DOTS)
   static constexpr bool DOTS = false;
+  // the op accumulates over its loaded values before the first transform (loaded(acc, b, line, jt, v))
+  static constexpr bool LOADACC = false;
+  // ROLLED stores: > 1: the op's store_all stores the thread's elements GROUP at a time, else store one at a time
+  static constexpr int GROUP = 1;
   // per-block data read once at kernel start, before any store (ops that need it define PRE and a Pre type)
   static constexpr bool PRE = false;
   struct Pre {};
@@ -237,89 +284,100 @@ struct OpRowsInvScaled : OpBase<T, N> {
   DBAR_D void store(Acc&, int b, int row, int pos, cx<T> v) const { this->outp(b)[(size_t)row * N + pos] = v; }
 };
 
-// IFFT_cols(in) and accumulate sum z^n s (n <= M) and sum conj(z) s in FP64.  Along a column x is fixed, so each
-// thread accumulates mu_k = sum_y y^k s (real weights, k <= M) and forms its share of
-// d_n = sum_k C(n,k) x^{n-k} i^k mu_k and conj-moment x mu_0 - i mu_1 once at the end (the binomial terms exceed
-// |z|^n by at most 2^{n/2}, i.e. < 50x at n = 11: a few ulps of FP64).
-template <typename T, int N>
-struct OpColsInvMoments : OpBase<T, N> {
-  static constexpr int DIR1 = +1;
-  static constexpr bool TWO = false;
-  static constexpr bool ROLLED = true;
+// Moments sum z^n s (n <= M) and sum conj(z) s of x-space values s, reduced in FP64.  Along a line one coordinate
+// is fixed (x on a column, y on a row); each thread accumulates mu_k = sum t^k s over its elements (t the varying
+// coordinate: real weights, k <= M) and the line's share of d_n = sum_k C(n,k) (fixed part)^(n-k) (t part)^k is
+// formed once at the end: on a column d_n = sum_k C(n,k) x^{n-k} i^k mu_k, conj moment x mu_0 - i mu_1; on a row
+// d_n = sum_k C(n,k) (iy)^{n-k} mu_k, conj moment mu_1 - iy mu_0 (the binomial terms exceed |z|^n by at most
+// 2^{n/2}, i.e. < 50x at n = 11: a few ulps of FP64).
+template <typename T, int N, bool ALONG_X>
+struct MomentsBase : OpBase<T, N> {
   static constexpr int NV = 2 * kNMom;
   static constexpr int NMU = 2 * (kMaxM + 1);  // mu_0 .. mu_kMaxM (re, im)
-  // Per-thread column moments are accumulated in the transform's precision (16 elements per thread; the FP32
-  // operator's s carries FP32 rounding anyway, and the regularisation is exact for any G coefficients); every
-  // reduction beyond the thread and the binomial combination run in FP64.
+  // Per-thread moments are accumulated in the transform's precision (16 elements per thread; the FP32 operator's s
+  // carries FP32 rounding anyway, and the regularisation is exact for any G coefficients); every reduction beyond
+  // the thread and the binomial combination run in FP64.
   struct Acc {
-    T v[NMU];  // mu_k = sum_y y^k s over this thread's elements
-    double x;
-    int col;
+    T v[NMU];  // mu_k = sum t^k s over this thread's elements
   };
-  DBAR_D cx<T> load(int b, int col, int pos) const { return this->inp(b)[(size_t)pos * N + col]; }
-  DBAR_D void store(Acc& acc, int b, int col, int pos, cx<T> v) const {
-    const T y = xgrid_t<T, N>(pos, this->a.L);
-    acc.x = xgrid<N>(col, this->a.L);
-    acc.col = col;
+  // the fixed coordinate of line `line`
+  DBAR_D double fixed(int line) const { return xgrid<N>(line, this->a.L); }
+  // s at position pos of line `line` into this thread's mu_k
+  DBAR_D void add(Acc& acc, int b, int line, int pos, cx<T> v) const {
     cx<T> s = v;
-    // shifted regularisation: Taylor coefficients at xi = a are moments of s e^{-i a.x} = s e_k (ey here, ex below)
+    // shifted regularisation: Taylor coefficients at xi = a are moments of s e^{-i a.x} = s e_k (the varying
+    // coordinate's factor here, the fixed one's in combine_one)
     if (this->a.shv) {
       const size_t o = (size_t)b * this->a.e_bs + pos;
-      if constexpr (sizeof(T) == 8) s = s * this->a.ey[o];
-      else s = s * this->a.ey32[o];
+      if constexpr (sizeof(T) == 8) s = s * (ALONG_X ? this->a.ex[o] : this->a.ey[o]);
+      else s = s * (ALONG_X ? this->a.ex32[o] : this->a.ey32[o]);
     }
+    (void)line;
     // mu_0..mu_KK with KK fixed at compile time: the order M = 11 itself, else kMaxM (the extra mu_k are unused);
     // mu_1 is always needed (conj moment)
-    if (this->a.M == 11) accumulate<11>(acc, y, s);
-    else accumulate<kMaxM>(acc, y, s);
+    if (this->a.M == 11) accumulate<11>(acc, xgrid_t<T, N>(pos, this->a.L), s);
+    else accumulate<kMaxM>(acc, xgrid_t<T, N>(pos, this->a.L), s);
   }
   template <int KK>
-  DBAR_D static void accumulate(Acc& acc, T y, cx<T> s) {
-    T yp = T(1);
+  DBAR_D static void accumulate(Acc& acc, T t, cx<T> s) {
+    T tp = T(1);
 #pragma unroll
     for (int k = 0; k <= KK; ++k) {
-      acc.v[2 * k] += yp * s.re;
-      acc.v[2 * k + 1] += yp * s.im;
-      yp *= y;
+      acc.v[2 * k] += tp * s.re;
+      acc.v[2 * k + 1] += tp * s.im;
+      tp *= t;
     }
   }
-  // Moment q of one column from its mu_k: d_q = sum_{k<=q} C(q,k) x^{q-k} i^k mu_k for q <= M (0 for M < q <=
-  // kMaxM), and for q = kMaxM+1 the conj moment x mu_0 - i mu_1; with the shifted regularisation times the column
-  // factor e^{-2i k2 x}.  mu is (re, im) interleaved.
-  DBAR_D c64 combine_one(const double* mu, double x, int q, int b, int col) const {
+  // all of the thread's loaded values v[s] (position jt + s TPL) into its mu_k, the order's branch taken once
+  DBAR_D void add_loaded(Acc& acc, int b, int line, int jt, const cx<T>* v) const {
+    if (this->a.M == 11) add_all<11>(acc, b, jt, v);
+    else add_all<kMaxM>(acc, b, jt, v);
+    (void)line;
+  }
+  template <int KK>
+  DBAR_D void add_all(Acc& acc, int b, int jt, const cx<T>* v) const {
+    using G = LineGeom<N>;
+#pragma unroll
+    for (int s = 0; s < G::RMAX; ++s) {
+      const int pos = jt + s * G::TPL;
+      cx<T> sv = v[s];
+      if (this->a.shv) {
+        const size_t o = (size_t)b * this->a.e_bs + pos;
+        if constexpr (sizeof(T) == 8) sv = sv * (ALONG_X ? this->a.ex[o] : this->a.ey[o]);
+        else sv = sv * (ALONG_X ? this->a.ex32[o] : this->a.ey32[o]);
+      }
+      accumulate<KK>(acc, xgrid_t<T, N>(pos, this->a.L), sv);
+    }
+  }
+  // Moment q of one line from its mu_k (q <= M; 0 for M < q <= kMaxM; q = kMaxM+1: the conj moment), c its fixed
+  // coordinate; with the shifted regularisation times the line's factor of e_k.  mu is (re, im) interleaved.
+  DBAR_D c64 combine_one(const double* mu, double c, int q, int b, int line) const {
     double re = 0.0, im = 0.0;
     if (q == kMaxM + 1) {
-      re = x * mu[0] + mu[3];
-      im = x * mu[1] - mu[2];
+      if constexpr (ALONG_X) {  // mu_1 - i y mu_0
+        re = mu[2] + c * mu[1];
+        im = mu[3] - c * mu[0];
+      } else {  // x mu_0 - i mu_1
+        re = c * mu[0] + mu[3];
+        im = c * mu[1] - mu[2];
+      }
     } else if (q <= this->a.M) {
-      double xpow = 1.0;  // x^{q-k} for k = q, q-1, ..., 0
+      double cpow = 1.0;  // c^{q-k} for k = q, q-1, ..., 0
       for (int k = q; k >= 0; --k) {
-        const double c = kBinom.v[q][k] * xpow;
+        const double w = kBinom.v[q][k] * cpow;
         const double mr = mu[2 * k], mi = mu[2 * k + 1];
-        switch (k & 3) {  // i^k mu_k
-          case 0: re += c * mr; im += c * mi; break;
-          case 1: re -= c * mi; im += c * mr; break;
-          case 2: re -= c * mr; im -= c * mi; break;
-          default: re += c * mi; im -= c * mr; break;
+        switch ((ALONG_X ? q - k : k) & 3) {  // times i^k (column) or i^{q-k} (row)
+          case 0: re += w * mr; im += w * mi; break;
+          case 1: re -= w * mi; im += w * mr; break;
+          case 2: re -= w * mr; im -= w * mi; break;
+          default: re += w * mi; im -= w * mr; break;
         }
-        xpow *= x;
+        cpow *= c;
       }
     }
     c64 d{re, im};
-    if (this->a.shv) d = this->a.ex[(size_t)b * this->a.e_bs + col] * d;
+    if (this->a.shv) d = (ALONG_X ? this->a.ey : this->a.ex)[(size_t)b * this->a.e_bs + line] * d;
     return d;
-  }
-  // all moments of one thread's own partial sums (small tiles)
-  DBAR_D void combine(double* v, double x, int b, int col) const {
-    double mu[2 * (kMaxM + 1)];
-#pragma unroll
-    for (int q = 0; q < 2 * (kMaxM + 1); ++q) mu[q] = v[q];
-#pragma unroll 1
-    for (int q = 0; q < kNMom; ++q) {
-      const c64 d = combine_one(mu, x, q, b, col);
-      v[2 * q] = d.re;
-      v[2 * q + 1] = d.im;
-    }
   }
 
   template <int NT>
@@ -327,103 +385,165 @@ struct OpColsInvMoments : OpBase<T, N> {
     if (this->a.M == 11) finish_kk<NT, 11>(acc, b, tile, ntiles, scratch);
     else finish_kk<NT, kMaxM>(acc, b, tile, ntiles, scratch);
   }
+  // Block reduction: 1) each line's mu_k summed over its threads within a wave by shuffles (a column tile
+  // interleaves its lines, so a column's lanes differ by multiples of LN; a row's lanes are contiguous), parked in
+  // LDS per reduction group; 2) summed over the line's groups (one thread per line and value); 3) combined into the
+  // moments (one thread per line and moment); 4) the tile's partials: sum over its lines.
   template <int NT, int KK>
   DBAR_D void finish_kk(Acc& acc, int b, int tile, int ntiles, double* scratch) const {
     constexpr int NU = 2 * (KK + 1);  // mu values in use
     double* dst = this->a.part + (size_t)b * NV * ntiles + tile;
     constexpr int TPL = LineGeom<N>::TPL;
-    constexpr int LN = NT / TPL;  // columns per tile; thread tid serves column tid % LN
-    if constexpr (NT >= 64 && LN < 64) {
-      // 1) sum each column's mu_k over its threads: within a wave, lanes that differ by multiples of LN
-      __syncthreads();  // scratch aliases the transform's LDS
-      const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-      constexpr int NW = NT / 64;
+    constexpr int LN = NT / TPL;  // lines per tile
+    // reduction groups: runs of GS consecutive lanes on a row tile; (wave, column) pairs on a column tile of fewer
+    // than 64 columns (SHFL), else single threads
+    constexpr int GS = ALONG_X ? (TPL < 64 ? TPL : 64) : 1;
+    constexpr bool SHFL = !ALONG_X && NT >= 64 && LN < 64;
+    constexpr int NG = ALONG_X ? NT / GS : SHFL ? (NT / 64) * LN : NT;
+    __syncthreads();  // scratch aliases the transform's LDS
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
-      for (int q = 0; q < NU; ++q) {
-        T x = acc.v[q];
+    for (int q = 0; q < NU; ++q) {
+      T x = acc.v[q];
+      if constexpr (ALONG_X) {
+#pragma unroll
+        for (int off = GS / 2; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
+      } else if constexpr (SHFL) {
 #pragma unroll
         for (int off = 32; off >= LN; off >>= 1) x += __shfl_xor(x, off, 64);
-        acc.v[q] = x;
       }
-      double* sc = scratch;                    // [NW][LN][NMU]
-      double* colv = scratch + NW * LN * NMU;  // [LN][NV]
-      if (lane < LN) {
-#pragma unroll
-        for (int q = 0; q < NMU; ++q) sc[(wave * LN + lane) * NMU + q] = q < NU ? static_cast<double>(acc.v[q]) : 0.0;
-      }
-      __syncthreads();
-      // 2) each column's mu_k summed over its waves (one thread per column and value) ...
-      double* mus = colv + LN * NV;  // [LN][NMU]
-      for (int t = threadIdx.x; t < LN * NMU; t += NT) {
-        const int c = t / NMU, q = t % NMU;
-        double v = 0.0;
-        for (int w = 0; w < NW; ++w) v += sc[(w * LN + c) * NMU + q];
-        mus[c * NMU + q] = v;
-      }
-      __syncthreads();
-      // ... and combined into the moments (one thread per column and moment)
-      for (int t = threadIdx.x; t < LN * kNMom; t += NT) {
-        const int c = t / kNMom, q = t % kNMom;
-        const int col = tile * LN + c;
-        const c64 d = combine_one(mus + c * NMU, xgrid<N>(col, this->a.L), q, b, col);
-        colv[c * NV + 2 * q] = d.re;
-        colv[c * NV + 2 * q + 1] = d.im;
-      }
-      __syncthreads();
-      // 3) the tile's partials: sum over its columns
-      for (int q = threadIdx.x; q < NV; q += NT) {
-        double t = 0.0;
-        for (int c = 0; c < LN; ++c) t += colv[c * NV + q];
-        dst[(size_t)q * ntiles] = t;
-      }
+      acc.v[q] = x;
+    }
+    double* sc = scratch;                 // [NG][NMU]
+    double* colv = scratch + NG * NMU;    // [LN][NV]
+    double* mus = colv + LN * NV;         // [LN][NMU]
+    int g = -1;
+    if constexpr (ALONG_X) {
+      if (threadIdx.x % GS == 0) g = threadIdx.x / GS;
+    } else if constexpr (SHFL) {
+      if (lane < LN) g = wave * LN + lane;
     } else {
-      double v[NV];
+      g = threadIdx.x;  // thread t serves column t % LN
+    }
+    if (g >= 0) {
 #pragma unroll
-      for (int q = 0; q < NV; ++q) v[q] = q < NU ? static_cast<double>(acc.v[q]) : 0.0;
-      combine(v, acc.x, b, acc.col);
-      block_reduce_store<NT, NV>(v, dst, ntiles, scratch);
+      for (int q = 0; q < NMU; ++q) sc[g * NMU + q] = q < NU ? static_cast<double>(acc.v[q]) : 0.0;
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < LN * NMU; t += NT) {
+      const int c = t / NMU, q = t % NMU;
+      double v = 0.0;
+      if constexpr (ALONG_X) {
+        constexpr int GPL = TPL / GS;  // groups per row
+        for (int k = 0; k < GPL; ++k) v += sc[(c * GPL + k) * NMU + q];
+      } else if constexpr (SHFL) {
+        for (int w = 0; w < NT / 64; ++w) v += sc[(w * LN + c) * NMU + q];
+      } else {
+        for (int k = c; k < NT; k += LN) v += sc[k * NMU + q];
+      }
+      mus[c * NMU + q] = v;
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < LN * kNMom; t += NT) {
+      const int c = t / kNMom, q = t % kNMom;
+      const int line = tile * LN + c;
+      const c64 d = combine_one(mus + c * NMU, fixed(line), q, b, line);
+      colv[c * NV + 2 * q] = d.re;
+      colv[c * NV + 2 * q + 1] = d.im;
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < NV; q += NT) {
+      double t = 0.0;
+      for (int c = 0; c < LN; ++c) t += colv[c * NV + q];
+      dst[(size_t)q * ntiles] = t;
     }
   }
 };
 
+// IFFT_cols(in) and the moments of the result (second pass of F^{-1} S; nothing is stored)
+template <typename T, int N>
+struct OpColsInvMoments : MomentsBase<T, N, false> {
+  static constexpr int DIR1 = +1;
+  static constexpr bool TWO = false;
+  static constexpr bool ROLLED = true;
+  using Acc = typename MomentsBase<T, N, false>::Acc;
+  DBAR_D cx<T> load(int b, int col, int pos) const { return this->inp(b)[(size_t)pos * N + col]; }
+  DBAR_D void store(Acc& acc, int b, int col, int pos, cx<T> v) const { this->add(acc, b, col, pos, v); }
+};
+
+// x-space operator, first launch: the moments of the input s as it is read, then out = FFT_rows(s) (first pass of
+// F s)
+template <typename T, int N>
+struct OpRowsFwdMoments : MomentsBase<T, N, true> {
+  static constexpr int DIR1 = -1;
+  static constexpr bool TWO = false;
+  static constexpr bool LOADACC = true;
+  using Acc = typename MomentsBase<T, N, true>::Acc;
+  DBAR_D cx<T> load(int b, int row, int pos) const { return this->inp(b)[(size_t)row * N + pos]; }
+  DBAR_D void loaded(Acc& acc, int b, int row, int jt, const cx<T>* v) const { this->add_loaded(acc, b, row, jt, v); }
+  DBAR_D void store(Acc&, int b, int row, int pos, cx<T> v) const { this->outp(b)[(size_t)row * N + pos] = v; }
+};
+
 // R = (S - G)/xi (R(0) from coefG slot kMaxM+1), then out = IFFT_rows(phase * ci * R)
+// phase * ci * (S - G)/xi at (row, pos) of entry b, S = sv there (R(0) = coefG slot kMaxM+1 at xi = a)
+template <typename T, int N>
+DBAR_D cx<T> regularised(const LineArgs& a, int b, int row, int pos, cx<T> sv) {
+  const c64* __restrict__ c = a.coefG + (size_t)b * kNMom;
+  // xi - a with a = 2i conj(k) on the grid (not reduced modulo the period: the quotient only jumps at the edge),
+  // as integer wave numbers: L^2 |xi - a|^2 = m1^2 + m2^2 exactly
+  const int o1 = a.shv ? a.shv[2 * b] : 0, o2 = a.shv ? a.shv[2 * b + 1] : 0;
+  const int m1 = wavenum(pos, N) - o1, m2 = wavenum(row, N) - o2;
+  const int q = m1 * m1 + m2 * m2;
+  const double f = ((row + pos) & 1) ? -a.ci : a.ci;
+  if (q == 0) return cvt<T>(f * c[kMaxM + 1]);
+  const double invL = 1.0 / a.L;
+  // G in FP64 (conj(xi)^n overflows FP32 for |xi|^n > 3e38), only where e^{-|xi|^2} has not underflowed
+  if (static_cast<float>(q) < static_cast<float>(740.0 * a.L * a.L)) {
+    const double xi1 = m1 * invL, xi2 = m2 * invL;
+    const c64 xib{xi1, -xi2};
+    const int M = a.M;
+    c64 g = c[M];
+    for (int n = M - 1; n >= 0; --n) g = c[n] + xib * g;
+    sv = cvt<T>(cvt<double>(sv) - exp(-(xi1 * xi1 + xi2 * xi2)) * g);
+  }
+  // (S - G) / xi in the transform's precision
+  if constexpr (sizeof(T) == 8) {
+    const double t1 = m1 * invL, t2 = m2 * invL, ir2 = f / (t1 * t1 + t2 * t2);
+    return cx<T>{(sv.re * t1 + sv.im * t2) * ir2, (sv.im * t1 - sv.re * t2) * ir2};
+  } else {
+    const float il = static_cast<float>(invL);
+    const float t1 = static_cast<float>(m1) * il, t2 = static_cast<float>(m2) * il;
+    const float ir2 = static_cast<float>(f) * recip(t1 * t1 + t2 * t2);
+    return cx<T>{(sv.re * t1 + sv.im * t2) * ir2, (sv.im * t1 - sv.re * t2) * ir2};
+  }
+}
+
 template <typename T, int N>
 struct OpRowsInvRegular : OpBase<T, N> {
   static constexpr int DIR1 = +1;
   static constexpr bool TWO = false;
   using Acc = NoAcc;
   DBAR_D cx<T> load(int b, int row, int pos) const {
-    const c64* __restrict__ c = this->a.coefG + (size_t)b * kNMom;
-    // xi - a with a = 2i conj(k) on the grid (not reduced modulo the period: the quotient only jumps at the edge),
-    // as integer wave numbers: L^2 |xi - a|^2 = m1^2 + m2^2 exactly
-    const int o1 = this->a.shv ? this->a.shv[2 * b] : 0, o2 = this->a.shv ? this->a.shv[2 * b + 1] : 0;
-    const int m1 = wavenum(pos, N) - o1, m2 = wavenum(row, N) - o2;
-    const int q = m1 * m1 + m2 * m2;
-    const double f = ((row + pos) & 1) ? -this->a.ci : this->a.ci;
-    if (q == 0) return cvt<T>(f * c[kMaxM + 1]);
-    cx<T> sv = this->inp(b)[(size_t)row * N + pos];
-    const double invL = 1.0 / this->a.L;
-    // G in FP64 (conj(xi)^n overflows FP32 for |xi|^n > 3e38), only where e^{-|xi|^2} has not underflowed
-    if (static_cast<float>(q) < static_cast<float>(740.0 * this->a.L * this->a.L)) {
-      const double xi1 = m1 * invL, xi2 = m2 * invL;
-      const c64 xib{xi1, -xi2};
-      const int M = this->a.M;
-      c64 g = c[M];
-      for (int n = M - 1; n >= 0; --n) g = c[n] + xib * g;
-      sv = cvt<T>(cvt<double>(sv) - exp(-(xi1 * xi1 + xi2 * xi2)) * g);
-    }
-    // (S - G) / xi in the transform's precision
-    if constexpr (sizeof(T) == 8) {
-      const double t1 = m1 * invL, t2 = m2 * invL, ir2 = f / (t1 * t1 + t2 * t2);
-      return cx<T>{(sv.re * t1 + sv.im * t2) * ir2, (sv.im * t1 - sv.re * t2) * ir2};
-    } else {
-      const float il = static_cast<float>(invL);
-      const float t1 = static_cast<float>(m1) * il, t2 = static_cast<float>(m2) * il;
-      const float ir2 = static_cast<float>(f) * recip(t1 * t1 + t2 * t2);
-      return cx<T>{(sv.re * t1 + sv.im * t2) * ir2, (sv.im * t1 - sv.re * t2) * ir2};
-    }
+    return regularised<T, N>(this->a, b, row, pos, this->inp(b)[(size_t)row * N + pos]);
   }
   DBAR_D void store(Acc&, int b, int row, int pos, cx<T> v) const { this->outp(b)[(size_t)row * N + pos] = v; }
+};
+
+// x-space operator, second launch: S = cf phase FFT_cols(in) (the second pass of F s), R = (S - G)/xi, then
+// out = IFFT_cols(phase ci R), between the two column transforms (rolled through LDS: the FP64 G terms)
+template <typename T, int N>
+struct OpColsFwdRegInv : OpBase<T, N> {
+  static constexpr int DIR1 = -1;
+  static constexpr bool TWO = true;
+  static constexpr bool ROLLED = true;
+  using Acc = NoAcc;
+  DBAR_D cx<T> load(int b, int col, int pos) const { return this->inp(b)[(size_t)pos * N + col]; }
+  template <class A>
+  DBAR_D void mid(int b, int col, int pos, cx<T>& v) const {
+    const T f = static_cast<T>(((col + pos) & 1) ? -this->a.cf : this->a.cf);
+    v = regularised<T, N>(this->a, b, pos, col, f * v);  // row = xi2 index (pos), position = xi1 index (col)
+  }
+  DBAR_D void store(Acc&, int b, int col, int pos, cx<T> v) const { this->outp(b)[(size_t)pos * N + col] = v; }
 };
 
 // r = IFFT_cols(in); h = r + tail; [hout = h]; u = q_k conj(h); out = FFT_cols(u)   (TAILONLY: stop after hout)
@@ -544,6 +664,151 @@ struct OpRowsFwdEpilogue : OpBase<T, N> {
   }
 };
 
+// x-space operator, third launch: r = IFFT_rows(in) (second pass of F^{-1} R), h = r + sum d_n omega_n, and the
+// x-space form of A: out = alpha s + beta q_k conj(h) + gamma Y (F^{-1} of S + i F(q_k conj(h)) is s + i q_k conj(h));
+// optional |out|^2 partials and the products Re<V_i, out> of the first Gram-Schmidt pass.  TAILONLY: hout = h.
+// Rows keep every global access of the epilogue and the products contiguous across a wave.
+template <typename T, int N, bool TAILONLY>
+struct OpRowsInvTailEpi : OpColsInvTail<T, N, false> {
+  static constexpr int DIR1 = +1;
+  static constexpr bool TWO = false;
+  static constexpr bool ROLLED = true;
+  static constexpr bool DOTS = !TAILONLY;
+  using Pre = typename OpColsInvTail<T, N, false>::Pre;
+  struct Acc {
+    double v[1];
+    double sdot;  // Re<S, out> over this thread's elements (S is the last vector of the fused products)
+  };
+  DBAR_D cx<T> load(int b, int row, int pos) const { return this->inp(b)[(size_t)row * N + pos]; }
+  // The stores run GROUP elements at a time: the group's global reads (q, the x factor of e_k, S, Y) are issued
+  // together ahead of its tails.  The LDS slot of each element (the row transform's output r) is replaced by the
+  // stored value, for the Gram-Schmidt products.
+  static constexpr int GROUP = LineGeom<N>::RMAX < 4 ? LineGeom<N>::RMAX : 4;
+  struct GroupIn {
+    cx<T> q[GROUP], s[GROUP], y[GROUP], ex[GROUP];
+  };
+  // the group's q (times the x factor of e_k on the plain operator), S and Y
+  DBAR_D void group_load(GroupIn& g, int b, int row, int jt, int s0) const {
+    using G = LineGeom<N>;
+    const LineArgs& a = this->a;
+    const size_t base = (size_t)row * N;
+    const cx<T>* Qb = static_cast<const cx<T>*>(a.Q) + (size_t)b * a.Q_bs + base;
+    const cx<T>* Sb = static_cast<const cx<T>*>(a.S) + (size_t)b * a.S_bs + base;
+    const cx<T>* Yb = static_cast<const cx<T>*>(a.Y) + (size_t)b * a.Y_bs + base;
+    const size_t eo = (size_t)b * a.e_bs;
+#pragma unroll
+    for (int u = 0; u < GROUP; ++u) {
+      const int pos = jt + (s0 + u) * G::TPL;
+      g.q[u] = Qb[pos];
+      g.s[u] = a.alpha != 0.0 ? Sb[pos] : cx<T>{T(0), T(0)};
+      g.y[u] = a.gamma != 0.0 ? Yb[pos] : cx<T>{T(0), T(0)};
+      if (a.shv) g.ex[u] = cx<T>{T(1), T(0)};
+      else if constexpr (sizeof(T) == 8) g.ex[u] = a.ex[eo + pos];
+      else g.ex[u] = a.ex32[eo + pos];
+    }
+  }
+  template <int LS>
+  DBAR_D void store_all(Acc& acc, int b, int row, int jt, cx<T>* my, const Pre& p) const {
+    using G = LineGeom<N>;
+    static_assert(G::RMAX % GROUP == 0, "whole groups");
+    const LineArgs& a = this->a;
+    const size_t base = (size_t)row * N;
+    if constexpr (TAILONLY) {
+      cx<T>* hb = static_cast<cx<T>*>(a.hout) + (size_t)b * a.hout_bs + base;
+#pragma unroll 1
+      for (int s = 0; s < G::RMAX; ++s) {
+        const int pos = jt + s * G::TPL;
+        hb[pos] = this->h_at(b, pos, row, my[G::padded(pos) * LS], p);
+      }
+    } else {
+      // the y factor of e_k is the row's (1 with the shifted regularisation, where q stands alone)
+      cx<T> ey{T(1), T(0)};
+      if (!a.shv) {
+        if constexpr (sizeof(T) == 8) ey = a.ey[(size_t)b * a.e_bs + row];
+        else ey = a.ey32[(size_t)b * a.e_bs + row];
+      }
+#pragma unroll 1
+      for (int s0 = 0; s0 < G::RMAX; s0 += GROUP) {
+        GroupIn cur;
+        group_load(cur, b, row, jt, s0);
+#pragma unroll
+        for (int u = 0; u < GROUP; ++u) {
+          const int pos = jt + (s0 + u) * G::TPL;
+          cx<T>& slot = my[G::padded(pos) * LS];
+          const cx<T> h = this->h_at(b, pos, row, slot, p);  // x index pos, y index row
+          const cx<T> w = (cur.q[u] * (cur.ex[u] * ey)) * conj(h);
+          cx<T> ot;
+          if constexpr (sizeof(T) == 8) {
+            ot = a.beta * w + a.alpha * cur.s[u] + a.gamma * cur.y[u];
+          } else {  // the FP32 operator's result is FP32: form it in FP32
+            ot = cvt<T>(a.beta) * w + static_cast<T>(a.alpha) * cur.s[u] + static_cast<T>(a.gamma) * cur.y[u];
+          }
+          this->outp(b)[base + pos] = ot;
+          slot = ot;
+          const c64 od = cvt<double>(ot), sd = cvt<double>(cur.s[u]);
+          acc.v[0] += norm2(od);
+          acc.sdot += sd.re * od.re + sd.im * od.im;
+        }
+      }
+    }
+  }
+  template <int NT>
+  DBAR_D void finish(Acc& acc, int b, int tile, int ntiles, double* scratch) const {
+    if (TAILONLY || !this->a.want_norm) return;
+    block_reduce_store<NT, 1>(acc.v, this->a.part + (size_t)b * ntiles + tile, 0, scratch);
+  }
+  // Re<V_i, out> over this tile for i < dot_nv (FP64 accumulation, the order fixed); V_{dot_nv - 1} is S, whose
+  // products the stores accumulated.  Each wave reduces its products by shuffles and parks them in LDS; one barrier
+  // then serves all of them (the waves read their next V_i while others still compute).
+  template <int NT>
+  DBAR_D void dots(const Acc& acc, const cx<T>* v, int b, int row, int jt, int tile, int ntiles,
+                   double* scratch) const {
+    using G = LineGeom<N>;
+    const LineArgs& a = this->a;
+    const int nv = a.dot_nv;
+    if (nv <= 0) return;
+    const cx<T>* V = static_cast<const cx<T>*>(a.dotV) + (size_t)b * a.dotV_bs + (size_t)row * N;
+    double* dst = a.dot_part + (size_t)b * nv * ntiles + tile;
+    auto partial = [&](int i) {
+      const cx<T>* Vi = V + (size_t)i * N * N;
+      double p4[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int s = 0; s < G::RMAX; ++s) {
+        const c64 y = cvt<double>(Vi[jt + s * G::TPL]);
+        const c64 w = cvt<double>(v[s]);
+        p4[s & 3] += y.re * w.re + y.im * w.im;
+      }
+      return (p4[0] + p4[1]) + (p4[2] + p4[3]);
+    };
+    if constexpr (NT >= 64) {
+      constexpr int NW = NT / 64;
+      const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+      __syncthreads();  // scratch aliases the LDS the stores and the norm reduction used
+      double x = wsum64(acc.sdot);
+      if (lane == 0) scratch[(nv - 1) * NW + wave] = x;
+#pragma unroll 1
+      for (int i = 0; i < nv - 1; ++i) {
+        x = wsum64(partial(i));
+        if (lane == 0) scratch[i * NW + wave] = x;
+      }
+      __syncthreads();
+      for (int i = threadIdx.x; i < nv; i += NT) {
+        double t = 0.0;
+        for (int q = 0; q < NW; ++q) t += scratch[i * NW + q];
+        dst[(size_t)i * ntiles] = t;
+      }
+    } else {
+      const double last[1] = {acc.sdot};
+      block_reduce_store<NT, 1>(last, dst + (size_t)(nv - 1) * ntiles, 0, scratch);
+#pragma unroll 1
+      for (int i = 0; i < nv - 1; ++i) {
+        const double val[1] = {partial(i)};
+        block_reduce_store<NT, 1>(val, dst + (size_t)i * ntiles, 0, scratch);
+      }
+    }
+  }
+};
+
 // out = FFT_cols(Q e_k)
 template <typename T, int N>
 struct OpColsFwdPotential : OpBase<T, N> {
@@ -617,9 +882,11 @@ __global__ void __launch_bounds__(LINES * LineGeom<N>::TPL, MinWaves<LINES * Lin
   const cx<T>* tw = static_cast<const cx<T>*>(op.a.tw);
   if constexpr (COLS) fill_pass1_table<T, N>(lds_t1, tw, tid, NT);
 
+  typename Op::Acc acc{};
   cx<T> v[G::RMAX];
 #pragma unroll
   for (int s = 0; s < G::RMAX; ++s) v[s] = op.load(b, line, jt + s * G::TPL);
+  if constexpr (Op::LOADACC) op.loaded(acc, b, line, jt, v);
   // LDS: a row tile keeps each line contiguous (one line per wave or less); a column tile interleaves its lines
   // element by element, so that the lanes of a wave (consecutive columns) hit consecutive banks
   constexpr int LS = COLS ? LINES : 1;
@@ -651,15 +918,24 @@ __global__ void __launch_bounds__(LINES * LineGeom<N>::TPL, MinWaves<LINES * Lin
     }
     line_fft<T, N, -Op::DIR1, LS, COLS>(v, jt, my, tw, lds_t1);
   }
-  typename Op::Acc acc{};
   if constexpr (Op::ROLLED && !Op::TWO) {
 #pragma unroll
     for (int s = 0; s < G::RMAX; ++s) my[G::padded(jt + s * G::TPL) * LS] = v[s];
+    if constexpr (Op::GROUP > 1) {
+      op.template store_all<LS>(acc, b, line, jt, my, pre);
+    } else {
 #pragma unroll 1
-    for (int s = 0; s < G::RMAX; ++s) {
-      const int pos = jt + s * G::TPL;
-      if constexpr (Op::PRE) op.store(acc, b, line, pos, my[G::padded(pos) * LS], pre);
-      else op.store(acc, b, line, pos, my[G::padded(pos) * LS]);
+      for (int s = 0; s < G::RMAX; ++s) {
+        const int pos = jt + s * G::TPL;
+        if constexpr (Op::PRE) op.store(acc, b, line, pos, my[G::padded(pos) * LS], pre);
+        else op.store(acc, b, line, pos, my[G::padded(pos) * LS]);
+      }
+    }
+    // the stored values (the stores may replace them) back to registers for the products below, before the
+    // reductions reuse the LDS (the thread's own positions: no barrier)
+    if constexpr (Op::DOTS) {
+#pragma unroll
+      for (int s = 0; s < G::RMAX; ++s) v[s] = my[G::padded(jt + s * G::TPL) * LS];
     }
   } else {
 #pragma unroll
@@ -669,8 +945,7 @@ __global__ void __launch_bounds__(LINES * LineGeom<N>::TPL, MinWaves<LINES * Lin
     }
   }
   op.template finish<NT>(acc, b, tile, gridDim.x, reinterpret_cast<double*>(lds));
-  if constexpr (Op::DOTS && !COLS)
-    op.template dots<NT>(acc, v, b, line, jt, tile, gridDim.x, reinterpret_cast<double*>(lds));
+  if constexpr (Op::DOTS) op.template dots<NT>(acc, v, b, line, jt, tile, gridDim.x, reinterpret_cast<double*>(lds));
 }
 
 template <typename T, int N, bool COLS, class Op, int V = 0>
@@ -707,6 +982,10 @@ void launch_lines(LineOp op, const LineArgs& a, hipStream_t s) {
     case LineOp::ColsFwdPotential: launch_cols<T, N, OpColsFwdPotential<T, N>>(a, s); break;
     case LineOp::ColsFwdPlain: launch_cols<T, N, OpColsPlain<T, N, -1>>(a, s); break;
     case LineOp::ColsInvPlain: launch_cols<T, N, OpColsPlain<T, N, +1>>(a, s); break;
+    case LineOp::RowsFwdMoments: launch_op<T, N, false, OpRowsFwdMoments<T, N>>(a, s); break;
+    case LineOp::ColsFwdRegularInv: launch_cols<T, N, OpColsFwdRegInv<T, N>>(a, s); break;
+    case LineOp::RowsInvTailEpilogue: launch_op<T, N, false, OpRowsInvTailEpi<T, N, false>>(a, s); break;
+    case LineOp::RowsInvTail: launch_op<T, N, false, OpRowsInvTailEpi<T, N, true>>(a, s); break;
   }
 }
 

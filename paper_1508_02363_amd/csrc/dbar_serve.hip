@@ -184,7 +184,7 @@ static void worker(dbar_session* s, SClass* cp) {
       (void)hipMemcpyAsync(c.tolv.p, c.h_tol.data(), c.cap * sizeof(double), hipMemcpyHostToDevice, c.stream);
       if (mixed) launch_convert<float, double>(w.Q64.p, n, w.Q32.p, n, n, c.cap, nm, 1.0, c.stream);
       c.P.rhs(w.Q64.p, n, w.T64.p, static_cast<c64*>(w.bvec.p), c.cap, nm, 0u, c.stream);
-      launch_reduce(static_cast<double*>(w.part_vec.p), 1, line_tiles(c.N, false, true),
+      launch_reduce(static_cast<double*>(w.part_vec.p), 1, c.P.rhs_blocks(),
                     static_cast<double*>(w.nred.p), c.cap, nm, c.stream);
       launch_ctl_check(w, 0.0, 1, nm, static_cast<const double*>(c.tolv.p), c.stream);
       if (mixed)

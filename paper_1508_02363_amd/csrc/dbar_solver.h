@@ -89,6 +89,7 @@ struct BatchCfg {
   int reorth = 1;
   int check_every = 4;
   double inner_tol = 1e-5;
+  int xspace = 0;  // the plain method iterates on s = F^{-1} S
 };
 
 // Device workspace for a batch of B entries on an N x N grid with restart m.
@@ -139,8 +140,14 @@ struct Pipeline {
   c32* dmom32 = nullptr;
   double* part_mom = nullptr;
   double* part_vec = nullptr;
+  // apply / rhs act on s = F^{-1} S (the plain method's x-space form) instead of S
+  bool xspace = false;
 
   LineArgs base(int B, const int* act, unsigned flags) const;
+  // tiles (blocks per entry) of the launch whose partials (norms, Gram-Schmidt products) apply leaves
+  int apply_tiles(bool fp64) const;
+  // blocks per entry of rhs's norm partials
+  int rhs_blocks() const;
   template <typename T>
   void moments(const void* in, size_t in_bs, void* Tbuf, int B, const int* act, unsigned flags, hipStream_t s) const;
   template <typename T>
@@ -168,6 +175,14 @@ struct Pipeline {
             hipStream_t s, unsigned flags = 0u, bool phase_out = false, bool accumulate = false) const;
   template <typename T>
   void transform(bool inverse, const void* in, void* out, void* Tbuf, hipStream_t s) const;
+  // x-space operator: F^{-1} A(F s) = alpha s + beta i q_k conj(h(F s)) + gamma Y (three line launches)
+  template <typename T>
+  void apply_x(const void* in, size_t in_bs, void* out, size_t out_bs, const void* Qp, size_t Q_bs, void* Tbuf,
+               int B, const int* act, double alpha, double beta, const void* Y, size_t Y_bs, bool want_norm,
+               hipStream_t s, const DotReq* dr) const;
+  // batched: S = F s (out, FP64) and m = h(F s) (hout, may alias Tbuf's role: computed in place)
+  void S_of_x(const void* x, void* Sout, void* Tbuf, int B, hipStream_t s) const;
+  void h_of_x(const void* x, void* hout, int B, hipStream_t s) const;
 };
 
 void launch_roll_add(const c64* f, const c64* h, const int* shv, int N, c64* out, int B, hipStream_t s);

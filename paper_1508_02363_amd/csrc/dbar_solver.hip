@@ -525,8 +525,122 @@ template <typename T>
 void Pipeline::apply(const void* in, size_t in_bs, void* out, size_t out_bs, const void* Qp, size_t Q_bs, void* Tbuf,
                      int B, const int* act, double alpha, double beta, const void* Y, size_t Y_bs, bool want_norm,
                      hipStream_t s, const DotReq* dr) const {
+  if (xspace) {
+    apply_x<T>(in, in_bs, out, out_bs, Qp, Q_bs, Tbuf, B, act, alpha, beta, Y, Y_bs, want_norm, s, dr);
+    return;
+  }
   apply_impl<T>(in, in_bs, out, out_bs, Qp, Q_bs, Tbuf, B, act, alpha, beta, Y, Y_bs, want_norm, 0u, nullptr, 0, s,
                 dr);
+}
+
+int Pipeline::apply_tiles(bool fp64) const { return line_tiles(N, false, fp64); }  // both forms end on rows
+int Pipeline::rhs_blocks() const { return xspace ? vec_blocks(n) : line_tiles(N, false, true); }
+
+// The operator on s = F^{-1} S.  With S = F s (F: cf phase FFT2, F^{-1}: ci phase IFFT2, F^{-1} F = identity),
+// F^{-1} A(S) = alpha s + beta i q_k conj(h(S)) + gamma Y: the moments of s are read as s is loaded, F s runs as the
+// row pass of the first launch and the column pass of the second, which divides by xi and starts F^{-1}, and the
+// third launch finishes F^{-1} along rows, adds the closed-form tail and forms the result in x-space.
+template <typename T>
+void Pipeline::apply_x(const void* in, size_t in_bs, void* out, size_t out_bs, const void* Qp, size_t Q_bs,
+                       void* Tbuf, int B, const int* act, double alpha, double beta, const void* Y, size_t Y_bs,
+                       bool want_norm, hipStream_t s, const DotReq* dr) const {
+  LineArgs a = base(B, act, 0u);
+  a.tw = tw_of<T>(tw);
+  a.in = in;
+  a.in_bs = in_bs;
+  a.out = Tbuf;
+  a.out_bs = n;
+  a.part = part_mom;
+  launch_lines_any<T>(N, LineOp::RowsFwdMoments, a, s);
+  {
+    const double dx = 2.0 * kPi * L / N;
+    TimerScope ts(kStageMoments, 0.0, B, act, s);
+    hipLaunchKernelGGL(k_moments, dim3(B), dim3(256), 0, s, part_mom, line_tiles(N, false, sizeof(T) == 8), act,
+                       dx * dx / (2.0 * kPi), M, coefG, dmom, dmom32);
+  }
+  a.in = Tbuf;  // in place: a column tile is read whole before it is written
+  a.in_bs = n;
+  launch_lines_any<T>(N, LineOp::ColsFwdRegularInv, a, s);
+  a.Q = Qp;
+  a.Q_bs = Q_bs;
+  a.out = out;
+  a.out_bs = out_bs;
+  a.S = in;
+  a.S_bs = in_bs;
+  a.alpha = alpha;
+  a.beta = c64{0.0, beta};
+  a.Y = Y;
+  a.Y_bs = Y_bs;
+  a.gamma = Y ? 1.0 : 0.0;
+  a.want_norm = want_norm ? 1 : 0;
+  a.part = part_vec;
+  if (dr) {
+    a.dotV = dr->V;
+    a.dotV_bs = dr->V_bs;
+    a.dot_nv = dr->nv;
+    a.dot_part = dr->part;
+  }
+  launch_lines_any<T>(N, LineOp::RowsInvTailEpilogue, a, s);
+}
+
+// S = F s for a batch (FP64, strides n): the column pass, then the row pass with the cf phase scaling
+void Pipeline::S_of_x(const void* x, void* Sout, void* Tbuf, int B, hipStream_t s) const {
+  LineArgs a = base(B, nullptr, 0u);
+  a.tw = tw_of<double>(tw);
+  a.in = x;
+  a.in_bs = n;
+  a.out = Tbuf;
+  a.out_bs = n;
+  launch_lines_any<double>(N, LineOp::ColsFwdPlain, a, s);
+  a.in = Tbuf;
+  a.out = Sout;
+  a.alpha = 0.0;
+  a.beta = c64{1.0, 0.0};
+  launch_lines_any<double>(N, LineOp::RowsFwdEpilogue, a, s);
+}
+
+// m = h(F s) for a batch (FP64): moments and F s, the regularised division, F^{-1} and the tail, in place in hout
+void Pipeline::h_of_x(const void* x, void* hout, int B, hipStream_t s) const {
+  LineArgs a = base(B, nullptr, 0u);
+  a.tw = tw_of<double>(tw);
+  a.in = x;
+  a.in_bs = n;
+  a.out = hout;
+  a.out_bs = n;
+  a.part = part_mom;
+  launch_lines_any<double>(N, LineOp::RowsFwdMoments, a, s);
+  {
+    const double dx = 2.0 * kPi * L / N;
+    TimerScope ts(kStageMoments, 0.0, B, nullptr, s);
+    hipLaunchKernelGGL(k_moments, dim3(B), dim3(256), 0, s, part_mom, line_tiles(N, false, true), nullptr,
+                       dx * dx / (2.0 * kPi), M, coefG, dmom, dmom32);
+  }
+  a.in = hout;
+  launch_lines_any<double>(N, LineOp::ColsFwdRegularInv, a, s);
+  a.hout = hout;  // in place: a row tile is read whole before it is written
+  a.hout_bs = n;
+  launch_lines_any<double>(N, LineOp::RowsInvTail, a, s);
+}
+
+// x-space right-hand side F^{-1} b = -i q_k = -i Q e_k (b = -i F(q_k)), with |.|^2 partials per block
+__global__ void __launch_bounds__(256) k_rhs_x(const c64* Q, size_t Q_bs, const c64* ex, const c64* ey, size_t e_bs,
+                                               int N, c64* out, double* part, int B) {
+  const int b = blockIdx.y;
+  if (b >= B) return;
+  const size_t n = (size_t)N * N;
+  double acc = 0.0;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    const int pos = (int)(i / N), col = (int)(i % N);
+    const c64 q = Q[(size_t)b * Q_bs + i] * (ex[(size_t)b * e_bs + col] * ey[(size_t)b * e_bs + pos]);
+    const c64 v{q.im, -q.re};
+    out[(size_t)b * n + i] = v;
+    acc += v.re * v.re + v.im * v.im;
+  }
+  __shared__ double red[4];
+  acc = wsum(acc);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) part[(size_t)b * gridDim.x + blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
 // H(h) = -i F(Q conj(F^{-1}(h/(xi - a)))) (equation eqh2), into Hout
@@ -546,10 +660,16 @@ void Pipeline::apply_B(const void* in, size_t in_bs, void* out, size_t out_bs, c
                 in_bs, s, dr);
 }
 
-// b = -i F(Q e_k) (FP64; e_k = 1 with kUnitPhase), with |b|^2 partials
+// b = -i F(Q e_k) (FP64; e_k = 1 with kUnitPhase), with |b|^2 partials (rhs_blocks() per entry); in x-space -i Q e_k
 void Pipeline::rhs(const void* Q64p, size_t Q_bs, void* T64, c64* bout, int B, const int* act, unsigned flags,
                    hipStream_t s) const {
   LineArgs a = base(B, act, flags & kUnitPhase);
+  if (xspace) {
+    TimerScope ts(kStageConvert, 2.0 * (double)n * sizeof(c64), B, act, s);
+    hipLaunchKernelGGL(k_rhs_x, dim3(rhs_blocks(), B), dim3(256), 0, s, static_cast<const c64*>(Q64p), Q_bs, a.ex,
+                       a.ey, a.e_bs, N, bout, part_vec, B);
+    return;
+  }
   a.tw = tw_of<double>(tw);
   a.Q = Q64p;
   a.Q_bs = Q_bs;
@@ -623,7 +743,10 @@ void Pipeline::transform(bool inverse, const void* in, void* out, void* Tbuf, hi
                                   hipStream_t) const;                                                            \
   template void Pipeline::h_of<T>(const void*, size_t, void*, size_t, void*, int, const int*, hipStream_t,         \
                                   unsigned, bool, bool) const;                                                   \
-  template void Pipeline::transform<T>(bool, const void*, void*, void*, hipStream_t) const;
+  template void Pipeline::transform<T>(bool, const void*, void*, void*, hipStream_t) const;                      \
+  template void Pipeline::apply_x<T>(const void*, size_t, void*, size_t, const void*, size_t, void*, int,          \
+                                     const int*, double, double, const void*, size_t, bool, hipStream_t,          \
+                                     const DotReq*) const;
 DBAR_PIPE_INST(double)
 DBAR_PIPE_INST(float)
 #undef DBAR_PIPE_INST
@@ -716,7 +839,7 @@ int krylov_cycle(const Pipeline& P, Work& w, const BatchCfg& cfg, int it_budget,
       va.w_bs = V_bs;
       va.part = part;
       va.want_self = 0;
-      int nblk = line_tiles(w.N, false, sizeof(T) == 8);  // pass 0: partials of the operator's last kernel
+      int nblk = P.apply_tiles(sizeof(T) == 8);  // pass 0: partials of the operator's last kernel
       if (pass > 0) {
         launch_dots<T>(va, s);
         nblk = nvb;
@@ -744,7 +867,7 @@ int krylov_cycle(const Pipeline& P, Work& w, const BatchCfg& cfg, int it_budget,
   for (; j < mlim; ++j) {
     bool done = false;
     if (graphs) {
-      const auto key = std::make_tuple((int)sizeof(T) + 16 * cfg.method, j, cfg.reorth, B);
+      const auto key = std::make_tuple((int)sizeof(T) + 16 * cfg.method + 64 * (P.xspace ? 1 : 0), j, cfg.reorth, B);
       auto it = w.graphs.find(key);
       if (it != w.graphs.end()) {
         done = hipGraphLaunch(it->second, s) == hipSuccess;
@@ -804,8 +927,8 @@ void end_cycle(const Pipeline& P, Work& w, int nv, void* r_out, hipStream_t s, i
                       true, s);
   else
     P.apply<double>(w.x.p, n, r_out, r_bs, w.Q64.p, w.Q_bs, w.T64.p, B, live, -1.0, -1.0, w.bvec.p, n, true, s);
-  launch_reduce(static_cast<double*>(w.part_vec.p), 1, line_tiles(w.N, false, true), static_cast<double*>(w.nred.p),
-                B, live, s);
+  launch_reduce(static_cast<double*>(w.part_vec.p), 1, P.apply_tiles(true), static_cast<double*>(w.nred.p), B, live,
+                s);
 }
 
 template int krylov_cycle<float>(const Pipeline&, Work&, const BatchCfg&, int, hipStream_t);
@@ -836,7 +959,7 @@ int run_batch(const Pipeline& P, Work& w, const BatchCfg& cfg, hipStream_t s, st
   // b = -i F(q_k), |b|
   // plain: b = -i F(Q e_k); iterated (equation eqh2): b = -i F(Q)
   P.rhs(w.Q64.p, w.Q_bs, w.T64.p, static_cast<c64*>(w.bvec.p), B, nullptr, cfg.method == 1 ? kUnitPhase : 0u, s);
-  launch_reduce(static_cast<double*>(w.part_vec.p), 1, line_tiles(w.N, false, true), nred, B, nullptr, s);
+  launch_reduce(static_cast<double*>(w.part_vec.p), 1, P.rhs_blocks(), nred, B, nullptr, s);
   if (hipMemsetAsync(w.x.p, 0, (size_t)B * n * sizeof(c64), s) != hipSuccess)
     return fail(DBAR_EDEVICE, "hipMemsetAsync failed");
   for (int b = 0; b < B; ++b) w.host_live[b] = 1;
@@ -948,6 +1071,8 @@ int solve_impl(const dbar_grid* grid, const void* Q, bool q_on_device, int64_t n
   if (o.check_every <= 0) o.check_every = 4;
   if (!(o.inner_tol > 0.0) || o.inner_tol >= 1.0) o.inner_tol = 1e-5;
   if (o.method != 0 && o.method != 1) return fail(DBAR_EINVAL, "method must be 0 (plain) or 1 (iterated)");
+  if (o.space != DBAR_SPACE_X && o.space != DBAR_SPACE_XI)
+    return fail(DBAR_EINVAL, "space must be DBAR_SPACE_X or DBAR_SPACE_XI");
   if (o.method == 1) {
     for (int64_t j = 0; j < 2 * nk; ++j) {
       const double m = 2.0 * k[j] * grid->L;
@@ -999,6 +1124,8 @@ int solve_impl(const dbar_grid* grid, const void* Q, bool q_on_device, int64_t n
   if (cfg.method == 1 && (rc = w.Hbuf.ensure((size_t)B * n * sizeof(c64)))) return rc;
   cfg.check_every = o.mode == DBAR_MODE_PLAIN ? 1 : o.check_every;
   cfg.inner_tol = o.inner_tol;
+  cfg.xspace = o.method == 0 && o.space == DBAR_SPACE_X ? 1 : 0;
+  P.xspace = cfg.xspace != 0;
   std::vector<EntryResult> hres(B);
   std::vector<int> shifts(2 * (size_t)B);
   int result = DBAR_OK;
@@ -1017,8 +1144,22 @@ int solve_impl(const dbar_grid* grid, const void* Q, bool q_on_device, int64_t n
                         static_cast<c64*>(w.ey.p), static_cast<c32*>(w.ex32.p), static_cast<c32*>(w.ey32.p), nb, s);
     std::vector<int> its;
     if ((rc = run_batch(P, w, cfg, s, its))) return rc;
-    // outputs: S = x, m = h(x) (plain); the iterated method forms S and m from h below
-    if (S && cfg.method == 0) {
+    // outputs: S = x, m = h(x) (plain in xi-space); S = F x, m = h(F x) (plain in x-space, S into bvec); the iterated
+    // method forms S and m from h below
+    if (cfg.xspace) {
+      P.S_of_x(w.x.p, w.bvec.p, w.T64.p, nb, s);
+      if (S && hipMemcpyAsync(static_cast<char*>(S) + (size_t)k0 * n * sizeof(c64), w.bvec.p,
+                              (size_t)nb * n * sizeof(c64),
+                              out_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s) != hipSuccess)
+        return fail(DBAR_EDEVICE, "S copy failed");
+      if (m) {
+        P.h_of_x(w.x.p, w.T64.p, nb, s);
+        if (hipMemcpyAsync(static_cast<char*>(m) + (size_t)k0 * n * sizeof(c64), w.T64.p,
+                           (size_t)nb * n * sizeof(c64),
+                           out_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s) != hipSuccess)
+          return fail(DBAR_EDEVICE, "m copy failed");
+      }
+    } else if (S && cfg.method == 0) {
       char* dst = static_cast<char*>(S) + (size_t)k0 * n * sizeof(c64);
       if (hipMemcpyAsync(dst, w.x.p, (size_t)nb * n * sizeof(c64),
                          out_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s) != hipSuccess)
@@ -1040,7 +1181,8 @@ int solve_impl(const dbar_grid* grid, const void* Q, bool q_on_device, int64_t n
                               (size_t)nb * n * sizeof(c64),
                               out_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s) != hipSuccess)
         return fail(DBAR_EDEVICE, "m copy failed");
-    } else if (m && cfg.method == 0) {
+    }
+    if (m && cfg.method == 0 && !cfg.xspace) {
       P.h_of<double>(w.x.p, n, w.T64.p, n, w.bvec.p, nb, nullptr, s);  // bvec reused as scratch
       char* dst = static_cast<char*>(m) + (size_t)k0 * n * sizeof(c64);
       if (hipMemcpyAsync(dst, w.T64.p, (size_t)nb * n * sizeof(c64),
@@ -1048,7 +1190,7 @@ int solve_impl(const dbar_grid* grid, const void* Q, bool q_on_device, int64_t n
         return fail(DBAR_EDEVICE, "m copy failed");
     }
     hipLaunchKernelGGL(k_gather_results, dim3(ctl_blocks(nb)), dim3(64), 0, s, static_cast<const Ctl*>(w.ctl.p),
-                       static_cast<const c64*>(post ? w.bvec.p : w.x.p), n, static_cast<const c64*>(w.x.p),
+                       static_cast<const c64*>(post || cfg.xspace ? w.bvec.p : w.x.p), n, static_cast<const c64*>(w.x.p),
                        cfg.method == 1 ? static_cast<const int*>(w.shv.p) : nullptr, N,
                        static_cast<EntryResult*>(w.results.p), nb);
     (void)hipMemcpyAsync(hres.data(), w.results.p, (size_t)nb * sizeof(EntryResult), hipMemcpyDeviceToHost, s);
@@ -1098,7 +1240,7 @@ void dbar_default_opts(dbar_opts* o) {
   o->reorth = 1;
   o->check_every = 4;
   o->method = 0;
-  o->reserved = 0;
+  o->space = DBAR_SPACE_X;
   o->inner_tol = 1e-5;
 }
 
@@ -1149,6 +1291,7 @@ int dbar_autotune(const dbar_grid* grid, int32_t precision, int32_t batch, dbar_
   if ((rc = w.setup(N, batch, 1, precision == DBAR_FP64 ? DBAR_FP64 : DBAR_MIXED, true))) return rc;
   Pipeline P;
   if ((rc = make_pipeline(grid, w, &P))) return rc;
+  P.xspace = true;  // the operator as the plain method's solves apply it
   // zero inputs: the kernels' work does not depend on the data (k = 0, Q = 0, S = 0)
   const size_t vb = precision == DBAR_FP64 ? sizeof(c64) : sizeof(c32);
   if (hipMemsetAsync(w.x.p, 0, (size_t)batch * n * sizeof(c64), s) != hipSuccess ||

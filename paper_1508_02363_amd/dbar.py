@@ -13,7 +13,8 @@ import numpy as np
 
 from . import _lib
 from ._lib import (DBAR_EAGAIN, DBAR_ENOCONV, DBAR_FP32, DBAR_FP64, DBAR_METHOD_ITERATED,  # noqa: F401
-                   DBAR_METHOD_PLAIN, DBAR_MIXED, DBAR_MODE_BATCHED, DBAR_MODE_PLAIN, DBAR_OK, DbarError, check)
+                   DBAR_METHOD_PLAIN, DBAR_MIXED, DBAR_MODE_BATCHED, DBAR_MODE_PLAIN, DBAR_OK, DBAR_SPACE_X,
+                   DBAR_SPACE_XI, DbarError, check)
 
 _D = ctypes.POINTER(ctypes.c_double)
 
@@ -49,9 +50,10 @@ def default_opts() -> _lib.Opts:
 
 
 def make_opts(precision=DBAR_FP64, mode=DBAR_MODE_BATCHED, restart=0, max_iter=1000, batch=0, use_graph=1,
-              reorth=1, check_every=4, inner_tol=1e-5, method=DBAR_METHOD_PLAIN) -> _lib.Opts:
+              reorth=1, check_every=4, inner_tol=1e-5, method=DBAR_METHOD_PLAIN, space=DBAR_SPACE_X) -> _lib.Opts:
     o = default_opts()
     o.method = method
+    o.space = space
     o.precision, o.mode, o.restart, o.max_iter, o.batch = precision, mode, restart, max_iter, batch
     o.use_graph, o.reorth, o.check_every, o.inner_tol = use_graph, reorth, check_every, inner_tol
     return o

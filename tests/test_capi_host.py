@@ -59,6 +59,22 @@ def test_invalid_arguments_are_rejected(kw):
     assert _lib.load().dbar_last_error().decode()
 
 
+@pytest.mark.parametrize("opt", [dict(space=2), dict(space=-1), dict(method=2)])
+def test_invalid_solver_options_are_rejected(opt):
+    lib = _lib.load()
+    g = _lib.Grid(16, 11, 2.0)
+    o = _lib.Opts()
+    lib.dbar_default_opts(ctypes.byref(o))
+    assert o.space == _lib.DBAR_SPACE_X
+    for k, v in opt.items():
+        setattr(o, k, v)
+    Qa, ka, S = np.zeros(2 * 256), np.array([0.5, 0.25]), np.zeros(2 * 256)
+    D = ctypes.POINTER(ctypes.c_double)
+    rc = lib.dbar_solve(ctypes.byref(g), Qa.ctypes.data_as(D), 1, ka.ctypes.data_as(D), 1e-12, ctypes.byref(o),
+                        S.ctypes.data_as(D), None, None)
+    assert rc == _lib.DBAR_EINVAL and lib.dbar_last_error().decode()
+
+
 def test_nan_in_potential_is_rejected():
     Q = np.zeros(2 * 16 * 16)
     Q[7] = np.nan

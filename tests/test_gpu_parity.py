@@ -275,3 +275,33 @@ def test_plain_method_at_k_zero(prec):
         ref = O.solve(g, Q, k, tol=1e-13)
         assert info[j].status == 0 and relerr(S[j], ref.S) < 1e-10 and relerr(m[j], ref.m) < 1e-10, j
     assert np.array_equal(S[0], S[2])
+
+
+@pytest.mark.parametrize("space", [D.DBAR_SPACE_X, D.DBAR_SPACE_XI])
+@pytest.mark.parametrize("prec", [D.DBAR_FP64, D.DBAR_MIXED])
+def test_solve_in_both_spaces(prec, space):
+    """GMRES on s = F^{-1} S (default) and on S itself: both against the oracle, N = 64 (several column tiles),
+    a ragged batch of 5 with k = 0 in it."""
+    N, L = 64, 3.0
+    g = O.make_grid(N, L)
+    Q = W.potential_gaussian_sum(N, L, seed=61)
+    ks = [0.0] + list(W.k_disk(6, 2.5, seed=62))
+    S, m, info = D.solve(Q, ks, L, tol=1e-12, batch=5, precision=prec, space=space)
+    for j, k in enumerate(ks):
+        ref = O.solve(g, Q, k, tol=1e-13)
+        assert info[j].status == 0 and info[j].rel_residual <= 1e-12, j
+        assert relerr(S[j], ref.S) < 1e-10 and relerr(m[j], ref.m) < 1e-10, j
+        assert abs(info[j].m1 - ref.m1) <= 1e-10 * max(abs(ref.m1), 1e-300), j
+
+
+def test_spaces_take_the_same_krylov_steps():
+    """F is unitary up to a constant, so FP64 GMRES on s and on S runs the same iterations (up to rounding) and
+    reports the same residual ratio."""
+    N, L = 128, 5.0
+    Q = W.potential_gaussian_sum(N, L, seed=63)
+    ks = W.k_disk(8, 3.0, seed=64)
+    Sx, mx, ix = D.solve(Q, ks, L, tol=1e-12, batch=8, space=D.DBAR_SPACE_X)
+    Sq, mq, iq = D.solve(Q, ks, L, tol=1e-12, batch=8, space=D.DBAR_SPACE_XI)
+    for j in range(len(ks)):
+        assert abs(ix[j].iters - iq[j].iters) <= 1, j
+        assert relerr(Sx[j], Sq[j]) < 1e-10 and relerr(mx[j], mq[j]) < 1e-10, j
