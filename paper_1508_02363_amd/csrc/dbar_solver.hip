@@ -45,52 +45,6 @@ DBAR_D double wsum(double x) {
   return x;
 }
 
-// d_n = w sum_tiles part, c_n = (-i/2)^n d_n / n! (equation fourreeg4 with Gchoice), R(0) = (-i/2) dt
-__global__ void __launch_bounds__(256) k_moments(const double* part, int ntiles, const int* act, double wscale, int M,
-                                                 c64* coefG, c64* dmom, c32* dmom32) {
-  constexpr int NV = 2 * kNMom;
-  const int b = blockIdx.x;
-  if (act && !act[b]) return;
-  __shared__ double tot[NV];
-  // wave w sums values v = w, w + 4, ...; every lane issues all of its loads before the wave reductions
-  constexpr int PER = (NV + 3) / 4;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  double acc[PER];
-#pragma unroll
-  for (int j = 0; j < PER; ++j) acc[j] = 0.0;
-  for (int i = lane; i < ntiles; i += 64) {
-#pragma unroll
-    for (int j = 0; j < PER; ++j) {
-      const int v = wave + 4 * j;
-      if (v < NV) acc[j] += part[((size_t)b * NV + v) * ntiles + i];
-    }
-  }
-#pragma unroll
-  for (int j = 0; j < PER; ++j) {
-    const double t = wsum(acc[j]);
-    const int v = wave + 4 * j;
-    if (lane == 0 && v < NV) tot[v] = t * wscale;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    c64* cg = coefG + (size_t)b * kNMom;
-    c64* dm = dmom + (size_t)b * kNMom;
-    c32* dm32 = dmom32 + (size_t)b * kNMom;
-    c64 p{1.0, 0.0};
-    const c64 mh{0.0, -0.5};
-    for (int n = 0; n <= kMaxM; ++n) {
-      const c64 d{tot[2 * n], tot[2 * n + 1]};
-      dm[n] = n <= M ? d : c64{0.0, 0.0};
-      dm32[n] = cvt<float>(dm[n]);
-      cg[n] = n <= M ? kInvFactC[n] * (p * d) : c64{0.0, 0.0};
-      p = p * mh;
-    }
-    const c64 dt{tot[2 * (kMaxM + 1)], tot[2 * (kMaxM + 1) + 1]};
-    cg[kMaxM + 1] = mh * dt;
-    dm[kMaxM + 1] = dt;
-    dm32[kMaxM + 1] = cvt<float>(dt);
-  }
-}
 
 // Deterministic block reduction of one entry's partials: red[v] = sum_blk part[v * nblk + blk] for v < nval
 // (wave w sums the values v = w, w + NW, ...; lanes stride over the partials).  1024 threads.
@@ -100,12 +54,48 @@ DBAR_D void reduce_entry(const double* __restrict__ part, int nval, int nblk, do
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int v = wave; v < nval; v += NW) {
     const double* p = part + (size_t)v * nblk;
-    double acc = 0.0;
-    for (int i = lane; i < nblk; i += 64) acc += p[i];
+    // eight independent partial sums per lane: the loads of a chunk are in flight together
+    double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    int i = lane;
+    for (; i + 7 * 64 < nblk; i += 8 * 64) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) a[u] += p[i + u * 64];
+    }
+    for (; i < nblk; i += 64) a[0] += p[i];
+    double acc = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
     acc = wsum(acc);
     if (lane == 0) red[v] = acc;
   }
   __syncthreads();
+}
+
+// d_n = w sum_tiles part, c_n = (-i/2)^n d_n / n! (equation fourreeg4 with Gchoice), R(0) = (-i/2) dt.  One block
+// of kCtlThreads per entry.
+__global__ void __launch_bounds__(kCtlThreads) k_moments(const double* part, int ntiles, const int* act,
+                                                         double wscale, int M, c64* coefG, c64* dmom, c32* dmom32) {
+  constexpr int NV = 2 * kNMom;
+  const int b = blockIdx.x;
+  if (act && !act[b]) return;
+  __shared__ double tot[NV];
+  reduce_entry(part + (size_t)b * NV * ntiles, NV, ntiles, tot);
+  if (threadIdx.x == 0) {
+    c64* cg = coefG + (size_t)b * kNMom;
+    c64* dm = dmom + (size_t)b * kNMom;
+    c32* dm32 = dmom32 + (size_t)b * kNMom;
+    c64 p{1.0, 0.0};
+    const c64 mh{0.0, -0.5};
+    for (int n = 0; n <= kMaxM; ++n) {
+      const c64 d{wscale * tot[2 * n], wscale * tot[2 * n + 1]};
+      dm[n] = n <= M ? d : c64{0.0, 0.0};
+      dm32[n] = cvt<float>(dm[n]);
+      cg[n] = n <= M ? kInvFactC[n] * (p * d) : c64{0.0, 0.0};
+      p = p * mh;
+    }
+    const c64 dt{wscale * tot[2 * (kMaxM + 1)], wscale * tot[2 * (kMaxM + 1) + 1]};
+    cg[kMaxM + 1] = mh * dt;
+    dm[kMaxM + 1] = dt;
+    dm32[kMaxM + 1] = cvt<float>(dt);
+  }
 }
 
 // Gram-Schmidt pass `pass` of step j: h_i = <v_i, w> from the partials, coef_i = sigma_i^2 h_i (the basis is kept
@@ -478,7 +468,7 @@ void Pipeline::moments(const void* in, size_t in_bs, void* Tbuf, int B, const in
   launch_lines_any<T>(N, LineOp::ColsInvMoments, a, s);
   const double dx = 2.0 * kPi * L / N;
   TimerScope ts(kStageMoments, 0.0, B, act, s);
-  hipLaunchKernelGGL(k_moments, dim3(B), dim3(256), 0, s, part_mom, line_tiles(N, true, sizeof(T) == 8), act,
+  hipLaunchKernelGGL(k_moments, dim3(B), dim3(kCtlThreads), 0, s, part_mom, line_tiles(N, true, sizeof(T) == 8), act,
                      dx * dx / (2.0 * kPi), M, coefG, dmom, dmom32);
 }
 
@@ -555,7 +545,7 @@ void Pipeline::apply_x(const void* in, size_t in_bs, void* out, size_t out_bs, c
   {
     const double dx = 2.0 * kPi * L / N;
     TimerScope ts(kStageMoments, 0.0, B, act, s);
-    hipLaunchKernelGGL(k_moments, dim3(B), dim3(256), 0, s, part_mom, line_tiles(N, false, sizeof(T) == 8), act,
+    hipLaunchKernelGGL(k_moments, dim3(B), dim3(kCtlThreads), 0, s, part_mom, line_tiles(N, false, sizeof(T) == 8), act,
                        dx * dx / (2.0 * kPi), M, coefG, dmom, dmom32);
   }
   a.in = Tbuf;  // in place: a column tile is read whole before it is written
@@ -612,7 +602,7 @@ void Pipeline::h_of_x(const void* x, void* hout, int B, hipStream_t s) const {
   {
     const double dx = 2.0 * kPi * L / N;
     TimerScope ts(kStageMoments, 0.0, B, nullptr, s);
-    hipLaunchKernelGGL(k_moments, dim3(B), dim3(256), 0, s, part_mom, line_tiles(N, false, true), nullptr,
+    hipLaunchKernelGGL(k_moments, dim3(B), dim3(kCtlThreads), 0, s, part_mom, line_tiles(N, false, true), nullptr,
                        dx * dx / (2.0 * kPi), M, coefG, dmom, dmom32);
   }
   a.in = hout;
