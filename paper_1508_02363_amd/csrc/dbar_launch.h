@@ -25,7 +25,6 @@ enum class LineOp : int {
   ColsFwdRegularInv = 10, // S = cf phase FFT_cols(in); R = (S - G)/xi, R(0) = (-i/2) dt; out = IFFT_cols(phase ci R)
   RowsInvTailEpilogue = 11, // r = IFFT_rows(in); h = r + sum d_n omega_n; out = alpha S + beta q_k conj(h) + gamma Y;
                             // optional |out|^2 -> part and Gram-Schmidt products -> dot_part
-  RowsInvTail = 12,   // r = IFFT_rows(in); hout = r + sum d_n omega_n
 };
 
 struct LineArgs {
@@ -45,7 +44,8 @@ struct LineArgs {
   const c64* coefG = nullptr;  // [b][kNMom]: c_0..c_M, slot kMaxM+1 = R(0) = (-i/2) dt
   const c64* dmom = nullptr;   // [b][kNMom]: d_0..d_M (tail weights)
   const c32* dmom32 = nullptr; // the same rounded to FP32 (FP32 operator)
-  void* hout = nullptr;        size_t hout_bs = 0;
+  void* hout = nullptr;        size_t hout_bs = 0;  // ColsInvTail(Fwd), RowsInvTail(Epilogue): h (optional on the latter)
+  void* sout = nullptr;        size_t sout_bs = 0;  // ColsFwdRegularInv: S before the division (optional)
   double* part = nullptr;      // per-block partial sums [b][tile][nval]
   const void* tw = nullptr;    // twiddle table exp(-2 pi i j / N), j < N, in the transform's precision
   double L = 1.0, ci = 1.0, cf = 1.0;

@@ -529,8 +529,9 @@ struct OpRowsInvRegular : OpBase<T, N> {
   DBAR_D void store(Acc&, int b, int row, int pos, cx<T> v) const { this->outp(b)[(size_t)row * N + pos] = v; }
 };
 
-// x-space operator, second launch: S = cf phase FFT_cols(in) (the second pass of F s), R = (S - G)/xi, then
-// out = IFFT_cols(phase ci R), between the two column transforms (rolled through LDS: the FP64 G terms)
+// x-space operator, second launch: S = cf phase FFT_cols(in) (the second pass of F s; optionally stored to sout),
+// R = (S - G)/xi, then out = IFFT_cols(phase ci R), between the two column transforms (rolled through LDS: the FP64
+// G terms)
 template <typename T, int N>
 struct OpColsFwdRegInv : OpBase<T, N> {
   static constexpr int DIR1 = -1;
@@ -541,7 +542,9 @@ struct OpColsFwdRegInv : OpBase<T, N> {
   template <class A>
   DBAR_D void mid(int b, int col, int pos, cx<T>& v) const {
     const T f = static_cast<T>(((col + pos) & 1) ? -this->a.cf : this->a.cf);
-    v = regularised<T, N>(this->a, b, pos, col, f * v);  // row = xi2 index (pos), position = xi1 index (col)
+    const cx<T> S = f * v;
+    if (this->a.sout) (static_cast<cx<T>*>(this->a.sout) + (size_t)b * this->a.sout_bs)[(size_t)pos * N + col] = S;
+    v = regularised<T, N>(this->a, b, pos, col, S);  // row = xi2 index (pos), position = xi1 index (col)
   }
   DBAR_D void store(Acc&, int b, int col, int pos, cx<T> v) const { this->outp(b)[(size_t)pos * N + col] = v; }
 };
@@ -666,14 +669,14 @@ struct OpRowsFwdEpilogue : OpBase<T, N> {
 
 // x-space operator, third launch: r = IFFT_rows(in) (second pass of F^{-1} R), h = r + sum d_n omega_n, and the
 // x-space form of A: out = alpha s + beta q_k conj(h) + gamma Y (F^{-1} of S + i F(q_k conj(h)) is s + i q_k conj(h));
-// optional |out|^2 partials and the products Re<V_i, out> of the first Gram-Schmidt pass.  TAILONLY: hout = h.
+// optional |out|^2 partials, h itself (hout) and the products Re<V_i, out> of the first Gram-Schmidt pass.
 // Rows keep every global access of the epilogue and the products contiguous across a wave.
-template <typename T, int N, bool TAILONLY>
+template <typename T, int N>
 struct OpRowsInvTailEpi : OpColsInvTail<T, N, false> {
   static constexpr int DIR1 = +1;
   static constexpr bool TWO = false;
   static constexpr bool ROLLED = true;
-  static constexpr bool DOTS = !TAILONLY;
+  static constexpr bool DOTS = true;
   using Pre = typename OpColsInvTail<T, N, false>::Pre;
   struct Acc {
     double v[1];
@@ -713,48 +716,40 @@ struct OpRowsInvTailEpi : OpColsInvTail<T, N, false> {
     static_assert(G::RMAX % GROUP == 0, "whole groups");
     const LineArgs& a = this->a;
     const size_t base = (size_t)row * N;
-    if constexpr (TAILONLY) {
-      cx<T>* hb = static_cast<cx<T>*>(a.hout) + (size_t)b * a.hout_bs + base;
+    // the y factor of e_k is the row's (1 with the shifted regularisation, where q stands alone)
+    cx<T> ey{T(1), T(0)};
+    if (!a.shv) {
+      if constexpr (sizeof(T) == 8) ey = a.ey[(size_t)b * a.e_bs + row];
+      else ey = a.ey32[(size_t)b * a.e_bs + row];
+    }
 #pragma unroll 1
-      for (int s = 0; s < G::RMAX; ++s) {
-        const int pos = jt + s * G::TPL;
-        hb[pos] = this->h_at(b, pos, row, my[G::padded(pos) * LS], p);
-      }
-    } else {
-      // the y factor of e_k is the row's (1 with the shifted regularisation, where q stands alone)
-      cx<T> ey{T(1), T(0)};
-      if (!a.shv) {
-        if constexpr (sizeof(T) == 8) ey = a.ey[(size_t)b * a.e_bs + row];
-        else ey = a.ey32[(size_t)b * a.e_bs + row];
-      }
-#pragma unroll 1
-      for (int s0 = 0; s0 < G::RMAX; s0 += GROUP) {
-        GroupIn cur;
-        group_load(cur, b, row, jt, s0);
+    for (int s0 = 0; s0 < G::RMAX; s0 += GROUP) {
+      GroupIn cur;
+      group_load(cur, b, row, jt, s0);
 #pragma unroll
-        for (int u = 0; u < GROUP; ++u) {
-          const int pos = jt + (s0 + u) * G::TPL;
-          cx<T>& slot = my[G::padded(pos) * LS];
-          const cx<T> h = this->h_at(b, pos, row, slot, p);  // x index pos, y index row
-          const cx<T> w = (cur.q[u] * (cur.ex[u] * ey)) * conj(h);
-          cx<T> ot;
-          if constexpr (sizeof(T) == 8) {
-            ot = a.beta * w + a.alpha * cur.s[u] + a.gamma * cur.y[u];
-          } else {  // the FP32 operator's result is FP32: form it in FP32
-            ot = cvt<T>(a.beta) * w + static_cast<T>(a.alpha) * cur.s[u] + static_cast<T>(a.gamma) * cur.y[u];
-          }
-          this->outp(b)[base + pos] = ot;
-          slot = ot;
-          const c64 od = cvt<double>(ot), sd = cvt<double>(cur.s[u]);
-          acc.v[0] += norm2(od);
-          acc.sdot += sd.re * od.re + sd.im * od.im;
+      for (int u = 0; u < GROUP; ++u) {
+        const int pos = jt + (s0 + u) * G::TPL;
+        cx<T>& slot = my[G::padded(pos) * LS];
+        const cx<T> h = this->h_at(b, pos, row, slot, p);  // x index pos, y index row
+        if (a.hout) (static_cast<cx<T>*>(a.hout) + (size_t)b * a.hout_bs)[base + pos] = h;
+        const cx<T> w = (cur.q[u] * (cur.ex[u] * ey)) * conj(h);
+        cx<T> ot;
+        if constexpr (sizeof(T) == 8) {
+          ot = a.beta * w + a.alpha * cur.s[u] + a.gamma * cur.y[u];
+        } else {  // the FP32 operator's result is FP32: form it in FP32
+          ot = cvt<T>(a.beta) * w + static_cast<T>(a.alpha) * cur.s[u] + static_cast<T>(a.gamma) * cur.y[u];
         }
+        this->outp(b)[base + pos] = ot;
+        slot = ot;
+        const c64 od = cvt<double>(ot), sd = cvt<double>(cur.s[u]);
+        acc.v[0] += norm2(od);
+        acc.sdot += sd.re * od.re + sd.im * od.im;
       }
     }
   }
   template <int NT>
   DBAR_D void finish(Acc& acc, int b, int tile, int ntiles, double* scratch) const {
-    if (TAILONLY || !this->a.want_norm) return;
+    if (!this->a.want_norm) return;
     block_reduce_store<NT, 1>(acc.v, this->a.part + (size_t)b * ntiles + tile, 0, scratch);
   }
   // Re<V_i, out> over this tile for i < dot_nv (FP64 accumulation, the order fixed); V_{dot_nv - 1} is S, whose
@@ -984,8 +979,7 @@ void launch_lines(LineOp op, const LineArgs& a, hipStream_t s) {
     case LineOp::ColsInvPlain: launch_cols<T, N, OpColsPlain<T, N, +1>>(a, s); break;
     case LineOp::RowsFwdMoments: launch_op<T, N, false, OpRowsFwdMoments<T, N>>(a, s); break;
     case LineOp::ColsFwdRegularInv: launch_cols<T, N, OpColsFwdRegInv<T, N>>(a, s); break;
-    case LineOp::RowsInvTailEpilogue: launch_op<T, N, false, OpRowsInvTailEpi<T, N, false>>(a, s); break;
-    case LineOp::RowsInvTail: launch_op<T, N, false, OpRowsInvTailEpi<T, N, true>>(a, s); break;
+    case LineOp::RowsInvTailEpilogue: launch_op<T, N, false, OpRowsInvTailEpi<T, N>>(a, s); break;
   }
 }
 

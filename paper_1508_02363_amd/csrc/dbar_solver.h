@@ -106,6 +106,7 @@ struct Work {
   size_t Q_bs = 0;
   DevBuf x, bvec, T64, r64, T32, V, Q64, Q32, ex, ey, ex32, ey32, coefG, dmom, dmom32, part_mom, part_vec, part_norm,
       dred, nred, ctl, act, live, kvals, results, shv, unit, unit32, Hbuf;
+  DevBuf Sx, mx;  // x-space solves: S = F x and m = h(S) of the last residual evaluation (FP64)
   PinnedInts host_act, host_live;
   int setup(int N_, int B_, int m_, int prec_, bool shared_q);
   size_t vec_bytes(int prec) const;
@@ -156,9 +157,10 @@ struct Pipeline {
                   unsigned flags, const void* S_ep, size_t S_ep_bs, hipStream_t s, const DotReq* dr = nullptr) const;
   // A(S) of the plain method (Section 4), as alpha S + beta i F(q_k conj(h(S))) + gamma Y
   template <typename T>
+  // In x-space Sout / Hout (strides n, may be null) also receive S = F s and h(S) of the input.
   void apply(const void* in, size_t in_bs, void* out, size_t out_bs, const void* Qp, size_t Q_bs, void* Tbuf, int B,
              const int* act, double alpha, double beta, const void* Y, size_t Y_bs, bool want_norm,
-             hipStream_t s, const DotReq* dr = nullptr) const;
+             hipStream_t s, const DotReq* dr = nullptr, void* Sout = nullptr, void* Hout = nullptr) const;
   // H(h) of equation eqh2
   template <typename T>
   void H_of(const void* in, size_t in_bs, void* Hout, size_t H_bs, const void* Qp, size_t Q_bs, void* Tbuf, int B,
@@ -179,10 +181,7 @@ struct Pipeline {
   template <typename T>
   void apply_x(const void* in, size_t in_bs, void* out, size_t out_bs, const void* Qp, size_t Q_bs, void* Tbuf,
                int B, const int* act, double alpha, double beta, const void* Y, size_t Y_bs, bool want_norm,
-               hipStream_t s, const DotReq* dr) const;
-  // batched: S = F s (out, FP64) and m = h(F s) (hout, may alias Tbuf's role: computed in place)
-  void S_of_x(const void* x, void* Sout, void* Tbuf, int B, hipStream_t s) const;
-  void h_of_x(const void* x, void* hout, int B, hipStream_t s) const;
+               hipStream_t s, const DotReq* dr, void* Sout, void* Hout) const;
 };
 
 void launch_roll_add(const c64* f, const c64* h, const int* shv, int N, c64* out, int B, hipStream_t s);

@@ -340,6 +340,7 @@ Work& Work::operator=(Work&& o) noexcept {
   dred = std::move(o.dred); nred = std::move(o.nred); ctl = std::move(o.ctl); act = std::move(o.act);
   live = std::move(o.live); kvals = std::move(o.kvals); results = std::move(o.results);
   shv = std::move(o.shv); unit = std::move(o.unit); Hbuf = std::move(o.Hbuf);
+  Sx = std::move(o.Sx); mx = std::move(o.mx);
   host_act = std::move(o.host_act); host_live = std::move(o.host_live);
   graphs = std::move(o.graphs);
   graph_epoch = o.graph_epoch;
@@ -514,9 +515,9 @@ void Pipeline::apply_impl(const void* in, size_t in_bs, void* out, size_t out_bs
 template <typename T>
 void Pipeline::apply(const void* in, size_t in_bs, void* out, size_t out_bs, const void* Qp, size_t Q_bs, void* Tbuf,
                      int B, const int* act, double alpha, double beta, const void* Y, size_t Y_bs, bool want_norm,
-                     hipStream_t s, const DotReq* dr) const {
+                     hipStream_t s, const DotReq* dr, void* Sout, void* Hout) const {
   if (xspace) {
-    apply_x<T>(in, in_bs, out, out_bs, Qp, Q_bs, Tbuf, B, act, alpha, beta, Y, Y_bs, want_norm, s, dr);
+    apply_x<T>(in, in_bs, out, out_bs, Qp, Q_bs, Tbuf, B, act, alpha, beta, Y, Y_bs, want_norm, s, dr, Sout, Hout);
     return;
   }
   apply_impl<T>(in, in_bs, out, out_bs, Qp, Q_bs, Tbuf, B, act, alpha, beta, Y, Y_bs, want_norm, 0u, nullptr, 0, s,
@@ -533,7 +534,7 @@ int Pipeline::rhs_blocks() const { return xspace ? vec_blocks(n) : line_tiles(N,
 template <typename T>
 void Pipeline::apply_x(const void* in, size_t in_bs, void* out, size_t out_bs, const void* Qp, size_t Q_bs,
                        void* Tbuf, int B, const int* act, double alpha, double beta, const void* Y, size_t Y_bs,
-                       bool want_norm, hipStream_t s, const DotReq* dr) const {
+                       bool want_norm, hipStream_t s, const DotReq* dr, void* Sout, void* Hout) const {
   LineArgs a = base(B, act, 0u);
   a.tw = tw_of<T>(tw);
   a.in = in;
@@ -550,7 +551,12 @@ void Pipeline::apply_x(const void* in, size_t in_bs, void* out, size_t out_bs, c
   }
   a.in = Tbuf;  // in place: a column tile is read whole before it is written
   a.in_bs = n;
+  a.sout = Sout;
+  a.sout_bs = n;
   launch_lines_any<T>(N, LineOp::ColsFwdRegularInv, a, s);
+  a.sout = nullptr;
+  a.hout = Hout;
+  a.hout_bs = n;
   a.Q = Qp;
   a.Q_bs = Q_bs;
   a.out = out;
@@ -571,45 +577,6 @@ void Pipeline::apply_x(const void* in, size_t in_bs, void* out, size_t out_bs, c
     a.dot_part = dr->part;
   }
   launch_lines_any<T>(N, LineOp::RowsInvTailEpilogue, a, s);
-}
-
-// S = F s for a batch (FP64, strides n): the column pass, then the row pass with the cf phase scaling
-void Pipeline::S_of_x(const void* x, void* Sout, void* Tbuf, int B, hipStream_t s) const {
-  LineArgs a = base(B, nullptr, 0u);
-  a.tw = tw_of<double>(tw);
-  a.in = x;
-  a.in_bs = n;
-  a.out = Tbuf;
-  a.out_bs = n;
-  launch_lines_any<double>(N, LineOp::ColsFwdPlain, a, s);
-  a.in = Tbuf;
-  a.out = Sout;
-  a.alpha = 0.0;
-  a.beta = c64{1.0, 0.0};
-  launch_lines_any<double>(N, LineOp::RowsFwdEpilogue, a, s);
-}
-
-// m = h(F s) for a batch (FP64): moments and F s, the regularised division, F^{-1} and the tail, in place in hout
-void Pipeline::h_of_x(const void* x, void* hout, int B, hipStream_t s) const {
-  LineArgs a = base(B, nullptr, 0u);
-  a.tw = tw_of<double>(tw);
-  a.in = x;
-  a.in_bs = n;
-  a.out = hout;
-  a.out_bs = n;
-  a.part = part_mom;
-  launch_lines_any<double>(N, LineOp::RowsFwdMoments, a, s);
-  {
-    const double dx = 2.0 * kPi * L / N;
-    TimerScope ts(kStageMoments, 0.0, B, nullptr, s);
-    hipLaunchKernelGGL(k_moments, dim3(B), dim3(kCtlThreads), 0, s, part_mom, line_tiles(N, false, true), nullptr,
-                       dx * dx / (2.0 * kPi), M, coefG, dmom, dmom32);
-  }
-  a.in = hout;
-  launch_lines_any<double>(N, LineOp::ColsFwdRegularInv, a, s);
-  a.hout = hout;  // in place: a row tile is read whole before it is written
-  a.hout_bs = n;
-  launch_lines_any<double>(N, LineOp::RowsInvTail, a, s);
 }
 
 // x-space right-hand side F^{-1} b = -i q_k = -i Q e_k (b = -i F(q_k)), with |.|^2 partials per block
@@ -725,7 +692,7 @@ void Pipeline::transform(bool inverse, const void* in, void* out, void* Tbuf, hi
 #define DBAR_PIPE_INST(T)                                                                                        \
   template void Pipeline::apply<T>(const void*, size_t, void*, size_t, const void*, size_t, void*, int,            \
                                    const int*, double, double, const void*, size_t, bool, hipStream_t,            \
-                                   const DotReq*) const;                                                          \
+                                   const DotReq*, void*, void*) const;                                            \
   template void Pipeline::apply_B<T>(const void*, size_t, void*, size_t, const void*, size_t, void*, void*, int,   \
                                      const int*, double, double, const void*, size_t, bool, hipStream_t,          \
                                      const DotReq*) const;                                                        \
@@ -736,7 +703,7 @@ void Pipeline::transform(bool inverse, const void* in, void* out, void* Tbuf, hi
   template void Pipeline::transform<T>(bool, const void*, void*, void*, hipStream_t) const;                      \
   template void Pipeline::apply_x<T>(const void*, size_t, void*, size_t, const void*, size_t, void*, int,          \
                                      const int*, double, double, const void*, size_t, bool, hipStream_t,          \
-                                     const DotReq*) const;
+                                     const DotReq*, void*, void*) const;
 DBAR_PIPE_INST(double)
 DBAR_PIPE_INST(float)
 #undef DBAR_PIPE_INST
@@ -915,8 +882,9 @@ void end_cycle(const Pipeline& P, Work& w, int nv, void* r_out, hipStream_t s, i
   if (method == 1)
     P.apply_B<double>(w.x.p, n, r_out, r_bs, w.Q64.p, w.Q_bs, w.T64.p, w.Hbuf.p, B, live, -1.0, -1.0, w.bvec.p, n,
                       true, s);
-  else
-    P.apply<double>(w.x.p, n, r_out, r_bs, w.Q64.p, w.Q_bs, w.T64.p, B, live, -1.0, -1.0, w.bvec.p, n, true, s);
+  else  // x-space: S = F x and m = h(S) of this x come along (the last evaluation's are the outputs)
+    P.apply<double>(w.x.p, n, r_out, r_bs, w.Q64.p, w.Q_bs, w.T64.p, B, live, -1.0, -1.0, w.bvec.p, n, true, s,
+                    nullptr, P.xspace ? w.Sx.p : nullptr, P.xspace ? w.mx.p : nullptr);
   launch_reduce(static_cast<double*>(w.part_vec.p), 1, P.apply_tiles(true), static_cast<double*>(w.nred.p), B, live,
                 s);
 }
@@ -938,6 +906,15 @@ void launch_ctl_start(Work& w, double abs_tol, double rel_tol, const double* tol
                      static_cast<int*>(w.act.p), abs_tol, rel_tol, tolv, w.B);
 }
 
+__global__ void k_zero_done(c64* a, c64* b2, const int* live, size_t n) {
+  const int b = blockIdx.y;
+  if (live[b]) return;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    a[(size_t)b * n + i] = c64{0.0, 0.0};
+    b2[(size_t)b * n + i] = c64{0.0, 0.0};
+  }
+}
+
 int run_batch(const Pipeline& P, Work& w, const BatchCfg& cfg, hipStream_t s, std::vector<int>& iters_out) {
   const int B = w.B;
   const size_t n = w.n;
@@ -957,6 +934,10 @@ int run_batch(const Pipeline& P, Work& w, const BatchCfg& cfg, hipStream_t s, st
     return fail(DBAR_EDEVICE, "hipMemcpyAsync failed");
   // r0 = b (x0 = 0); entries with b = 0 are done at once
   hipLaunchKernelGGL(k_ctl_check, dim3(ctl_blocks(B)), dim3(64), 0, s, ctl, nred, live, 0.0, 1, nullptr, nullptr, B);
+  if (P.xspace) {  // S = m = 0 for entries with b = 0 (no residual evaluation writes them)
+    hipLaunchKernelGGL(k_zero_done, dim3(std::min<size_t>(1024, (n + 255) / 256), B), dim3(256), 0, s,
+                       static_cast<c64*>(w.Sx.p), static_cast<c64*>(w.mx.p), live, n);
+  }
   if (mixed) {
     launch_convert<float, double>(w.bvec.p, n, w.V.p, n * (w.m + 1), n, B, nullptr, 1.0, s);
   } else {
@@ -1086,7 +1067,7 @@ int solve_impl(const dbar_grid* grid, const void* Q, bool q_on_device, int64_t n
     // fit the batch to free memory: basis + 6 vectors per entry
     size_t fr = 0, tot = 0;
     if (hipMemGetInfo(&fr, &tot) == hipSuccess) {
-      const size_t per = n * ((o.restart + 1) * (o.precision == DBAR_MIXED ? 8 : 16) + 6 * 16) + 65536;
+      const size_t per = n * ((o.restart + 1) * (o.precision == DBAR_MIXED ? 8 : 16) + 8 * 16) + 65536;
       const size_t cap = (size_t)(0.7 * (double)fr) / per;
       if (cap >= 1 && (size_t)B > cap) B = (int)cap;
     }
@@ -1116,6 +1097,8 @@ int solve_impl(const dbar_grid* grid, const void* Q, bool q_on_device, int64_t n
   cfg.inner_tol = o.inner_tol;
   cfg.xspace = o.method == 0 && o.space == DBAR_SPACE_X ? 1 : 0;
   P.xspace = cfg.xspace != 0;
+  if (cfg.xspace && ((rc = w.Sx.ensure((size_t)B * n * sizeof(c64))) || (rc = w.mx.ensure((size_t)B * n * sizeof(c64)))))
+    return rc;
   std::vector<EntryResult> hres(B);
   std::vector<int> shifts(2 * (size_t)B);
   int result = DBAR_OK;
@@ -1137,18 +1120,14 @@ int solve_impl(const dbar_grid* grid, const void* Q, bool q_on_device, int64_t n
     // outputs: S = x, m = h(x) (plain in xi-space); S = F x, m = h(F x) (plain in x-space, S into bvec); the iterated
     // method forms S and m from h below
     if (cfg.xspace) {
-      P.S_of_x(w.x.p, w.bvec.p, w.T64.p, nb, s);
-      if (S && hipMemcpyAsync(static_cast<char*>(S) + (size_t)k0 * n * sizeof(c64), w.bvec.p,
+      if (S && hipMemcpyAsync(static_cast<char*>(S) + (size_t)k0 * n * sizeof(c64), w.Sx.p,
                               (size_t)nb * n * sizeof(c64),
                               out_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s) != hipSuccess)
         return fail(DBAR_EDEVICE, "S copy failed");
-      if (m) {
-        P.h_of_x(w.x.p, w.T64.p, nb, s);
-        if (hipMemcpyAsync(static_cast<char*>(m) + (size_t)k0 * n * sizeof(c64), w.T64.p,
-                           (size_t)nb * n * sizeof(c64),
-                           out_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s) != hipSuccess)
-          return fail(DBAR_EDEVICE, "m copy failed");
-      }
+      if (m && hipMemcpyAsync(static_cast<char*>(m) + (size_t)k0 * n * sizeof(c64), w.mx.p,
+                              (size_t)nb * n * sizeof(c64),
+                              out_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s) != hipSuccess)
+        return fail(DBAR_EDEVICE, "m copy failed");
     } else if (S && cfg.method == 0) {
       char* dst = static_cast<char*>(S) + (size_t)k0 * n * sizeof(c64);
       if (hipMemcpyAsync(dst, w.x.p, (size_t)nb * n * sizeof(c64),
@@ -1180,7 +1159,8 @@ int solve_impl(const dbar_grid* grid, const void* Q, bool q_on_device, int64_t n
         return fail(DBAR_EDEVICE, "m copy failed");
     }
     hipLaunchKernelGGL(k_gather_results, dim3(ctl_blocks(nb)), dim3(64), 0, s, static_cast<const Ctl*>(w.ctl.p),
-                       static_cast<const c64*>(post || cfg.xspace ? w.bvec.p : w.x.p), n, static_cast<const c64*>(w.x.p),
+                       static_cast<const c64*>(post ? w.bvec.p : cfg.xspace ? w.Sx.p : w.x.p), n,
+                       static_cast<const c64*>(w.x.p),
                        cfg.method == 1 ? static_cast<const int*>(w.shv.p) : nullptr, N,
                        static_cast<EntryResult*>(w.results.p), nb);
     (void)hipMemcpyAsync(hres.data(), w.results.p, (size_t)nb * sizeof(EntryResult), hipMemcpyDeviceToHost, s);

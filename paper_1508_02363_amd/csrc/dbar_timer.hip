@@ -52,14 +52,13 @@ __global__ void k_count_active(const int* act, int B, int* out) {
 const char* stage_name(int stage) {
   static const char* lines[] = {"RowsInvScaled", "ColsInvMoments", "RowsInvRegular", "ColsInvTailFwd",
                                 "ColsInvTail",   "RowsFwdEpilogue", "ColsFwdPotential", "ColsFwdPlain",
-                                "ColsInvPlain",  "RowsFwdMoments", "ColsFwdRegularInv", "RowsInvTailEpilogue",
-                                "RowsInvTail"};
+                                "ColsInvPlain",  "RowsFwdMoments", "ColsFwdRegularInv", "RowsInvTailEpilogue"};
   static std::string names[kNumStages];
   if (stage < 0 || stage >= kNumStages) return "?";
   if (names[stage].empty()) {
     if (stage < kStageDots) {
       const int op = stage / 2;
-      names[stage] = std::string("lines.") + (op < 13 ? lines[op] : "?") + (stage % 2 ? ".f32" : ".f64");
+      names[stage] = std::string("lines.") + (op < 12 ? lines[op] : "?") + (stage % 2 ? ".f32" : ".f64");
     } else if (stage < kStageUpdate) {
       names[stage] = stage == kStageDots ? "krylov.dots.f64" : "krylov.dots.f32";
     } else if (stage < kStageAxpy) {
