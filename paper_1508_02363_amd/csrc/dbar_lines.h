@@ -686,7 +686,8 @@ struct OpRowsInvTailEpi : OpColsInvTail<T, N, false> {
   // The stores run GROUP elements at a time: the group's global reads (q, the x factor of e_k, S, Y) are issued
   // together ahead of its tails.  The LDS slot of each element (the row transform's output r) is replaced by the
   // stored value, for the Gram-Schmidt products.
-  static constexpr int GROUP = LineGeom<N>::RMAX < 4 ? LineGeom<N>::RMAX : 4;
+  static constexpr int GROUP_W = sizeof(T) == 4 ? 8 : 4;  // FP64: register-bound at 4
+  static constexpr int GROUP = LineGeom<N>::RMAX < GROUP_W ? LineGeom<N>::RMAX : GROUP_W;
   struct GroupIn {
     cx<T> q[GROUP], s[GROUP], y[GROUP], ex[GROUP];
   };
