@@ -56,8 +56,8 @@ struct SClass {
   std::vector<std::shared_ptr<SReq>> slots;
   std::deque<std::shared_ptr<SReq>> queue;
   std::thread th;
-  DevBuf newmask, finmask, tolv;
-  std::vector<int> h_new, h_fin, h_live;
+  DevBuf newmask, tolv;
+  std::vector<int> h_new, h_live;
   std::vector<double> h_tol;
   std::vector<c64> h_k;  // per-slot k (host source of the async upload; stable until the stream synchronises)
   bool ready = false;
@@ -85,7 +85,7 @@ static size_t footprint_of(int N, int prec, int restart, int cap_hint) {
   const size_t n = (size_t)N * N;
   const bool mixed = prec == DBAR_MIXED;
   size_t per = n * ((size_t)(restart + 1) * (mixed ? sizeof(c32) : sizeof(c64)));  // Krylov basis
-  per += n * sizeof(c64) * (mixed ? 5 : 4);                                       // x, b, T64, Q64 (+ r64)
+  per += n * sizeof(c64) * (mixed ? 7 : 6);                                       // x, b, T64, Q64, S, m (+ r64)
   per += mixed ? n * sizeof(c32) * 2 : 0;                                          // T32, Q32
   per += 2 * (size_t)N * sizeof(c64) + sizeof(Ctl) + 2 * kNMom * sizeof(c64);
   per += (size_t)2 * kNMom * 1024 * sizeof(double) + (size_t)(kMaxRestart + 3) * vec_blocks(n) * sizeof(double);
@@ -99,14 +99,16 @@ static int class_init(SClass& c) {
   if (rc) return rc;
   dbar_grid g{c.N, c.M, c.L};
   if ((rc = make_pipeline(&g, c.w, &c.P))) return rc;
+  // GMRES on s = F^{-1} S; S and m come out of the residual evaluations
+  c.P.xspace = true;
+  const size_t nb = (size_t)c.cap * c.N * c.N * sizeof(c64);
+  if ((rc = c.w.Sx.ensure(nb)) || (rc = c.w.mx.ensure(nb))) return rc;
   if ((rc = c.newmask.ensure(c.cap * sizeof(int)))) return rc;
-  if ((rc = c.finmask.ensure(c.cap * sizeof(int)))) return rc;
   if ((rc = c.tolv.ensure(c.cap * sizeof(double)))) return rc;
   if (hipStreamCreateWithFlags(&c.stream, hipStreamNonBlocking) != hipSuccess)
     return fail(DBAR_EDEVICE, "stream creation failed");
   c.slots.assign(c.cap, nullptr);
   c.h_new.assign(c.cap, 0);
-  c.h_fin.assign(c.cap, 0);
   c.h_live.assign(c.cap, 0);
   c.h_tol.assign(c.cap, 1e-10);
   c.h_k.assign(c.cap, c64{0.0, 0.0});
@@ -187,6 +189,7 @@ static void worker(dbar_session* s, SClass* cp) {
       launch_reduce(static_cast<double*>(w.part_vec.p), 1, c.P.rhs_blocks(),
                     static_cast<double*>(w.nred.p), c.cap, nm, c.stream);
       launch_ctl_check(w, 0.0, 1, nm, static_cast<const double*>(c.tolv.p), c.stream);
+      launch_zero_done(w, nm, c.stream);  // admitted requests with b = 0: S = m = 0
       if (mixed)
         launch_convert<float, double>(w.bvec.p, n, w.V.p, V_bs, n, c.cap, nm, 1.0, c.stream);
       else
@@ -222,7 +225,6 @@ static void worker(dbar_session* s, SClass* cp) {
       return;
     }
     // ---- finish converged (or exhausted) requests
-    std::fill(c.h_fin.begin(), c.h_fin.end(), 0);
     std::vector<int> fin;
     for (int b = 0; b < c.cap; ++b) {
       if (!c.slots[b] || !c.h_live[b]) continue;
@@ -230,25 +232,22 @@ static void worker(dbar_session* s, SClass* cp) {
       const bool done = live_now[b] == 0;
       const bool exhausted = !done && c.slots[b]->iters >= cfg.max_iter;
       if (done || exhausted || ran == 0) {
-        c.h_fin[b] = 1;
         c.h_live[b] = 0;
         fin.push_back(b);
         c.slots[b]->info.status = done ? DBAR_OK : DBAR_ENOCONV;
       }
     }
     if (fin.empty()) continue;
-    (void)hipMemcpyAsync(c.finmask.p, c.h_fin.data(), c.cap * sizeof(int), hipMemcpyHostToDevice, c.stream);
     (void)hipMemcpyAsync(w.live.p, c.h_live.data(), c.cap * sizeof(int), hipMemcpyHostToDevice, c.stream);
-    c.P.h_of<double>(w.x.p, n, w.T64.p, n, w.bvec.p, c.cap, static_cast<const int*>(c.finmask.p), c.stream);
     std::vector<Ctl> ctl_out(fin.size());
     for (size_t i = 0; i < fin.size(); ++i) {
       const int b = fin[i];
       SReq& r = *c.slots[b];
       r.S.resize(n);
       r.m.resize(n);
-      (void)hipMemcpyAsync(r.S.data(), static_cast<c64*>(w.x.p) + (size_t)b * n, n * sizeof(c64),
+      (void)hipMemcpyAsync(r.S.data(), static_cast<c64*>(w.Sx.p) + (size_t)b * n, n * sizeof(c64),
                            hipMemcpyDeviceToHost, c.stream);
-      (void)hipMemcpyAsync(r.m.data(), static_cast<c64*>(w.T64.p) + (size_t)b * n, n * sizeof(c64),
+      (void)hipMemcpyAsync(r.m.data(), static_cast<c64*>(w.mx.p) + (size_t)b * n, n * sizeof(c64),
                            hipMemcpyDeviceToHost, c.stream);
       (void)hipMemcpyAsync(&ctl_out[i], static_cast<Ctl*>(w.ctl.p) + b, sizeof(Ctl), hipMemcpyDeviceToHost,
                            c.stream);

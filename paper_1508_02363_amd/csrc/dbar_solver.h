@@ -198,6 +198,8 @@ int make_pipeline(const dbar_grid* g, Work& w, Pipeline* p);
 void launch_phase_tables(const c64* kv_dev, int N, double L, c64* ex, c64* ey, c32* ex32, c32* ey32, int B,
                          hipStream_t s);
 int run_batch(const Pipeline& P, Work& w, const BatchCfg& cfg, hipStream_t s, std::vector<int>& iters_out);
+// x-space: S = m = 0 (w.Sx, w.mx) for entries that are not live (and in mask, if given): done before any residual
+void launch_zero_done(Work& w, const int* mask, hipStream_t s);
 int ctl_blocks(int B);
 // one lockstep Krylov cycle over the entries flagged in w.act; returns the iterations run
 template <typename T>

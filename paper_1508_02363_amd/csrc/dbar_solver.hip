@@ -581,9 +581,9 @@ void Pipeline::apply_x(const void* in, size_t in_bs, void* out, size_t out_bs, c
 
 // x-space right-hand side F^{-1} b = -i q_k = -i Q e_k (b = -i F(q_k)), with |.|^2 partials per block
 __global__ void __launch_bounds__(256) k_rhs_x(const c64* Q, size_t Q_bs, const c64* ex, const c64* ey, size_t e_bs,
-                                               int N, c64* out, double* part, int B) {
+                                               int N, c64* out, double* part, int B, const int* act) {
   const int b = blockIdx.y;
-  if (b >= B) return;
+  if (b >= B || (act && !act[b])) return;
   const size_t n = (size_t)N * N;
   double acc = 0.0;
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
@@ -624,7 +624,7 @@ void Pipeline::rhs(const void* Q64p, size_t Q_bs, void* T64, c64* bout, int B, c
   if (xspace) {
     TimerScope ts(kStageConvert, 2.0 * (double)n * sizeof(c64), B, act, s);
     hipLaunchKernelGGL(k_rhs_x, dim3(rhs_blocks(), B), dim3(256), 0, s, static_cast<const c64*>(Q64p), Q_bs, a.ex,
-                       a.ey, a.e_bs, N, bout, part_vec, B);
+                       a.ey, a.e_bs, N, bout, part_vec, B, act);
     return;
   }
   a.tw = tw_of<double>(tw);
@@ -906,13 +906,19 @@ void launch_ctl_start(Work& w, double abs_tol, double rel_tol, const double* tol
                      static_cast<int*>(w.act.p), abs_tol, rel_tol, tolv, w.B);
 }
 
-__global__ void k_zero_done(c64* a, c64* b2, const int* live, size_t n) {
+__global__ void k_zero_done(c64* a, c64* b2, const int* live, const int* mask, size_t n) {
   const int b = blockIdx.y;
-  if (live[b]) return;
+  if (live[b] || (mask && !mask[b])) return;
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
     a[(size_t)b * n + i] = c64{0.0, 0.0};
     b2[(size_t)b * n + i] = c64{0.0, 0.0};
   }
+}
+
+void launch_zero_done(Work& w, const int* mask, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_done, dim3((unsigned)std::min<size_t>(1024, (w.n + 255) / 256), w.B), dim3(256), 0, s,
+                     static_cast<c64*>(w.Sx.p), static_cast<c64*>(w.mx.p), static_cast<const int*>(w.live.p), mask,
+                     w.n);
 }
 
 int run_batch(const Pipeline& P, Work& w, const BatchCfg& cfg, hipStream_t s, std::vector<int>& iters_out) {
@@ -935,8 +941,7 @@ int run_batch(const Pipeline& P, Work& w, const BatchCfg& cfg, hipStream_t s, st
   // r0 = b (x0 = 0); entries with b = 0 are done at once
   hipLaunchKernelGGL(k_ctl_check, dim3(ctl_blocks(B)), dim3(64), 0, s, ctl, nred, live, 0.0, 1, nullptr, nullptr, B);
   if (P.xspace) {  // S = m = 0 for entries with b = 0 (no residual evaluation writes them)
-    hipLaunchKernelGGL(k_zero_done, dim3(std::min<size_t>(1024, (n + 255) / 256), B), dim3(256), 0, s,
-                       static_cast<c64*>(w.Sx.p), static_cast<c64*>(w.mx.p), live, n);
+    launch_zero_done(w, nullptr, s);
   }
   if (mixed) {
     launch_convert<float, double>(w.bvec.p, n, w.V.p, n * (w.m + 1), n, B, nullptr, 1.0, s);
