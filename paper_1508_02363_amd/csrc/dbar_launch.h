@@ -46,6 +46,8 @@ struct LineArgs {
   const c32* dmom32 = nullptr; // the same rounded to FP32 (FP32 operator)
   void* hout = nullptr;        size_t hout_bs = 0;  // ColsInvTail(Fwd), RowsInvTail(Epilogue): h (optional on the latter)
   void* sout = nullptr;        size_t sout_bs = 0;  // ColsFwdRegularInv: S before the division (optional)
+  void* out32 = nullptr;       size_t out32_bs = 0; // RowsInvTailEpilogue (FP64): the result rounded to FP32 (optional;
+                                                    // out may then be null)
   double* part = nullptr;      // per-block partial sums [b][tile][nval]
   const void* tw = nullptr;    // twiddle table exp(-2 pi i j / N), j < N, in the transform's precision
   double L = 1.0, ci = 1.0, cf = 1.0;

@@ -740,7 +740,10 @@ struct OpRowsInvTailEpi : OpColsInvTail<T, N, false> {
         } else {  // the FP32 operator's result is FP32: form it in FP32
           ot = cvt<T>(a.beta) * w + static_cast<T>(a.alpha) * cur.s[u] + static_cast<T>(a.gamma) * cur.y[u];
         }
-        this->outp(b)[base + pos] = ot;
+        if (a.out) this->outp(b)[base + pos] = ot;
+        if constexpr (sizeof(T) == 8) {
+          if (a.out32) (static_cast<c32*>(a.out32) + (size_t)b * a.out32_bs)[base + pos] = cvt<float>(ot);
+        }
         slot = ot;
         const c64 od = cvt<double>(ot), sd = cvt<double>(cur.s[u]);
         acc.v[0] += norm2(od);

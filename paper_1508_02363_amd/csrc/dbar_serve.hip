@@ -207,9 +207,7 @@ static void worker(dbar_session* s, SClass* cp) {
       end_cycle<double>(c.P, w, ran, w.V.p, c.stream);
     }
     launch_ctl_check(w, 0.0, 0, nullptr, static_cast<const double*>(c.tolv.p), c.stream);
-    if (mixed)
-      launch_convert<float, double>(w.r64.p, n, w.V.p, V_bs, n, c.cap, static_cast<const int*>(w.live.p), 1.0,
-                                    c.stream);
+    // (x-space: the residual evaluation wrote the next cycle's FP32 basis vector itself)
     std::vector<int> live_now(c.cap);
     (void)hipMemcpyAsync(live_now.data(), w.live.p, c.cap * sizeof(int), hipMemcpyDeviceToHost, c.stream);
     if (hipStreamSynchronize(c.stream) != hipSuccess) {

@@ -117,6 +117,15 @@ constexpr unsigned kShifted = 1u;    // regularise about xi = a = 2i conj(k) (Se
 constexpr unsigned kUnitPhase = 2u;  // k = 0 phase (the operator K0 of equation shift)
 
 // Gram-Schmidt products fused into the operator's last kernel: Re<V_i, out> for i < nv as per-tile partials
+// Extra outputs of the x-space operator: S = F s and h(S) of the input (strides n), and the result rounded to FP32
+// (r32, stride r32_bs; with out = null the FP64 result itself is not stored).  Any may be null.
+struct XOut {
+  void* S = nullptr;
+  void* h = nullptr;
+  void* r32 = nullptr;
+  size_t r32_bs = 0;
+};
+
 struct DotReq {
   const void* V = nullptr;
   size_t V_bs = 0;
@@ -155,12 +164,12 @@ struct Pipeline {
   void apply_impl(const void* in, size_t in_bs, void* out, size_t out_bs, const void* Qp, size_t Q_bs, void* Tbuf,
                   int B, const int* act, double alpha, double beta, const void* Y, size_t Y_bs, bool want_norm,
                   unsigned flags, const void* S_ep, size_t S_ep_bs, hipStream_t s, const DotReq* dr = nullptr) const;
-  // A(S) of the plain method (Section 4), as alpha S + beta i F(q_k conj(h(S))) + gamma Y
+  // A(S) of the plain method (Section 4), as alpha S + beta i F(q_k conj(h(S))) + gamma Y; in x-space (xspace) the
+  // same on s = F^{-1} S, with the extra outputs xo names (may be null)
   template <typename T>
-  // In x-space Sout / Hout (strides n, may be null) also receive S = F s and h(S) of the input.
   void apply(const void* in, size_t in_bs, void* out, size_t out_bs, const void* Qp, size_t Q_bs, void* Tbuf, int B,
              const int* act, double alpha, double beta, const void* Y, size_t Y_bs, bool want_norm,
-             hipStream_t s, const DotReq* dr = nullptr, void* Sout = nullptr, void* Hout = nullptr) const;
+             hipStream_t s, const DotReq* dr = nullptr, const XOut* xo = nullptr) const;
   // H(h) of equation eqh2
   template <typename T>
   void H_of(const void* in, size_t in_bs, void* Hout, size_t H_bs, const void* Qp, size_t Q_bs, void* Tbuf, int B,
@@ -181,7 +190,7 @@ struct Pipeline {
   template <typename T>
   void apply_x(const void* in, size_t in_bs, void* out, size_t out_bs, const void* Qp, size_t Q_bs, void* Tbuf,
                int B, const int* act, double alpha, double beta, const void* Y, size_t Y_bs, bool want_norm,
-               hipStream_t s, const DotReq* dr, void* Sout, void* Hout) const;
+               hipStream_t s, const DotReq* dr, const XOut* xo) const;
 };
 
 void launch_roll_add(const c64* f, const c64* h, const int* shv, int N, c64* out, int B, hipStream_t s);

@@ -515,9 +515,9 @@ void Pipeline::apply_impl(const void* in, size_t in_bs, void* out, size_t out_bs
 template <typename T>
 void Pipeline::apply(const void* in, size_t in_bs, void* out, size_t out_bs, const void* Qp, size_t Q_bs, void* Tbuf,
                      int B, const int* act, double alpha, double beta, const void* Y, size_t Y_bs, bool want_norm,
-                     hipStream_t s, const DotReq* dr, void* Sout, void* Hout) const {
+                     hipStream_t s, const DotReq* dr, const XOut* xo) const {
   if (xspace) {
-    apply_x<T>(in, in_bs, out, out_bs, Qp, Q_bs, Tbuf, B, act, alpha, beta, Y, Y_bs, want_norm, s, dr, Sout, Hout);
+    apply_x<T>(in, in_bs, out, out_bs, Qp, Q_bs, Tbuf, B, act, alpha, beta, Y, Y_bs, want_norm, s, dr, xo);
     return;
   }
   apply_impl<T>(in, in_bs, out, out_bs, Qp, Q_bs, Tbuf, B, act, alpha, beta, Y, Y_bs, want_norm, 0u, nullptr, 0, s,
@@ -534,7 +534,7 @@ int Pipeline::rhs_blocks() const { return xspace ? vec_blocks(n) : line_tiles(N,
 template <typename T>
 void Pipeline::apply_x(const void* in, size_t in_bs, void* out, size_t out_bs, const void* Qp, size_t Q_bs,
                        void* Tbuf, int B, const int* act, double alpha, double beta, const void* Y, size_t Y_bs,
-                       bool want_norm, hipStream_t s, const DotReq* dr, void* Sout, void* Hout) const {
+                       bool want_norm, hipStream_t s, const DotReq* dr, const XOut* xo) const {
   LineArgs a = base(B, act, 0u);
   a.tw = tw_of<T>(tw);
   a.in = in;
@@ -551,12 +551,14 @@ void Pipeline::apply_x(const void* in, size_t in_bs, void* out, size_t out_bs, c
   }
   a.in = Tbuf;  // in place: a column tile is read whole before it is written
   a.in_bs = n;
-  a.sout = Sout;
+  a.sout = xo ? xo->S : nullptr;
   a.sout_bs = n;
   launch_lines_any<T>(N, LineOp::ColsFwdRegularInv, a, s);
   a.sout = nullptr;
-  a.hout = Hout;
+  a.hout = xo ? xo->h : nullptr;
   a.hout_bs = n;
+  a.out32 = xo ? xo->r32 : nullptr;
+  a.out32_bs = xo ? xo->r32_bs : 0;
   a.Q = Qp;
   a.Q_bs = Q_bs;
   a.out = out;
@@ -692,7 +694,7 @@ void Pipeline::transform(bool inverse, const void* in, void* out, void* Tbuf, hi
 #define DBAR_PIPE_INST(T)                                                                                        \
   template void Pipeline::apply<T>(const void*, size_t, void*, size_t, const void*, size_t, void*, int,            \
                                    const int*, double, double, const void*, size_t, bool, hipStream_t,            \
-                                   const DotReq*, void*, void*) const;                                            \
+                                   const DotReq*, const XOut*) const;                                             \
   template void Pipeline::apply_B<T>(const void*, size_t, void*, size_t, const void*, size_t, void*, void*, int,   \
                                      const int*, double, double, const void*, size_t, bool, hipStream_t,          \
                                      const DotReq*) const;                                                        \
@@ -703,7 +705,7 @@ void Pipeline::transform(bool inverse, const void* in, void* out, void* Tbuf, hi
   template void Pipeline::transform<T>(bool, const void*, void*, void*, hipStream_t) const;                      \
   template void Pipeline::apply_x<T>(const void*, size_t, void*, size_t, const void*, size_t, void*, int,          \
                                      const int*, double, double, const void*, size_t, bool, hipStream_t,          \
-                                     const DotReq*, void*, void*) const;
+                                     const DotReq*, const XOut*) const;
 DBAR_PIPE_INST(double)
 DBAR_PIPE_INST(float)
 #undef DBAR_PIPE_INST
@@ -882,9 +884,21 @@ void end_cycle(const Pipeline& P, Work& w, int nv, void* r_out, hipStream_t s, i
   if (method == 1)
     P.apply_B<double>(w.x.p, n, r_out, r_bs, w.Q64.p, w.Q_bs, w.T64.p, w.Hbuf.p, B, live, -1.0, -1.0, w.bvec.p, n,
                       true, s);
-  else  // x-space: S = F x and m = h(S) of this x come along (the last evaluation's are the outputs)
-    P.apply<double>(w.x.p, n, r_out, r_bs, w.Q64.p, w.Q_bs, w.T64.p, B, live, -1.0, -1.0, w.bvec.p, n, true, s,
-                    nullptr, P.xspace ? w.Sx.p : nullptr, P.xspace ? w.mx.p : nullptr);
+  else if (!P.xspace)
+    P.apply<double>(w.x.p, n, r_out, r_bs, w.Q64.p, w.Q_bs, w.T64.p, B, live, -1.0, -1.0, w.bvec.p, n, true, s);
+  else {
+    // x-space: S = F x and m = h(S) of this x come along (the last evaluation's are the outputs); the mixed
+    // solver's residual goes straight to the next cycle's first basis vector in FP32
+    XOut xo;
+    xo.S = w.Sx.p;
+    xo.h = w.mx.p;
+    if (sizeof(T) == 4) {
+      xo.r32 = w.V.p;
+      xo.r32_bs = n * (w.m + 1);
+    }
+    P.apply<double>(w.x.p, n, sizeof(T) == 4 ? nullptr : r_out, r_bs, w.Q64.p, w.Q_bs, w.T64.p, B, live, -1.0, -1.0,
+                    w.bvec.p, n, true, s, nullptr, &xo);
+  }
   launch_reduce(static_cast<double*>(w.part_vec.p), 1, P.apply_tiles(true), static_cast<double*>(w.nred.p), B, live,
                 s);
 }
@@ -969,7 +983,7 @@ int run_batch(const Pipeline& P, Work& w, const BatchCfg& cfg, hipStream_t s, st
     }
     total += ran;
     hipLaunchKernelGGL(k_ctl_check, dim3(ctl_blocks(B)), dim3(64), 0, s, ctl, nred, live, cfg.tol, 0, nullptr, nullptr, B);
-    if (mixed) launch_convert<float, double>(w.r64.p, n, w.V.p, n * (w.m + 1), n, B, live, 1.0, s);
+    if (mixed && !P.xspace) launch_convert<float, double>(w.r64.p, n, w.V.p, n * (w.m + 1), n, B, live, 1.0, s);
     if (ran == 0) break;
   }
   if (hipStreamSynchronize(s) != hipSuccess) return fail(DBAR_EDEVICE, "stream synchronize failed");
