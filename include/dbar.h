@@ -84,7 +84,8 @@ typedef struct {
                           the grid (three line-transform launches per application instead of five); F is unitary up
                           to a constant, so the Krylov steps and the residual ratio are those of S up to rounding.
                           DBAR_SPACE_XI: S itself, as written in Section 4.  The iterated method always uses xi. */
-  double inner_tol;    /* DBAR_MIXED: residual reduction asked of each FP32 inner solve (default 1e-5) */
+  double inner_tol;    /* DBAR_MIXED: residual reduction asked of each FP32 inner solve; 0 (default) = 1e-6 for
+                          the plain method in x-space, 1e-5 otherwise */
 } dbar_opts;
 
 enum { DBAR_METHOD_PLAIN = 0, DBAR_METHOD_ITERATED = 1 };

@@ -138,7 +138,7 @@ static void worker(dbar_session* s, SClass* cp) {
   cfg.max_iter = 1000;
   cfg.reorth = 1;
   cfg.check_every = 4;
-  cfg.inner_tol = 1e-5;
+  cfg.inner_tol = 1e-6;  // x-space inner solves
   while (!s->stop.load()) {
     // ---- admission at the cycle boundary
     std::vector<int> admitted;

@@ -88,7 +88,7 @@ struct BatchCfg {
   int max_iter = 1000;
   int reorth = 1;
   int check_every = 4;
-  double inner_tol = 1e-5;
+  double inner_tol = 1e-6;
   int xspace = 0;  // the plain method iterates on s = F^{-1} S
 };
 

@@ -50,7 +50,7 @@ def default_opts() -> _lib.Opts:
 
 
 def make_opts(precision=DBAR_FP64, mode=DBAR_MODE_BATCHED, restart=0, max_iter=1000, batch=0, use_graph=1,
-              reorth=1, check_every=4, inner_tol=1e-5, method=DBAR_METHOD_PLAIN, space=DBAR_SPACE_X) -> _lib.Opts:
+              reorth=1, check_every=4, inner_tol=0.0, method=DBAR_METHOD_PLAIN, space=DBAR_SPACE_X) -> _lib.Opts:
     o = default_opts()
     o.method = method
     o.space = space

@@ -96,7 +96,7 @@ def test_request_footprint_is_monotone_in_grid_and_restart():
 def test_default_opts():
     o = _lib.Opts()
     _lib.load().dbar_default_opts(ctypes.byref(o))
-    assert o.max_iter == 1000 and o.reorth == 1 and o.precision == _lib.DBAR_FP64 and o.inner_tol == 1e-5
+    assert o.max_iter == 1000 and o.reorth == 1 and o.precision == _lib.DBAR_FP64 and o.inner_tol == 0.0
 
 
 def test_reflection_and_reconstruction_reject_bad_arguments():
