@@ -81,7 +81,9 @@ def stored_traffic(kernel: str):
 def stage_of_kernel(name: str):
     """Stage name (as reported by the library's launch timer) of a demangled kernel name from rocprofv3."""
     ops = {"OpRowsInvScaled": "RowsInvScaled", "OpColsInvMoments": "ColsInvMoments", "OpRowsInvRegular":
-           "RowsInvRegular", "OpRowsFwdEpilogue": "RowsFwdEpilogue", "OpColsFwdPotential": "ColsFwdPotential"}
+           "RowsInvRegular", "OpRowsFwdEpilogue": "RowsFwdEpilogue", "OpColsFwdPotential": "ColsFwdPotential",
+           "OpRowsFwdMoments": "RowsFwdMoments", "OpColsFwdRegInv": "ColsFwdRegularInv",
+           "OpRowsInvTailEpi": "RowsInvTailEpilogue"}
     prec = "f32" if "<float" in name else "f64"
     if "k_lines" in name:
         if "OpColsInvTail" in name:
