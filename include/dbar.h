@@ -79,13 +79,14 @@ typedef struct {
   int32_t method;      /* DBAR_METHOD_PLAIN (Section 4, default) or DBAR_METHOD_ITERATED (Section 5.3: the once-iterated
                           equation eqh2 for h with the regularisation about xi = 2i conj(k), for large |k|; needs
                           2 L Re k and 2 L Im k to be integers, i.e. 2k on the xi grid, else DBAR_EINVAL) */
-  int32_t space;       /* plain method: the vector GMRES iterates on.  DBAR_SPACE_X (default): s = F^{-1} S, on which
-                          the operator is s + i q_k conj(h) and the moments of equation fourreeg4 are plain sums over
-                          the grid (three line-transform launches per application instead of five); F is unitary up
-                          to a constant, so the Krylov steps and the residual ratio are those of S up to rounding.
-                          DBAR_SPACE_XI: S itself, as written in Section 4.  The iterated method always uses xi. */
-  double inner_tol;    /* DBAR_MIXED: residual reduction asked of each FP32 inner solve; 0 (default) = 1e-6 for
-                          the plain method in x-space, 1e-5 otherwise */
+  int32_t space;       /* the vector GMRES iterates on.  DBAR_SPACE_X (default): s = F^{-1} S (iterated method:
+                          F^{-1} h), on which the plain operator is s + i q_k conj(h) and the moments of equation
+                          fourreeg4 are plain sums over the grid (three line-transform launches per application
+                          instead of five; six instead of ten for the iterated method's B); F is unitary up to a
+                          constant, so the Krylov steps and the residual ratio are those of S up to rounding.
+                          DBAR_SPACE_XI: S (or h) itself, as written in Sections 4 and 5.3. */
+  double inner_tol;    /* DBAR_MIXED: residual reduction asked of each FP32 inner solve; 0 (default) = 1e-6 in
+                          x-space, 1e-5 in xi-space */
 } dbar_opts;
 
 enum { DBAR_METHOD_PLAIN = 0, DBAR_METHOD_ITERATED = 1 };

@@ -189,7 +189,7 @@ static void worker(dbar_session* s, SClass* cp) {
       launch_reduce(static_cast<double*>(w.part_vec.p), 1, c.P.rhs_blocks(),
                     static_cast<double*>(w.nred.p), c.cap, nm, c.stream);
       launch_ctl_check(w, 0.0, 1, nm, static_cast<const double*>(c.tolv.p), c.stream);
-      launch_zero_done(w, nm, c.stream);  // admitted requests with b = 0: S = m = 0
+      launch_zero_done(w, nm, false, c.stream);  // admitted requests with b = 0: S = m = 0
       if (mixed)
         launch_convert<float, double>(w.bvec.p, n, w.V.p, V_bs, n, c.cap, nm, 1.0, c.stream);
       else

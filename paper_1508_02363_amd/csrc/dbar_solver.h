@@ -107,6 +107,7 @@ struct Work {
   DevBuf x, bvec, T64, r64, T32, V, Q64, Q32, ex, ey, ex32, ey32, coefG, dmom, dmom32, part_mom, part_vec, part_norm,
       dred, nred, ctl, act, live, kvals, results, shv, unit, unit32, Hbuf;
   DevBuf Sx, mx;  // x-space solves: S = F x and m = h(S) of the last residual evaluation (FP64)
+  DevBuf Fx, Ax;  // x-space iterated solves: f = H(h) and the shifted inverse of h of the last residual evaluation
   PinnedInts host_act, host_live;
   int setup(int N_, int B_, int m_, int prec_, bool shared_q);
   size_t vec_bytes(int prec) const;
@@ -122,6 +123,17 @@ constexpr unsigned kUnitPhase = 2u;  // k = 0 phase (the operator K0 of equation
 struct XOut {
   void* S = nullptr;
   void* h = nullptr;
+  void* r32 = nullptr;
+  size_t r32_bs = 0;
+};
+
+// Extra outputs of the x-space iterated operator (Section 5.3; ξ-space arrays except ha and h0, strides n): h = F eta,
+// f = H(h), ha = the shifted regularised inverse of h, h0 = h(f); r32 as in XOut.  Any may be null.
+struct XOutB {
+  void* hxi = nullptr;
+  void* f = nullptr;
+  void* ha = nullptr;
+  void* h0 = nullptr;
   void* r32 = nullptr;
   size_t r32_bs = 0;
 };
@@ -176,9 +188,10 @@ struct Pipeline {
             const int* act, hipStream_t s) const;
   // B(h) = h - K0(H(h)) of equation eqh2, as alpha h + beta i F(Q conj(F^{-1}(H/xi))) + gamma Y
   template <typename T>
+  // In x-space (xspace) the same on eta = F^{-1} h: eta + i q conj(h0(F psi)) with psi = F^{-1} H(F eta) in Hbuf.
   void apply_B(const void* in, size_t in_bs, void* out, size_t out_bs, const void* Qp, size_t Q_bs, void* Tbuf,
                void* Hbuf, int B, const int* act, double alpha, double beta, const void* Y, size_t Y_bs,
-               bool want_norm, hipStream_t s, const DotReq* dr = nullptr) const;
+               bool want_norm, hipStream_t s, const DotReq* dr = nullptr, const XOutB* xb = nullptr) const;
   void rhs(const void* Q64p, size_t Q_bs, void* T64, c64* bout, int B, const int* act, unsigned flags,
            hipStream_t s) const;
   template <typename T>
@@ -187,13 +200,16 @@ struct Pipeline {
   template <typename T>
   void transform(bool inverse, const void* in, void* out, void* Tbuf, hipStream_t s) const;
   // x-space operator: F^{-1} A(F s) = alpha s + beta i q_k conj(h(F s)) + gamma Y (three line launches)
+  // flags: kShifted / kUnitPhase as in base(); S_ep: the alpha term's vector (null: the input)
   template <typename T>
   void apply_x(const void* in, size_t in_bs, void* out, size_t out_bs, const void* Qp, size_t Q_bs, void* Tbuf,
                int B, const int* act, double alpha, double beta, const void* Y, size_t Y_bs, bool want_norm,
-               hipStream_t s, const DotReq* dr, const XOut* xo) const;
+               hipStream_t s, const DotReq* dr, const XOut* xo, unsigned flags = 0u, const void* S_ep = nullptr,
+               size_t S_ep_bs = 0) const;
 };
 
 void launch_roll_add(const c64* f, const c64* h, const int* shv, int N, c64* out, int B, hipStream_t s);
+void launch_add_phase(c64* m, const c64* ha, const c64* ex, const c64* ey, int N, int B, hipStream_t s);
 
 int validate_grid(const dbar_grid* g);
 // batched solve behind dbar_solve / dbar_solve_device; r_out (host, nk complex or NULL) receives i h(2i conj k) of
@@ -207,8 +223,9 @@ int make_pipeline(const dbar_grid* g, Work& w, Pipeline* p);
 void launch_phase_tables(const c64* kv_dev, int N, double L, c64* ex, c64* ey, c32* ex32, c32* ey32, int B,
                          hipStream_t s);
 int run_batch(const Pipeline& P, Work& w, const BatchCfg& cfg, hipStream_t s, std::vector<int>& iters_out);
-// x-space: S = m = 0 (w.Sx, w.mx) for entries that are not live (and in mask, if given): done before any residual
-void launch_zero_done(Work& w, const int* mask, hipStream_t s);
+// x-space: the residual evaluation's outputs (w.Sx, w.mx; with iterated also w.Fx, w.Ax) = 0 for entries that are
+// not live (and in mask, if given): those no residual evaluation writes
+void launch_zero_done(Work& w, const int* mask, bool iterated, hipStream_t s);
 int ctl_blocks(int B);
 // one lockstep Krylov cycle over the entries flagged in w.act; returns the iterations run
 template <typename T>

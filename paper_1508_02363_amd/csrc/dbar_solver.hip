@@ -534,8 +534,9 @@ int Pipeline::rhs_blocks() const { return xspace ? vec_blocks(n) : line_tiles(N,
 template <typename T>
 void Pipeline::apply_x(const void* in, size_t in_bs, void* out, size_t out_bs, const void* Qp, size_t Q_bs,
                        void* Tbuf, int B, const int* act, double alpha, double beta, const void* Y, size_t Y_bs,
-                       bool want_norm, hipStream_t s, const DotReq* dr, const XOut* xo) const {
-  LineArgs a = base(B, act, 0u);
+                       bool want_norm, hipStream_t s, const DotReq* dr, const XOut* xo, unsigned flags,
+                       const void* S_ep, size_t S_ep_bs) const {
+  LineArgs a = base(B, act, flags);
   a.tw = tw_of<T>(tw);
   a.in = in;
   a.in_bs = in_bs;
@@ -563,8 +564,8 @@ void Pipeline::apply_x(const void* in, size_t in_bs, void* out, size_t out_bs, c
   a.Q_bs = Q_bs;
   a.out = out;
   a.out_bs = out_bs;
-  a.S = in;
-  a.S_bs = in_bs;
+  a.S = S_ep ? S_ep : in;
+  a.S_bs = S_ep ? S_ep_bs : in_bs;
   a.alpha = alpha;
   a.beta = c64{0.0, beta};
   a.Y = Y;
@@ -613,7 +614,28 @@ void Pipeline::H_of(const void* in, size_t in_bs, void* Hout, size_t H_bs, const
 template <typename T>
 void Pipeline::apply_B(const void* in, size_t in_bs, void* out, size_t out_bs, const void* Qp, size_t Q_bs,
                        void* Tbuf, void* Hbuf, int B, const int* act, double alpha, double beta, const void* Y,
-                       size_t Y_bs, bool want_norm, hipStream_t s, const DotReq* dr) const {
+                       size_t Y_bs, bool want_norm, hipStream_t s, const DotReq* dr, const XOutB* xb) const {
+  if (xspace) {
+    // psi = F^{-1} H(F eta) = -i q conj(h_a(F eta)) (regularised about xi = a; q alone): the operator's three launches
+    // with the shifted regularisation and alpha = 0 ...
+    XOut xh;
+    if (xb) {
+      xh.S = xb->hxi;
+      xh.h = xb->ha;
+    }
+    apply_x<T>(in, in_bs, Hbuf, n, Qp, Q_bs, Tbuf, B, act, 0.0, -1.0, nullptr, 0, false, s, nullptr, &xh, kShifted);
+    // ... then eta + i q conj(h0(F psi)) (k = 0 phase, about xi = 0), the alpha term and the products taken with eta
+    XOut x0;
+    if (xb) {
+      x0.S = xb->f;
+      x0.h = xb->h0;
+      x0.r32 = xb->r32;
+      x0.r32_bs = xb->r32_bs;
+    }
+    apply_x<T>(Hbuf, n, out, out_bs, Qp, Q_bs, Tbuf, B, act, alpha, beta, Y, Y_bs, want_norm, s, dr, &x0,
+               kUnitPhase, in, in_bs);
+    return;
+  }
   H_of<T>(in, in_bs, Hbuf, n, Qp, Q_bs, Tbuf, B, act, s);
   apply_impl<T>(Hbuf, n, out, out_bs, Qp, Q_bs, Tbuf, B, act, alpha, beta, Y, Y_bs, want_norm, kUnitPhase, in,
                 in_bs, s, dr);
@@ -697,7 +719,7 @@ void Pipeline::transform(bool inverse, const void* in, void* out, void* Tbuf, hi
                                    const DotReq*, const XOut*) const;                                             \
   template void Pipeline::apply_B<T>(const void*, size_t, void*, size_t, const void*, size_t, void*, void*, int,   \
                                      const int*, double, double, const void*, size_t, bool, hipStream_t,          \
-                                     const DotReq*) const;                                                        \
+                                     const DotReq*, const XOutB*) const;                                          \
   template void Pipeline::H_of<T>(const void*, size_t, void*, size_t, const void*, size_t, void*, int, const int*, \
                                   hipStream_t) const;                                                            \
   template void Pipeline::h_of<T>(const void*, size_t, void*, size_t, void*, int, const int*, hipStream_t,         \
@@ -705,7 +727,7 @@ void Pipeline::transform(bool inverse, const void* in, void* out, void* Tbuf, hi
   template void Pipeline::transform<T>(bool, const void*, void*, void*, hipStream_t) const;                      \
   template void Pipeline::apply_x<T>(const void*, size_t, void*, size_t, const void*, size_t, void*, int,          \
                                      const int*, double, double, const void*, size_t, bool, hipStream_t,          \
-                                     const DotReq*, const XOut*) const;
+                                     const DotReq*, const XOut*, unsigned, const void*, size_t) const;
 DBAR_PIPE_INST(double)
 DBAR_PIPE_INST(float)
 #undef DBAR_PIPE_INST
@@ -721,6 +743,23 @@ __global__ void k_roll_add(const c64* f, const c64* h, const int* shv, int N, c6
     const size_t src = (size_t)((p2 + o2) & (N - 1)) * N + ((p1 + o1) & (N - 1));
     out[(size_t)b * n + i] = f[(size_t)b * n + i] + h[(size_t)b * n + src];
   }
+}
+
+// m += e_k h_a on the x grid (e_k = ex[x index] ey[y index]): the second term of m in the iterated method
+__global__ void k_add_phase(c64* m, const c64* ha, const c64* ex, const c64* ey, int N, int B) {
+  const int b = blockIdx.y;
+  if (b >= B) return;
+  const size_t n = (size_t)N * N;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    const int p2 = (int)(i / N), p1 = (int)(i % N);
+    const size_t o = (size_t)b * n + i;
+    m[o] = m[o] + (ex[(size_t)b * N + p1] * ey[(size_t)b * N + p2]) * ha[o];
+  }
+}
+
+void launch_add_phase(c64* m, const c64* ha, const c64* ex, const c64* ey, int N, int B, hipStream_t s) {
+  TimerScope ts(kStageConvert, 3.0 * (double)N * N * sizeof(c64), B, nullptr, s);
+  hipLaunchKernelGGL(k_add_phase, dim3(std::min(4096, (N * N + 255) / 256), B), dim3(256), 0, s, m, ha, ex, ey, N, B);
 }
 
 void launch_roll_add(const c64* f, const c64* h, const int* shv, int N, c64* out, int B, hipStream_t s) {
@@ -881,10 +920,24 @@ void end_cycle(const Pipeline& P, Work& w, int nv, void* r_out, hipStream_t s, i
   va.coef_bs = sizeof(Ctl) / sizeof(double);
   launch_axpy_multi<double, T>(va, s);
   const size_t r_bs = sizeof(T) == 8 ? n * (w.m + 1) : n;
-  if (method == 1)
+  if (method == 1 && !P.xspace) {
     P.apply_B<double>(w.x.p, n, r_out, r_bs, w.Q64.p, w.Q_bs, w.T64.p, w.Hbuf.p, B, live, -1.0, -1.0, w.bvec.p, n,
                       true, s);
-  else if (!P.xspace)
+  } else if (method == 1) {
+    // x-space iterated method: h = F eta, f = H(h), the shifted inverse of h and h(f) come along (S, m, m1 and r are
+    // formed from the last evaluation's); the mixed solver's residual goes straight to the next FP32 basis vector
+    XOutB xb;
+    xb.hxi = w.Sx.p;
+    xb.f = w.Fx.p;
+    xb.ha = w.Ax.p;
+    xb.h0 = w.mx.p;
+    if (sizeof(T) == 4) {
+      xb.r32 = w.V.p;
+      xb.r32_bs = n * (w.m + 1);
+    }
+    P.apply_B<double>(w.x.p, n, sizeof(T) == 4 ? nullptr : r_out, r_bs, w.Q64.p, w.Q_bs, w.T64.p, w.Hbuf.p, B, live,
+                      -1.0, -1.0, w.bvec.p, n, true, s, nullptr, &xb);
+  } else if (!P.xspace)
     P.apply<double>(w.x.p, n, r_out, r_bs, w.Q64.p, w.Q_bs, w.T64.p, B, live, -1.0, -1.0, w.bvec.p, n, true, s);
   else {
     // x-space: S = F x and m = h(S) of this x come along (the last evaluation's are the outputs); the mixed
@@ -920,19 +973,22 @@ void launch_ctl_start(Work& w, double abs_tol, double rel_tol, const double* tol
                      static_cast<int*>(w.act.p), abs_tol, rel_tol, tolv, w.B);
 }
 
-__global__ void k_zero_done(c64* a, c64* b2, const int* live, const int* mask, size_t n) {
+__global__ void k_zero_done(c64* a0, c64* a1, c64* a2, c64* a3, const int* live, const int* mask, size_t n) {
   const int b = blockIdx.y;
   if (live[b] || (mask && !mask[b])) return;
-  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-    a[(size_t)b * n + i] = c64{0.0, 0.0};
-    b2[(size_t)b * n + i] = c64{0.0, 0.0};
+  c64* const arr[4] = {a0, a1, a2, a3};
+  for (int k = 0; k < 4; ++k) {
+    if (!arr[k]) continue;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+      arr[k][(size_t)b * n + i] = c64{0.0, 0.0};
   }
 }
 
-void launch_zero_done(Work& w, const int* mask, hipStream_t s) {
+void launch_zero_done(Work& w, const int* mask, bool iterated, hipStream_t s) {
   hipLaunchKernelGGL(k_zero_done, dim3((unsigned)std::min<size_t>(1024, (w.n + 255) / 256), w.B), dim3(256), 0, s,
-                     static_cast<c64*>(w.Sx.p), static_cast<c64*>(w.mx.p), static_cast<const int*>(w.live.p), mask,
-                     w.n);
+                     static_cast<c64*>(w.Sx.p), static_cast<c64*>(w.mx.p),
+                     iterated ? static_cast<c64*>(w.Fx.p) : nullptr, iterated ? static_cast<c64*>(w.Ax.p) : nullptr,
+                     static_cast<const int*>(w.live.p), mask, w.n);
 }
 
 int run_batch(const Pipeline& P, Work& w, const BatchCfg& cfg, hipStream_t s, std::vector<int>& iters_out) {
@@ -955,7 +1011,7 @@ int run_batch(const Pipeline& P, Work& w, const BatchCfg& cfg, hipStream_t s, st
   // r0 = b (x0 = 0); entries with b = 0 are done at once
   hipLaunchKernelGGL(k_ctl_check, dim3(ctl_blocks(B)), dim3(64), 0, s, ctl, nred, live, 0.0, 1, nullptr, nullptr, B);
   if (P.xspace) {  // S = m = 0 for entries with b = 0 (no residual evaluation writes them)
-    launch_zero_done(w, nullptr, s);
+    launch_zero_done(w, nullptr, cfg.method == 1, s);
   }
   if (mixed) {
     launch_convert<float, double>(w.bvec.p, n, w.V.p, n * (w.m + 1), n, B, nullptr, 1.0, s);
@@ -1061,7 +1117,7 @@ int solve_impl(const dbar_grid* grid, const void* Q, bool q_on_device, int64_t n
   if (o.check_every <= 0) o.check_every = 4;
   // default: the x-space FP32 operator keeps 1e-6 attainable per cycle (its moments are exact sums of the FP32
   // vector); the xi-space one forms them after an FP32 round trip and stalls near 1e-5
-  const bool xspace_solve = o.method == 0 && o.space == DBAR_SPACE_X;
+  const bool xspace_solve = o.space == DBAR_SPACE_X;
   if (!(o.inner_tol > 0.0) || o.inner_tol >= 1.0) o.inner_tol = xspace_solve ? 1e-6 : 1e-5;
   if (o.method != 0 && o.method != 1) return fail(DBAR_EINVAL, "method must be 0 (plain) or 1 (iterated)");
   if (o.space != DBAR_SPACE_X && o.space != DBAR_SPACE_XI)
@@ -1117,9 +1173,12 @@ int solve_impl(const dbar_grid* grid, const void* Q, bool q_on_device, int64_t n
   if (cfg.method == 1 && (rc = w.Hbuf.ensure((size_t)B * n * sizeof(c64)))) return rc;
   cfg.check_every = o.mode == DBAR_MODE_PLAIN ? 1 : o.check_every;
   cfg.inner_tol = o.inner_tol;
-  cfg.xspace = o.method == 0 && o.space == DBAR_SPACE_X ? 1 : 0;
+  cfg.xspace = o.space == DBAR_SPACE_X ? 1 : 0;
   P.xspace = cfg.xspace != 0;
   if (cfg.xspace && ((rc = w.Sx.ensure((size_t)B * n * sizeof(c64))) || (rc = w.mx.ensure((size_t)B * n * sizeof(c64)))))
+    return rc;
+  if (cfg.xspace && cfg.method == 1 &&
+      ((rc = w.Fx.ensure((size_t)B * n * sizeof(c64))) || (rc = w.Ax.ensure((size_t)B * n * sizeof(c64)))))
     return rc;
   std::vector<EntryResult> hres(B);
   std::vector<int> shifts(2 * (size_t)B);
@@ -1139,25 +1198,37 @@ int solve_impl(const dbar_grid* grid, const void* Q, bool q_on_device, int64_t n
                         static_cast<c64*>(w.ey.p), static_cast<c32*>(w.ex32.p), static_cast<c32*>(w.ey32.p), nb, s);
     std::vector<int> its;
     if ((rc = run_batch(P, w, cfg, s, its))) return rc;
-    // outputs: S = x, m = h(x) (plain in xi-space); S = F x, m = h(F x) (plain in x-space, S into bvec); the iterated
-    // method forms S and m from h below
-    if (cfg.xspace) {
-      if (S && hipMemcpyAsync(static_cast<char*>(S) + (size_t)k0 * n * sizeof(c64), w.Sx.p,
-                              (size_t)nb * n * sizeof(c64),
-                              out_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s) != hipSuccess)
-        return fail(DBAR_EDEVICE, "S copy failed");
-      if (m && hipMemcpyAsync(static_cast<char*>(m) + (size_t)k0 * n * sizeof(c64), w.mx.p,
-                              (size_t)nb * n * sizeof(c64),
-                              out_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s) != hipSuccess)
-        return fail(DBAR_EDEVICE, "m copy failed");
-    } else if (S && cfg.method == 0) {
-      char* dst = static_cast<char*>(S) + (size_t)k0 * n * sizeof(c64);
-      if (hipMemcpyAsync(dst, w.x.p, (size_t)nb * n * sizeof(c64),
-                         out_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s) != hipSuccess)
-        return fail(DBAR_EDEVICE, "S copy failed");
-    }
-    const bool post = cfg.method == 1 && (S || m || !r_out);
-    if (post) {
+    // outputs.  Plain on s: S and m from the last residual evaluation.  Iterated on s: S = f + h o (xi + a) (equation
+    // Sform, formed in place in Fx) and m = h(f) + e_k F^{-1}(h/(xi - a)) (in place in mx) from that evaluation's
+    // h, f and inverses.  On S: S = x and m = h(x) (plain), or formed from h below (iterated).  S0src holds S(0) for
+    // m1, hsrc the iterated method's xi-space h (r = i h(a)).
+    const bool form = cfg.method == 1 && (S || m || !r_out);  // dbar_reflection alone needs only h(a)
+    const c64* S0src = static_cast<const c64*>(w.x.p);
+    const c64* hsrc = static_cast<const c64*>(w.x.p);
+    const void* Sout = nullptr;
+    const void* mout = nullptr;
+    if (cfg.xspace && cfg.method == 0) {
+      S0src = static_cast<const c64*>(w.Sx.p);
+      Sout = w.Sx.p;
+      mout = w.mx.p;
+    } else if (cfg.xspace) {
+      hsrc = static_cast<const c64*>(w.Sx.p);
+      if (form) {
+        launch_roll_add(static_cast<const c64*>(w.Fx.p), static_cast<const c64*>(w.Sx.p),
+                        static_cast<const int*>(w.shv.p), N, static_cast<c64*>(w.Fx.p), nb, s);
+        launch_add_phase(static_cast<c64*>(w.mx.p), static_cast<const c64*>(w.Ax.p), static_cast<const c64*>(w.ex.p),
+                         static_cast<const c64*>(w.ey.p), N, nb, s);
+        S0src = static_cast<const c64*>(w.Fx.p);
+        Sout = w.Fx.p;
+        mout = w.mx.p;
+      }
+    } else if (cfg.method == 0) {
+      Sout = w.x.p;
+      if (m) {
+        P.h_of<double>(w.x.p, n, w.T64.p, n, w.bvec.p, nb, nullptr, s);  // bvec reused as scratch
+        mout = w.T64.p;
+      }
+    } else if (form) {
       // f = H(h) (into Hbuf), S = f + h o (xi + a) (into bvec), m = h(f) + e_k F^{-1}(h/(xi - a)) (into T64)
       c64* Hb = static_cast<c64*>(w.Hbuf.p);
       c64* Sb = static_cast<c64*>(w.bvec.p);
@@ -1165,25 +1236,21 @@ int solve_impl(const dbar_grid* grid, const void* Q, bool q_on_device, int64_t n
       P.h_of<double>(Hb, n, w.T64.p, n, Sb, nb, nullptr, s);
       P.h_of<double>(w.x.p, n, w.T64.p, n, Sb, nb, nullptr, s, kShifted, true, true);
       launch_roll_add(Hb, static_cast<const c64*>(w.x.p), static_cast<const int*>(w.shv.p), N, Sb, nb, s);
-      if (S && hipMemcpyAsync(static_cast<char*>(S) + (size_t)k0 * n * sizeof(c64), Sb, (size_t)nb * n * sizeof(c64),
-                              out_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s) != hipSuccess)
-        return fail(DBAR_EDEVICE, "S copy failed");
-      if (m && hipMemcpyAsync(static_cast<char*>(m) + (size_t)k0 * n * sizeof(c64), w.T64.p,
-                              (size_t)nb * n * sizeof(c64),
-                              out_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s) != hipSuccess)
-        return fail(DBAR_EDEVICE, "m copy failed");
+      S0src = Sb;
+      Sout = Sb;
+      mout = w.T64.p;
     }
-    if (m && cfg.method == 0 && !cfg.xspace) {
-      P.h_of<double>(w.x.p, n, w.T64.p, n, w.bvec.p, nb, nullptr, s);  // bvec reused as scratch
-      char* dst = static_cast<char*>(m) + (size_t)k0 * n * sizeof(c64);
-      if (hipMemcpyAsync(dst, w.T64.p, (size_t)nb * n * sizeof(c64),
-                         out_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s) != hipSuccess)
-        return fail(DBAR_EDEVICE, "m copy failed");
-    }
-    hipLaunchKernelGGL(k_gather_results, dim3(ctl_blocks(nb)), dim3(64), 0, s, static_cast<const Ctl*>(w.ctl.p),
-                       static_cast<const c64*>(post ? w.bvec.p : cfg.xspace ? w.Sx.p : w.x.p), n,
-                       static_cast<const c64*>(w.x.p),
-                       cfg.method == 1 ? static_cast<const int*>(w.shv.p) : nullptr, N,
+    const hipMemcpyKind kind = out_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    if (S && Sout &&
+        hipMemcpyAsync(static_cast<char*>(S) + (size_t)k0 * n * sizeof(c64), Sout, (size_t)nb * n * sizeof(c64), kind,
+                       s) != hipSuccess)
+      return fail(DBAR_EDEVICE, "S copy failed");
+    if (m && mout &&
+        hipMemcpyAsync(static_cast<char*>(m) + (size_t)k0 * n * sizeof(c64), mout, (size_t)nb * n * sizeof(c64), kind,
+                       s) != hipSuccess)
+      return fail(DBAR_EDEVICE, "m copy failed");
+    hipLaunchKernelGGL(k_gather_results, dim3(ctl_blocks(nb)), dim3(64), 0, s, static_cast<const Ctl*>(w.ctl.p), S0src,
+                       n, hsrc, cfg.method == 1 ? static_cast<const int*>(w.shv.p) : nullptr, N,
                        static_cast<EntryResult*>(w.results.p), nb);
     (void)hipMemcpyAsync(hres.data(), w.results.p, (size_t)nb * sizeof(EntryResult), hipMemcpyDeviceToHost, s);
     (void)hipMemcpyAsync(w.host_live.data(), w.live.p, nb * sizeof(int), hipMemcpyDeviceToHost, s);
@@ -1199,8 +1266,8 @@ int solve_impl(const dbar_grid* grid, const void* Q, bool q_on_device, int64_t n
         I.outer = c.cycles;
         I.reserved = 0;
         I.rel_residual = c.bnorm > 0.0 ? c.rnorm / c.bnorm : 0.0;
-        I.m1_re = post || cfg.method == 0 ? -c.s00.im : 0.0;  // m1 = i S(0); not formed on the r-only path
-        I.m1_im = post || cfg.method == 0 ? c.s00.re : 0.0;
+        I.m1_re = form || cfg.method == 0 ? -c.s00.im : 0.0;  // m1 = i S(0); not formed on the r-only path
+        I.m1_im = form || cfg.method == 0 ? c.s00.re : 0.0;
       }
       if (r_out) {  // r = i h(2i conj k)
         r_out[2 * (k0 + b)] = -c.hsh.im;

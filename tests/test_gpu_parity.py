@@ -187,15 +187,16 @@ def test_max_iter_reports_no_convergence():
     assert np.all(np.isfinite(S)) and np.all(np.isfinite(m))
 
 
+@pytest.mark.parametrize("space", [D.DBAR_SPACE_X, D.DBAR_SPACE_XI])
 @pytest.mark.parametrize("prec", [D.DBAR_FP64, D.DBAR_MIXED])
-def test_iterated_method_fig2_case(prec):
+def test_iterated_method_fig2_case(prec, space):
     """Section 5.3 solver on the GPU against the oracle's, at the Fig. 2 parameters (k = 8.5936 = 55/6.4, L = 3.2,
-    N = 128), where the plain method cannot represent the solution."""
+    N = 128), where the plain method cannot represent the solution; GMRES on F^{-1} h (default) and on h."""
     L, k, N = 3.2, 55 / 6.4, 128
     g = O.make_grid(N, L)
     Q = W.potential_gaussian(N, L, 1.0)
     ref = O.solve_iterated(g, Q, k, tol=1e-14)
-    S, m, info = D.solve(Q, [k], L, tol=1e-12, method=D.DBAR_METHOD_ITERATED, precision=prec)
+    S, m, info = D.solve(Q, [k], L, tol=1e-12, method=D.DBAR_METHOD_ITERATED, precision=prec, space=space)
     assert info[0].status == 0 and info[0].rel_residual <= 1e-12
     assert relerr(S[0], ref.S) < 1e-10
     assert relerr(m[0], ref.m) < 1e-10
@@ -305,3 +306,27 @@ def test_spaces_take_the_same_krylov_steps():
     for j in range(len(ks)):
         assert abs(ix[j].iters - iq[j].iters) <= 1, j
         assert relerr(Sx[j], Sq[j]) < 1e-10 and relerr(mx[j], mq[j]) < 1e-10, j
+
+
+@pytest.mark.parametrize("prec", [D.DBAR_FP64, D.DBAR_MIXED])
+def test_iterated_method_spaces_agree_on_a_batch(prec):
+    """The iterated solver on F^{-1} h and on h: a ragged batch of 6 grid k (2kL integer, one k = 0), S, m and m1 to
+    the oracle's tolerance, iteration counts within one."""
+    N, L = 64, 3.0
+    g = O.make_grid(N, L)
+    Q = W.potential_gaussian_sum(N, L, seed=71)
+    ks = [0.0, (1 + 2j) / (2 * L), (-3 + 1j) / (2 * L), (5 - 4j) / (2 * L), (-7 - 2j) / (2 * L), (2 + 9j) / (2 * L)]
+    out = {}
+    for sp in (D.DBAR_SPACE_X, D.DBAR_SPACE_XI):
+        out[sp] = D.solve(Q, ks, L, tol=1e-12, batch=4, precision=prec, method=D.DBAR_METHOD_ITERATED, space=sp)
+    for j, k in enumerate(ks[:3]):
+        ref = O.solve_iterated(g, Q, k, tol=1e-13)
+        S, m, info = out[D.DBAR_SPACE_X]
+        assert info[j].status == 0 and relerr(S[j], ref.S) < 1e-10 and relerr(m[j], ref.m) < 1e-10, j
+    Sx, mx, ix = out[D.DBAR_SPACE_X]
+    Sq, mq, iq = out[D.DBAR_SPACE_XI]
+    for j in range(len(ks)):
+        assert relerr(Sx[j], Sq[j]) < 1e-10 and relerr(mx[j], mq[j]) < 1e-10, j
+        assert abs(ix[j].m1 - iq[j].m1) <= 1e-10 * max(abs(iq[j].m1), 1e-300), j
+        if prec == D.DBAR_FP64:
+            assert abs(ix[j].iters - iq[j].iters) <= 1, j
