@@ -261,7 +261,8 @@ struct OpBase {
   template <int NT, class Acc> DBAR_D void finish(Acc&, int, int, int, double*) const {}
   // after the stores: dots over the values the stores left in the thread's registers (ops that define DOTS)
   static constexpr bool DOTS = false;
-  // the op accumulates over its loaded values before the first transform (loaded(acc, b, line, jt, v))
+  // the op works on its loaded values before the first transform (loaded(acc, b, line, jt, v, tile, ntiles, scratch)
+  // may change them; it must be called by all threads of the block)
   static constexpr bool LOADACC = false;
   // ROLLED stores: > 1: the op's store_all stores the thread's elements GROUP at a time, else store one at a time
   static constexpr int GROUP = 1;
@@ -472,7 +473,9 @@ struct OpColsInvMoments : MomentsBase<T, N, false> {
 };
 
 // x-space operator, first launch: the moments of the input s as it is read, then out = FFT_rows(s) (first pass of
-// F s)
+// F s).  With upd_coef set it first completes the Gram-Schmidt step that produced s: s -= sum_i coef_i V_i over the
+// upd_nv earlier basis vectors (FP64 accumulation, as the update kernel), stores s back in place and leaves the
+// |s|^2 partials in upd_part[b][tile] -- the operator's first launch reads s anyway.
 template <typename T, int N>
 struct OpRowsFwdMoments : MomentsBase<T, N, true> {
   static constexpr int DIR1 = -1;
@@ -480,7 +483,37 @@ struct OpRowsFwdMoments : MomentsBase<T, N, true> {
   static constexpr bool LOADACC = true;
   using Acc = typename MomentsBase<T, N, true>::Acc;
   DBAR_D cx<T> load(int b, int row, int pos) const { return this->inp(b)[(size_t)row * N + pos]; }
-  DBAR_D void loaded(Acc& acc, int b, int row, int jt, const cx<T>* v) const { this->add_loaded(acc, b, row, jt, v); }
+  template <int NT>
+  DBAR_D void loaded(Acc& acc, int b, int row, int jt, cx<T>* v, int tile, int ntiles, double* scratch) const {
+    using G = LineGeom<N>;
+    const LineArgs& a = this->a;
+    if (a.upd_coef) {
+      const double* coef = a.upd_coef + (size_t)b * a.upd_coef_bs;
+      const cx<T>* V = static_cast<const cx<T>*>(a.dotV) + (size_t)b * a.dotV_bs + (size_t)row * N;
+      c64 w[G::RMAX];
+#pragma unroll
+      for (int s = 0; s < G::RMAX; ++s) w[s] = cvt<double>(v[s]);
+#pragma unroll 1
+      for (int i = 0; i < a.upd_nv; ++i) {
+        const double c = coef[i];
+        if (c == 0.0) continue;  // also keeps never-written basis slots (any bit pattern) out of the sum
+        const cx<T>* Vi = V + (size_t)i * N * N;
+#pragma unroll
+        for (int s = 0; s < G::RMAX; ++s) w[s] = w[s] - c * cvt<double>(Vi[jt + s * G::TPL]);
+      }
+      cx<T>* out = static_cast<cx<T>*>(a.upd_out) + (size_t)b * a.in_bs + (size_t)row * N;
+      double nrm[1] = {0.0};
+#pragma unroll
+      for (int s = 0; s < G::RMAX; ++s) {
+        v[s] = cvt<T>(w[s]);
+        out[jt + s * G::TPL] = v[s];
+        nrm[0] += norm2(cvt<double>(v[s]));
+      }
+      block_reduce_store<NT, 1>(nrm, a.upd_part + (size_t)b * ntiles + tile, 0, scratch);
+      __syncthreads();  // the scratch aliases the LDS the transform's first exchange writes
+    }
+    this->add_loaded(acc, b, row, jt, v);
+  }
   DBAR_D void store(Acc&, int b, int row, int pos, cx<T> v) const { this->outp(b)[(size_t)row * N + pos] = v; }
 };
 
@@ -885,7 +918,7 @@ __global__ void __launch_bounds__(LINES * LineGeom<N>::TPL, MinWaves<LINES * Lin
   cx<T> v[G::RMAX];
 #pragma unroll
   for (int s = 0; s < G::RMAX; ++s) v[s] = op.load(b, line, jt + s * G::TPL);
-  if constexpr (Op::LOADACC) op.loaded(acc, b, line, jt, v);
+  if constexpr (Op::LOADACC) op.template loaded<NT>(acc, b, line, jt, v, tile, gridDim.x, reinterpret_cast<double*>(lds));
   // LDS: a row tile keeps each line contiguous (one line per wave or less); a column tile interleaves its lines
   // element by element, so that the lanes of a wave (consecutive columns) hit consecutive banks
   constexpr int LS = COLS ? LINES : 1;

@@ -138,6 +138,16 @@ struct XOutB {
   size_t r32_bs = 0;
 };
 
+// A pending classical Gram-Schmidt update folded into the x-space operator's first launch (see apply_x_first).
+struct UpdReq {
+  const void* V = nullptr;
+  size_t V_bs = 0;
+  int nv = 0;
+  const double* coef = nullptr;
+  int coef_bs = 0;
+  double* part = nullptr;  // |v|^2 partials [b][row tile]
+};
+
 struct DotReq {
   const void* V = nullptr;
   size_t V_bs = 0;
@@ -200,6 +210,17 @@ struct Pipeline {
   template <typename T>
   void transform(bool inverse, const void* in, void* out, void* Tbuf, hipStream_t s) const;
   // x-space operator: F^{-1} A(F s) = alpha s + beta i q_k conj(h(F s)) + gamma Y (three line launches)
+  // The same in two parts: the first launch and the moment reduction (with u, in -= sum coef_i V_i first, written back
+  // in place), then the division, the inverse transform and the result (which expects the first part's Tbuf and
+  // moments).
+  template <typename T>
+  void apply_x_first(const void* in, size_t in_bs, void* Tbuf, int B, const int* act, unsigned flags,
+                     const UpdReq* u, hipStream_t s) const;
+  template <typename T>
+  void apply_x_rest(const void* in, size_t in_bs, void* out, size_t out_bs, const void* Qp, size_t Q_bs, void* Tbuf,
+                    int B, const int* act, double alpha, double beta, const void* Y, size_t Y_bs, bool want_norm,
+                    hipStream_t s, const DotReq* dr, const XOut* xo, unsigned flags, const void* S_ep,
+                    size_t S_ep_bs) const;
   // flags: kShifted / kUnitPhase as in base(); S_ep: the alpha term's vector (null: the input)
   template <typename T>
   void apply_x(const void* in, size_t in_bs, void* out, size_t out_bs, const void* Qp, size_t Q_bs, void* Tbuf,

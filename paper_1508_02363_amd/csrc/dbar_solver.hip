@@ -532,10 +532,8 @@ int Pipeline::rhs_blocks() const { return xspace ? vec_blocks(n) : line_tiles(N,
 // row pass of the first launch and the column pass of the second, which divides by xi and starts F^{-1}, and the
 // third launch finishes F^{-1} along rows, adds the closed-form tail and forms the result in x-space.
 template <typename T>
-void Pipeline::apply_x(const void* in, size_t in_bs, void* out, size_t out_bs, const void* Qp, size_t Q_bs,
-                       void* Tbuf, int B, const int* act, double alpha, double beta, const void* Y, size_t Y_bs,
-                       bool want_norm, hipStream_t s, const DotReq* dr, const XOut* xo, unsigned flags,
-                       const void* S_ep, size_t S_ep_bs) const {
+void Pipeline::apply_x_first(const void* in, size_t in_bs, void* Tbuf, int B, const int* act, unsigned flags,
+                             const UpdReq* u, hipStream_t s) const {
   LineArgs a = base(B, act, flags);
   a.tw = tw_of<T>(tw);
   a.in = in;
@@ -543,15 +541,33 @@ void Pipeline::apply_x(const void* in, size_t in_bs, void* out, size_t out_bs, c
   a.out = Tbuf;
   a.out_bs = n;
   a.part = part_mom;
-  launch_lines_any<T>(N, LineOp::RowsFwdMoments, a, s);
-  {
-    const double dx = 2.0 * kPi * L / N;
-    TimerScope ts(kStageMoments, 0.0, B, act, s);
-    hipLaunchKernelGGL(k_moments, dim3(B), dim3(kCtlThreads), 0, s, part_mom, line_tiles(N, false, sizeof(T) == 8), act,
-                       dx * dx / (2.0 * kPi), M, coefG, dmom, dmom32);
+  if (u) {
+    a.dotV = u->V;
+    a.dotV_bs = u->V_bs;
+    a.upd_nv = u->nv;
+    a.upd_coef = u->coef;
+    a.upd_coef_bs = u->coef_bs;
+    a.upd_out = const_cast<void*>(in);
+    a.upd_part = u->part;
   }
+  launch_lines_any<T>(N, LineOp::RowsFwdMoments, a, s);
+  const double dx = 2.0 * kPi * L / N;
+  TimerScope ts(kStageMoments, 0.0, B, act, s);
+  hipLaunchKernelGGL(k_moments, dim3(B), dim3(kCtlThreads), 0, s, part_mom, line_tiles(N, false, sizeof(T) == 8), act,
+                     dx * dx / (2.0 * kPi), M, coefG, dmom, dmom32);
+}
+
+template <typename T>
+void Pipeline::apply_x_rest(const void* in, size_t in_bs, void* out, size_t out_bs, const void* Qp, size_t Q_bs,
+                            void* Tbuf, int B, const int* act, double alpha, double beta, const void* Y, size_t Y_bs,
+                            bool want_norm, hipStream_t s, const DotReq* dr, const XOut* xo, unsigned flags,
+                            const void* S_ep, size_t S_ep_bs) const {
+  LineArgs a = base(B, act, flags);
+  a.tw = tw_of<T>(tw);
   a.in = Tbuf;  // in place: a column tile is read whole before it is written
   a.in_bs = n;
+  a.out = Tbuf;
+  a.out_bs = n;
   a.sout = xo ? xo->S : nullptr;
   a.sout_bs = n;
   launch_lines_any<T>(N, LineOp::ColsFwdRegularInv, a, s);
@@ -580,6 +596,16 @@ void Pipeline::apply_x(const void* in, size_t in_bs, void* out, size_t out_bs, c
     a.dot_part = dr->part;
   }
   launch_lines_any<T>(N, LineOp::RowsInvTailEpilogue, a, s);
+}
+
+template <typename T>
+void Pipeline::apply_x(const void* in, size_t in_bs, void* out, size_t out_bs, const void* Qp, size_t Q_bs,
+                       void* Tbuf, int B, const int* act, double alpha, double beta, const void* Y, size_t Y_bs,
+                       bool want_norm, hipStream_t s, const DotReq* dr, const XOut* xo, unsigned flags,
+                       const void* S_ep, size_t S_ep_bs) const {
+  apply_x_first<T>(in, in_bs, Tbuf, B, act, flags, nullptr, s);
+  apply_x_rest<T>(in, in_bs, out, out_bs, Qp, Q_bs, Tbuf, B, act, alpha, beta, Y, Y_bs, want_norm, s, dr, xo, flags,
+                  S_ep, S_ep_bs);
 }
 
 // x-space right-hand side F^{-1} b = -i q_k = -i Q e_k (b = -i F(q_k)), with |.|^2 partials per block
@@ -727,7 +753,12 @@ void Pipeline::transform(bool inverse, const void* in, void* out, void* Tbuf, hi
   template void Pipeline::transform<T>(bool, const void*, void*, void*, hipStream_t) const;                      \
   template void Pipeline::apply_x<T>(const void*, size_t, void*, size_t, const void*, size_t, void*, int,          \
                                      const int*, double, double, const void*, size_t, bool, hipStream_t,          \
-                                     const DotReq*, const XOut*, unsigned, const void*, size_t) const;
+                                     const DotReq*, const XOut*, unsigned, const void*, size_t) const;            \
+  template void Pipeline::apply_x_first<T>(const void*, size_t, void*, int, const int*, unsigned, const UpdReq*,  \
+                                           hipStream_t) const;                                                    \
+  template void Pipeline::apply_x_rest<T>(const void*, size_t, void*, size_t, const void*, size_t, void*, int,     \
+                                          const int*, double, double, const void*, size_t, bool, hipStream_t,     \
+                                          const DotReq*, const XOut*, unsigned, const void*, size_t) const;
 DBAR_PIPE_INST(double)
 DBAR_PIPE_INST(float)
 #undef DBAR_PIPE_INST
@@ -812,9 +843,40 @@ int krylov_cycle(const Pipeline& P, Work& w, const BatchCfg& cfg, int it_budget,
   char* V = static_cast<char*>(w.V.p);
   const int mlim = std::min(w.m, it_budget);
 
+  // x-space plain method with one Gram-Schmidt pass: the update of step j runs inside the first launch of step j + 1's
+  // operator (which reads the new vector anyway); step 0 starts the operator on v_0 itself, and the update of the
+  // cycle's last step also transforms a vector no step will use (one launch's worth of waste per cycle).
+  const bool fused = P.xspace && cfg.method == 0 && cfg.reorth == 1;
   auto enqueue = [&](int j) {
     void* vj = V + (size_t)j * n * sizeof(cx<T>);
     void* vj1 = V + (size_t)(j + 1) * n * sizeof(cx<T>);
+    if (fused) {
+      DotReq dr;
+      dr.V = V;
+      dr.V_bs = V_bs;
+      dr.nv = j + 1;
+      dr.part = part;
+      if (j == 0) P.apply_x_first<T>(vj, V_bs, Tbuf, B, act, 0u, nullptr, s);
+      P.apply_x_rest<T>(vj, V_bs, vj1, V_bs, Qp, w.Q_bs, Tbuf, B, act, 1.0, 1.0, nullptr, 0, false, s, &dr, nullptr, 0u,
+                        nullptr, 0);
+      {
+        TimerScope ts(kStageControl, 0.0, B, nullptr, s);
+        hipLaunchKernelGGL(k_ctl_coef, dim3(B), dim3(kCtlThreads), 0, s, ctl, part, j + 1,
+                           P.apply_tiles(sizeof(T) == 8), act, j, 0);
+      }
+      UpdReq u;
+      u.V = V;
+      u.V_bs = V_bs;
+      u.nv = j + 1;
+      u.coef = &ctl[0].coef[0];
+      u.coef_bs = sizeof(Ctl) / sizeof(double);
+      u.part = pnorm;
+      P.apply_x_first<T>(vj1, V_bs, Tbuf, B, act, 0u, &u, s);
+      TimerScope ts(kStageControl, 0.0, B, nullptr, s);
+      hipLaunchKernelGGL(k_ctl_givens, dim3(B), dim3(kCtlThreads), 0, s, ctl, pnorm, line_tiles(w.N, false, sizeof(T) == 8),
+                         act, j, w.m);
+      return;
+    }
     // the first Gram-Schmidt pass's products Re<V_i, w>, i <= j, come out of the operator's last kernel
     DotReq dr;
     dr.V = V;
@@ -866,6 +928,7 @@ int krylov_cycle(const Pipeline& P, Work& w, const BatchCfg& cfg, int it_budget,
     bool done = false;
     if (graphs) {
       const auto key = std::make_tuple((int)sizeof(T) + 16 * cfg.method + 64 * (P.xspace ? 1 : 0), j, cfg.reorth, B);
+      // (the fused order depends only on these: x-space, method 0, reorth 1)
       auto it = w.graphs.find(key);
       if (it != w.graphs.end()) {
         done = hipGraphLaunch(it->second, s) == hipSuccess;
