@@ -66,6 +66,8 @@ struct LineArgs {
   // at dotV as above), written back to upd_out (the input's own address), |in|^2 partials to upd_part[b][tile]
   const double* upd_coef = nullptr;  int upd_coef_bs = 0;
   int upd_nv = 0;
+  double upd_sign = 1.0;       // -1: in += sum coef_i V_i
+  int upd_v32 = 0;             // the V_i are FP32 (an FP64 launch updating with an FP32 basis)
   void* upd_out = nullptr;
   double* upd_part = nullptr;
 };

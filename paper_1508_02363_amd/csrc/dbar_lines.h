@@ -473,9 +473,10 @@ struct OpColsInvMoments : MomentsBase<T, N, false> {
 };
 
 // x-space operator, first launch: the moments of the input s as it is read, then out = FFT_rows(s) (first pass of
-// F s).  With upd_coef set it first completes the Gram-Schmidt step that produced s: s -= sum_i coef_i V_i over the
-// upd_nv earlier basis vectors (FP64 accumulation, as the update kernel), stores s back in place and leaves the
-// |s|^2 partials in upd_part[b][tile] -- the operator's first launch reads s anyway.
+// F s).  With upd_coef set it first updates s by a combination of basis vectors, s -= upd_sign sum_i coef_i V_i over
+// upd_nv of them (FP64 accumulation, as the vector kernels; V in FP32 if upd_v32), and stores s back in place: the
+// Gram-Schmidt step that produced s (with its |s|^2 partials in upd_part[b][tile]), or the solution update
+// x += sum y_i V_i of a cycle end (upd_sign -1) -- the operator's first launch reads s anyway.
 template <typename T, int N>
 struct OpRowsFwdMoments : MomentsBase<T, N, true> {
   static constexpr int DIR1 = -1;
@@ -495,11 +496,17 @@ struct OpRowsFwdMoments : MomentsBase<T, N, true> {
       for (int s = 0; s < G::RMAX; ++s) w[s] = cvt<double>(v[s]);
 #pragma unroll 1
       for (int i = 0; i < a.upd_nv; ++i) {
-        const double c = coef[i];
+        const double c = a.upd_sign * coef[i];
         if (c == 0.0) continue;  // also keeps never-written basis slots (any bit pattern) out of the sum
-        const cx<T>* Vi = V + (size_t)i * N * N;
+        if (sizeof(T) == 8 && a.upd_v32) {
+          const c32* Vi = static_cast<const c32*>(a.dotV) + (size_t)b * a.dotV_bs + (size_t)row * N + (size_t)i * N * N;
 #pragma unroll
-        for (int s = 0; s < G::RMAX; ++s) w[s] = w[s] - c * cvt<double>(Vi[jt + s * G::TPL]);
+          for (int s = 0; s < G::RMAX; ++s) w[s] = w[s] - c * cvt<double>(Vi[jt + s * G::TPL]);
+        } else {
+          const cx<T>* Vi = V + (size_t)i * N * N;
+#pragma unroll
+          for (int s = 0; s < G::RMAX; ++s) w[s] = w[s] - c * cvt<double>(Vi[jt + s * G::TPL]);
+        }
       }
       cx<T>* out = static_cast<cx<T>*>(a.upd_out) + (size_t)b * a.in_bs + (size_t)row * N;
       double nrm[1] = {0.0};
@@ -509,8 +516,10 @@ struct OpRowsFwdMoments : MomentsBase<T, N, true> {
         out[jt + s * G::TPL] = v[s];
         nrm[0] += norm2(cvt<double>(v[s]));
       }
-      block_reduce_store<NT, 1>(nrm, a.upd_part + (size_t)b * ntiles + tile, 0, scratch);
-      __syncthreads();  // the scratch aliases the LDS the transform's first exchange writes
+      if (a.upd_part) {
+        block_reduce_store<NT, 1>(nrm, a.upd_part + (size_t)b * ntiles + tile, 0, scratch);
+        __syncthreads();  // the scratch aliases the LDS the transform's first exchange writes
+      }
     }
     this->add_loaded(acc, b, row, jt, v);
   }

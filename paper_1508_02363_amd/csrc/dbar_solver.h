@@ -145,7 +145,9 @@ struct UpdReq {
   int nv = 0;
   const double* coef = nullptr;
   int coef_bs = 0;
-  double* part = nullptr;  // |v|^2 partials [b][row tile]
+  double* part = nullptr;  // |v|^2 partials [b][row tile] (null: none)
+  double sign = 1.0;       // in -= sign sum coef_i V_i
+  bool v32 = false;        // V in FP32 (FP64 input)
 };
 
 struct DotReq {

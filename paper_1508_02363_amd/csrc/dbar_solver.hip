@@ -549,6 +549,8 @@ void Pipeline::apply_x_first(const void* in, size_t in_bs, void* Tbuf, int B, co
     a.upd_coef_bs = u->coef_bs;
     a.upd_out = const_cast<void*>(in);
     a.upd_part = u->part;
+    a.upd_sign = u->sign;
+    a.upd_v32 = u->v32 ? 1 : 0;
   }
   launch_lines_any<T>(N, LineOp::RowsFwdMoments, a, s);
   const double dx = 2.0 * kPi * L / N;
@@ -981,7 +983,9 @@ void end_cycle(const Pipeline& P, Work& w, int nv, void* r_out, hipStream_t s, i
   va.w_bs = n;
   va.coef = &ctl[0].coef[0];
   va.coef_bs = sizeof(Ctl) / sizeof(double);
-  launch_axpy_multi<double, T>(va, s);
+  // the plain x-space residual's first launch reads x anyway: x += sum y_i V_i runs inside it
+  const bool fuse_axpy = P.xspace && method == 0;
+  if (!fuse_axpy) launch_axpy_multi<double, T>(va, s);
   const size_t r_bs = sizeof(T) == 8 ? n * (w.m + 1) : n;
   if (method == 1 && !P.xspace) {
     P.apply_B<double>(w.x.p, n, r_out, r_bs, w.Q64.p, w.Q_bs, w.T64.p, w.Hbuf.p, B, live, -1.0, -1.0, w.bvec.p, n,
@@ -1012,8 +1016,17 @@ void end_cycle(const Pipeline& P, Work& w, int nv, void* r_out, hipStream_t s, i
       xo.r32 = w.V.p;
       xo.r32_bs = n * (w.m + 1);
     }
-    P.apply<double>(w.x.p, n, sizeof(T) == 4 ? nullptr : r_out, r_bs, w.Q64.p, w.Q_bs, w.T64.p, B, live, -1.0, -1.0,
-                    w.bvec.p, n, true, s, nullptr, &xo);
+    UpdReq u;
+    u.V = w.V.p;
+    u.V_bs = n * (w.m + 1);
+    u.nv = nv;
+    u.coef = &ctl[0].coef[0];
+    u.coef_bs = sizeof(Ctl) / sizeof(double);
+    u.sign = -1.0;
+    u.v32 = sizeof(T) == 4;
+    P.apply_x_first<double>(w.x.p, n, w.T64.p, B, live, 0u, &u, s);
+    P.apply_x_rest<double>(w.x.p, n, sizeof(T) == 4 ? nullptr : r_out, r_bs, w.Q64.p, w.Q_bs, w.T64.p, B, live, -1.0,
+                           -1.0, w.bvec.p, n, true, s, nullptr, &xo, 0u, nullptr, 0);
   }
   launch_reduce(static_cast<double*>(w.part_vec.p), 1, P.apply_tiles(true), static_cast<double*>(w.nred.p), B, live,
                 s);
