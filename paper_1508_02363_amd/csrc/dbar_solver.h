@@ -108,6 +108,12 @@ struct Work {
       dred, nred, ctl, act, live, kvals, results, shv, unit, unit32, Hbuf;
   DevBuf Sx, mx;  // x-space solves: S = F x and m = h(S) of the last residual evaluation (FP64)
   DevBuf Fx, Ax;  // x-space iterated solves: f = H(h) and the shifted inverse of h of the last residual evaluation
+  // Where an x-space solve leaves S and m: the caller's device arrays when it passes them (set per batch), else null
+  // (then Sx / mx, or Fx for the iterated method's S, and the caller gets a copy)
+  void* outS = nullptr;
+  void* outm = nullptr;
+  void* S_dst(int method) { return outS ? outS : method == 1 ? Fx.p : Sx.p; }
+  void* m_dst() { return outm ? outm : mx.p; }
   PinnedInts host_act, host_live;
   int setup(int N_, int B_, int m_, int prec_, bool shared_q);
   size_t vec_bytes(int prec) const;

@@ -997,7 +997,7 @@ void end_cycle(const Pipeline& P, Work& w, int nv, void* r_out, hipStream_t s, i
     xb.hxi = w.Sx.p;
     xb.f = w.Fx.p;
     xb.ha = w.Ax.p;
-    xb.h0 = w.mx.p;
+    xb.h0 = w.m_dst();
     if (sizeof(T) == 4) {
       xb.r32 = w.V.p;
       xb.r32_bs = n * (w.m + 1);
@@ -1010,8 +1010,8 @@ void end_cycle(const Pipeline& P, Work& w, int nv, void* r_out, hipStream_t s, i
     // x-space: S = F x and m = h(S) of this x come along (the last evaluation's are the outputs); the mixed
     // solver's residual goes straight to the next cycle's first basis vector in FP32
     XOut xo;
-    xo.S = w.Sx.p;
-    xo.h = w.mx.p;
+    xo.S = w.S_dst(0);
+    xo.h = w.m_dst();
     if (sizeof(T) == 4) {
       xo.r32 = w.V.p;
       xo.r32_bs = n * (w.m + 1);
@@ -1061,8 +1061,10 @@ __global__ void k_zero_done(c64* a0, c64* a1, c64* a2, c64* a3, const int* live,
 }
 
 void launch_zero_done(Work& w, const int* mask, bool iterated, hipStream_t s) {
+  // plain: S and m where they are left; iterated: h (Sx), f (Fx), the shifted inverse (Ax) and m, from which S is
+  // formed
   hipLaunchKernelGGL(k_zero_done, dim3((unsigned)std::min<size_t>(1024, (w.n + 255) / 256), w.B), dim3(256), 0, s,
-                     static_cast<c64*>(w.Sx.p), static_cast<c64*>(w.mx.p),
+                     static_cast<c64*>(iterated ? w.Sx.p : w.S_dst(0)), static_cast<c64*>(w.m_dst()),
                      iterated ? static_cast<c64*>(w.Fx.p) : nullptr, iterated ? static_cast<c64*>(w.Ax.p) : nullptr,
                      static_cast<const int*>(w.live.p), mask, w.n);
 }
@@ -1262,6 +1264,8 @@ int solve_impl(const dbar_grid* grid, const void* Q, bool q_on_device, int64_t n
   for (int64_t k0 = 0; k0 < nk; k0 += B) {
     const int nb = (int)std::min<int64_t>(B, nk - k0);
     w.B = nb;
+    w.outS = cfg.xspace && out_on_device && S ? static_cast<char*>(S) + (size_t)k0 * n * sizeof(c64) : nullptr;
+    w.outm = cfg.xspace && out_on_device && m ? static_cast<char*>(m) + (size_t)k0 * n * sizeof(c64) : nullptr;
     if (hipMemcpyAsync(w.kvals.p, k + 2 * k0, (size_t)nb * sizeof(c64), hipMemcpyHostToDevice, s) != hipSuccess)
       return fail(DBAR_EDEVICE, "k upload failed");
     if (cfg.method == 1) {
@@ -1283,20 +1287,21 @@ int solve_impl(const dbar_grid* grid, const void* Q, bool q_on_device, int64_t n
     const c64* hsrc = static_cast<const c64*>(w.x.p);
     const void* Sout = nullptr;
     const void* mout = nullptr;
+    // (x-space outputs the solve wrote straight into the caller's device arrays need no copy)
     if (cfg.xspace && cfg.method == 0) {
-      S0src = static_cast<const c64*>(w.Sx.p);
-      Sout = w.Sx.p;
-      mout = w.mx.p;
+      S0src = static_cast<const c64*>(w.S_dst(0));
+      Sout = w.outS ? nullptr : w.Sx.p;
+      mout = w.outm ? nullptr : w.mx.p;
     } else if (cfg.xspace) {
       hsrc = static_cast<const c64*>(w.Sx.p);
       if (form) {
         launch_roll_add(static_cast<const c64*>(w.Fx.p), static_cast<const c64*>(w.Sx.p),
-                        static_cast<const int*>(w.shv.p), N, static_cast<c64*>(w.Fx.p), nb, s);
-        launch_add_phase(static_cast<c64*>(w.mx.p), static_cast<const c64*>(w.Ax.p), static_cast<const c64*>(w.ex.p),
-                         static_cast<const c64*>(w.ey.p), N, nb, s);
-        S0src = static_cast<const c64*>(w.Fx.p);
-        Sout = w.Fx.p;
-        mout = w.mx.p;
+                        static_cast<const int*>(w.shv.p), N, static_cast<c64*>(w.S_dst(1)), nb, s);
+        launch_add_phase(static_cast<c64*>(w.m_dst()), static_cast<const c64*>(w.Ax.p),
+                         static_cast<const c64*>(w.ex.p), static_cast<const c64*>(w.ey.p), N, nb, s);
+        S0src = static_cast<const c64*>(w.S_dst(1));
+        Sout = w.outS ? nullptr : w.Fx.p;
+        mout = w.outm ? nullptr : w.mx.p;
       }
     } else if (cfg.method == 0) {
       Sout = w.x.p;
@@ -1351,6 +1356,8 @@ int solve_impl(const dbar_grid* grid, const void* Q, bool q_on_device, int64_t n
       }
     }
   }
+  w.outS = nullptr;
+  w.outm = nullptr;
   if (result == DBAR_ENOCONV) fail(DBAR_ENOCONV, "GMRES reached max_iter before tol for some k");
   return result;
 }

@@ -330,3 +330,26 @@ def test_iterated_method_spaces_agree_on_a_batch(prec):
         assert abs(ix[j].m1 - iq[j].m1) <= 1e-10 * max(abs(iq[j].m1), 1e-300), j
         if prec == D.DBAR_FP64:
             assert abs(ix[j].iters - iq[j].iters) <= 1, j
+
+
+@pytest.mark.parametrize("method", [D.DBAR_METHOD_PLAIN, D.DBAR_METHOD_ITERATED])
+def test_device_outputs_equal_host_outputs(method):
+    """solve_device writes S and m straight into the caller's tensors (several batches of a ragged k list): the
+    values, m1 and the iteration counts equal those of the host-buffer call (which stages them), bit for bit."""
+    N, L = 64, 3.0
+    Q = W.potential_gaussian_sum(N, L, seed=81)
+    ks = [0.0, (2 - 1j) / (2 * L), (-4 + 3j) / (2 * L), (1 + 5j) / (2 * L), (-6 - 2j) / (2 * L)]
+    kw = dict(tol=1e-12, batch=2, precision=D.DBAR_MIXED, method=method)
+    Sh, mh, ih = D.solve(Q, ks, L, **kw)
+    Sd, md, idv = D.solve_device(torch.from_numpy(Q).to("cuda:0"), ks, L, **kw)
+    assert np.array_equal(Sd.cpu().numpy(), Sh) and np.array_equal(md.cpu().numpy(), mh)
+    assert [i.iters for i in idv] == [i.iters for i in ih] and [i.m1 for i in idv] == [i.m1 for i in ih]
+
+
+def test_device_outputs_zero_potential():
+    """b = 0: no residual is evaluated, yet the caller's (uninitialised) tensors come back as S = m = 0."""
+    N, L = 32, 3.0
+    Qd = torch.zeros((N, N), dtype=torch.complex128, device="cuda:0")
+    for method, ks in ((D.DBAR_METHOD_PLAIN, [1 + 1j, 0.5]), (D.DBAR_METHOD_ITERATED, [0.0, 1.0 / (2 * L)])):
+        S, m, info = D.solve_device(Qd, ks, L, tol=1e-12, method=method)
+        assert torch.all(S == 0) and torch.all(m == 0) and all(i.status == 0 and i.iters == 0 for i in info)
