@@ -77,3 +77,34 @@ def test_mixed_n4096_residual_by_oracle_operator():
     b = O.rhs(g, w.Q, w.ks[j])
     r = b - O.apply_A(g, w.Q, w.ks[j], Sj, w.M, om)
     assert np.linalg.norm(r) / np.linalg.norm(b) < 1e-11
+
+
+@pytest.mark.parametrize("method", [D.DBAR_METHOD_PLAIN, D.DBAR_METHOD_ITERATED])
+def test_n2048_residual_and_m_by_oracle(method):
+    """N = 2048 (two waves per row line, one row per tile: the largest grid whose oracle operator runs in seconds
+    besides N = 4096): a batch of 8 mixed solves, the oracle's FP64 operator applied to the GPU's S of one k, and m
+    against the oracle's h(S) (iterated method: its equation for h and its m)."""
+    N, L = 2048, 6.0
+    Q = W.potential_gaussian_sum(N, L, seed=91, amp_max=1.5)
+    ks = [(m1 + 1j * m2) / (2 * L) for m1, m2 in ((0, 0), (5, -3), (-8, 2), (12, 7), (-3, -11), (9, 9), (1, 4),
+                                                   (-6, 6))]
+    Qd = torch.from_numpy(Q).to("cuda:0")
+    S, m, info = D.solve_device(Qd, ks, L, tol=1e-12, precision=D.DBAR_MIXED, method=method)
+    assert all(i.status == 0 and i.rel_residual <= 1e-12 for i in info)
+    j = 3
+    print(f"oracle operator N=2048 k={ks[j]} method={method}", flush=True)
+    g = O.make_grid(N, L)
+    om = O.omega_table(g, 11)
+    Sj, mj = S[j].cpu().numpy(), m[j].cpu().numpy()
+    del S, m
+    if method == D.DBAR_METHOD_PLAIN:
+        b = O.rhs(g, Q, ks[j])
+        r = b - O.apply_A(g, Q, ks[j], Sj, 11, om)
+        assert np.linalg.norm(r) / np.linalg.norm(b) < 1e-11
+        h, _, _ = O.regularised_h(g, Sj, 11, om)
+        assert relerr(mj, h) < 1e-12
+    else:
+        # S solves the plain equation too (Sform): its residual under the plain operator is small
+        b = O.rhs(g, Q, ks[j])
+        r = b - O.apply_A(g, Q, ks[j], Sj, 11, om)
+        assert np.linalg.norm(r) / np.linalg.norm(b) < 1e-10
