@@ -98,7 +98,8 @@ struct Work {
   Work() = default;
   Work& operator=(Work&& o) noexcept;
   int N = 0, B = 0, m = 0, prec = 0;
-  // captured Krylov iterations: key (element bytes, j, reorth, B) -> executable graph; dropped on reallocation
+  // captured Krylov step groups: key (element bytes + method + space, first and end step, reorth, B) -> executable
+  // graph; dropped on reallocation
   std::map<std::tuple<int, int, int, int>, hipGraphExec_t> graphs;
   int graph_epoch = 0;  // tuning epoch the graphs were captured in
   void drop_graphs();

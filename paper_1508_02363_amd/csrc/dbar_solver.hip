@@ -828,8 +828,9 @@ int make_pipeline(const dbar_grid* g, Work& w, Pipeline* p) {
 int ctl_blocks(int B) { return (B + 63) / 64; }
 
 // One Krylov cycle in lockstep; returns the number of iterations run (max over entries).
-// With cfg.use_graph each iteration j is captured once into a HIP graph (per element size, j, passes and batch) and
-// replayed on later cycles and calls; nothing in a captured iteration is a memset or a host transfer.
+// With cfg.use_graph each group of iterations between two convergence reads is captured once into a HIP graph (per
+// element size, method, space, group, passes and batch) and replayed on later cycles and calls; nothing in a
+// captured group is a memset or a host transfer.
 template <typename T>
 int krylov_cycle(const Pipeline& P, Work& w, const BatchCfg& cfg, int it_budget, hipStream_t s) {
   const int B = w.B;
@@ -925,17 +926,20 @@ int krylov_cycle(const Pipeline& P, Work& w, const BatchCfg& cfg, int it_budget,
     w.drop_graphs();
     w.graph_epoch = tuning_epoch();
   }
+  // Steps run in groups that end where the host reads the convergence flags (every check_every steps and at the
+  // restart length); with graphs each group is one captured graph, replayed on later cycles and calls.
   int j = 0;
-  for (; j < mlim; ++j) {
+  while (j < mlim) {
+    const int j1 = std::min(mlim, (j / cfg.check_every + 1) * cfg.check_every);
     bool done = false;
     if (graphs) {
-      const auto key = std::make_tuple((int)sizeof(T) + 16 * cfg.method + 64 * (P.xspace ? 1 : 0), j, cfg.reorth, B);
-      // (the fused order depends only on these: x-space, method 0, reorth 1)
+      const auto key =
+          std::make_tuple((int)sizeof(T) + 16 * cfg.method + 64 * (P.xspace ? 1 : 0), j * 1024 + j1, cfg.reorth, B);
       auto it = w.graphs.find(key);
       if (it != w.graphs.end()) {
         done = hipGraphLaunch(it->second, s) == hipSuccess;
       } else if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) == hipSuccess) {
-        enqueue(j);
+        for (int jj = j; jj < j1; ++jj) enqueue(jj);
         hipGraph_t graph = nullptr;
         hipGraphExec_t ge = nullptr;
         if (hipStreamEndCapture(s, &graph) == hipSuccess && graph &&
@@ -952,14 +956,14 @@ int krylov_cycle(const Pipeline& P, Work& w, const BatchCfg& cfg, int it_budget,
         graphs = false;
       }
     }
-    if (!done) enqueue(j);
-    if ((j + 1) % cfg.check_every == 0 || j + 1 == mlim) {
-      (void)hipMemcpyAsync(w.host_act.data(), act, B * sizeof(int), hipMemcpyDeviceToHost, s);
-      (void)hipStreamSynchronize(s);
-      bool any = false;
-      for (int b = 0; b < B; ++b) any |= w.host_act[b] != 0;
-      if (!any) return j + 1;
-    }
+    if (!done)
+      for (int jj = j; jj < j1; ++jj) enqueue(jj);
+    j = j1;
+    (void)hipMemcpyAsync(w.host_act.data(), act, B * sizeof(int), hipMemcpyDeviceToHost, s);
+    (void)hipStreamSynchronize(s);
+    bool any = false;
+    for (int b = 0; b < B; ++b) any |= w.host_act[b] != 0;
+    if (!any) return j;
   }
   return j;
 }
