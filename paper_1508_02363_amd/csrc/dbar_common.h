@@ -38,6 +38,20 @@ template <typename T> DBAR_HD cx<T> mul_i(cx<T> a) { return {-a.im, a.re}; }    
 template <typename T> DBAR_HD cx<T> mul_mi(cx<T> a) { return {a.im, -a.re}; }    // -i * a
 template <typename T> DBAR_HD T norm2(cx<T> a) { return a.re * a.re + a.im * a.im; }
 
+DBAR_HD float fmar(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+DBAR_HD double fmar(double a, double b, double c) { return __builtin_fma(a, b, c); }
+// a * b + c as four fused multiply-adds (the operators above take six instructions for it: the addition of c cannot
+// be contracted into the product's last step)
+template <typename T> DBAR_HD cx<T> cfma(cx<T> a, cx<T> b, cx<T> c) {
+  return {fmar(a.re, b.re, fmar(-a.im, b.im, c.re)), fmar(a.re, b.im, fmar(a.im, b.re, c.im))};
+}
+// Re(conj(a) b) as a double, for FP64 accumulation.  FP32 data: the product is formed in FP32 (one fused rounding);
+// its error, relative to |a||b| per element and of random sign, is below what the FP32 data carry themselves.
+template <typename T> DBAR_HD double rdot(cx<T> a, cx<T> b) {
+  if constexpr (sizeof(T) == 4) return static_cast<double>(fmar(a.im, b.im, a.re * b.re));
+  else return a.re * b.re + a.im * b.im;
+}
+
 template <typename To, typename From> DBAR_HD cx<To> cvt(cx<From> a) {
   return cx<To>{static_cast<To>(a.re), static_cast<To>(a.im)};
 }

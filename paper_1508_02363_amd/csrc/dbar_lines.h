@@ -133,7 +133,7 @@ DBAR_D cx<TT> tail_sum(TT x, TT y, const cx<TT> (&d)[kMaxM + 1]) {
     const cx<TT> w{x * ir2, -y * ir2};
     cx<TT> acc = d[MM];
 #pragma unroll
-    for (int n = MM - 1; n >= 0; --n) acc = d[n] + w * acc;
+    for (int n = MM - 1; n >= 0; --n) acc = cfma(w, acc, d[n]);
     return mul_i(w * acc);
   }
   const TT eu = exp(-u);
@@ -157,7 +157,7 @@ DBAR_D cx<TT> tail_sum(TT x, TT y, const cx<TT> (&d)[kMaxM + 1]) {
 #pragma unroll
     for (int n = MM - 1; n >= 0; --n) {
       E = u * E + eu * TT(kInvFact[n + 1]);
-      acc = E * d[n] + zeta * acc;
+      acc = cfma(zeta, acc, E * d[n]);
     }
     acc = zeta * acc;
   } else {
@@ -173,7 +173,7 @@ DBAR_D cx<TT> tail_sum(TT x, TT y, const cx<TT> (&d)[kMaxM + 1]) {
     const cx<TT> w{x * ir2, -y * ir2};  // 1/z
     acc = P[MM] * d[MM];
 #pragma unroll
-    for (int n = MM - 1; n >= 0; --n) acc = P[n] * d[n] + w * acc;
+    for (int n = MM - 1; n >= 0; --n) acc = cfma(w, acc, P[n] * d[n]);
     acc = w * acc;
   }
   return mul_i(acc);
@@ -514,7 +514,7 @@ struct OpRowsFwdMoments : MomentsBase<T, N, true> {
       for (int s = 0; s < G::RMAX; ++s) {
         v[s] = cvt<T>(w[s]);
         out[jt + s * G::TPL] = v[s];
-        nrm[0] += norm2(cvt<double>(v[s]));
+        nrm[0] += rdot(v[s], v[s]);
       }
       if (a.upd_part) {
         block_reduce_store<NT, 1>(nrm, a.upd_part + (size_t)b * ntiles + tile, 0, scratch);
@@ -545,7 +545,7 @@ DBAR_D cx<T> regularised(const LineArgs& a, int b, int row, int pos, cx<T> sv) {
     const c64 xib{xi1, -xi2};
     const int M = a.M;
     c64 g = c[M];
-    for (int n = M - 1; n >= 0; --n) g = c[n] + xib * g;
+    for (int n = M - 1; n >= 0; --n) g = cfma(xib, g, c[n]);
     sv = cvt<T>(cvt<double>(sv) - exp(-(xi1 * xi1 + xi2 * xi2)) * g);
   }
   // (S - G) / xi in the transform's precision
@@ -728,7 +728,9 @@ struct OpRowsInvTailEpi : OpColsInvTail<T, N, false> {
   // The stores run GROUP elements at a time: the group's global reads (q, the x factor of e_k, S, Y) are issued
   // together ahead of its tails.  The LDS slot of each element (the row transform's output r) is replaced by the
   // stored value, for the Gram-Schmidt products.
-  static constexpr int GROUP_W = sizeof(T) == 4 ? 8 : 4;  // FP64: register-bound at 4
+  // four at a time: wider groups hold more registers than the loads in flight repay (the FP32 launch drops to three
+  // waves per SIMD at eight)
+  static constexpr int GROUP_W = 4;
   static constexpr int GROUP = LineGeom<N>::RMAX < GROUP_W ? LineGeom<N>::RMAX : GROUP_W;
   struct GroupIn {
     cx<T> q[GROUP], s[GROUP], y[GROUP], ex[GROUP];
@@ -787,9 +789,8 @@ struct OpRowsInvTailEpi : OpColsInvTail<T, N, false> {
           if (a.out32) (static_cast<c32*>(a.out32) + (size_t)b * a.out32_bs)[base + pos] = cvt<float>(ot);
         }
         slot = ot;
-        const c64 od = cvt<double>(ot), sd = cvt<double>(cur.s[u]);
-        acc.v[0] += norm2(od);
-        acc.sdot += sd.re * od.re + sd.im * od.im;
+        acc.v[0] += rdot(ot, ot);
+        acc.sdot += rdot(cur.s[u], ot);
       }
     }
   }
@@ -814,11 +815,7 @@ struct OpRowsInvTailEpi : OpColsInvTail<T, N, false> {
       const cx<T>* Vi = V + (size_t)i * N * N;
       double p4[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int s = 0; s < G::RMAX; ++s) {
-        const c64 y = cvt<double>(Vi[jt + s * G::TPL]);
-        const c64 w = cvt<double>(v[s]);
-        p4[s & 3] += y.re * w.re + y.im * w.im;
-      }
+      for (int s = 0; s < G::RMAX; ++s) p4[s & 3] += rdot(Vi[jt + s * G::TPL], v[s]);
       return (p4[0] + p4[1]) + (p4[2] + p4[3]);
     };
     if constexpr (NT >= 64) {
