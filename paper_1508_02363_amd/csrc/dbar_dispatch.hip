@@ -67,9 +67,10 @@ static double line_bytes(int N, LineOp op, const LineArgs& a, size_t es) {
     case LineOp::ColsInvPlain: return 2 * P;
     case LineOp::RowsFwdMoments: return 2 * P + (a.upd_coef ? P + a.upd_nv * (a.upd_v32 ? P / 2 : P) : 0.0);
     case LineOp::ColsFwdRegularInv: return 2 * P + (a.sout ? P : 0.0);
-    case LineOp::RowsInvTailEpilogue:  // in, q_k (counted per entry), out, S, Y, h, the FP32 copy, earlier basis
+    case LineOp::RowsInvTailEpilogue:  // in, q_k (counted per entry), out, S, Y (unless formed from q_k), h, the FP32
+                                       // copy, earlier basis
       return 2 * P + (a.out ? P : 0.0) + (a.out32 ? P / 2 : 0.0) + (a.alpha != 0.0 ? P : 0.0) +
-             (a.gamma != 0.0 ? P : 0.0) + (a.hout ? P : 0.0) +
+             (a.gamma != 0.0 && !a.y_rhs ? P : 0.0) + (a.hout ? P : 0.0) +
              (a.dot_nv > 0 ? (a.dot_nv - (a.alpha != 0.0 ? 1 : 0)) * P : 0.0);
   }
   return 0.0;

@@ -53,6 +53,8 @@ struct LineArgs {
   double L = 1.0, ci = 1.0, cf = 1.0;
   int M = 11;
   double alpha = 0.0, gamma = 0.0;
+  int y_rhs = 0;               // RowsInvTailEpilogue: the gamma term is -i q_k, formed from the epilogue's own q_k
+                               // (the x-space right-hand side; Y is not read)
   c64 beta{0.0, 0.0};
   int want_norm = 0;           // RowsFwdEpilogue, RowsInvTailEpilogue: accumulate |out|^2 partials
   int tile = 0;                // column stages: tile width variant (columns per tile = default << tile)

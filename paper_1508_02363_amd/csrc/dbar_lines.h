@@ -749,7 +749,7 @@ struct OpRowsInvTailEpi : OpColsInvTail<T, N, false> {
       const int pos = jt + (s0 + u) * G::TPL;
       g.q[u] = Qb[pos];
       g.s[u] = a.alpha != 0.0 ? Sb[pos] : cx<T>{T(0), T(0)};
-      g.y[u] = a.gamma != 0.0 ? Yb[pos] : cx<T>{T(0), T(0)};
+      g.y[u] = (a.gamma != 0.0 && !a.y_rhs) ? Yb[pos] : cx<T>{T(0), T(0)};
       if (a.shv) g.ex[u] = cx<T>{T(1), T(0)};
       else if constexpr (sizeof(T) == 8) g.ex[u] = a.ex[eo + pos];
       else g.ex[u] = a.ex32[eo + pos];
@@ -777,12 +777,14 @@ struct OpRowsInvTailEpi : OpColsInvTail<T, N, false> {
         cx<T>& slot = my[G::padded(pos) * LS];
         const cx<T> h = this->h_at(b, pos, row, slot, p);  // x index pos, y index row
         if (a.hout) (static_cast<cx<T>*>(a.hout) + (size_t)b * a.hout_bs)[base + pos] = h;
-        const cx<T> w = (cur.q[u] * (cur.ex[u] * ey)) * conj(h);
+        const cx<T> qk = cur.q[u] * (cur.ex[u] * ey);
+        const cx<T> w = qk * conj(h);
+        const cx<T> yv = a.y_rhs ? mul_mi(qk) : cur.y[u];
         cx<T> ot;
         if constexpr (sizeof(T) == 8) {
-          ot = a.beta * w + a.alpha * cur.s[u] + a.gamma * cur.y[u];
+          ot = a.beta * w + a.alpha * cur.s[u] + a.gamma * yv;
         } else {  // the FP32 operator's result is FP32: form it in FP32
-          ot = cvt<T>(a.beta) * w + static_cast<T>(a.alpha) * cur.s[u] + static_cast<T>(a.gamma) * cur.y[u];
+          ot = cvt<T>(a.beta) * w + static_cast<T>(a.alpha) * cur.s[u] + static_cast<T>(a.gamma) * yv;
         }
         if (a.out) this->outp(b)[base + pos] = ot;
         if constexpr (sizeof(T) == 8) {

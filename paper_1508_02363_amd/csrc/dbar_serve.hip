@@ -185,15 +185,11 @@ static void worker(dbar_session* s, SClass* cp) {
       (void)hipMemcpyAsync(w.live.p, c.h_live.data(), c.cap * sizeof(int), hipMemcpyHostToDevice, c.stream);
       (void)hipMemcpyAsync(c.tolv.p, c.h_tol.data(), c.cap * sizeof(double), hipMemcpyHostToDevice, c.stream);
       if (mixed) launch_convert<float, double>(w.Q64.p, n, w.Q32.p, n, n, c.cap, nm, 1.0, c.stream);
-      c.P.rhs(w.Q64.p, n, w.T64.p, static_cast<c64*>(w.bvec.p), c.cap, nm, 0u, c.stream);
+      c.P.rhs_x(w.Q64.p, n, w.V.p, V_bs, mixed, c.cap, nm, 0u, c.stream);  // the first basis vector
       launch_reduce(static_cast<double*>(w.part_vec.p), 1, c.P.rhs_blocks(),
                     static_cast<double*>(w.nred.p), c.cap, nm, c.stream);
       launch_ctl_check(w, 0.0, 1, nm, static_cast<const double*>(c.tolv.p), c.stream);
       launch_zero_done(w, nm, false, c.stream);  // admitted requests with b = 0: S = m = 0
-      if (mixed)
-        launch_convert<float, double>(w.bvec.p, n, w.V.p, V_bs, n, c.cap, nm, 1.0, c.stream);
-      else
-        launch_convert<double, double>(w.bvec.p, n, w.V.p, V_bs, n, c.cap, nm, 1.0, c.stream);
     }
     // ---- one Krylov cycle for everything in flight
     launch_ctl_start(w, mixed ? 0.3 : 0.5, mixed ? cfg.inner_tol : 0.0, static_cast<const double*>(c.tolv.p),

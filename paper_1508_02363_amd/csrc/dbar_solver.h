@@ -123,6 +123,9 @@ struct Work {
 // The operator pipeline for one grid (pointers into a Work).
 constexpr unsigned kShifted = 1u;    // regularise about xi = a = 2i conj(k) (Section 5.1, equation dbarinvShift)
 constexpr unsigned kUnitPhase = 2u;  // k = 0 phase (the operator K0 of equation shift)
+// Y argument of the x-space operator standing for its right-hand side -i q_k (q_k as the operator's phase flags give
+// it): the last launch forms it from the q_k it reads anyway, so a residual b - A(x) reads no b array
+inline const void* const kYRhs = reinterpret_cast<const void*>(static_cast<uintptr_t>(1));
 
 // Gram-Schmidt products fused into the operator's last kernel: Re<V_i, out> for i < nv as per-tile partials
 // Extra outputs of the x-space operator: S = F s and h(S) of the input (strides n), and the result rounded to FP32
@@ -213,6 +216,10 @@ struct Pipeline {
                bool want_norm, hipStream_t s, const DotReq* dr = nullptr, const XOutB* xb = nullptr) const;
   void rhs(const void* Q64p, size_t Q_bs, void* T64, c64* bout, int B, const int* act, unsigned flags,
            hipStream_t s) const;
+  // x-space: -i q_k straight into out (stride out_bs; FP32 if out32, the first basis vector of a mixed solve), with
+  // the |.|^2 partials of its FP64 values (rhs_blocks() per entry)
+  void rhs_x(const void* Q64p, size_t Q_bs, void* out, size_t out_bs, bool out32, int B, const int* act,
+             unsigned flags, hipStream_t s) const;
   template <typename T>
   void h_of(const void* in, size_t in_bs, void* hout, size_t hout_bs, void* Tbuf, int B, const int* act,
             hipStream_t s, unsigned flags = 0u, bool phase_out = false, bool accumulate = false) const;

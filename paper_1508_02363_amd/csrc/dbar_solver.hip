@@ -586,7 +586,8 @@ void Pipeline::apply_x_rest(const void* in, size_t in_bs, void* out, size_t out_
   a.S_bs = S_ep ? S_ep_bs : in_bs;
   a.alpha = alpha;
   a.beta = c64{0.0, beta};
-  a.Y = Y;
+  a.y_rhs = Y == kYRhs ? 1 : 0;
+  a.Y = a.y_rhs ? nullptr : Y;
   a.Y_bs = Y_bs;
   a.gamma = Y ? 1.0 : 0.0;
   a.want_norm = want_norm ? 1 : 0;
@@ -611,8 +612,10 @@ void Pipeline::apply_x(const void* in, size_t in_bs, void* out, size_t out_bs, c
 }
 
 // x-space right-hand side F^{-1} b = -i q_k = -i Q e_k (b = -i F(q_k)), with |.|^2 partials per block
+template <typename TO>
 __global__ void __launch_bounds__(256) k_rhs_x(const c64* Q, size_t Q_bs, const c64* ex, const c64* ey, size_t e_bs,
-                                               int N, c64* out, double* part, int B, const int* act) {
+                                               int N, cx<TO>* out, size_t out_bs, double* part, int B,
+                                               const int* act) {
   const int b = blockIdx.y;
   if (b >= B || (act && !act[b])) return;
   const size_t n = (size_t)N * N;
@@ -621,7 +624,7 @@ __global__ void __launch_bounds__(256) k_rhs_x(const c64* Q, size_t Q_bs, const 
     const int pos = (int)(i / N), col = (int)(i % N);
     const c64 q = Q[(size_t)b * Q_bs + i] * (ex[(size_t)b * e_bs + col] * ey[(size_t)b * e_bs + pos]);
     const c64 v{q.im, -q.re};
-    out[(size_t)b * n + i] = v;
+    out[(size_t)b * out_bs + i] = cvt<TO>(v);
     acc += v.re * v.re + v.im * v.im;
   }
   __shared__ double red[4];
@@ -629,6 +632,20 @@ __global__ void __launch_bounds__(256) k_rhs_x(const c64* Q, size_t Q_bs, const 
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
   __syncthreads();
   if (threadIdx.x == 0) part[(size_t)b * gridDim.x + blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+void Pipeline::rhs_x(const void* Q64p, size_t Q_bs, void* out, size_t out_bs, bool out32, int B, const int* act,
+                     unsigned flags, hipStream_t s) const {
+  const LineArgs a = base(B, act, flags & kUnitPhase);
+  TimerScope ts(kStageConvert, (double)n * (sizeof(c64) + (out32 ? sizeof(c32) : sizeof(c64))), B, act, s);
+  const dim3 grid(rhs_blocks(), B);
+  const c64* Q = static_cast<const c64*>(Q64p);
+  if (out32)
+    hipLaunchKernelGGL(k_rhs_x<float>, grid, dim3(256), 0, s, Q, Q_bs, a.ex, a.ey, a.e_bs, N, static_cast<c32*>(out),
+                       out_bs, part_vec, B, act);
+  else
+    hipLaunchKernelGGL(k_rhs_x<double>, grid, dim3(256), 0, s, Q, Q_bs, a.ex, a.ey, a.e_bs, N, static_cast<c64*>(out),
+                       out_bs, part_vec, B, act);
 }
 
 // H(h) = -i F(Q conj(F^{-1}(h/(xi - a)))) (equation eqh2), into Hout
@@ -672,13 +689,11 @@ void Pipeline::apply_B(const void* in, size_t in_bs, void* out, size_t out_bs, c
 // b = -i F(Q e_k) (FP64; e_k = 1 with kUnitPhase), with |b|^2 partials (rhs_blocks() per entry); in x-space -i Q e_k
 void Pipeline::rhs(const void* Q64p, size_t Q_bs, void* T64, c64* bout, int B, const int* act, unsigned flags,
                    hipStream_t s) const {
-  LineArgs a = base(B, act, flags & kUnitPhase);
   if (xspace) {
-    TimerScope ts(kStageConvert, 2.0 * (double)n * sizeof(c64), B, act, s);
-    hipLaunchKernelGGL(k_rhs_x, dim3(rhs_blocks(), B), dim3(256), 0, s, static_cast<const c64*>(Q64p), Q_bs, a.ex,
-                       a.ey, a.e_bs, N, bout, part_vec, B, act);
+    rhs_x(Q64p, Q_bs, bout, n, false, B, act, flags, s);
     return;
   }
+  LineArgs a = base(B, act, flags & kUnitPhase);
   a.tw = tw_of<double>(tw);
   a.Q = Q64p;
   a.Q_bs = Q_bs;
@@ -1007,7 +1022,7 @@ void end_cycle(const Pipeline& P, Work& w, int nv, void* r_out, hipStream_t s, i
       xb.r32_bs = n * (w.m + 1);
     }
     P.apply_B<double>(w.x.p, n, sizeof(T) == 4 ? nullptr : r_out, r_bs, w.Q64.p, w.Q_bs, w.T64.p, w.Hbuf.p, B, live,
-                      -1.0, -1.0, w.bvec.p, n, true, s, nullptr, &xb);
+                      -1.0, -1.0, kYRhs, 0, true, s, nullptr, &xb);
   } else if (!P.xspace)
     P.apply<double>(w.x.p, n, r_out, r_bs, w.Q64.p, w.Q_bs, w.T64.p, B, live, -1.0, -1.0, w.bvec.p, n, true, s);
   else {
@@ -1030,7 +1045,7 @@ void end_cycle(const Pipeline& P, Work& w, int nv, void* r_out, hipStream_t s, i
     u.v32 = sizeof(T) == 4;
     P.apply_x_first<double>(w.x.p, n, w.T64.p, B, live, 0u, &u, s);
     P.apply_x_rest<double>(w.x.p, n, sizeof(T) == 4 ? nullptr : r_out, r_bs, w.Q64.p, w.Q_bs, w.T64.p, B, live, -1.0,
-                           -1.0, w.bvec.p, n, true, s, nullptr, &xo, 0u, nullptr, 0);
+                           -1.0, kYRhs, 0, true, s, nullptr, &xo, 0u, nullptr, 0);
   }
   launch_reduce(static_cast<double*>(w.part_vec.p), 1, P.apply_tiles(true), static_cast<double*>(w.nred.p), B, live,
                 s);
@@ -1082,8 +1097,13 @@ int run_batch(const Pipeline& P, Work& w, const BatchCfg& cfg, hipStream_t s, st
   int* live = static_cast<int*>(w.live.p);
   double* nred = static_cast<double*>(w.nred.p);
   // b = -i F(q_k), |b|
-  // plain: b = -i F(Q e_k); iterated (equation eqh2): b = -i F(Q)
-  P.rhs(w.Q64.p, w.Q_bs, w.T64.p, static_cast<c64*>(w.bvec.p), B, nullptr, cfg.method == 1 ? kUnitPhase : 0u, s);
+  // plain: b = -i F(Q e_k); iterated (equation eqh2): b = -i F(Q).  In x-space -i q_k goes straight to the first basis
+  // vector (the residuals form it in their last launch: no b array)
+  const unsigned rhs_flags = cfg.method == 1 ? kUnitPhase : 0u;
+  if (P.xspace)
+    P.rhs_x(w.Q64.p, w.Q_bs, w.V.p, n * (w.m + 1), mixed, B, nullptr, rhs_flags, s);
+  else
+    P.rhs(w.Q64.p, w.Q_bs, w.T64.p, static_cast<c64*>(w.bvec.p), B, nullptr, rhs_flags, s);
   launch_reduce(static_cast<double*>(w.part_vec.p), 1, P.rhs_blocks(), nred, B, nullptr, s);
   if (hipMemsetAsync(w.x.p, 0, (size_t)B * n * sizeof(c64), s) != hipSuccess)
     return fail(DBAR_EDEVICE, "hipMemsetAsync failed");
@@ -1094,8 +1114,7 @@ int run_batch(const Pipeline& P, Work& w, const BatchCfg& cfg, hipStream_t s, st
   hipLaunchKernelGGL(k_ctl_check, dim3(ctl_blocks(B)), dim3(64), 0, s, ctl, nred, live, 0.0, 1, nullptr, nullptr, B);
   if (P.xspace) {  // S = m = 0 for entries with b = 0 (no residual evaluation writes them)
     launch_zero_done(w, nullptr, cfg.method == 1, s);
-  }
-  if (mixed) {
+  } else if (mixed) {
     launch_convert<float, double>(w.bvec.p, n, w.V.p, n * (w.m + 1), n, B, nullptr, 1.0, s);
   } else {
     launch_convert<double, double>(w.bvec.p, n, w.V.p, n * (w.m + 1), n, B, nullptr, 1.0, s);
