@@ -70,6 +70,7 @@ struct LineArgs {
   int upd_nv = 0;
   double upd_sign = 1.0;       // -1: in += sum coef_i V_i
   int upd_v32 = 0;             // the V_i are FP32 (an FP64 launch updating with an FP32 basis)
+  int upd_zero = 0;            // the input counts as zero (its loaded values are ignored)
   void* upd_out = nullptr;
   double* upd_part = nullptr;
 };

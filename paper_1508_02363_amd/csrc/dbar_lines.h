@@ -493,7 +493,7 @@ struct OpRowsFwdMoments : MomentsBase<T, N, true> {
       const cx<T>* V = static_cast<const cx<T>*>(a.dotV) + (size_t)b * a.dotV_bs + (size_t)row * N;
       c64 w[G::RMAX];
 #pragma unroll
-      for (int s = 0; s < G::RMAX; ++s) w[s] = cvt<double>(v[s]);
+      for (int s = 0; s < G::RMAX; ++s) w[s] = a.upd_zero ? c64{0.0, 0.0} : cvt<double>(v[s]);
 #pragma unroll 1
       for (int i = 0; i < a.upd_nv; ++i) {
         const double c = a.upd_sign * coef[i];

@@ -113,6 +113,9 @@ struct Work {
   // (then Sx / mx, or Fx for the iterated method's S, and the caller gets a copy)
   void* outS = nullptr;
   void* outm = nullptr;
+  // x holds zero without having been written: the next solution update (fused into the residual's first launch)
+  // writes x = sum y_i V_i instead of adding to it
+  bool x_zero = false;
   void* S_dst(int method) { return outS ? outS : method == 1 ? Fx.p : Sx.p; }
   void* m_dst() { return outm ? outm : mx.p; }
   PinnedInts host_act, host_live;
@@ -158,6 +161,11 @@ struct UpdReq {
   double* part = nullptr;  // |v|^2 partials [b][row tile] (null: none)
   double sign = 1.0;       // in -= sign sum coef_i V_i
   bool v32 = false;        // V in FP32 (FP64 input)
+  bool zero_in = false;    // the input counts as zero (never read): in = -sign sum coef_i V_i
+  // with ctl set, the launch that reduces the moments also takes the Givens step of Krylov step j (restart m) from the
+  // |v|^2 partials in part
+  Ctl* ctl = nullptr;
+  int j = 0, m = 0;
 };
 
 struct DotReq {

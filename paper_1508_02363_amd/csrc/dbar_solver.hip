@@ -69,13 +69,11 @@ DBAR_D void reduce_entry(const double* __restrict__ part, int nval, int nblk, do
   __syncthreads();
 }
 
-// d_n = w sum_tiles part, c_n = (-i/2)^n d_n / n! (equation fourreeg4 with Gchoice), R(0) = (-i/2) dt.  One block
-// of kCtlThreads per entry.
-__global__ void __launch_bounds__(kCtlThreads) k_moments(const double* part, int ntiles, const int* act,
-                                                         double wscale, int M, c64* coefG, c64* dmom, c32* dmom32) {
+// d_n = w sum_tiles part, c_n = (-i/2)^n d_n / n! (equation fourreeg4 with Gchoice), R(0) = (-i/2) dt, for entry b.
+// All kCtlThreads threads of the block.
+DBAR_D void moments_entry(int b, const double* part, int ntiles, double wscale, int M, c64* coefG, c64* dmom,
+                          c32* dmom32) {
   constexpr int NV = 2 * kNMom;
-  const int b = blockIdx.x;
-  if (act && !act[b]) return;
   __shared__ double tot[NV];
   reduce_entry(part + (size_t)b * NV * ntiles, NV, ntiles, tot);
   if (threadIdx.x == 0) {
@@ -98,6 +96,14 @@ __global__ void __launch_bounds__(kCtlThreads) k_moments(const double* part, int
   }
 }
 
+// One block of kCtlThreads per entry.
+__global__ void __launch_bounds__(kCtlThreads) k_moments(const double* part, int ntiles, const int* act,
+                                                         double wscale, int M, c64* coefG, c64* dmom, c32* dmom32) {
+  const int b = blockIdx.x;
+  if (act && !act[b]) return;
+  moments_entry(b, part, ntiles, wscale, M, coefG, dmom, dmom32);
+}
+
 // Gram-Schmidt pass `pass` of step j: h_i = <v_i, w> from the partials, coef_i = sigma_i^2 h_i (the basis is kept
 // unnormalised, v_i / ||v_i|| = sigma_i v_i), hsum_i accumulates sigma_i h_i over the passes.  One block per entry.
 __global__ void __launch_bounds__(kCtlThreads) k_ctl_coef(Ctl* ctl, const double* part, int nval, int nblk,
@@ -117,11 +123,9 @@ __global__ void __launch_bounds__(kCtlThreads) k_ctl_coef(Ctl* ctl, const double
 }
 
 // Column j of the Hessenberg matrix from hsum and beta = ||w_new|| (reduced from the update's partials), Givens
-// rotation, residual estimate; the entry leaves the cycle when the estimate meets its threshold.  One block per entry.
-__global__ void __launch_bounds__(kCtlThreads) k_ctl_givens(Ctl* ctl, const double* pnorm, int nblk, int* act, int j,
-                                                            int m) {
-  const int b = blockIdx.x;
-  if (!act[b]) return;
+// rotation, residual estimate; the entry leaves the cycle when the estimate meets its threshold.  All kCtlThreads
+// threads of entry b's block.
+DBAR_D void givens_entry(int b, Ctl* ctl, const double* pnorm, int nblk, int* act, int j, int m) {
   __shared__ double red[1];
   reduce_entry(pnorm + (size_t)b * nblk, 1, nblk, red);
   if (threadIdx.x != 0) return;
@@ -148,6 +152,25 @@ __global__ void __launch_bounds__(kCtlThreads) k_ctl_givens(Ctl* ctl, const doub
   c.jn = j + 1;
   c.iters += 1;
   if (c.resid <= c.thresh || j + 1 >= m || beta == 0.0) act[b] = 0;
+}
+
+__global__ void __launch_bounds__(kCtlThreads) k_ctl_givens(Ctl* ctl, const double* pnorm, int nblk, int* act, int j,
+                                                            int m) {
+  const int b = blockIdx.x;
+  if (!act[b]) return;
+  givens_entry(b, ctl, pnorm, nblk, act, j, m);
+}
+
+// The moments of the next basis vector (whose update and transform just ran) and the Givens step of the Krylov step
+// that produced it, in one launch: the moments are used only if the entry stays active.
+__global__ void __launch_bounds__(kCtlThreads) k_moments_givens(const double* part, int ntiles, double wscale, int M,
+                                                                c64* coefG, c64* dmom, c32* dmom32, Ctl* ctl,
+                                                                const double* pnorm, int nblk, int* act, int j,
+                                                                int m) {
+  const int b = blockIdx.x;
+  if (!act[b]) return;
+  moments_entry(b, part, ntiles, wscale, M, coefG, dmom, dmom32);
+  givens_entry(b, ctl, pnorm, nblk, act, j, m);
 }
 
 // y = H^{-1} g (upper triangular jn x jn), coef_i = y_i sigma_i, zero beyond jn
@@ -551,12 +574,18 @@ void Pipeline::apply_x_first(const void* in, size_t in_bs, void* Tbuf, int B, co
     a.upd_part = u->part;
     a.upd_sign = u->sign;
     a.upd_v32 = u->v32 ? 1 : 0;
+    a.upd_zero = u->zero_in ? 1 : 0;
   }
   launch_lines_any<T>(N, LineOp::RowsFwdMoments, a, s);
   const double dx = 2.0 * kPi * L / N;
+  const int tiles = line_tiles(N, false, sizeof(T) == 8);
   TimerScope ts(kStageMoments, 0.0, B, act, s);
-  hipLaunchKernelGGL(k_moments, dim3(B), dim3(kCtlThreads), 0, s, part_mom, line_tiles(N, false, sizeof(T) == 8), act,
-                     dx * dx / (2.0 * kPi), M, coefG, dmom, dmom32);
+  if (u && u->ctl)
+    hipLaunchKernelGGL(k_moments_givens, dim3(B), dim3(kCtlThreads), 0, s, part_mom, tiles, dx * dx / (2.0 * kPi), M,
+                       coefG, dmom, dmom32, u->ctl, u->part, tiles, const_cast<int*>(act), u->j, u->m);
+  else
+    hipLaunchKernelGGL(k_moments, dim3(B), dim3(kCtlThreads), 0, s, part_mom, tiles, act, dx * dx / (2.0 * kPi), M,
+                       coefG, dmom, dmom32);
 }
 
 template <typename T>
@@ -889,10 +918,10 @@ int krylov_cycle(const Pipeline& P, Work& w, const BatchCfg& cfg, int it_budget,
       u.coef = &ctl[0].coef[0];
       u.coef_bs = sizeof(Ctl) / sizeof(double);
       u.part = pnorm;
+      u.ctl = ctl;  // step j's Givens step rides on the moment reduction of v_{j+1}
+      u.j = j;
+      u.m = w.m;
       P.apply_x_first<T>(vj1, V_bs, Tbuf, B, act, 0u, &u, s);
-      TimerScope ts(kStageControl, 0.0, B, nullptr, s);
-      hipLaunchKernelGGL(k_ctl_givens, dim3(B), dim3(kCtlThreads), 0, s, ctl, pnorm, line_tiles(w.N, false, sizeof(T) == 8),
-                         act, j, w.m);
       return;
     }
     // the first Gram-Schmidt pass's products Re<V_i, w>, i <= j, come out of the operator's last kernel
@@ -1043,6 +1072,8 @@ void end_cycle(const Pipeline& P, Work& w, int nv, void* r_out, hipStream_t s, i
     u.coef_bs = sizeof(Ctl) / sizeof(double);
     u.sign = -1.0;
     u.v32 = sizeof(T) == 4;
+    u.zero_in = w.x_zero;
+    w.x_zero = false;
     P.apply_x_first<double>(w.x.p, n, w.T64.p, B, live, 0u, &u, s);
     P.apply_x_rest<double>(w.x.p, n, sizeof(T) == 4 ? nullptr : r_out, r_bs, w.Q64.p, w.Q_bs, w.T64.p, B, live, -1.0,
                            -1.0, kYRhs, 0, true, s, nullptr, &xo, 0u, nullptr, 0);
@@ -1105,7 +1136,9 @@ int run_batch(const Pipeline& P, Work& w, const BatchCfg& cfg, hipStream_t s, st
   else
     P.rhs(w.Q64.p, w.Q_bs, w.T64.p, static_cast<c64*>(w.bvec.p), B, nullptr, rhs_flags, s);
   launch_reduce(static_cast<double*>(w.part_vec.p), 1, P.rhs_blocks(), nred, B, nullptr, s);
-  if (hipMemsetAsync(w.x.p, 0, (size_t)B * n * sizeof(c64), s) != hipSuccess)
+  // x = 0: the plain x-space residual's first launch writes x = sum y_i V_i on the first update (no memset)
+  w.x_zero = P.xspace && cfg.method == 0;
+  if (!w.x_zero && hipMemsetAsync(w.x.p, 0, (size_t)B * n * sizeof(c64), s) != hipSuccess)
     return fail(DBAR_EDEVICE, "hipMemsetAsync failed");
   for (int b = 0; b < B; ++b) w.host_live[b] = 1;
   if (hipMemcpyAsync(live, w.host_live.data(), B * sizeof(int), hipMemcpyHostToDevice, s) != hipSuccess)
