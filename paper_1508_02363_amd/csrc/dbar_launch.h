@@ -64,6 +64,7 @@ struct LineArgs {
   const void* dotV = nullptr;  size_t dotV_bs = 0;
   int dot_nv = 0;
   double* dot_part = nullptr;
+  int dot_self = 0;            // RowsInvTailEpilogue: |out|^2 as one more value, slot dot_nv (dot_nv + 1 per entry)
   // RowsFwdMoments: the pending Gram-Schmidt update of its input, in = in - sum_{i < upd_nv} upd_coef[b][i] V_i (V_i
   // at dotV as above), written back to upd_out (the input's own address), |in|^2 partials to upd_part[b][tile]
   const double* upd_coef = nullptr;  int upd_coef_bs = 0;

@@ -802,7 +802,8 @@ struct OpRowsInvTailEpi : OpColsInvTail<T, N, false> {
     block_reduce_store<NT, 1>(acc.v, this->a.part + (size_t)b * ntiles + tile, 0, scratch);
   }
   // Re<V_i, out> over this tile for i < dot_nv (FP64 accumulation, the order fixed); V_{dot_nv - 1} is S, whose
-  // products the stores accumulated.  Each wave reduces its products by shuffles and parks them in LDS; one barrier
+  // products the stores accumulated, as they did |out|^2 (value dot_nv with dot_self).  Each wave reduces its
+  // products by shuffles and parks them in LDS; one barrier
   // then serves all of them (the waves read their next V_i while others still compute).
   template <int NT>
   DBAR_D void dots(const Acc& acc, const cx<T>* v, int b, int row, int jt, int tile, int ntiles,
@@ -811,8 +812,9 @@ struct OpRowsInvTailEpi : OpColsInvTail<T, N, false> {
     const LineArgs& a = this->a;
     const int nv = a.dot_nv;
     if (nv <= 0) return;
+    const int nval = nv + (a.dot_self ? 1 : 0);
     const cx<T>* V = static_cast<const cx<T>*>(a.dotV) + (size_t)b * a.dotV_bs + (size_t)row * N;
-    double* dst = a.dot_part + (size_t)b * nv * ntiles + tile;
+    double* dst = a.dot_part + (size_t)b * nval * ntiles + tile;
     auto partial = [&](int i) {
       const cx<T>* Vi = V + (size_t)i * N * N;
       double p4[4] = {0.0, 0.0, 0.0, 0.0};
@@ -826,13 +828,17 @@ struct OpRowsInvTailEpi : OpColsInvTail<T, N, false> {
       __syncthreads();  // scratch aliases the LDS the stores and the norm reduction used
       double x = wsum64(acc.sdot);
       if (lane == 0) scratch[(nv - 1) * NW + wave] = x;
+      if (a.dot_self) {
+        x = wsum64(acc.v[0]);
+        if (lane == 0) scratch[nv * NW + wave] = x;
+      }
 #pragma unroll 1
       for (int i = 0; i < nv - 1; ++i) {
         x = wsum64(partial(i));
         if (lane == 0) scratch[i * NW + wave] = x;
       }
       __syncthreads();
-      for (int i = threadIdx.x; i < nv; i += NT) {
+      for (int i = threadIdx.x; i < nval; i += NT) {
         double t = 0.0;
         for (int q = 0; q < NW; ++q) t += scratch[i * NW + q];
         dst[(size_t)i * ntiles] = t;
@@ -840,6 +846,7 @@ struct OpRowsInvTailEpi : OpColsInvTail<T, N, false> {
     } else {
       const double last[1] = {acc.sdot};
       block_reduce_store<NT, 1>(last, dst + (size_t)(nv - 1) * ntiles, 0, scratch);
+      if (a.dot_self) block_reduce_store<NT, 1>(acc.v, dst + (size_t)nv * ntiles, 0, scratch);
 #pragma unroll 1
       for (int i = 0; i < nv - 1; ++i) {
         const double val[1] = {partial(i)};

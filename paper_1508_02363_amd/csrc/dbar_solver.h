@@ -173,6 +173,7 @@ struct DotReq {
   size_t V_bs = 0;
   int nv = 0;
   double* part = nullptr;
+  bool self = false;  // x-space: |out|^2 too, as value nv (nv + 1 values per entry)
 };
 
 struct Pipeline {

@@ -104,33 +104,9 @@ __global__ void __launch_bounds__(kCtlThreads) k_moments(const double* part, int
   moments_entry(b, part, ntiles, wscale, M, coefG, dmom, dmom32);
 }
 
-// Gram-Schmidt pass `pass` of step j: h_i = <v_i, w> from the partials, coef_i = sigma_i^2 h_i (the basis is kept
-// unnormalised, v_i / ||v_i|| = sigma_i v_i), hsum_i accumulates sigma_i h_i over the passes.  One block per entry.
-__global__ void __launch_bounds__(kCtlThreads) k_ctl_coef(Ctl* ctl, const double* part, int nval, int nblk,
-                                                          const int* act, int j, int pass) {
-  const int b = blockIdx.x;
-  if (!act[b]) return;
-  __shared__ double red[kMaxRestart + 2];
-  reduce_entry(part + (size_t)b * nval * nblk, nval, nblk, red);
-  if (threadIdx.x == 0) {
-    Ctl& c = ctl[b];
-    for (int i = 0; i <= j; ++i) {
-      const double h = red[i];
-      c.coef[i] = c.sigma[i] * c.sigma[i] * h;
-      c.hsum[i] = (pass ? c.hsum[i] : 0.0) + c.sigma[i] * h;
-    }
-  }
-}
-
-// Column j of the Hessenberg matrix from hsum and beta = ||w_new|| (reduced from the update's partials), Givens
-// rotation, residual estimate; the entry leaves the cycle when the estimate meets its threshold.  All kCtlThreads
-// threads of entry b's block.
-DBAR_D void givens_entry(int b, Ctl* ctl, const double* pnorm, int nblk, int* act, int j, int m) {
-  __shared__ double red[1];
-  reduce_entry(pnorm + (size_t)b * nblk, 1, nblk, red);
-  if (threadIdx.x != 0) return;
-  Ctl& c = ctl[b];
-  const double beta = sqrt(fmax(red[0], 0.0));
+// Column j of the Hessenberg matrix from hsum and beta = ||v_{j+1}|| (unnormalised basis: column j is sigma_j times the
+// products of A v_j), the previous Givens rotations applied, the new rotation, g and the residual estimate |g_{j+1}|.
+DBAR_D void givens_commit(Ctl& c, int j, double beta) {
   const double sj = c.sigma[j];
   double* col = c.H + (size_t)j * (kMaxRestart + 1);
   for (int i = 0; i <= j; ++i) col[i] = sj * c.hsum[i];
@@ -151,6 +127,60 @@ DBAR_D void givens_entry(int b, Ctl* ctl, const double* pnorm, int nblk, int* ac
   c.resid = fabs(c.g[j + 1]);
   c.jn = j + 1;
   c.iters += 1;
+}
+
+// Gram-Schmidt pass `pass` of step j: h_i = <v_i, w> from the partials, coef_i = sigma_i^2 h_i (the basis is kept
+// unnormalised, v_i / ||v_i|| = sigma_i v_i), hsum_i accumulates sigma_i h_i over the passes.  One block per entry.
+// early (one pass, value j + 1 of the partials = ||w||^2): the step's convergence is decided here, before the update
+// that forms v_{j+1} runs.  With one classical pass v_{j+1} = w - sum_i hsum_i q_i (q_i = sigma_i v_i orthonormal), so
+// ||v_{j+1}||^2 = ||w||^2 - sum_i hsum_i^2; where that difference keeps at least 1e-4 of ||w||^2 (the FP64 sums of
+// products then fix beta to about 1e-3 relative or better), the rotation it implies gives the residual estimate, and
+// an entry that meets its threshold (or the restart length) takes its last Givens step with this beta and leaves the
+// cycle: the update, transform and moments of a v_{j+1} no step would use are not run for it.  Otherwise the step
+// waits for the exact norm from the update, as without `early`.
+__global__ void __launch_bounds__(kCtlThreads) k_ctl_coef(Ctl* ctl, const double* part, int nval, int nblk, int* act,
+                                                          int j, int pass, int early, int m) {
+  const int b = blockIdx.x;
+  if (!act[b]) return;
+  __shared__ double red[kMaxRestart + 2];
+  reduce_entry(part + (size_t)b * nval * nblk, nval, nblk, red);
+  if (threadIdx.x == 0) {
+    Ctl& c = ctl[b];
+    double p2 = 0.0;
+    for (int i = 0; i <= j; ++i) {
+      const double h = red[i];
+      c.coef[i] = c.sigma[i] * c.sigma[i] * h;
+      c.hsum[i] = (pass ? c.hsum[i] : 0.0) + c.sigma[i] * h;
+      p2 += c.hsum[i] * c.hsum[i];
+    }
+    if (early) {
+      const double wn2 = red[j + 1], b2 = wn2 - p2;
+      if (b2 > 1e-4 * wn2) {
+        const double beta = sqrt(b2), sj = c.sigma[j];
+        // column j's last entry after the previous rotations, without touching the record
+        double top = sj * c.hsum[0];
+        for (int i = 0; i < j; ++i) top = -c.sn[i] * top + c.cs[i] * (sj * c.hsum[i + 1]);
+        const double sub = sj * beta, den = hypot(top, sub);
+        const double resid = den > 0.0 ? fabs(sub / den * c.g[j]) : 0.0;
+        if (resid <= c.thresh || j + 1 >= m) {
+          givens_commit(c, j, beta);
+          act[b] = 0;
+        }
+      }
+    }
+  }
+}
+
+// Column j of the Hessenberg matrix from hsum and beta = ||w_new|| (reduced from the update's partials), Givens
+// rotation, residual estimate; the entry leaves the cycle when the estimate meets its threshold.  All kCtlThreads
+// threads of entry b's block.
+DBAR_D void givens_entry(int b, Ctl* ctl, const double* pnorm, int nblk, int* act, int j, int m) {
+  __shared__ double red[1];
+  reduce_entry(pnorm + (size_t)b * nblk, 1, nblk, red);
+  if (threadIdx.x != 0) return;
+  Ctl& c = ctl[b];
+  const double beta = sqrt(fmax(red[0], 0.0));
+  givens_commit(c, j, beta);
   if (c.resid <= c.thresh || j + 1 >= m || beta == 0.0) act[b] = 0;
 }
 
@@ -626,6 +656,7 @@ void Pipeline::apply_x_rest(const void* in, size_t in_bs, void* out, size_t out_
     a.dotV_bs = dr->V_bs;
     a.dot_nv = dr->nv;
     a.dot_part = dr->part;
+    a.dot_self = dr->self ? 1 : 0;
   }
   launch_lines_any<T>(N, LineOp::RowsInvTailEpilogue, a, s);
 }
@@ -903,13 +934,14 @@ int krylov_cycle(const Pipeline& P, Work& w, const BatchCfg& cfg, int it_budget,
       dr.V_bs = V_bs;
       dr.nv = j + 1;
       dr.part = part;
+      dr.self = true;  // ||w||^2 for the early convergence decision
       if (j == 0) P.apply_x_first<T>(vj, V_bs, Tbuf, B, act, 0u, nullptr, s);
       P.apply_x_rest<T>(vj, V_bs, vj1, V_bs, Qp, w.Q_bs, Tbuf, B, act, 1.0, 1.0, nullptr, 0, false, s, &dr, nullptr, 0u,
                         nullptr, 0);
       {
         TimerScope ts(kStageControl, 0.0, B, nullptr, s);
-        hipLaunchKernelGGL(k_ctl_coef, dim3(B), dim3(kCtlThreads), 0, s, ctl, part, j + 1,
-                           P.apply_tiles(sizeof(T) == 8), act, j, 0);
+        hipLaunchKernelGGL(k_ctl_coef, dim3(B), dim3(kCtlThreads), 0, s, ctl, part, j + 2,
+                           P.apply_tiles(sizeof(T) == 8), act, j, 0, 1, w.m);
       }
       UpdReq u;
       u.V = V;
@@ -953,7 +985,8 @@ int krylov_cycle(const Pipeline& P, Work& w, const BatchCfg& cfg, int it_budget,
       }
       {
         TimerScope ts(kStageControl, 0.0, B, nullptr, s);
-        hipLaunchKernelGGL(k_ctl_coef, dim3(B), dim3(kCtlThreads), 0, s, ctl, part, j + 1, nblk, act, j, pass);
+        hipLaunchKernelGGL(k_ctl_coef, dim3(B), dim3(kCtlThreads), 0, s, ctl, part, j + 1, nblk, act, j, pass, 0,
+                           w.m);
       }
       va.coef = &ctl[0].coef[0];
       va.coef_bs = sizeof(Ctl) / sizeof(double);
