@@ -922,8 +922,9 @@ int krylov_cycle(const Pipeline& P, Work& w, const BatchCfg& cfg, int it_budget,
   const int mlim = std::min(w.m, it_budget);
 
   // x-space plain method with one Gram-Schmidt pass: the update of step j runs inside the first launch of step j + 1's
-  // operator (which reads the new vector anyway); step 0 starts the operator on v_0 itself, and the update of the
-  // cycle's last step also transforms a vector no step will use (one launch's worth of waste per cycle).
+  // operator (which reads the new vector anyway); step 0 starts the operator on v_0 itself.  The step's convergence is
+  // decided from ||w||^2 and the products before that update (k_ctl_coef), so an entry's last step runs no update, and
+  // its Givens step otherwise rides on the moment reduction of v_{j+1}.
   const bool fused = P.xspace && cfg.method == 0 && cfg.reorth == 1;
   auto enqueue = [&](int j) {
     void* vj = V + (size_t)j * n * sizeof(cx<T>);
