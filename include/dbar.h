@@ -87,6 +87,12 @@ typedef struct {
                           DBAR_SPACE_XI: S (or h) itself, as written in Sections 4 and 5.3. */
   double inner_tol;    /* DBAR_MIXED: residual reduction asked of each FP32 inner solve; 0 (default) = 1e-6 in
                           x-space, 1e-5 in xi-space */
+  int32_t orth_window; /* plain method in x-space with one Gram-Schmidt pass: each new basis vector is orthogonalised
+                          against the last orth_window vectors only (the Hessenberg matrix is then banded above the
+                          window and the residual estimate a quasi-residual, which the FP64 residual recomputed at
+                          every cycle end checks).  0 = against all of them (classical GMRES).  Default set by
+                          dbar_default_opts; negative or above the restart length: DBAR_EINVAL.  Other methods and
+                          spaces always orthogonalise fully. */
 } dbar_opts;
 
 enum { DBAR_METHOD_PLAIN = 0, DBAR_METHOD_ITERATED = 1 };

@@ -139,6 +139,7 @@ static void worker(dbar_session* s, SClass* cp) {
   cfg.reorth = 1;
   cfg.check_every = 4;
   cfg.inner_tol = 1e-6;  // x-space inner solves
+  cfg.orth_window = kDefaultOrthWindow;
   while (!s->stop.load()) {
     // ---- admission at the cycle boundary
     std::vector<int> admitted;

@@ -139,7 +139,7 @@ DBAR_D void givens_commit(Ctl& c, int j, double beta) {
 // cycle: the update, transform and moments of a v_{j+1} no step would use are not run for it.  Otherwise the step
 // waits for the exact norm from the update, as without `early`.
 __global__ void __launch_bounds__(kCtlThreads) k_ctl_coef(Ctl* ctl, const double* part, int nval, int nblk, int* act,
-                                                          int j, int pass, int early, int m) {
+                                                          int j, int pass, int early, int m, int lo) {
   const int b = blockIdx.x;
   if (!act[b]) return;
   __shared__ double red[kMaxRestart + 2];
@@ -147,14 +147,15 @@ __global__ void __launch_bounds__(kCtlThreads) k_ctl_coef(Ctl* ctl, const double
   if (threadIdx.x == 0) {
     Ctl& c = ctl[b];
     double p2 = 0.0;
-    for (int i = 0; i <= j; ++i) {
-      const double h = red[i];
+    for (int i = 0; i < lo; ++i) c.coef[i] = c.hsum[i] = 0.0;  // outside the window (one pass)
+    for (int i = lo; i <= j; ++i) {
+      const double h = red[i - lo];
       c.coef[i] = c.sigma[i] * c.sigma[i] * h;
       c.hsum[i] = (pass ? c.hsum[i] : 0.0) + c.sigma[i] * h;
       p2 += c.hsum[i] * c.hsum[i];
     }
     if (early) {
-      const double wn2 = red[j + 1], b2 = wn2 - p2;
+      const double wn2 = red[j - lo + 1], b2 = wn2 - p2;
       if (b2 > 1e-4 * wn2) {
         const double beta = sqrt(b2), sj = c.sigma[j];
         // column j's last entry after the previous rotations, without touching the record
@@ -930,10 +931,13 @@ int krylov_cycle(const Pipeline& P, Work& w, const BatchCfg& cfg, int it_budget,
     void* vj = V + (size_t)j * n * sizeof(cx<T>);
     void* vj1 = V + (size_t)(j + 1) * n * sizeof(cx<T>);
     if (fused) {
+      // the window of basis vectors this step orthogonalises against: v_lo .. v_j (all of them without a window)
+      const int lo = cfg.orth_window > 0 ? std::max(0, j - cfg.orth_window + 1) : 0;
+      char* Vlo = V + (size_t)lo * n * sizeof(cx<T>);
       DotReq dr;
-      dr.V = V;
+      dr.V = Vlo;
       dr.V_bs = V_bs;
-      dr.nv = j + 1;
+      dr.nv = j - lo + 1;
       dr.part = part;
       dr.self = true;  // ||w||^2 for the early convergence decision
       if (j == 0) P.apply_x_first<T>(vj, V_bs, Tbuf, B, act, 0u, nullptr, s);
@@ -941,14 +945,14 @@ int krylov_cycle(const Pipeline& P, Work& w, const BatchCfg& cfg, int it_budget,
                         nullptr, 0);
       {
         TimerScope ts(kStageControl, 0.0, B, nullptr, s);
-        hipLaunchKernelGGL(k_ctl_coef, dim3(B), dim3(kCtlThreads), 0, s, ctl, part, j + 2,
-                           P.apply_tiles(sizeof(T) == 8), act, j, 0, 1, w.m);
+        hipLaunchKernelGGL(k_ctl_coef, dim3(B), dim3(kCtlThreads), 0, s, ctl, part, j - lo + 2,
+                           P.apply_tiles(sizeof(T) == 8), act, j, 0, 1, w.m, lo);
       }
       UpdReq u;
-      u.V = V;
+      u.V = Vlo;
       u.V_bs = V_bs;
-      u.nv = j + 1;
-      u.coef = &ctl[0].coef[0];
+      u.nv = j - lo + 1;
+      u.coef = &ctl[0].coef[lo];
       u.coef_bs = sizeof(Ctl) / sizeof(double);
       u.part = pnorm;
       u.ctl = ctl;  // step j's Givens step rides on the moment reduction of v_{j+1}
@@ -987,7 +991,7 @@ int krylov_cycle(const Pipeline& P, Work& w, const BatchCfg& cfg, int it_budget,
       {
         TimerScope ts(kStageControl, 0.0, B, nullptr, s);
         hipLaunchKernelGGL(k_ctl_coef, dim3(B), dim3(kCtlThreads), 0, s, ctl, part, j + 1, nblk, act, j, pass, 0,
-                           w.m);
+                           w.m, 0);
       }
       va.coef = &ctl[0].coef[0];
       va.coef_bs = sizeof(Ctl) / sizeof(double);
@@ -1012,7 +1016,8 @@ int krylov_cycle(const Pipeline& P, Work& w, const BatchCfg& cfg, int it_budget,
     bool done = false;
     if (graphs) {
       const auto key =
-          std::make_tuple((int)sizeof(T) + 16 * cfg.method + 64 * (P.xspace ? 1 : 0), j * 1024 + j1, cfg.reorth, B);
+          std::make_tuple((int)sizeof(T) + 16 * cfg.method + 64 * (P.xspace ? 1 : 0), j * 1024 + j1,
+                          cfg.reorth + 16 * (fused ? cfg.orth_window : 0), B);
       auto it = w.graphs.find(key);
       if (it != w.graphs.end()) {
         done = hipGraphLaunch(it->second, s) == hipSuccess;
@@ -1283,6 +1288,8 @@ int solve_impl(const dbar_grid* grid, const void* Q, bool q_on_device, int64_t n
   if (o.max_iter <= 0) o.max_iter = 1000;
   if (o.reorth < 1 || o.reorth > 2) o.reorth = 1;
   if (o.check_every <= 0) o.check_every = 4;
+  if (o.orth_window < 0 || o.orth_window > o.restart)
+    return fail(DBAR_EINVAL, "orth_window must be in [0, restart]");
   // default: the x-space FP32 operator keeps 1e-6 attainable per cycle (its moments are exact sums of the FP32
   // vector); the xi-space one forms them after an FP32 round trip and stalls near 1e-5
   const bool xspace_solve = o.space == DBAR_SPACE_X;
@@ -1341,6 +1348,7 @@ int solve_impl(const dbar_grid* grid, const void* Q, bool q_on_device, int64_t n
   if (cfg.method == 1 && (rc = w.Hbuf.ensure((size_t)B * n * sizeof(c64)))) return rc;
   cfg.check_every = o.mode == DBAR_MODE_PLAIN ? 1 : o.check_every;
   cfg.inner_tol = o.inner_tol;
+  cfg.orth_window = o.orth_window;
   cfg.xspace = o.space == DBAR_SPACE_X ? 1 : 0;
   P.xspace = cfg.xspace != 0;
   if (cfg.xspace && ((rc = w.Sx.ensure((size_t)B * n * sizeof(c64))) || (rc = w.mx.ensure((size_t)B * n * sizeof(c64)))))
@@ -1474,6 +1482,7 @@ void dbar_default_opts(dbar_opts* o) {
   o->method = 0;
   o->space = DBAR_SPACE_X;
   o->inner_tol = 0.0;
+  o->orth_window = kDefaultOrthWindow;
 }
 
 const char* dbar_last_error(void) { return g_last_error.c_str(); }

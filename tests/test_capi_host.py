@@ -59,7 +59,8 @@ def test_invalid_arguments_are_rejected(kw):
     assert _lib.load().dbar_last_error().decode()
 
 
-@pytest.mark.parametrize("opt", [dict(space=2), dict(space=-1), dict(method=2)])
+@pytest.mark.parametrize("opt", [dict(space=2), dict(space=-1), dict(method=2), dict(orth_window=-1),
+                                 dict(orth_window=65)])
 def test_invalid_solver_options_are_rejected(opt):
     lib = _lib.load()
     g = _lib.Grid(16, 11, 2.0)
@@ -97,6 +98,7 @@ def test_default_opts():
     o = _lib.Opts()
     _lib.load().dbar_default_opts(ctypes.byref(o))
     assert o.max_iter == 1000 and o.reorth == 1 and o.precision == _lib.DBAR_FP64 and o.inner_tol == 0.0
+    assert o.orth_window == 2
 
 
 def test_reflection_and_reconstruction_reject_bad_arguments():

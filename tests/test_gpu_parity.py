@@ -301,11 +301,31 @@ def test_spaces_take_the_same_krylov_steps():
     N, L = 128, 5.0
     Q = W.potential_gaussian_sum(N, L, seed=63)
     ks = W.k_disk(8, 3.0, seed=64)
-    Sx, mx, ix = D.solve(Q, ks, L, tol=1e-12, batch=8, space=D.DBAR_SPACE_X)
+    Sx, mx, ix = D.solve(Q, ks, L, tol=1e-12, batch=8, space=D.DBAR_SPACE_X, orth_window=0)
     Sq, mq, iq = D.solve(Q, ks, L, tol=1e-12, batch=8, space=D.DBAR_SPACE_XI)
     for j in range(len(ks)):
         assert abs(ix[j].iters - iq[j].iters) <= 1, j
         assert relerr(Sx[j], Sq[j]) < 1e-10 and relerr(mx[j], mq[j]) < 1e-10, j
+
+
+@pytest.mark.parametrize("prec", [D.DBAR_FP64, D.DBAR_MIXED])
+def test_gram_schmidt_window_reaches_the_full_solution(prec):
+    """Orthogonalising each new basis vector against the last few only changes the Krylov steps, not the answer: every
+    window gives S and m of the fully orthogonalised solve to the tolerance, with the FP64 residual met, and the
+    oracle's S at k = 0."""
+    N, L = 128, 5.0
+    g = O.make_grid(N, L)
+    Q = W.potential_gaussian_sum(N, L, seed=65)
+    ks = np.concatenate([[0.0], W.k_disk(6, 3.0, seed=66)])
+    S0, m0, i0 = D.solve(Q, ks, L, tol=1e-12, batch=7, precision=prec, orth_window=0)
+    ref = O.solve(g, Q, ks[0], tol=1e-13)
+    for win in (1, 2, 3):
+        S, m, info = D.solve(Q, ks, L, tol=1e-12, batch=7, precision=prec, orth_window=win)
+        for j in range(len(ks)):
+            assert info[j].status == 0 and info[j].rel_residual <= 1e-12, (win, j)
+            assert relerr(S[j], S0[j]) < 1e-10 and relerr(m[j], m0[j]) < 1e-10, (win, j)
+            assert info[j].iters <= 2 * i0[j].iters + 4, (win, j)
+        assert relerr(S[0], ref.S) < 1e-10, win
 
 
 @pytest.mark.parametrize("prec", [D.DBAR_FP64, D.DBAR_MIXED])
