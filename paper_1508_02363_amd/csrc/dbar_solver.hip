@@ -49,11 +49,13 @@ DBAR_D double wsum(double x) {
 // Deterministic block reduction of one entry's partials: red[v] = sum_blk part[v * nblk + blk] for v < nval
 // (wave w sums the values v = w, w + NW, ...; lanes stride over the partials).  1024 threads.
 constexpr int kCtlThreads = 1024;
-DBAR_D void reduce_entry(const double* __restrict__ part, int nval, int nblk, double* red) {
+// Values v >= nv1 come from part2 (v - nv1 of it, same nblk) when part2 is given.
+DBAR_D void reduce_entry(const double* __restrict__ part, int nval, int nblk, double* red,
+                         const double* __restrict__ part2 = nullptr, int nv1 = 0) {
   constexpr int NW = kCtlThreads / 64;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int v = wave; v < nval; v += NW) {
-    const double* p = part + (size_t)v * nblk;
+    const double* p = (part2 && v >= nv1) ? part2 + (size_t)(v - nv1) * nblk : part + (size_t)v * nblk;
     // eight independent partial sums per lane: the loads of a chunk are in flight together
     double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     int i = lane;
@@ -69,31 +71,35 @@ DBAR_D void reduce_entry(const double* __restrict__ part, int nval, int nblk, do
   __syncthreads();
 }
 
-// d_n = w sum_tiles part, c_n = (-i/2)^n d_n / n! (equation fourreeg4 with Gchoice), R(0) = (-i/2) dt, for entry b.
+// d_n = w sum_tiles part, c_n = (-i/2)^n d_n / n! (equation fourreeg4 with Gchoice), R(0) = (-i/2) dt, for entry b,
+// from the reduced tile sums tot: thread n < kNMom forms slot n ((-i/2)^n = (-i)^n 2^-n exactly).
+DBAR_D void moments_combine(int b, const double* tot, double wscale, int M, c64* coefG, c64* dmom, c32* dmom32) {
+  const int n = threadIdx.x;
+  if (n >= kNMom) return;
+  const c64 d{wscale * tot[2 * n], wscale * tot[2 * n + 1]};
+  c64* cg = coefG + (size_t)b * kNMom;
+  c64* dm = dmom + (size_t)b * kNMom;
+  c32* dm32 = dmom32 + (size_t)b * kNMom;
+  if (n == kMaxM + 1) {  // the conj(z) moment: R(0) = (-i/2) dt
+    cg[n] = c64{0.0, -0.5} * d;
+    dm[n] = d;
+    dm32[n] = cvt<float>(d);
+    return;
+  }
+  const double s = ldexp(1.0, -n);
+  const c64 p = (n & 3) == 0 ? c64{s, 0.0} : (n & 3) == 1 ? c64{0.0, -s} : (n & 3) == 2 ? c64{-s, 0.0} : c64{0.0, s};
+  dm[n] = n <= M ? d : c64{0.0, 0.0};
+  dm32[n] = cvt<float>(dm[n]);
+  cg[n] = n <= M ? kInvFactC[n] * (p * d) : c64{0.0, 0.0};
+}
+
 // All kCtlThreads threads of the block.
 DBAR_D void moments_entry(int b, const double* part, int ntiles, double wscale, int M, c64* coefG, c64* dmom,
                           c32* dmom32) {
   constexpr int NV = 2 * kNMom;
   __shared__ double tot[NV];
   reduce_entry(part + (size_t)b * NV * ntiles, NV, ntiles, tot);
-  if (threadIdx.x == 0) {
-    c64* cg = coefG + (size_t)b * kNMom;
-    c64* dm = dmom + (size_t)b * kNMom;
-    c32* dm32 = dmom32 + (size_t)b * kNMom;
-    c64 p{1.0, 0.0};
-    const c64 mh{0.0, -0.5};
-    for (int n = 0; n <= kMaxM; ++n) {
-      const c64 d{wscale * tot[2 * n], wscale * tot[2 * n + 1]};
-      dm[n] = n <= M ? d : c64{0.0, 0.0};
-      dm32[n] = cvt<float>(dm[n]);
-      cg[n] = n <= M ? kInvFactC[n] * (p * d) : c64{0.0, 0.0};
-      p = p * mh;
-    }
-    const c64 dt{wscale * tot[2 * (kMaxM + 1)], wscale * tot[2 * (kMaxM + 1) + 1]};
-    cg[kMaxM + 1] = mh * dt;
-    dm[kMaxM + 1] = dt;
-    dm32[kMaxM + 1] = cvt<float>(dt);
-  }
+  moments_combine(b, tot, wscale, M, coefG, dmom, dmom32);
 }
 
 // One block of kCtlThreads per entry.
@@ -200,8 +206,16 @@ __global__ void __launch_bounds__(kCtlThreads) k_moments_givens(const double* pa
                                                                 int m) {
   const int b = blockIdx.x;
   if (!act[b]) return;
-  moments_entry(b, part, ntiles, wscale, M, coefG, dmom, dmom32);
-  givens_entry(b, ctl, pnorm, nblk, act, j, m);
+  constexpr int NV = 2 * kNMom;
+  __shared__ double tot[NV + 1];  // the moment sums, then |v_{j+1}|^2
+  reduce_entry(part + (size_t)b * NV * ntiles, NV + 1, ntiles, tot, pnorm + (size_t)b * nblk, NV);
+  moments_combine(b, tot, wscale, M, coefG, dmom, dmom32);  // wave 0
+  if (threadIdx.x == 64) {                                   // wave 1
+    Ctl& c = ctl[b];
+    const double beta = sqrt(fmax(tot[NV], 0.0));
+    givens_commit(c, j, beta);
+    if (c.resid <= c.thresh || j + 1 >= m || beta == 0.0) act[b] = 0;
+  }
 }
 
 // y = H^{-1} g (upper triangular jn x jn), coef_i = y_i sigma_i, zero beyond jn
