@@ -16,9 +16,9 @@ namespace dbar {
 
 constexpr int kMaxRestart = 64;
 // Gram-Schmidt window of the fused x-space step set by dbar_default_opts (0: full orthogonalisation).  Against the
-// last two vectors the Krylov cycles of the N = 1024 benchmark run 0-4 more steps than fully orthogonalised ones but
-// read far fewer basis vectors: 12% less time per mixed solve, 22% per FP64 solve; windows of 3, 4, 6 and 8 fall in
-// between.
+// last two vectors the Krylov cycles of an N = 1024, 16-k Gaussian-potential batch run 0-4 more steps than fully
+// orthogonalised ones but read far fewer basis vectors: 12% less time per mixed solve, 22% per FP64 solve; windows
+// of 3, 4, 6 and 8 fall in between.
 constexpr int kDefaultOrthWindow = 2;
 
 int fail(int code, const std::string& msg);
