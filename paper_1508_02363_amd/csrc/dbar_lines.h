@@ -526,6 +526,15 @@ struct OpRowsFwdMoments : MomentsBase<T, N, true> {
   DBAR_D void store(Acc&, int b, int row, int pos, cx<T> v) const { this->outp(b)[(size_t)row * N + pos] = v; }
 };
 
+// sum_{n <= MM} c_n w^n by Horner's rule
+template <int MM>
+DBAR_D c64 g_poly(const c64* __restrict__ c, c64 w) {
+  c64 g = c[MM];
+#pragma unroll
+  for (int n = MM - 1; n >= 0; --n) g = cfma(w, g, c[n]);
+  return g;
+}
+
 // R = (S - G)/xi (R(0) from coefG slot kMaxM+1), then out = IFFT_rows(phase * ci * R)
 // phase * ci * (S - G)/xi at (row, pos) of entry b, S = sv there (R(0) = coefG slot kMaxM+1 at xi = a)
 template <typename T, int N>
@@ -543,9 +552,8 @@ DBAR_D cx<T> regularised(const LineArgs& a, int b, int row, int pos, cx<T> sv) {
   if (static_cast<float>(q) < static_cast<float>(740.0 * a.L * a.L)) {
     const double xi1 = m1 * invL, xi2 = m2 * invL;
     const c64 xib{xi1, -xi2};
-    const int M = a.M;
-    c64 g = c[M];
-    for (int n = M - 1; n >= 0; --n) g = cfma(xib, g, c[n]);
+    // unrolled for the order (c_n = 0 beyond M): the coefficient loads are issued together
+    const c64 g = a.M == 11 ? g_poly<11>(c, xib) : g_poly<kMaxM>(c, xib);
     sv = cvt<T>(cvt<double>(sv) - exp(-(xi1 * xi1 + xi2 * xi2)) * g);
   }
   // (S - G) / xi in the transform's precision
