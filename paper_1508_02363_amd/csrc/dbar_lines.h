@@ -93,8 +93,8 @@ DBAR_D TT recip(TT r) {
 
 // Coefficients c_k = prod_{j=1..k} (M+1)/(M+1+j) of F(u) = (M+1)! sum_k u^k/(M+1+k)! in powers of v = u/(M+1), and
 // the number of terms after which the rest is below half a rounding unit of F for every v < 1 (FP32 or FP64), for
-// the orders the tail is instantiated with (M = 11 and kMaxM).  Read from constant memory in a rolled loop: unrolled,
-// the compiler keeps every coefficient in a register.
+// the orders the tail is instantiated with (M = 11 and kMaxM).  Read from constant memory in a loop unrolled by four:
+// fully unrolled, the compiler keeps every coefficient in a register; rolled, each step waits for its own read.
 constexpr int kSerK32[2] = {25, 28}, kSerK64[2] = {40, 45};
 struct SeriesTables {
   double d[2][45];
@@ -149,7 +149,7 @@ DBAR_D cx<TT> tail_sum(TT x, TT y, const cx<TT> (&d)[kMaxM + 1]) {
     else c = kSeries.f[W];
     const TT v = u * TT(1.0 / (MM + 1));
     TT F = c[K - 1];
-#pragma unroll 1
+#pragma unroll 4
     for (int k = K - 2; k >= 0; --k) F = F * v + c[k];
     TT E = eu * F * TT(kInvFact[MM + 1]);
     const cx<TT> zeta{TT(0.25) * x, TT(-0.25) * y};
