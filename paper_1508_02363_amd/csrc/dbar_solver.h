@@ -229,6 +229,15 @@ struct Pipeline {
   void apply_B(const void* in, size_t in_bs, void* out, size_t out_bs, const void* Qp, size_t Q_bs, void* Tbuf,
                void* Hbuf, int B, const int* act, double alpha, double beta, const void* Y, size_t Y_bs,
                bool want_norm, hipStream_t s, const DotReq* dr = nullptr, const XOutB* xb = nullptr) const;
+  // x-space B in two parts as apply_x_first / apply_x_rest: the first launch of the shifted pass and its moment
+  // reduction (with u: the pending update of the input first), then the rest of both passes
+  template <typename T>
+  void apply_B_first(const void* in, size_t in_bs, void* Tbuf, int B, const int* act, const UpdReq* u,
+                     hipStream_t s) const;
+  template <typename T>
+  void apply_B_rest(const void* in, size_t in_bs, void* out, size_t out_bs, const void* Qp, size_t Q_bs, void* Tbuf,
+                    void* Hbuf, int B, const int* act, double alpha, double beta, const void* Y, size_t Y_bs,
+                    bool want_norm, hipStream_t s, const DotReq* dr, const XOutB* xb) const;
   void rhs(const void* Q64p, size_t Q_bs, void* T64, c64* bout, int B, const int* act, unsigned flags,
            hipStream_t s) const;
   // x-space: -i q_k straight into out (stride out_bs; FP32 if out32, the first basis vector of a mixed solve), with

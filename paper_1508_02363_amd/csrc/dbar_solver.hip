@@ -736,29 +736,44 @@ void Pipeline::apply_B(const void* in, size_t in_bs, void* out, size_t out_bs, c
                        void* Tbuf, void* Hbuf, int B, const int* act, double alpha, double beta, const void* Y,
                        size_t Y_bs, bool want_norm, hipStream_t s, const DotReq* dr, const XOutB* xb) const {
   if (xspace) {
-    // psi = F^{-1} H(F eta) = -i q conj(h_a(F eta)) (regularised about xi = a; q alone): the operator's three launches
-    // with the shifted regularisation and alpha = 0 ...
-    XOut xh;
-    if (xb) {
-      xh.S = xb->hxi;
-      xh.h = xb->ha;
-    }
-    apply_x<T>(in, in_bs, Hbuf, n, Qp, Q_bs, Tbuf, B, act, 0.0, -1.0, nullptr, 0, false, s, nullptr, &xh, kShifted);
-    // ... then eta + i q conj(h0(F psi)) (k = 0 phase, about xi = 0), the alpha term and the products taken with eta
-    XOut x0;
-    if (xb) {
-      x0.S = xb->f;
-      x0.h = xb->h0;
-      x0.r32 = xb->r32;
-      x0.r32_bs = xb->r32_bs;
-    }
-    apply_x<T>(Hbuf, n, out, out_bs, Qp, Q_bs, Tbuf, B, act, alpha, beta, Y, Y_bs, want_norm, s, dr, &x0,
-               kUnitPhase, in, in_bs);
+    apply_B_first<T>(in, in_bs, Tbuf, B, act, nullptr, s);
+    apply_B_rest<T>(in, in_bs, out, out_bs, Qp, Q_bs, Tbuf, Hbuf, B, act, alpha, beta, Y, Y_bs, want_norm, s, dr, xb);
     return;
   }
   H_of<T>(in, in_bs, Hbuf, n, Qp, Q_bs, Tbuf, B, act, s);
   apply_impl<T>(Hbuf, n, out, out_bs, Qp, Q_bs, Tbuf, B, act, alpha, beta, Y, Y_bs, want_norm, kUnitPhase, in,
                 in_bs, s, dr);
+}
+
+// x-space B on eta: psi = F^{-1} H(F eta) = -i q conj(h_a(F eta)) (regularised about xi = a; q alone), the operator's
+// three launches with the shifted regularisation and alpha = 0 (the first of them here) ...
+template <typename T>
+void Pipeline::apply_B_first(const void* in, size_t in_bs, void* Tbuf, int B, const int* act, const UpdReq* u,
+                             hipStream_t s) const {
+  apply_x_first<T>(in, in_bs, Tbuf, B, act, kShifted, u, s);
+}
+
+template <typename T>
+void Pipeline::apply_B_rest(const void* in, size_t in_bs, void* out, size_t out_bs, const void* Qp, size_t Q_bs,
+                            void* Tbuf, void* Hbuf, int B, const int* act, double alpha, double beta, const void* Y,
+                            size_t Y_bs, bool want_norm, hipStream_t s, const DotReq* dr, const XOutB* xb) const {
+  XOut xh;
+  if (xb) {
+    xh.S = xb->hxi;
+    xh.h = xb->ha;
+  }
+  apply_x_rest<T>(in, in_bs, Hbuf, n, Qp, Q_bs, Tbuf, B, act, 0.0, -1.0, nullptr, 0, false, s, nullptr, &xh, kShifted,
+                  nullptr, 0);
+  // ... then eta + i q conj(h0(F psi)) (k = 0 phase, about xi = 0), the alpha term and the products taken with eta
+  XOut x0;
+  if (xb) {
+    x0.S = xb->f;
+    x0.h = xb->h0;
+    x0.r32 = xb->r32;
+    x0.r32_bs = xb->r32_bs;
+  }
+  apply_x<T>(Hbuf, n, out, out_bs, Qp, Q_bs, Tbuf, B, act, alpha, beta, Y, Y_bs, want_norm, s, dr, &x0, kUnitPhase,
+             in, in_bs);
 }
 
 // b = -i F(Q e_k) (FP64; e_k = 1 with kUnitPhase), with |b|^2 partials (rhs_blocks() per entry); in x-space -i Q e_k
@@ -838,6 +853,11 @@ void Pipeline::transform(bool inverse, const void* in, void* out, void* Tbuf, hi
   template void Pipeline::apply_B<T>(const void*, size_t, void*, size_t, const void*, size_t, void*, void*, int,   \
                                      const int*, double, double, const void*, size_t, bool, hipStream_t,          \
                                      const DotReq*, const XOutB*) const;                                          \
+  template void Pipeline::apply_B_first<T>(const void*, size_t, void*, int, const int*, const UpdReq*,             \
+                                           hipStream_t) const;                                                    \
+  template void Pipeline::apply_B_rest<T>(const void*, size_t, void*, size_t, const void*, size_t, void*, void*,   \
+                                          int, const int*, double, double, const void*, size_t, bool,             \
+                                          hipStream_t, const DotReq*, const XOutB*) const;                        \
   template void Pipeline::H_of<T>(const void*, size_t, void*, size_t, const void*, size_t, void*, int, const int*, \
                                   hipStream_t) const;                                                            \
   template void Pipeline::h_of<T>(const void*, size_t, void*, size_t, void*, int, const int*, hipStream_t,         \
@@ -936,17 +956,19 @@ int krylov_cycle(const Pipeline& P, Work& w, const BatchCfg& cfg, int it_budget,
   char* V = static_cast<char*>(w.V.p);
   const int mlim = std::min(w.m, it_budget);
 
-  // x-space plain method with one Gram-Schmidt pass: the update of step j runs inside the first launch of step j + 1's
-  // operator (which reads the new vector anyway); step 0 starts the operator on v_0 itself.  The step's convergence is
-  // decided from ||w||^2 and the products before that update (k_ctl_coef), so an entry's last step runs no update, and
-  // its Givens step otherwise rides on the moment reduction of v_{j+1}.
-  const bool fused = P.xspace && cfg.method == 0 && cfg.reorth == 1;
+  // x-space, one Gram-Schmidt pass: the update of step j runs inside the first launch of step j + 1's operator (which
+  // reads the new vector anyway; for the iterated method the first launch of B's shifted pass); step 0 starts the
+  // operator on v_0 itself.  The step's convergence is decided from ||w||^2 and the products before that update
+  // (k_ctl_coef), so an entry's last step runs no update, and its Givens step otherwise rides on the moment reduction
+  // of v_{j+1}.  The Gram-Schmidt window applies to the plain method.
+  const bool fused = P.xspace && cfg.reorth == 1;
+  const int window = cfg.method == 0 ? cfg.orth_window : 0;
   auto enqueue = [&](int j) {
     void* vj = V + (size_t)j * n * sizeof(cx<T>);
     void* vj1 = V + (size_t)(j + 1) * n * sizeof(cx<T>);
     if (fused) {
       // the window of basis vectors this step orthogonalises against: v_lo .. v_j (all of them without a window)
-      const int lo = cfg.orth_window > 0 ? std::max(0, j - cfg.orth_window + 1) : 0;
+      const int lo = window > 0 ? std::max(0, j - window + 1) : 0;
       char* Vlo = V + (size_t)lo * n * sizeof(cx<T>);
       DotReq dr;
       dr.V = Vlo;
@@ -954,9 +976,15 @@ int krylov_cycle(const Pipeline& P, Work& w, const BatchCfg& cfg, int it_budget,
       dr.nv = j - lo + 1;
       dr.part = part;
       dr.self = true;  // ||w||^2 for the early convergence decision
-      if (j == 0) P.apply_x_first<T>(vj, V_bs, Tbuf, B, act, 0u, nullptr, s);
-      P.apply_x_rest<T>(vj, V_bs, vj1, V_bs, Qp, w.Q_bs, Tbuf, B, act, 1.0, 1.0, nullptr, 0, false, s, &dr, nullptr, 0u,
-                        nullptr, 0);
+      if (cfg.method == 1) {
+        if (j == 0) P.apply_B_first<T>(vj, V_bs, Tbuf, B, act, nullptr, s);
+        P.apply_B_rest<T>(vj, V_bs, vj1, V_bs, Qp, w.Q_bs, Tbuf, w.Hbuf.p, B, act, 1.0, 1.0, nullptr, 0, false, s, &dr,
+                          nullptr);
+      } else {
+        if (j == 0) P.apply_x_first<T>(vj, V_bs, Tbuf, B, act, 0u, nullptr, s);
+        P.apply_x_rest<T>(vj, V_bs, vj1, V_bs, Qp, w.Q_bs, Tbuf, B, act, 1.0, 1.0, nullptr, 0, false, s, &dr, nullptr,
+                          0u, nullptr, 0);
+      }
       {
         TimerScope ts(kStageControl, 0.0, B, nullptr, s);
         hipLaunchKernelGGL(k_ctl_coef, dim3(B), dim3(kCtlThreads), 0, s, ctl, part, j - lo + 2,
@@ -972,7 +1000,10 @@ int krylov_cycle(const Pipeline& P, Work& w, const BatchCfg& cfg, int it_budget,
       u.ctl = ctl;  // step j's Givens step rides on the moment reduction of v_{j+1}
       u.j = j;
       u.m = w.m;
-      P.apply_x_first<T>(vj1, V_bs, Tbuf, B, act, 0u, &u, s);
+      if (cfg.method == 1)
+        P.apply_B_first<T>(vj1, V_bs, Tbuf, B, act, &u, s);
+      else
+        P.apply_x_first<T>(vj1, V_bs, Tbuf, B, act, 0u, &u, s);
       return;
     }
     // the first Gram-Schmidt pass's products Re<V_i, w>, i <= j, come out of the operator's last kernel
@@ -1031,7 +1062,7 @@ int krylov_cycle(const Pipeline& P, Work& w, const BatchCfg& cfg, int it_budget,
     if (graphs) {
       const auto key =
           std::make_tuple((int)sizeof(T) + 16 * cfg.method + 64 * (P.xspace ? 1 : 0), j * 1024 + j1,
-                          cfg.reorth + 16 * (fused ? cfg.orth_window : 0), B);
+                          cfg.reorth + 16 * (fused ? window : 0), B);
       auto it = w.graphs.find(key);
       if (it != w.graphs.end()) {
         done = hipGraphLaunch(it->second, s) == hipSuccess;
@@ -1084,9 +1115,19 @@ void end_cycle(const Pipeline& P, Work& w, int nv, void* r_out, hipStream_t s, i
   va.w_bs = n;
   va.coef = &ctl[0].coef[0];
   va.coef_bs = sizeof(Ctl) / sizeof(double);
-  // the plain x-space residual's first launch reads x anyway: x += sum y_i V_i runs inside it
-  const bool fuse_axpy = P.xspace && method == 0;
+  // the x-space residual's first launch reads x anyway: x += sum y_i V_i runs inside it
+  const bool fuse_axpy = P.xspace;
   if (!fuse_axpy) launch_axpy_multi<double, T>(va, s);
+  UpdReq u;  // the fused solution update
+  u.V = w.V.p;
+  u.V_bs = n * (w.m + 1);
+  u.nv = nv;
+  u.coef = &ctl[0].coef[0];
+  u.coef_bs = sizeof(Ctl) / sizeof(double);
+  u.sign = -1.0;
+  u.v32 = sizeof(T) == 4;
+  u.zero_in = fuse_axpy && w.x_zero;
+  if (fuse_axpy) w.x_zero = false;
   const size_t r_bs = sizeof(T) == 8 ? n * (w.m + 1) : n;
   if (method == 1 && !P.xspace) {
     P.apply_B<double>(w.x.p, n, r_out, r_bs, w.Q64.p, w.Q_bs, w.T64.p, w.Hbuf.p, B, live, -1.0, -1.0, w.bvec.p, n,
@@ -1103,8 +1144,9 @@ void end_cycle(const Pipeline& P, Work& w, int nv, void* r_out, hipStream_t s, i
       xb.r32 = w.V.p;
       xb.r32_bs = n * (w.m + 1);
     }
-    P.apply_B<double>(w.x.p, n, sizeof(T) == 4 ? nullptr : r_out, r_bs, w.Q64.p, w.Q_bs, w.T64.p, w.Hbuf.p, B, live,
-                      -1.0, -1.0, kYRhs, 0, true, s, nullptr, &xb);
+    P.apply_B_first<double>(w.x.p, n, w.T64.p, B, live, &u, s);
+    P.apply_B_rest<double>(w.x.p, n, sizeof(T) == 4 ? nullptr : r_out, r_bs, w.Q64.p, w.Q_bs, w.T64.p, w.Hbuf.p, B,
+                           live, -1.0, -1.0, kYRhs, 0, true, s, nullptr, &xb);
   } else if (!P.xspace)
     P.apply<double>(w.x.p, n, r_out, r_bs, w.Q64.p, w.Q_bs, w.T64.p, B, live, -1.0, -1.0, w.bvec.p, n, true, s);
   else {
@@ -1117,16 +1159,6 @@ void end_cycle(const Pipeline& P, Work& w, int nv, void* r_out, hipStream_t s, i
       xo.r32 = w.V.p;
       xo.r32_bs = n * (w.m + 1);
     }
-    UpdReq u;
-    u.V = w.V.p;
-    u.V_bs = n * (w.m + 1);
-    u.nv = nv;
-    u.coef = &ctl[0].coef[0];
-    u.coef_bs = sizeof(Ctl) / sizeof(double);
-    u.sign = -1.0;
-    u.v32 = sizeof(T) == 4;
-    u.zero_in = w.x_zero;
-    w.x_zero = false;
     P.apply_x_first<double>(w.x.p, n, w.T64.p, B, live, 0u, &u, s);
     P.apply_x_rest<double>(w.x.p, n, sizeof(T) == 4 ? nullptr : r_out, r_bs, w.Q64.p, w.Q_bs, w.T64.p, B, live, -1.0,
                            -1.0, kYRhs, 0, true, s, nullptr, &xo, 0u, nullptr, 0);
@@ -1189,8 +1221,8 @@ int run_batch(const Pipeline& P, Work& w, const BatchCfg& cfg, hipStream_t s, st
   else
     P.rhs(w.Q64.p, w.Q_bs, w.T64.p, static_cast<c64*>(w.bvec.p), B, nullptr, rhs_flags, s);
   launch_reduce(static_cast<double*>(w.part_vec.p), 1, P.rhs_blocks(), nred, B, nullptr, s);
-  // x = 0: the plain x-space residual's first launch writes x = sum y_i V_i on the first update (no memset)
-  w.x_zero = P.xspace && cfg.method == 0;
+  // x = 0: the x-space residual's first launch writes x = sum y_i V_i on the first update (no memset)
+  w.x_zero = P.xspace;
   if (!w.x_zero && hipMemsetAsync(w.x.p, 0, (size_t)B * n * sizeof(c64), s) != hipSuccess)
     return fail(DBAR_EDEVICE, "hipMemsetAsync failed");
   for (int b = 0; b < B; ++b) w.host_live[b] = 1;
