@@ -70,7 +70,8 @@ typedef struct {
   int32_t max_iter;    /* cap on GMRES iterations per k, all cycles together; default 1000 */
   int32_t precision;   /* DBAR_FP64 or DBAR_MIXED */
   int32_t mode;        /* DBAR_MODE_BATCHED or DBAR_MODE_PLAIN */
-  int32_t batch;       /* k values per launch in batched mode; 0 = choose from free device memory */
+  int32_t batch;       /* k values per launch in batched mode; 0 = the tuner's choice for this grid size, else 64, or
+                          on grids below N = 512 about 2^24 / N^2 (N = 128: 1024); capped by free device memory */
   int32_t use_graph;   /* batched mode: replay Krylov iterations from captured HIP graphs (1 = on) */
   int32_t reorth;      /* Gram-Schmidt passes: 1 = classical (default), 2 = classical twice.  One pass loses
                           orthogonality to ~1e-3 on this operator but GMRES reaches the same residual in the same

@@ -1274,7 +1274,7 @@ static bool all_finite(const double* p, size_t cnt) {
   return true;
 }
 
-// batch size chosen by the tuner per (N, precision); 0 = not tuned (use min(nk, 64))
+// batch size chosen by the tuner per (N, precision); 0 = not tuned (the default below)
 static std::atomic<int> g_batch[2][12];
 static int batch_slot(int N) {
   int i = 0;
@@ -1360,7 +1360,10 @@ int solve_impl(const dbar_grid* grid, const void* Q, bool q_on_device, int64_t n
     if (!all_finite(static_cast<const double*>(Q), 2 * n)) return fail(DBAR_EINVAL, "Q contains NaN or Inf");
   }
   const int tuned = tuned_batch(N, o.precision == DBAR_FP64);
-  int B = o.mode == DBAR_MODE_PLAIN ? 1 : (o.batch > 0 ? o.batch : (int)std::min<int64_t>(nk, tuned > 0 ? tuned : 64));
+  // untuned default: 64 entries, or on small grids enough entries for about 2^24 grid points per launch (N = 128:
+  // 1024), which a launch needs to fill the GPU
+  const int dflt = (int)std::max<int64_t>(64, std::min<int64_t>(4096, (int64_t(1) << 24) / ((int64_t)N * N)));
+  int B = o.mode == DBAR_MODE_PLAIN ? 1 : (o.batch > 0 ? o.batch : (int)std::min<int64_t>(nk, tuned > 0 ? tuned : dflt));
   B = (int)std::min<int64_t>(B, nk);
   if (o.mode != DBAR_MODE_PLAIN && o.batch <= 0) {
     // fit the batch to free memory: basis + 6 vectors per entry
