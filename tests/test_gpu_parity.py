@@ -329,6 +329,38 @@ def test_gram_schmidt_window_reaches_the_full_solution(prec):
 
 
 @pytest.mark.parametrize("prec", [D.DBAR_FP64, D.DBAR_MIXED])
+def test_gram_schmidt_window_with_short_restarts(prec):
+    """Restart lengths shorter than a cycle's convergence (several restarts per refinement cycle), with windows up to the
+    restart length: the same converged S and m as the full method with a long restart."""
+    N, L = 64, 4.0
+    Q = W.potential_gaussian_sum(N, L, seed=67)
+    ks = W.k_disk(5, 2.5, seed=68)
+    S0, m0, _ = D.solve(Q, ks, L, tol=1e-12, batch=5, precision=prec, orth_window=0, restart=40)
+    for restart, win in ((4, 2), (4, 4), (6, 1)):
+        S, m, info = D.solve(Q, ks, L, tol=1e-12, batch=5, precision=prec, orth_window=win, restart=restart)
+        for j in range(len(ks)):
+            assert info[j].status == 0 and info[j].rel_residual <= 1e-12, (restart, win, j)
+            assert relerr(S[j], S0[j]) < 1e-10 and relerr(m[j], m0[j]) < 1e-10, (restart, win, j)
+
+
+@pytest.mark.parametrize("prec", [D.DBAR_FP64, D.DBAR_MIXED])
+def test_iterated_fused_step_matches_separate_update(prec):
+    """The iterated method on F^{-1} h with its Gram-Schmidt update fused into B's first launch (one pass) and with
+    separate update launches (two passes): the same S, m and m1 to the tolerance, iteration counts within one."""
+    N, L = 64, 3.0
+    Q = W.potential_gaussian_sum(N, L, seed=73)
+    ks = [0.0, (3 - 1j) / (2 * L), (-5 + 6j) / (2 * L), (9 + 2j) / (2 * L)]
+    S1, m1, i1 = D.solve(Q, ks, L, tol=1e-12, batch=4, precision=prec, method=D.DBAR_METHOD_ITERATED, reorth=1)
+    S2, m2, i2 = D.solve(Q, ks, L, tol=1e-12, batch=4, precision=prec, method=D.DBAR_METHOD_ITERATED, reorth=2)
+    for j in range(len(ks)):
+        assert i1[j].status == 0 and i1[j].rel_residual <= 1e-12, j
+        assert relerr(S1[j], S2[j]) < 1e-10 and relerr(m1[j], m2[j]) < 1e-10, j
+        assert abs(i1[j].m1 - i2[j].m1) <= 1e-10 * max(abs(i2[j].m1), 1e-300), j
+        if prec == D.DBAR_FP64:
+            assert abs(i1[j].iters - i2[j].iters) <= 1, j
+
+
+@pytest.mark.parametrize("prec", [D.DBAR_FP64, D.DBAR_MIXED])
 def test_iterated_method_spaces_agree_on_a_batch(prec):
     """The iterated solver on F^{-1} h and on h: a ragged batch of 6 grid k (2kL integer, one k = 0), S, m and m1 to
     the oracle's tolerance, iteration counts within one."""
