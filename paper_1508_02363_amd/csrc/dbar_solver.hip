@@ -1055,9 +1055,11 @@ int krylov_cycle(const Pipeline& P, Work& w, const BatchCfg& cfg, int it_budget,
   }
   // Steps run in groups that end where the host reads the convergence flags (every check_every steps and at the
   // restart length); with graphs each group is one captured graph, replayed on later cycles and calls.
-  int j = 0;
+  // Groups are check_every steps long; once at most a quarter of the batch is still active the cycle is near its end
+  // and the groups halve, so that the steps launched after the last entry converged (which run empty) stay few.
+  int j = 0, len = cfg.check_every;
   while (j < mlim) {
-    const int j1 = std::min(mlim, (j / cfg.check_every + 1) * cfg.check_every);
+    const int j1 = std::min(mlim, j + len);
     bool done = false;
     if (graphs) {
       const auto key =
@@ -1089,9 +1091,10 @@ int krylov_cycle(const Pipeline& P, Work& w, const BatchCfg& cfg, int it_budget,
     j = j1;
     (void)hipMemcpyAsync(w.host_act.data(), act, B * sizeof(int), hipMemcpyDeviceToHost, s);
     (void)hipStreamSynchronize(s);
-    bool any = false;
-    for (int b = 0; b < B; ++b) any |= w.host_act[b] != 0;
-    if (!any) return j;
+    int active = 0;
+    for (int b = 0; b < B; ++b) active += w.host_act[b] != 0;
+    if (active == 0) return j;
+    if (4 * active <= B) len = std::max(1, cfg.check_every / 2);
   }
   return j;
 }
