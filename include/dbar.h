@@ -91,7 +91,9 @@ typedef struct {
   int32_t orth_window; /* plain method in x-space with one Gram-Schmidt pass: each new basis vector is orthogonalised
                           against the last orth_window vectors only (the Hessenberg matrix is then banded above the
                           window and the residual estimate a quasi-residual, which the FP64 residual recomputed at
-                          every cycle end checks).  0 = against all of them (classical GMRES).  Default set by
+                          every cycle end checks).  0 = against all of them (classical GMRES).  A windowed cycle that
+                          leaves an entry unconverged at the restart length (strong potentials can stall under the
+                          window) switches the rest of that batch to full orthogonalisation.  Default set by
                           dbar_default_opts; negative or above the restart length: DBAR_EINVAL.  Other methods and
                           spaces always orthogonalise fully. */
 } dbar_opts;

@@ -122,6 +122,9 @@ struct Work {
   // x holds zero without having been written: the next solution update (fused into the residual's first launch)
   // writes x = sum y_i V_i instead of adding to it
   bool x_zero = false;
+  // a windowed Krylov cycle reached the restart length with entries still active: the window no longer serves this
+  // batch (strong potentials stall under truncated orthogonalisation), and its later cycles orthogonalise fully
+  bool full_orth = false;
   void* S_dst(int method) { return outS ? outS : method == 1 ? Fx.p : Sx.p; }
   void* m_dst() { return outm ? outm : mx.p; }
   PinnedInts host_act, host_live;

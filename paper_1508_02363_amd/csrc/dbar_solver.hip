@@ -172,6 +172,7 @@ __global__ void __launch_bounds__(kCtlThreads) k_ctl_coef(Ctl* ctl, const double
         if (resid <= c.thresh || j + 1 >= m) {
           givens_commit(c, j, beta);
           act[b] = 0;
+          if (resid > c.thresh) act[gridDim.x + b] = 1;  // stopped by the restart length
         }
       }
     }
@@ -189,6 +190,7 @@ DBAR_D void givens_entry(int b, Ctl* ctl, const double* pnorm, int nblk, int* ac
   const double beta = sqrt(fmax(red[0], 0.0));
   givens_commit(c, j, beta);
   if (c.resid <= c.thresh || j + 1 >= m || beta == 0.0) act[b] = 0;
+  if (c.resid > c.thresh && j + 1 >= m && beta != 0.0) act[gridDim.x + b] = 1;  // stopped by the restart length
 }
 
 __global__ void __launch_bounds__(kCtlThreads) k_ctl_givens(Ctl* ctl, const double* pnorm, int nblk, int* act, int j,
@@ -215,6 +217,7 @@ __global__ void __launch_bounds__(kCtlThreads) k_moments_givens(const double* pa
     const double beta = sqrt(fmax(tot[NV], 0.0));
     givens_commit(c, j, beta);
     if (c.resid <= c.thresh || j + 1 >= m || beta == 0.0) act[b] = 0;
+    if (c.resid > c.thresh && j + 1 >= m && beta != 0.0) act[gridDim.x + b] = 1;  // stopped by the restart length
   }
 }
 
@@ -240,6 +243,7 @@ __global__ void k_ctl_start(Ctl* ctl, const double* nred, const int* live, int* 
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= B) return;
   Ctl& c = ctl[b];
+  act[B + b] = 0;  // set by the Givens step when the restart length, not the threshold, ends the entry's cycle
   if (!live[b]) {
     act[b] = 0;
     return;
@@ -470,9 +474,9 @@ int Work::setup(int N_, int B_, int m_, int prec_, bool shared_q) {
       return fail(DBAR_EDEVICE, "upload of the unit phase table failed");
   }
   if ((rc = results.ensure((size_t)B * sizeof(EntryResult)))) return rc;
-  if ((rc = act.ensure((size_t)B * sizeof(int)))) return rc;
+  if ((rc = act.ensure((size_t)2 * B * sizeof(int)))) return rc;  // [B, 2B): left a cycle at the restart length
   if ((rc = live.ensure((size_t)B * sizeof(int)))) return rc;
-  if ((rc = host_act.ensure(B))) return rc;
+  if ((rc = host_act.ensure(2 * B))) return rc;
   if ((rc = host_live.ensure(B))) return rc;
   const void* after[] = {x.p, V.p, T64.p, T32.p, ctl.p, act.p, part_vec.p, part_norm.p, part_mom.p, dred.p,
                          nred.p, Q32.p, Q64.p, ex.p, ey.p, coefG.p, dmom.p, shv.p, unit.p, Hbuf.p, ex32.p, ey32.p,
@@ -962,7 +966,7 @@ int krylov_cycle(const Pipeline& P, Work& w, const BatchCfg& cfg, int it_budget,
   // (k_ctl_coef), so an entry's last step runs no update, and its Givens step otherwise rides on the moment reduction
   // of v_{j+1}.  The Gram-Schmidt window applies to the plain method.
   const bool fused = P.xspace && cfg.reorth == 1;
-  const int window = cfg.method == 0 ? cfg.orth_window : 0;
+  const int window = cfg.method == 0 && !w.full_orth ? cfg.orth_window : 0;
   auto enqueue = [&](int j) {
     void* vj = V + (size_t)j * n * sizeof(cx<T>);
     void* vj1 = V + (size_t)(j + 1) * n * sizeof(cx<T>);
@@ -1089,10 +1093,12 @@ int krylov_cycle(const Pipeline& P, Work& w, const BatchCfg& cfg, int it_budget,
     if (!done)
       for (int jj = j; jj < j1; ++jj) enqueue(jj);
     j = j1;
-    (void)hipMemcpyAsync(w.host_act.data(), act, B * sizeof(int), hipMemcpyDeviceToHost, s);
+    (void)hipMemcpyAsync(w.host_act.data(), act, 2 * B * sizeof(int), hipMemcpyDeviceToHost, s);
     (void)hipStreamSynchronize(s);
-    int active = 0;
-    for (int b = 0; b < B; ++b) active += w.host_act[b] != 0;
+    int active = 0, stalled = 0;
+    for (int b = 0; b < B; ++b) active += w.host_act[b] != 0, stalled += w.host_act[B + b] != 0;
+    // a windowed cycle that left an entry at the restart length: orthogonalise fully from the next cycle on
+    if (stalled && fused && window > 0) w.full_orth = true;
     if (active == 0) return j;
     if (4 * active <= B) len = std::max(1, cfg.check_every / 2);
   }
@@ -1226,6 +1232,7 @@ int run_batch(const Pipeline& P, Work& w, const BatchCfg& cfg, hipStream_t s, st
   launch_reduce(static_cast<double*>(w.part_vec.p), 1, P.rhs_blocks(), nred, B, nullptr, s);
   // x = 0: the x-space residual's first launch writes x = sum y_i V_i on the first update (no memset)
   w.x_zero = P.xspace;
+  w.full_orth = false;
   if (!w.x_zero && hipMemsetAsync(w.x.p, 0, (size_t)B * n * sizeof(c64), s) != hipSuccess)
     return fail(DBAR_EDEVICE, "hipMemsetAsync failed");
   for (int b = 0; b < B; ++b) w.host_live[b] = 1;

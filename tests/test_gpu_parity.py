@@ -344,6 +344,25 @@ def test_gram_schmidt_window_with_short_restarts(prec):
 
 
 @pytest.mark.parametrize("prec", [D.DBAR_FP64, D.DBAR_MIXED])
+def test_strong_potential_converges_with_the_default_window(prec):
+    """A potential six times the benchmark's, where orthogonalising against the last two vectors alone stalls: the
+    default solve notices the stalled cycle, orthogonalises fully from then on, and converges to the full method's
+    solution (and the oracle's at one k)."""
+    N, L = 64, 4.0
+    g = O.make_grid(N, L)
+    Q = 6.0 * (0.8 + 0.6j) * np.exp(-np.abs(g.z) ** 2)
+    ks = np.array([0.5 + 0.5j, -1 + 0.3j, 2 - 1j])
+    S0, m0, i0 = D.solve(Q, ks, L, tol=1e-12, batch=3, precision=prec, orth_window=0)
+    S, m, info = D.solve(Q, ks, L, tol=1e-12, batch=3, precision=prec)
+    for j in range(len(ks)):
+        assert info[j].status == 0 and info[j].rel_residual <= 1e-12, j
+        assert relerr(S[j], S0[j]) < 1e-10 and relerr(m[j], m0[j]) < 1e-10, j
+        assert info[j].iters <= 3 * i0[j].iters + 40, j
+    ref = O.solve(g, Q, ks[0], tol=1e-13)
+    assert relerr(S[0], ref.S) < 1e-10
+
+
+@pytest.mark.parametrize("prec", [D.DBAR_FP64, D.DBAR_MIXED])
 def test_iterated_fused_step_matches_separate_update(prec):
     """The iterated method on F^{-1} h with its Gram-Schmidt update fused into B's first launch (one pass) and with
     separate update launches (two passes): the same S, m and m1 to the tolerance, iteration counts within one."""
