@@ -249,10 +249,16 @@ def test_taylor_order_extremes(M):
     ref = O.solve(g, Q, k, tol=1e-13, M=M)
     Sg, mg, info = D.solve(Q, [k], L, tol=1e-12, M=M, precision=D.DBAR_MIXED)
     assert info[0].status == 0 and relerr(Sg[0], ref.S) < 1e-10 and relerr(mg[0], ref.m) < 1e-10
+    # the iterated method (fused steps, shifted moments and tail at this order)
+    ki = (3 - 2j) / (2 * L)
+    refi = O.solve_iterated(g, Q, ki, tol=1e-13, M=M)
+    Si, mi, infoi = D.solve(Q, [ki], L, tol=1e-12, M=M, precision=D.DBAR_MIXED, method=D.DBAR_METHOD_ITERATED)
+    assert infoi[0].status == 0 and relerr(Si[0], refi.S) < 1e-10 and relerr(mi[0], refi.m) < 1e-10
 
 
 def test_default_batch_with_many_k():
-    """batch = 0 lets the library choose entries per launch (tuned or min(nk, 64), capped by memory)."""
+    """batch = 0 lets the library choose entries per launch (tuned, else 64 or about 2^24 / N^2 on small grids, capped
+    by nk and by memory)."""
     N, L = 32, 2.0
     g = O.make_grid(N, L)
     Q = W.potential_gaussian(N, L, 0.5 + 0.2j)
