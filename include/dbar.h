@@ -91,9 +91,10 @@ typedef struct {
   int32_t orth_window; /* plain method in x-space with one Gram-Schmidt pass: each new basis vector is orthogonalised
                           against the last orth_window vectors only (the Hessenberg matrix is then banded above the
                           window and the residual estimate a quasi-residual, which the FP64 residual recomputed at
-                          every cycle end checks).  0 = against all of them (classical GMRES).  A windowed cycle that
-                          leaves an entry unconverged at the restart length (strong potentials can stall under the
-                          window) switches the rest of that batch to full orthogonalisation.  Default set by
+                          every cycle end checks).  0 = against all of them (classical GMRES).  An entry that a
+                          windowed cycle leaves unconverged at the restart length (strong potentials can stall under
+                          the window) orthogonalises fully in its later cycles; the other entries of the batch keep
+                          the window, so every entry's iterates do not depend on the rest of the batch.  Default set by
                           dbar_default_opts; negative or above the restart length: DBAR_EINVAL.  Other methods and
                           spaces always orthogonalise fully. */
 } dbar_opts;
@@ -110,6 +111,13 @@ typedef struct {
   double rel_residual;  /* ||b - A(S)||_2 / ||b||_2, recomputed in FP64 with the FP64 operator at the end */
   double m1_re, m1_im;  /* m^(1) = i S(0), the 1/z coefficient of m (equation m1def); 0 from dbar_reflection and
                            dbar_reconstruct, which do not form S */
+  double cond_estimate; /* estimate of the condition number of A from the Krylov iteration: sigma_max / sigma_min of
+                           the (upper-triangular factor of the) Hessenberg matrix of the longest GMRES cycle of this
+                           solve (Section 4.1).  Its singular values lie inside A's, so it estimates cond(A) from
+                           below; 0 when no cycle ran (b = 0) */
+  double err_estimate;  /* cond_estimate * rel_residual: an estimate (not a bound) of the relative 2-norm error of S
+                           against the exact solution of the discrete system, i.e. against an FP64 solve to a tighter
+                           tolerance.  Since cond_estimate can fall short of cond(A), so can this */
 } dbar_info;
 /* With DBAR_METHOD_ITERATED, iters and rel_residual refer to the equation for h (eqh2); S = f + h o (xi + 2i conj k)
  * (equation Sform) and m = F^{-1}(S/xi) is evaluated through the shift theorem. */
@@ -222,8 +230,13 @@ int dbar_reconstruct(const dbar_grid* grid, const double* r, double t, double to
  * Serving: a request queue with continuous batching.  Requests (one k, one Q, one grid each) are admitted into
  * device-resident slots when the HBM budget allows, advance together in per-grid-size batches of Krylov
  * iterations, and leave as soon as they converge; new requests take the freed slots at the next iteration
- * boundary.  A worker thread drives the device.  All solves use DBAR_MIXED precision to the requested tolerance
- * (FP64 residual), or DBAR_FP64 if asked.
+ * boundary.  A worker thread per grid class drives the device.  All solves use DBAR_MIXED precision to the
+ * requested tolerance (FP64 residual), or DBAR_FP64 if asked.
+ * Admission by HBM footprint (dbar_request_footprint): a grid class reserves up to max_slots footprints of the
+ * budget when its first request arrives.  A request whose class cannot be reserved yet waits (first in, first out,
+ * with every later request behind it); a class that runs idle while requests wait releases its workspace.  Only a
+ * request whose footprint exceeds the whole budget is rejected (DBAR_ENOMEM from dbar_submit).  A result does not
+ * depend on which other requests share its batch.
  * ------------------------------------------------------------------------------------------------------------ */
 typedef struct dbar_session dbar_session;
 
@@ -236,9 +249,11 @@ typedef struct {
 } dbar_session_opts;
 
 typedef struct {
-  uint64_t submitted, completed, rejected;
-  uint64_t in_flight, queued;
-  size_t bytes_in_use;
+  uint64_t submitted, completed, rejected;  /* rejected: footprint above the whole budget */
+  uint64_t in_flight, queued;                /* queued: submitted, not yet in a slot (pending included) */
+  size_t bytes_in_use;                       /* footprints of the requests in flight */
+  size_t bytes_reserved;                     /* workspaces reserved by the grid classes alive */
+  uint64_t classes_created, classes_released;
 } dbar_session_stats;
 
 /* Create a session (opts may be NULL). */

@@ -57,7 +57,7 @@ class Opts(ctypes.Structure):
 class Info(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("iters", ctypes.c_int32), ("outer", ctypes.c_int32),
                 ("reserved", ctypes.c_int32), ("rel_residual", ctypes.c_double), ("m1_re", ctypes.c_double),
-                ("m1_im", ctypes.c_double)]
+                ("m1_im", ctypes.c_double), ("cond_estimate", ctypes.c_double), ("err_estimate", ctypes.c_double)]
 
 
 class SessionOpts(ctypes.Structure):
@@ -67,7 +67,9 @@ class SessionOpts(ctypes.Structure):
 
 class SessionStats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64), ("rejected", ctypes.c_uint64),
-                ("in_flight", ctypes.c_uint64), ("queued", ctypes.c_uint64), ("bytes_in_use", ctypes.c_size_t)]
+                ("in_flight", ctypes.c_uint64), ("queued", ctypes.c_uint64), ("bytes_in_use", ctypes.c_size_t),
+                ("bytes_reserved", ctypes.c_size_t), ("classes_created", ctypes.c_uint64),
+                ("classes_released", ctypes.c_uint64)]
 
 
 _lib = None

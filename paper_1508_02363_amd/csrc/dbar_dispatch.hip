@@ -50,26 +50,33 @@ int line_tiles(int N, bool cols, bool fp64) {
   return line_tiles_variant(N, cols, fp64, cols ? tile_variant(N, fp64) : 0);
 }
 
-// Algorithmic HBM bytes per batch entry of one stage (each array read or written once).
+// Algorithmic HBM bytes of one stage (each array read or written once): per batch entry, and once per launch for the
+// potential when all entries share it (Q_bs = 0: one array read at stride 0 by every entry).
+static double line_bytes_once(int N, LineOp op, const LineArgs& a, size_t es) {
+  const bool reads_q = op == LineOp::ColsInvTailFwd || op == LineOp::RowsInvTailEpilogue ||
+                       op == LineOp::ColsFwdPotential;
+  return reads_q && a.Q_bs == 0 ? (double)N * N * es : 0.0;
+}
 static double line_bytes(int N, LineOp op, const LineArgs& a, size_t es) {
   const double P = (double)N * N * es;
+  const double PQ = a.Q_bs == 0 ? 0.0 : P;  // the potential, when every entry reads its own
   switch (op) {
     case LineOp::RowsInvScaled: return 2 * P;
     case LineOp::ColsInvMoments: return P;
     case LineOp::RowsInvRegular: return 2 * P;
-    case LineOp::ColsInvTailFwd: return 3 * P + (a.hout ? P : 0.0);
+    case LineOp::ColsInvTailFwd: return 2 * P + PQ + (a.hout ? P : 0.0);
     case LineOp::ColsInvTail: return 2 * P;
     case LineOp::RowsFwdEpilogue:  // fused dots read V_i, i < dot_nv - 1, besides S (= V_{dot_nv - 1})
       return 2 * P + (a.alpha != 0.0 ? P : 0.0) + (a.gamma != 0.0 ? P : 0.0) +
              (a.dot_nv > 0 ? (a.dot_nv - (a.alpha != 0.0 ? 1 : 0)) * P : 0.0);
-    case LineOp::ColsFwdPotential: return 2 * P;
+    case LineOp::ColsFwdPotential: return P + PQ;
     case LineOp::ColsFwdPlain: return 2 * P;
     case LineOp::ColsInvPlain: return 2 * P;
     case LineOp::RowsFwdMoments: return 2 * P + (a.upd_coef ? P + a.upd_nv * (a.upd_v32 ? P / 2 : P) : 0.0);
     case LineOp::ColsFwdRegularInv: return 2 * P + (a.sout ? P : 0.0);
-    case LineOp::RowsInvTailEpilogue:  // in, q_k (counted per entry), out, S, Y (unless formed from q_k), h, the FP32
-                                       // copy, earlier basis
-      return 2 * P + (a.out ? P : 0.0) + (a.out32 ? P / 2 : 0.0) + (a.alpha != 0.0 ? P : 0.0) +
+    case LineOp::RowsInvTailEpilogue:  // in, Q (per entry unless shared), out, S, Y (unless formed from q_k), h, the
+                                       // FP32 copy, earlier basis
+      return P + PQ + (a.out ? P : 0.0) + (a.out32 ? P / 2 : 0.0) + (a.alpha != 0.0 ? P : 0.0) +
              (a.gamma != 0.0 && !a.y_rhs ? P : 0.0) + (a.hout ? P : 0.0) +
              (a.dot_nv > 0 ? (a.dot_nv - (a.alpha != 0.0 ? 1 : 0)) * P : 0.0);
   }
@@ -79,7 +86,7 @@ static double line_bytes(int N, LineOp op, const LineArgs& a, size_t es) {
 template <typename T>
 void launch_lines_any(int N, LineOp op, const LineArgs& a_in, hipStream_t s) {
   TimerScope ts(kStageLines + 2 * static_cast<int>(op) + (sizeof(T) == 4 ? 1 : 0),
-                line_bytes(N, op, a_in, sizeof(cx<T>)), a_in.B, a_in.act, s);
+                line_bytes(N, op, a_in, sizeof(cx<T>)), a_in.B, a_in.act, s, line_bytes_once(N, op, a_in, sizeof(cx<T>)));
   LineArgs a = a_in;
   a.tile = tile_variant(N, sizeof(T) == 8);
   switch (N) {

@@ -65,6 +65,11 @@ struct LineArgs {
   int dot_nv = 0;
   double* dot_part = nullptr;
   int dot_self = 0;            // RowsInvTailEpilogue: |out|^2 as one more value, slot dot_nv (dot_nv + 1 per entry)
+  // RowsInvTailEpilogue: per-entry Gram-Schmidt window inside a launch that covers more vectors.  Entries with
+  // dot_full[b] == 0 take no products with the first dot_skip vectors (their partials are written as 0); entries with
+  // dot_full[b] != 0 (orthogonalised against every vector) take all of them.  dot_full null: all entries take all.
+  const int* dot_full = nullptr;
+  int dot_skip = 0;
   // RowsFwdMoments: the pending Gram-Schmidt update of its input, in = in - sum_{i < upd_nv} upd_coef[b][i] V_i (V_i
   // at dotV as above), written back to upd_out (the input's own address), |in|^2 partials to upd_part[b][tile]
   const double* upd_coef = nullptr;  int upd_coef_bs = 0;
@@ -149,14 +154,17 @@ enum Stage : int {
 };
 const char* stage_name(int stage);
 bool timer_on();
-int timer_begin(int stage, double bytes_per_entry, int B, const int* act, hipStream_t s);
+// bytes_per_entry counts for every active entry of the launch; bytes_once (arrays shared by all entries of the launch,
+// such as one potential read at stride 0) counts once per launch with at least one active entry.
+int timer_begin(int stage, double bytes_per_entry, int B, const int* act, hipStream_t s, double bytes_once);
 void timer_end(int handle, hipStream_t s);
 
 struct TimerScope {
   int h = -1;
   hipStream_t s;
-  TimerScope(int stage, double bytes_per_entry, int B, const int* act, hipStream_t st) : s(st) {
-    if (timer_on()) h = timer_begin(stage, bytes_per_entry, B, act, st);
+  TimerScope(int stage, double bytes_per_entry, int B, const int* act, hipStream_t st, double bytes_once = 0.0)
+      : s(st) {
+    if (timer_on()) h = timer_begin(stage, bytes_per_entry, B, act, st, bytes_once);
   }
   ~TimerScope() {
     if (h >= 0) timer_end(h, s);

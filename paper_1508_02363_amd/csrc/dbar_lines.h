@@ -821,6 +821,8 @@ struct OpRowsInvTailEpi : OpColsInvTail<T, N, false> {
     const int nv = a.dot_nv;
     if (nv <= 0) return;
     const int nval = nv + (a.dot_self ? 1 : 0);
+    // vectors below the entry's Gram-Schmidt window (never V_{nv - 1}, the input itself)
+    const int skip = (a.dot_full && !a.dot_full[b]) ? a.dot_skip : 0;
     const cx<T>* V = static_cast<const cx<T>*>(a.dotV) + (size_t)b * a.dotV_bs + (size_t)row * N;
     double* dst = a.dot_part + (size_t)b * nval * ntiles + tile;
     auto partial = [&](int i) {
@@ -842,7 +844,7 @@ struct OpRowsInvTailEpi : OpColsInvTail<T, N, false> {
       }
 #pragma unroll 1
       for (int i = 0; i < nv - 1; ++i) {
-        x = wsum64(partial(i));
+        x = i < skip ? 0.0 : wsum64(partial(i));
         if (lane == 0) scratch[i * NW + wave] = x;
       }
       __syncthreads();
@@ -857,7 +859,7 @@ struct OpRowsInvTailEpi : OpColsInvTail<T, N, false> {
       if (a.dot_self) block_reduce_store<NT, 1>(acc.v, dst + (size_t)nv * ntiles, 0, scratch);
 #pragma unroll 1
       for (int i = 0; i < nv - 1; ++i) {
-        const double val[1] = {partial(i)};
+        const double val[1] = {i < skip ? 0.0 : partial(i)};
         block_reduce_store<NT, 1>(val, dst + (size_t)i * ntiles, 0, scratch);
       }
     }

@@ -5,7 +5,14 @@
 // repeats: admit queued requests into free slots (right-hand side, x = 0, first residual), run one lockstep Krylov
 // cycle over every slot in flight, update the solutions and recompute the FP64 residuals, then finish the requests
 // that converged (m = h(S), copy out) and free their slots.  New requests therefore join at the next cycle
-// boundary while others are mid-solve.  Admission is by device-memory footprint against the session budget.
+// boundary while others are mid-solve.
+//
+// Admission is by device-memory footprint against the session budget.  A class reserves cap request footprints when
+// it is created (cap = max_slots, or what the budget has left).  A request whose class does not exist and whose
+// footprint the remaining budget cannot hold waits in the session's pending queue (first in, first out; later
+// requests queue behind it, so none of them starves); a class that runs idle while requests are pending releases its
+// workspace and its reservation, and the pending requests' classes are created as the budget allows.  Only a request
+// larger than the whole budget is rejected.
 //
 // The paper motivates this by the need for solutions at many k (Section 1, and the outlook's parallelisation over
 // k); each slot is an independent solve of the Section 4 system with Q -> q_k.
@@ -62,6 +69,7 @@ struct SClass {
   std::vector<c64> h_k;  // per-slot k (host source of the async upload; stable until the stream synchronises)
   bool ready = false;
   int error = 0;
+  bool finished = false;  // the worker has returned: its thread can be joined
 };
 
 }  // namespace dbar
@@ -72,7 +80,9 @@ struct dbar_session {
   int device = 0;
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
-  std::map<std::tuple<int, int, double>, std::unique_ptr<dbar::SClass>> classes;
+  std::map<std::tuple<int, int, double>, std::unique_ptr<dbar::SClass>> classes;  // classes taking requests
+  std::vector<std::unique_ptr<dbar::SClass>> retired;  // released classes (their workers exit; joined later)
+  std::deque<std::shared_ptr<dbar::SReq>> pending;     // waiting for budget to create their class (FIFO)
   std::unordered_map<uint64_t, std::shared_ptr<dbar::SReq>> reqs;
   uint64_t next_ticket = 1;
   dbar_session_stats st{};
@@ -114,9 +124,42 @@ static int class_init(SClass& c) {
   c.h_k.assign(c.cap, c64{0.0, 0.0});
   c.w.B = c.cap;
   if (hipMemsetAsync(c.w.live.p, 0, c.cap * sizeof(int), c.stream) != hipSuccess ||
-      hipMemsetAsync(c.w.act.p, 0, c.cap * sizeof(int), c.stream) != hipSuccess)
+      hipMemsetAsync(c.w.act.p, 0, 3 * c.cap * sizeof(int), c.stream) != hipSuccess)
     return fail(DBAR_EDEVICE, "memset failed");
   return hipStreamSynchronize(c.stream) == hipSuccess ? DBAR_OK : fail(DBAR_EDEVICE, "sync failed");
+}
+
+static void schedule_pending(dbar_session* s);
+
+// Take class c out of the session (under s->mu): requests for its grid now go to the pending queue or a new class.
+static void detach_class(dbar_session* s, SClass& c) {
+  for (auto it = s->classes.begin(); it != s->classes.end(); ++it)
+    if (it->second.get() == &c) {
+      s->retired.push_back(std::move(it->second));
+      s->classes.erase(it);
+      return;
+    }
+}
+
+// The worker of a detached class: free its device memory, then return its reservation to the budget and admit what
+// the pending queue can now hold.
+static void release_class(dbar_session* s, SClass& c) {
+  if (c.stream) (void)hipStreamSynchronize(c.stream);
+  c.w = Work();
+  c.newmask = DevBuf();
+  c.tolv = DevBuf();
+  if (c.stream) (void)hipStreamDestroy(c.stream);
+  c.stream = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(s->mu);
+    s->allocated -= (size_t)c.cap * c.footprint;
+    s->st.bytes_reserved = s->allocated;
+    s->st.classes_released += 1;
+    c.finished = true;
+    schedule_pending(s);
+  }
+  s->cv_work.notify_all();
+  s->cv_done.notify_all();
 }
 
 static void worker(dbar_session* s, SClass* cp) {
@@ -127,8 +170,21 @@ static void worker(dbar_session* s, SClass* cp) {
     std::lock_guard<std::mutex> lock(s->mu);
     c.ready = rc == DBAR_OK;
     c.error = rc;
+    if (rc) {  // the requests routed to this class end with the error; the class gives its reservation back
+      for (auto& r : c.queue) {
+        r->state = 2;
+        r->info.status = rc;
+        r->t_done = Clock::now();
+        s->st.queued -= 1;
+      }
+      c.queue.clear();
+      detach_class(s, c);
+    }
   }
-  if (rc) return;
+  if (rc) {
+    release_class(s, c);
+    return;
+  }
   Work& w = c.w;
   const size_t n = w.n;
   const bool mixed = c.prec == DBAR_MIXED;
@@ -140,6 +196,8 @@ static void worker(dbar_session* s, SClass* cp) {
   cfg.check_every = 4;
   cfg.inner_tol = 1e-6;  // x-space inner solves
   cfg.orth_window = kDefaultOrthWindow;
+  cfg.use_graph = 1;     // Krylov step groups replayed from graphs captured per class (its own workspace and stream)
+  bool retire = false;
   while (!s->stop.load()) {
     // ---- admission at the cycle boundary
     std::vector<int> admitted;
@@ -148,6 +206,11 @@ static void worker(dbar_session* s, SClass* cp) {
       std::unique_lock<std::mutex> lock(s->mu);
       for (int b = 0; b < c.cap; ++b) any_live |= c.slots[b] != nullptr;
       if (!any_live && c.queue.empty()) {
+        if (!s->pending.empty()) {  // idle while others wait for budget: release this class
+          detach_class(s, c);
+          retire = true;
+          break;
+        }
         s->cv_work.wait_for(lock, std::chrono::milliseconds(2));
         continue;
       }
@@ -169,6 +232,7 @@ static void worker(dbar_session* s, SClass* cp) {
         SReq& r = *c.slots[b];
         c.h_new[b] = 1;
         c.h_live[b] = 1;
+        w.full_host[b] = 0;  // the slot's new solve starts with the Gram-Schmidt window (its device flag: the check)
         c.h_tol[b] = r.tol;
         (void)hipMemcpyAsync(static_cast<c64*>(w.Q64.p) + (size_t)b * n, r.Q.data(), n * sizeof(c64),
                              hipMemcpyHostToDevice, c.stream);
@@ -257,6 +321,8 @@ static void worker(dbar_session* s, SClass* cp) {
         r->info.iters = cc.iters;
         r->info.outer = cc.cycles;
         r->info.rel_residual = cc.bnorm > 0.0 ? cc.rnorm / cc.bnorm : 0.0;
+        r->info.cond_estimate = cc.kappa;
+        r->info.err_estimate = cc.kappa * r->info.rel_residual;
         r->info.m1_re = ok ? -r->S[0].im : 0.0;
         r->info.m1_im = ok ? r->S[0].re : 0.0;
         if (!ok) r->info.status = DBAR_EDEVICE;
@@ -270,6 +336,55 @@ static void worker(dbar_session* s, SClass* cp) {
     }
     s->cv_done.notify_all();
   }
+  if (retire) release_class(s, c);
+}
+
+// Create the class of request r if the remaining budget holds at least one of its footprints (under s->mu).
+static SClass* create_class(dbar_session* s, const SReq& r) {
+  const size_t fp = r.footprint;
+  const size_t left = s->budget > s->allocated ? s->budget - s->allocated : 0;
+  const int cap = (int)std::min<size_t>((size_t)s->o.max_slots, left / fp);
+  if (cap < 1) return nullptr;
+  // join the workers of released classes that have returned (not the calling worker itself, which releases its class
+  // and admits pending requests before it returns)
+  for (auto it = s->retired.begin(); it != s->retired.end();) {
+    if ((*it)->finished && (*it)->th.get_id() != std::this_thread::get_id()) {
+      if ((*it)->th.joinable()) (*it)->th.join();
+      it = s->retired.erase(it);
+    } else {
+      ++it;
+    }
+  }
+  auto c = std::make_unique<SClass>();
+  c->N = r.grid.n;
+  c->M = r.grid.M;
+  c->L = r.grid.L;
+  c->cap = cap;
+  c->prec = s->o.precision;
+  c->restart = s->o.restart;
+  c->footprint = fp;
+  s->allocated += (size_t)cap * fp;
+  s->st.bytes_reserved = s->allocated;
+  s->st.classes_created += 1;
+  SClass* cp = c.get();
+  s->classes.emplace(std::make_tuple(r.grid.n, r.grid.M, r.grid.L), std::move(c));
+  cp->th = std::thread(worker, s, cp);
+  return cp;
+}
+
+// Move pending requests, oldest first, into their classes (creating classes as the budget allows); stop at the first
+// request whose class cannot be created yet (under s->mu).
+static void schedule_pending(dbar_session* s) {
+  if (s->stop.load()) return;
+  while (!s->pending.empty()) {
+    auto r = s->pending.front();
+    auto it = s->classes.find(std::make_tuple(r->grid.n, r->grid.M, r->grid.L));
+    SClass* c = it != s->classes.end() ? it->second.get() : create_class(s, *r);
+    if (!c) break;
+    c->queue.push_back(r);
+    s->pending.pop_front();
+  }
+  s->cv_work.notify_all();
 }
 
 }  // namespace dbar
@@ -325,38 +440,19 @@ int dbar_submit(dbar_session* s, const dbar_grid* grid, const double* Q, const d
   r->footprint = footprint_of(grid->n, s->o.precision, s->o.restart, 1);
   r->t_submit = Clock::now();
   std::lock_guard<std::mutex> lock(s->mu);
-  auto key = std::make_tuple(grid->n, grid->M, grid->L);
-  auto it = s->classes.find(key);
-  if (it == s->classes.end()) {
-    const size_t fp = r->footprint;
-    const size_t left = s->budget > s->allocated ? s->budget - s->allocated : 0;
-    const int cap = (int)std::min<size_t>((size_t)s->o.max_slots, left / fp);
-    if (cap < 1) {
-      s->st.rejected += 1;
-      return fail(DBAR_ENOMEM, "request footprint exceeds the remaining HBM budget of the session");
-    }
-    auto c = std::make_unique<SClass>();
-    c->N = grid->n;
-    c->M = grid->M;
-    c->L = grid->L;
-    c->cap = cap;
-    c->prec = s->o.precision;
-    c->restart = s->o.restart;
-    c->footprint = fp;
-    s->allocated += (size_t)cap * fp;
-    SClass* cp = c.get();
-    it = s->classes.emplace(key, std::move(c)).first;
-    cp->th = std::thread(worker, s, cp);
+  if (r->footprint > s->budget) {
+    s->st.rejected += 1;
+    return fail(DBAR_ENOMEM, "request footprint (" + std::to_string(r->footprint) +
+                                 " bytes) exceeds the session's HBM budget (" + std::to_string(s->budget) + " bytes)");
   }
-  SClass& c = *it->second;
-  if (c.error) return fail(c.error, "the worker for this grid failed to start");
   r->ticket = s->next_ticket++;
-  c.queue.push_back(r);
   s->reqs[r->ticket] = r;
   s->st.submitted += 1;
   s->st.queued += 1;
   *ticket = r->ticket;
-  s->cv_work.notify_all();
+  // behind any request already waiting for budget; otherwise straight into its class
+  s->pending.push_back(r);
+  schedule_pending(s);
   return DBAR_OK;
 }
 
@@ -369,8 +465,10 @@ static int take_result(dbar_session* s, std::unordered_map<uint64_t, std::shared
   if (info) *info = r->info;
   if (latency_s) *latency_s = std::chrono::duration<double>(r->t_done - r->t_submit).count();
   s->reqs.erase(it);
-  return r->info.status == DBAR_EDEVICE ? fail(DBAR_EDEVICE, "device failure in the serving worker")
-                                        : (r->info.status == DBAR_ENOCONV ? DBAR_ENOCONV : DBAR_OK);
+  const int st = r->info.status;
+  if (st == DBAR_OK || st == DBAR_ENOCONV) return st;
+  return fail(st, st == DBAR_ENOMEM ? "the serving worker could not allocate its workspace"
+                                    : "device failure in the serving worker");
 }
 
 int dbar_poll(dbar_session* s, uint64_t ticket, double* S_out, double* m_out, dbar_info* info, double* latency_s) {
@@ -404,10 +502,20 @@ void dbar_session_destroy(dbar_session* s) {
   if (!s) return;
   s->stop.store(true);
   s->cv_work.notify_all();
-  for (auto& kv : s->classes)
-    if (kv.second->th.joinable()) kv.second->th.join();
+  // a worker may move its class from `classes` to `retired` while it exits: collect the threads under the lock, join
+  // them outside it
+  std::vector<SClass*> all;
+  {
+    std::lock_guard<std::mutex> lock(s->mu);
+    for (auto& kv : s->classes) all.push_back(kv.second.get());
+    for (auto& c : s->retired) all.push_back(c.get());
+  }
+  for (SClass* c : all)
+    if (c->th.joinable()) c->th.join();
   for (auto& kv : s->classes)
     if (kv.second->stream) (void)hipStreamDestroy(kv.second->stream);
+  for (auto& c : s->retired)
+    if (c->stream) (void)hipStreamDestroy(c->stream);
   delete s;
 }
 

@@ -76,7 +76,10 @@ struct Ctl {
   double H[kMaxRestart * (kMaxRestart + 1)];
   double cs[kMaxRestart], sn[kMaxRestart], g[kMaxRestart + 1];
   double bnorm, rnorm, thresh, resid;
-  int jn, iters, cycles, pad;
+  // condition estimate: sigma_max / sigma_min of the triangular factor of the longest cycle's Hessenberg matrix so far
+  // (kappa_n: that cycle's length; both cleared when the entry's solve starts)
+  double kappa;
+  int jn, iters, cycles, kappa_n;
 };
 
 struct EntryResult {
@@ -84,6 +87,7 @@ struct EntryResult {
   double bnorm, rnorm;
   c64 s00;
   c64 hsh;  // iterated method: h at the shift offset, h(2i conj k)
+  double kappa;
 };
 
 struct BatchCfg {
@@ -104,9 +108,13 @@ struct Work {
   Work() = default;
   Work& operator=(Work&& o) noexcept;
   int N = 0, B = 0, m = 0, prec = 0;
-  // captured Krylov step groups: key (element bytes + method + space, first and end step, reorth, B) -> executable
-  // graph; dropped on reallocation
-  std::map<std::tuple<int, int, int, int>, hipGraphExec_t> graphs;
+  // captured Krylov step groups -> executable graph; dropped on reallocation.  A captured kernel node keeps its
+  // arguments by value, so the key holds everything those arguments depend on besides the workspace pointers:
+  // element bytes + method + space, first and end step, reorth + Gram-Schmidt window + window mode, batch B, and the
+  // grid (N, M and the bit pattern of L: the transform scales 1/(2 pi L^2), dx^2/2pi and the xi grid are taken from
+  // them, and the kernels are specialised for M)
+  using GraphKey = std::tuple<int, int, int, int, int, int, uint64_t>;
+  std::map<GraphKey, hipGraphExec_t> graphs;
   int graph_epoch = 0;  // tuning epoch the graphs were captured in
   void drop_graphs();
   size_t n = 0;
@@ -122,9 +130,12 @@ struct Work {
   // x holds zero without having been written: the next solution update (fused into the residual's first launch)
   // writes x = sum y_i V_i instead of adding to it
   bool x_zero = false;
-  // a windowed Krylov cycle reached the restart length with entries still active: the window no longer serves this
-  // batch (strong potentials stall under truncated orthogonalisation), and its later cycles orthogonalise fully
-  bool full_orth = false;
+  // Per entry: a windowed Krylov cycle ended it at the restart length rather than at its threshold (strong potentials
+  // stall under truncated orthogonalisation), so its later cycles orthogonalise against every basis vector.  The
+  // device flags are act[2B + b] (set by the cycle start from the restart flags act[B + b], cleared when the entry's
+  // solve starts); this host mirror, updated from the flags the host reads anyway, tells whether a cycle's launches
+  // must cover the whole basis.  Other entries keep their window inside such launches.
+  std::vector<int> full_host;
   void* S_dst(int method) { return outS ? outS : method == 1 ? Fx.p : Sx.p; }
   void* m_dst() { return outm ? outm : mx.p; }
   PinnedInts host_act, host_live;
@@ -183,6 +194,8 @@ struct DotReq {
   int nv = 0;
   double* part = nullptr;
   bool self = false;  // x-space: |out|^2 too, as value nv (nv + 1 values per entry)
+  const int* full = nullptr;  // per-entry window (x-space): entries with full[b] == 0 skip the first `skip` vectors
+  int skip = 0;
 };
 
 struct Pipeline {
@@ -297,6 +310,8 @@ int krylov_cycle(const Pipeline& P, Work& w, const BatchCfg& cfg, int it_budget,
 // solution update from the cycle and the FP64 residual r = b - A(x) into r_out (norms into w.nred)
 template <typename T>
 void end_cycle(const Pipeline& P, Work& w, int nv, void* r_out, hipStream_t s, int method = 0);
+// condition estimate of each live entry from its last cycle's Hessenberg factor, where that cycle is the longest so far
+void launch_cond_estimate(Work& w, hipStream_t s);
 // residual check (first = 1: record ||b|| and reset the counters of the entries in mask); tolv: per-entry tol
 void launch_ctl_check(Work& w, double tol, int first, const int* mask, const double* tolv, hipStream_t s);
 // start a cycle for every live entry from its residual norm

@@ -144,8 +144,11 @@ DBAR_D void givens_commit(Ctl& c, int j, double beta) {
 // an entry that meets its threshold (or the restart length) takes its last Givens step with this beta and leaves the
 // cycle: the update, transform and moments of a v_{j+1} no step would use are not run for it.  Otherwise the step
 // waits for the exact norm from the update, as without `early`.
+// The partials cover the vectors lo..j; an entry whose own window starts later (full[b] == 0 with skip > 0: the launch
+// covers the whole basis for entries that orthogonalise fully) takes the vectors lo + skip..j only.
 __global__ void __launch_bounds__(kCtlThreads) k_ctl_coef(Ctl* ctl, const double* part, int nval, int nblk, int* act,
-                                                          int j, int pass, int early, int m, int lo) {
+                                                          int j, int pass, int early, int m, int lo, int skip,
+                                                          const int* full) {
   const int b = blockIdx.x;
   if (!act[b]) return;
   __shared__ double red[kMaxRestart + 2];
@@ -153,8 +156,9 @@ __global__ void __launch_bounds__(kCtlThreads) k_ctl_coef(Ctl* ctl, const double
   if (threadIdx.x == 0) {
     Ctl& c = ctl[b];
     double p2 = 0.0;
-    for (int i = 0; i < lo; ++i) c.coef[i] = c.hsum[i] = 0.0;  // outside the window (one pass)
-    for (int i = lo; i <= j; ++i) {
+    const int lob = lo + ((full && !full[b]) ? skip : 0);
+    for (int i = 0; i < lob; ++i) c.coef[i] = c.hsum[i] = 0.0;  // outside the window (one pass)
+    for (int i = lob; i <= j; ++i) {
       const double h = red[i - lo];
       c.coef[i] = c.sigma[i] * c.sigma[i] * h;
       c.hsum[i] = (pass ? c.hsum[i] : 0.0) + c.sigma[i] * h;
@@ -237,13 +241,81 @@ __global__ void k_ctl_trisolve(Ctl* ctl, const int* live, int B) {
   for (int i = n; i <= kMaxRestart; ++i) c.coef[i] = 0.0;
 }
 
+// Condition estimate of one entry (one wave per entry): the extreme singular values of the upper-triangular factor R
+// (jn x jn, column j in H[j * (kMaxRestart + 1)]) that the Givens rotations leave of the cycle's Hessenberg matrix --
+// the same singular values as the (jn + 1) x jn Hessenberg matrix, and those lie inside A's (sigma_max(H) <= sigma_max(A),
+// sigma_min(H) >= sigma_min(A)), so the ratio estimates cond(A) from below.  Power iteration on R^T R for sigma_max and
+// inverse iteration (a forward and a back substitution per step) for sigma_min, lane i holding component i.  Taken only
+// when the cycle is longer than the one behind the current estimate (the longest cycle has seen most of the spectrum).
+constexpr int kCondIters = 12;
+__global__ void __launch_bounds__(64) k_cond_estimate(Ctl* ctl, const int* live) {
+  const int b = blockIdx.x;
+  if (live && !live[b]) return;
+  Ctl& c = ctl[b];
+  const int n = c.jn;
+  if (n <= c.kappa_n || n < 1) return;
+  const int i = threadIdx.x;
+  constexpr int LD = kMaxRestart + 1;
+  auto R = [&](int row, int col) { return c.H[(size_t)col * LD + row]; };
+  for (int l = 0; l < n; ++l)
+    if (!(R(l, l) != 0.0)) return;  // breakdown (exact solution reached): keep the previous estimate
+  // sigma_max: x <- R^T R x, normalised
+  double x = i < n ? 1.0 + 0.01 * i : 0.0;
+  double nrm = sqrt(wsum(x * x));
+  x /= nrm;
+  double smax2 = 0.0;
+  for (int it = 0; it < kCondIters; ++it) {
+    double y = 0.0;  // (R x)_i = sum_{l >= i} R_il x_l
+    for (int l = 0; l < n; ++l) {
+      const double xl = __shfl(x, l, 64);
+      if (i < n && l >= i) y += R(i, l) * xl;
+    }
+    double z = 0.0;  // (R^T y)_i = sum_{l <= i} R_li y_l
+    for (int l = 0; l < n; ++l) {
+      const double yl = __shfl(y, l, 64);
+      if (i < n && l <= i) z += R(l, i) * yl;
+    }
+    smax2 = sqrt(wsum(z * z));  // |R^T R x| for |x| = 1
+    x = smax2 > 0.0 ? z / smax2 : 0.0;
+  }
+  // sigma_min: x <- (R^T R)^{-1} x = R^{-1} R^{-T} x, normalised
+  x = i < n ? 1.0 + 0.01 * i : 0.0;
+  nrm = sqrt(wsum(x * x));
+  x /= nrm;
+  double inv2 = 0.0;
+  for (int it = 0; it < kCondIters; ++it) {
+    double r = x, u = 0.0;  // R^T u = x (forward substitution, column by column)
+    for (int l = 0; l < n; ++l) {
+      const double ul = __shfl(r, l, 64) / R(l, l);
+      if (i == l) u = ul;
+      if (i > l && i < n) r -= R(l, i) * ul;
+    }
+    r = u;
+    double v = 0.0;  // R v = u (back substitution)
+    for (int l = n - 1; l >= 0; --l) {
+      const double vl = __shfl(r, l, 64) / R(l, l);
+      if (i == l) v = vl;
+      if (i < l) r -= R(i, l) * vl;
+    }
+    inv2 = sqrt(wsum(v * v));  // |(R^T R)^{-1} x| for |x| = 1
+    x = inv2 > 0.0 ? v / inv2 : 0.0;
+  }
+  if (i == 0 && smax2 > 0.0 && inv2 > 0.0) {
+    c.kappa = fmax(c.kappa, sqrt(smax2 * inv2));
+    c.kappa_n = n;
+  }
+}
+
 // start a Krylov cycle from the residual whose squared norm is nred[b] (already stored as v_0)
 __global__ void k_ctl_start(Ctl* ctl, const double* nred, const int* live, int* act, double abs_tol, double rel_tol,
                             const double* tolv, int B) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= B) return;
   Ctl& c = ctl[b];
-  act[B + b] = 0;  // set by the Givens step when the restart length, not the threshold, ends the entry's cycle
+  // an entry whose last cycle ended at the restart length orthogonalises fully from now on (read only by windowed
+  // cycles); the flag is set by the Givens step when the restart length, not the threshold, ends the entry's cycle
+  if (act[B + b]) act[2 * B + b] = 1;
+  act[B + b] = 0;
   if (!live[b]) {
     act[b] = 0;
     return;
@@ -260,8 +332,8 @@ __global__ void k_ctl_start(Ctl* ctl, const double* nred, const int* live, int* 
 }
 
 // after a recomputed residual: done when ||r|| <= tol ||b||
-__global__ void k_ctl_check(Ctl* ctl, const double* nred, int* live, double tol, int first, const int* mask,
-                            const double* tolv, int B) {
+__global__ void k_ctl_check(Ctl* ctl, const double* nred, int* live, int* act, double tol, int first,
+                            const int* mask, const double* tolv, int B) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= B || (!first && !live[b]) || (mask && !mask[b])) return;
   Ctl& c = ctl[b];
@@ -271,6 +343,10 @@ __global__ void k_ctl_check(Ctl* ctl, const double* nred, int* live, double tol,
     c.iters = 0;
     c.cycles = 0;
     c.jn = 0;
+    c.kappa = 0.0;
+    c.kappa_n = 0;
+    act[B + b] = 0;
+    act[2 * B + b] = 0;  // a new solve starts with the Gram-Schmidt window
   }
   c.rnorm = rn;
   c.cycles += 1;
@@ -307,7 +383,7 @@ __global__ void k_gather_results(const Ctl* ctl, const c64* x, size_t n, const c
     const int p1 = ((shv[2 * b] % N) + N) % N, p2 = ((shv[2 * b + 1] % N) + N) % N;
     hs = h[(size_t)b * n + (size_t)p2 * N + p1];
   }
-  out[b] = EntryResult{c.iters, c.cycles, c.bnorm, c.rnorm, x[(size_t)b * n], hs};
+  out[b] = EntryResult{c.iters, c.cycles, c.bnorm, c.rnorm, x[(size_t)b * n], hs, c.kappa};
 }
 
 void launch_phase_tables(const c64* kv_dev, int N, double L, c64* ex, c64* ey, c32* ex32, c32* ey32, int B,
@@ -474,7 +550,9 @@ int Work::setup(int N_, int B_, int m_, int prec_, bool shared_q) {
       return fail(DBAR_EDEVICE, "upload of the unit phase table failed");
   }
   if ((rc = results.ensure((size_t)B * sizeof(EntryResult)))) return rc;
-  if ((rc = act.ensure((size_t)2 * B * sizeof(int)))) return rc;  // [B, 2B): left a cycle at the restart length
+  // [B, 2B): left a cycle at the restart length; [2B, 3B): orthogonalises fully (see full_host)
+  if ((rc = act.ensure((size_t)3 * B * sizeof(int)))) return rc;
+  full_host.assign(B, 0);
   if ((rc = live.ensure((size_t)B * sizeof(int)))) return rc;
   if ((rc = host_act.ensure(2 * B))) return rc;
   if ((rc = host_live.ensure(B))) return rc;
@@ -676,6 +754,8 @@ void Pipeline::apply_x_rest(const void* in, size_t in_bs, void* out, size_t out_
     a.dot_nv = dr->nv;
     a.dot_part = dr->part;
     a.dot_self = dr->self ? 1 : 0;
+    a.dot_full = dr->full;
+    a.dot_skip = dr->skip;
   }
   launch_lines_any<T>(N, LineOp::RowsInvTailEpilogue, a, s);
 }
@@ -716,7 +796,9 @@ __global__ void __launch_bounds__(256) k_rhs_x(const c64* Q, size_t Q_bs, const 
 void Pipeline::rhs_x(const void* Q64p, size_t Q_bs, void* out, size_t out_bs, bool out32, int B, const int* act,
                      unsigned flags, hipStream_t s) const {
   const LineArgs a = base(B, act, flags & kUnitPhase);
-  TimerScope ts(kStageConvert, (double)n * (sizeof(c64) + (out32 ? sizeof(c32) : sizeof(c64))), B, act, s);
+  // the potential counted once when the entries share it (Q_bs = 0)
+  TimerScope ts(kStageConvert, (double)n * ((Q_bs ? sizeof(c64) : 0) + (out32 ? sizeof(c32) : sizeof(c64))), B, act, s,
+                Q_bs ? 0.0 : (double)n * sizeof(c64));
   const dim3 grid(rhs_blocks(), B);
   const c64* Q = static_cast<const c64*>(Q64p);
   if (out32)
@@ -966,13 +1048,21 @@ int krylov_cycle(const Pipeline& P, Work& w, const BatchCfg& cfg, int it_budget,
   // (k_ctl_coef), so an entry's last step runs no update, and its Givens step otherwise rides on the moment reduction
   // of v_{j+1}.  The Gram-Schmidt window applies to the plain method.
   const bool fused = P.xspace && cfg.reorth == 1;
-  const int window = cfg.method == 0 && !w.full_orth ? cfg.orth_window : 0;
+  const int window = cfg.method == 0 ? cfg.orth_window : 0;
+  // entries that stalled under the window in an earlier cycle orthogonalise fully: the launches then cover the whole
+  // basis, and the other entries skip the vectors below their own window inside them
+  bool any_full = false;
+  if (fused && window > 0)
+    for (int b = 0; b < B; ++b) any_full |= w.full_host[b] != 0;
+  const int* full = any_full ? act + 2 * B : nullptr;
   auto enqueue = [&](int j) {
     void* vj = V + (size_t)j * n * sizeof(cx<T>);
     void* vj1 = V + (size_t)(j + 1) * n * sizeof(cx<T>);
     if (fused) {
-      // the window of basis vectors this step orthogonalises against: v_lo .. v_j (all of them without a window)
-      const int lo = window > 0 ? std::max(0, j - window + 1) : 0;
+      // the window of basis vectors this step orthogonalises against: v_lo_win .. v_j (all of them without a window);
+      // the launch covers v_lo .. v_j
+      const int lo_win = window > 0 ? std::max(0, j - window + 1) : 0;
+      const int lo = any_full ? 0 : lo_win;
       char* Vlo = V + (size_t)lo * n * sizeof(cx<T>);
       DotReq dr;
       dr.V = Vlo;
@@ -980,6 +1070,8 @@ int krylov_cycle(const Pipeline& P, Work& w, const BatchCfg& cfg, int it_budget,
       dr.nv = j - lo + 1;
       dr.part = part;
       dr.self = true;  // ||w||^2 for the early convergence decision
+      dr.full = full;
+      dr.skip = lo_win - lo;
       if (cfg.method == 1) {
         if (j == 0) P.apply_B_first<T>(vj, V_bs, Tbuf, B, act, nullptr, s);
         P.apply_B_rest<T>(vj, V_bs, vj1, V_bs, Qp, w.Q_bs, Tbuf, w.Hbuf.p, B, act, 1.0, 1.0, nullptr, 0, false, s, &dr,
@@ -992,7 +1084,7 @@ int krylov_cycle(const Pipeline& P, Work& w, const BatchCfg& cfg, int it_budget,
       {
         TimerScope ts(kStageControl, 0.0, B, nullptr, s);
         hipLaunchKernelGGL(k_ctl_coef, dim3(B), dim3(kCtlThreads), 0, s, ctl, part, j - lo + 2,
-                           P.apply_tiles(sizeof(T) == 8), act, j, 0, 1, w.m, lo);
+                           P.apply_tiles(sizeof(T) == 8), act, j, 0, 1, w.m, lo, lo_win - lo, full);
       }
       UpdReq u;
       u.V = Vlo;
@@ -1040,7 +1132,7 @@ int krylov_cycle(const Pipeline& P, Work& w, const BatchCfg& cfg, int it_budget,
       {
         TimerScope ts(kStageControl, 0.0, B, nullptr, s);
         hipLaunchKernelGGL(k_ctl_coef, dim3(B), dim3(kCtlThreads), 0, s, ctl, part, j + 1, nblk, act, j, pass, 0,
-                           w.m, 0);
+                           w.m, 0, 0, nullptr);
       }
       va.coef = &ctl[0].coef[0];
       va.coef_bs = sizeof(Ctl) / sizeof(double);
@@ -1066,9 +1158,11 @@ int krylov_cycle(const Pipeline& P, Work& w, const BatchCfg& cfg, int it_budget,
     const int j1 = std::min(mlim, j + len);
     bool done = false;
     if (graphs) {
-      const auto key =
-          std::make_tuple((int)sizeof(T) + 16 * cfg.method + 64 * (P.xspace ? 1 : 0), j * 1024 + j1,
-                          cfg.reorth + 16 * (fused ? window : 0), B);
+      uint64_t Lbits = 0;
+      std::memcpy(&Lbits, &P.L, sizeof(Lbits));
+      const Work::GraphKey key((int)sizeof(T) + 16 * cfg.method + 64 * (P.xspace ? 1 : 0), j * 1024 + j1,
+                               cfg.reorth + 16 * (fused ? window : 0) + 4096 * (any_full ? 1 : 0), B, P.N, P.M,
+                               Lbits);
       auto it = w.graphs.find(key);
       if (it != w.graphs.end()) {
         done = hipGraphLaunch(it->second, s) == hipSuccess;
@@ -1095,10 +1189,13 @@ int krylov_cycle(const Pipeline& P, Work& w, const BatchCfg& cfg, int it_budget,
     j = j1;
     (void)hipMemcpyAsync(w.host_act.data(), act, 2 * B * sizeof(int), hipMemcpyDeviceToHost, s);
     (void)hipStreamSynchronize(s);
-    int active = 0, stalled = 0;
-    for (int b = 0; b < B; ++b) active += w.host_act[b] != 0, stalled += w.host_act[B + b] != 0;
-    // a windowed cycle that left an entry at the restart length: orthogonalise fully from the next cycle on
-    if (stalled && fused && window > 0) w.full_orth = true;
+    int active = 0;
+    for (int b = 0; b < B; ++b) {
+      active += w.host_act[b] != 0;
+      // an entry that left this cycle at the restart length orthogonalises fully from the next cycle on (the cycle
+      // start sets its device flag from the same restart flag)
+      if (w.host_act[B + b] != 0) w.full_host[b] = 1;
+    }
     if (active == 0) return j;
     if (4 * active <= B) len = std::max(1, cfg.check_every / 2);
   }
@@ -1113,6 +1210,7 @@ void end_cycle(const Pipeline& P, Work& w, int nv, void* r_out, hipStream_t s, i
   Ctl* ctl = static_cast<Ctl*>(w.ctl.p);
   int* live = static_cast<int*>(w.live.p);
   hipLaunchKernelGGL(k_ctl_trisolve, dim3(ctl_blocks(B)), dim3(64), 0, s, ctl, live, B);
+  launch_cond_estimate(w, s);
   VecArgs va;
   va.B = B;
   va.act = live;
@@ -1181,10 +1279,17 @@ template int krylov_cycle<double>(const Pipeline&, Work&, const BatchCfg&, int, 
 template void end_cycle<float>(const Pipeline&, Work&, int, void*, hipStream_t, int);
 template void end_cycle<double>(const Pipeline&, Work&, int, void*, hipStream_t, int);
 
+void launch_cond_estimate(Work& w, hipStream_t s) {
+  TimerScope ts(kStageControl, 0.0, w.B, nullptr, s);
+  hipLaunchKernelGGL(k_cond_estimate, dim3(w.B), dim3(64), 0, s, static_cast<Ctl*>(w.ctl.p),
+                     static_cast<const int*>(w.live.p));
+}
+
 void launch_ctl_check(Work& w, double tol, int first, const int* mask, const double* tolv, hipStream_t s) {
   TimerScope ts(kStageControl, 0.0, w.B, nullptr, s);
   hipLaunchKernelGGL(k_ctl_check, dim3(ctl_blocks(w.B)), dim3(64), 0, s, static_cast<Ctl*>(w.ctl.p),
-                     static_cast<const double*>(w.nred.p), static_cast<int*>(w.live.p), tol, first, mask, tolv, w.B);
+                     static_cast<const double*>(w.nred.p), static_cast<int*>(w.live.p), static_cast<int*>(w.act.p),
+                     tol, first, mask, tolv, w.B);
 }
 void launch_ctl_start(Work& w, double abs_tol, double rel_tol, const double* tolv, hipStream_t s) {
   TimerScope ts(kStageControl, 0.0, w.B, nullptr, s);
@@ -1232,14 +1337,15 @@ int run_batch(const Pipeline& P, Work& w, const BatchCfg& cfg, hipStream_t s, st
   launch_reduce(static_cast<double*>(w.part_vec.p), 1, P.rhs_blocks(), nred, B, nullptr, s);
   // x = 0: the x-space residual's first launch writes x = sum y_i V_i on the first update (no memset)
   w.x_zero = P.xspace;
-  w.full_orth = false;
+  w.full_host.assign(B, 0);  // device flags: cleared by the first residual check below
   if (!w.x_zero && hipMemsetAsync(w.x.p, 0, (size_t)B * n * sizeof(c64), s) != hipSuccess)
     return fail(DBAR_EDEVICE, "hipMemsetAsync failed");
   for (int b = 0; b < B; ++b) w.host_live[b] = 1;
   if (hipMemcpyAsync(live, w.host_live.data(), B * sizeof(int), hipMemcpyHostToDevice, s) != hipSuccess)
     return fail(DBAR_EDEVICE, "hipMemcpyAsync failed");
   // r0 = b (x0 = 0); entries with b = 0 are done at once
-  hipLaunchKernelGGL(k_ctl_check, dim3(ctl_blocks(B)), dim3(64), 0, s, ctl, nred, live, 0.0, 1, nullptr, nullptr, B);
+  hipLaunchKernelGGL(k_ctl_check, dim3(ctl_blocks(B)), dim3(64), 0, s, ctl, nred, live, act, 0.0, 1, nullptr, nullptr,
+                     B);
   if (P.xspace) {  // S = m = 0 for entries with b = 0 (no residual evaluation writes them)
     launch_zero_done(w, nullptr, cfg.method == 1, s);
   } else if (mixed) {
@@ -1267,7 +1373,8 @@ int run_batch(const Pipeline& P, Work& w, const BatchCfg& cfg, hipStream_t s, st
       end_cycle<double>(P, w, ran, w.V.p, s, cfg.method);
     }
     total += ran;
-    hipLaunchKernelGGL(k_ctl_check, dim3(ctl_blocks(B)), dim3(64), 0, s, ctl, nred, live, cfg.tol, 0, nullptr, nullptr, B);
+    hipLaunchKernelGGL(k_ctl_check, dim3(ctl_blocks(B)), dim3(64), 0, s, ctl, nred, live, act, cfg.tol, 0, nullptr,
+                       nullptr, B);
     if (mixed && !P.xspace) launch_convert<float, double>(w.r64.p, n, w.V.p, n * (w.m + 1), n, B, live, 1.0, s);
     if (ran == 0) break;
   }
@@ -1504,6 +1611,8 @@ int solve_impl(const dbar_grid* grid, const void* Q, bool q_on_device, int64_t n
         I.outer = c.cycles;
         I.reserved = 0;
         I.rel_residual = c.bnorm > 0.0 ? c.rnorm / c.bnorm : 0.0;
+        I.cond_estimate = c.kappa;
+        I.err_estimate = c.kappa * I.rel_residual;
         I.m1_re = form || cfg.method == 0 ? -c.s00.im : 0.0;  // m1 = i S(0); not formed on the r-only path
         I.m1_im = form || cfg.method == 0 ? c.s00.re : 0.0;
       }

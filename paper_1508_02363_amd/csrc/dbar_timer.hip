@@ -12,7 +12,7 @@ namespace dbar {
 namespace {
 struct Rec {
   int stage;
-  double bytes_per_entry;
+  double bytes_per_entry, bytes_once;
   int B;
   int slot;  // -1: all B entries active
   hipEvent_t e0, e1;
@@ -83,11 +83,12 @@ bool timer_on() { return g_on; }
 
 static std::mutex g_timer_mutex;
 
-int timer_begin(int stage, double bytes_per_entry, int B, const int* act, hipStream_t s) {
+int timer_begin(int stage, double bytes_per_entry, int B, const int* act, hipStream_t s, double bytes_once) {
   std::lock_guard<std::mutex> lock(g_timer_mutex);
   Rec r;
   r.stage = stage;
   r.bytes_per_entry = bytes_per_entry;
+  r.bytes_once = bytes_once;
   r.B = B;
   r.slot = -1;
   if (act && g_log.p && g_slot < kLogSlots) {
@@ -117,7 +118,7 @@ static int timer_collect() {
     const int active = r.slot >= 0 ? log[r.slot] : r.B;
     StageAgg& a = g_agg[r.stage];
     a.ms += ms;
-    a.bytes += r.bytes_per_entry * active;
+    a.bytes += r.bytes_per_entry * active + (active > 0 ? r.bytes_once : 0.0);
     a.launches += 1;
   }
   g_recs.clear();

@@ -41,6 +41,8 @@ class SolveInfo:
     outer: int
     rel_residual: float
     m1: complex
+    cond_estimate: float = 0.0
+    err_estimate: float = 0.0
 
 
 def default_opts() -> _lib.Opts:
@@ -64,7 +66,8 @@ def make_opts(precision=DBAR_FP64, mode=DBAR_MODE_BATCHED, restart=0, max_iter=1
 
 
 def _infos(arr) -> list[SolveInfo]:
-    return [SolveInfo(i.status, i.iters, i.outer, i.rel_residual, complex(i.m1_re, i.m1_im)) for i in arr]
+    return [SolveInfo(i.status, i.iters, i.outer, i.rel_residual, complex(i.m1_re, i.m1_im), i.cond_estimate,
+                      i.err_estimate) for i in arr]
 
 
 def solve(Q: np.ndarray, ks, L: float, tol: float = 1e-12, M: int = 11, want_m: bool = True, **opt_kw):
@@ -280,6 +283,11 @@ class Session:
 
     def __exit__(self, *exc):
         self.close()
+
+
+def request_footprint(N: int, L: float = 1.0, precision: int = DBAR_MIXED, restart: int = 0, M: int = 11) -> int:
+    """Device bytes a serving request on an N x N grid holds while in flight (its share of a class workspace)."""
+    return int(_lib.load().dbar_request_footprint(ctypes.byref(_grid(N, L, M)), int(precision), int(restart)))
 
 
 def release():

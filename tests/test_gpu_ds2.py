@@ -105,5 +105,25 @@ def test_reconstruction_table_n128():
     r, _ = D.reflection(q0, g.xi.ravel(), L)
     q = D.reconstruct(r.reshape(N, N), L)
     err = np.max(np.abs(q - q0))
-    print(f"N=128 L=3.2 reconstruction error {err:.3e}")
-    assert err < 1e-12
+    # the same round trip with every solve at 1e-13 (the oracle's tolerance)
+    r13, _ = D.reflection(q0, g.xi.ravel(), L, tol=1e-13)
+    q13 = D.reconstruct(r13.reshape(N, N), L, tol=1e-13)
+    err13 = np.max(np.abs(q13 - q0))
+    print(f"N=128 L=3.2 reconstruction error {err:.3e} (solves to 1e-12), {err13:.3e} (solves to 1e-13)")
+    assert err < 1e-12 and err13 < 1e-12
+
+
+def test_reflection_then_reconstruction_with_graphs():
+    """dbar_reconstruct right after dbar_reflection solves on the dual grid (another L) with the same N, batch and
+    method: it must not replay the graphs the reflection captured.  Graph and direct runs take the same steps and give
+    the same bits."""
+    N, L = 16, 1.075
+    g = O.make_grid(N, L)
+    q0 = np.exp(-np.abs(g.z) ** 2)
+    out = {}
+    for ug in (1, 0):
+        r, ir = D.reflection(q0, g.xi.ravel(), L, use_graph=ug)
+        q, iq = D.reconstruct(r.reshape(N, N), L, want_info=True, use_graph=ug)
+        out[ug] = (r, q, [(i.iters, i.outer) for i in ir], [(i.iters, i.outer) for i in iq])
+    assert out[1][2] == out[0][2] and out[1][3] == out[0][3]
+    assert np.array_equal(out[1][0], out[0][0]) and np.array_equal(out[1][1], out[0][1])

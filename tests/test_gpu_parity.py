@@ -430,3 +430,55 @@ def test_device_outputs_zero_potential():
     for method, ks in ((D.DBAR_METHOD_PLAIN, [1 + 1j, 0.5]), (D.DBAR_METHOD_ITERATED, [0.0, 1.0 / (2 * L)])):
         S, m, info = D.solve_device(Qd, ks, L, tol=1e-12, method=method)
         assert torch.all(S == 0) and torch.all(m == 0) and all(i.status == 0 and i.iters == 0 for i in info)
+
+
+@pytest.mark.parametrize("prec", [D.DBAR_FP64, D.DBAR_MIXED])
+def test_graphs_follow_the_grid_parameters(prec):
+    """Captured Krylov graphs keep their kernels' arguments (the transform scales from L, the M-specialised kernels) by
+    value: a later solve with the same N, batch and restart but another L or M must not replay them.  Each solve with
+    graphs equals the same solve with direct launches, bit for bit and in iteration counts."""
+    N = 64
+    ks = W.k_disk(4, 2.0, seed=32)
+    for (L1, M1), (L2, M2) in (((3.0, 11), (4.0, 11)), ((4.0, 11), (4.0, 5))):
+        Q1 = W.potential_gaussian_sum(N, L1, seed=31)
+        Q2 = W.potential_gaussian_sum(N, L2, seed=31)
+        D.solve(Q1, ks, L1, M=M1, tol=1e-12, batch=4, precision=prec, use_graph=1)  # captures
+        Sg, mg, ig = D.solve(Q2, ks, L2, M=M2, tol=1e-12, batch=4, precision=prec, use_graph=1)
+        Sd, md, idd = D.solve(Q2, ks, L2, M=M2, tol=1e-12, batch=4, precision=prec, use_graph=0)
+        assert [(a.iters, a.outer) for a in ig] == [(a.iters, a.outer) for a in idd], (L2, M2)
+        assert np.array_equal(Sg, Sd) and np.array_equal(mg, md), (L2, M2)
+
+
+@pytest.mark.parametrize("prec", [D.DBAR_FP64, D.DBAR_MIXED])
+def test_batch_entries_do_not_depend_on_each_other(prec):
+    """A strong potential (six times the benchmark's), where some entries stall under the Gram-Schmidt window and
+    switch to full orthogonalisation: every entry of the batch takes the same steps and reaches the same bits as the
+    same k solved alone, whatever the other entries did."""
+    N, L = 64, 4.0
+    g = O.make_grid(N, L)
+    Q = 6.0 * (0.8 + 0.6j) * np.exp(-np.abs(g.z) ** 2)
+    ks = np.array([0.5 + 0.5j, -1 + 0.3j, 2 - 1j, 0.1 - 0.2j])
+    S, m, info = D.solve(Q, ks, L, tol=1e-12, batch=len(ks), precision=prec)
+    for j, k in enumerate(ks):
+        S1, m1, i1 = D.solve(Q, [k], L, tol=1e-12, batch=1, precision=prec)
+        assert (info[j].iters, info[j].outer) == (i1[0].iters, i1[0].outer), j
+        assert np.array_equal(S[j], S1[0]) and np.array_equal(m[j], m1[0]), j
+
+
+@pytest.mark.parametrize("prec", [D.DBAR_FP64, D.DBAR_MIXED])
+def test_error_estimate_reported_per_result(prec):
+    """Every result carries a condition estimate from its Krylov Hessenberg matrix and err_estimate = estimate x the
+    FP64 residual; on the small-grid workload the estimate stays within the dense-LU condition numbers measured on
+    the CPU (below 50), and the error against the oracle is at the level the estimate states."""
+    w = W.workload("plain_n128")
+    g = O.make_grid(w.N, w.L)
+    ref = O.solve(g, w.Q, w.ks[0], tol=1e-13)
+    S, m, info = D.solve(w.Q, w.ks, w.L, tol=1e-12, precision=prec)
+    i = info[0]
+    print(f"cond_estimate {i.cond_estimate:.3f} err_estimate {i.err_estimate:.2e} "
+          f"err vs oracle {relerr(S[0], ref.S):.2e}")
+    assert 1.0 <= i.cond_estimate < 50.0
+    assert i.err_estimate == pytest.approx(i.cond_estimate * i.rel_residual, rel=1e-12)
+    assert i.err_estimate < 50 * 1e-12
+    _, _, i0 = D.solve(np.zeros((32, 32)), [1.0], 3.0, tol=1e-12, precision=prec)
+    assert i0[0].cond_estimate == 0.0 and i0[0].err_estimate == 0.0

@@ -4,6 +4,8 @@ the mixed-precision tolerance, and matches the oracle; the session's bookkeeping
 Tolerance: requests ask for ||b - A S|| <= 1e-10 ||b|| (FP64 residual after FP32 inner solves).  The discrete system
 has condition numbers below 50 (dense LU pins), so two such solves agree to about 1e-9; the test uses 1e-8 against
 the oracle and 1e-9 between alone and mixed runs."""
+import json
+import os
 import time
 
 import numpy as np
@@ -87,3 +89,104 @@ def test_zero_potential_request():
     with D.Session() as s:
         S, m, info, lat = s.wait(s.submit(np.zeros((32, 32)), 1 + 1j, 3.0))
         assert np.all(S == 0) and np.all(m == 0) and info.status == 0
+
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _same(a, b):
+    """alone vs in the mix: the same bits and the same Krylov steps (every entry's arithmetic is its own)."""
+    return np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and a[2].iters == b[2].iters
+
+
+def test_c5_stream_alone_equals_mix_and_oracle():
+    """36 requests of the seeded request stream (grids N = 256 ... 2048, Gaussian-sum and sech^2 potentials with
+    |A| <= 2, |k| <= 6) submitted at once: the grid classes run concurrently and requests join as slots free up
+    (max_slots = 8).  Each result equals the same request solved alone, bit for bit, and agrees with the oracle
+    (three small-grid requests solved in the test, and the N = 2048 request 14 against its stored oracle solution)."""
+    reqs = W.serving_stream(36, rate=1.0, seed=5)
+    assert {r.N for r in reqs} == {256, 512, 1024, 2048}
+    print("C5 stream: 36 requests in the mix", flush=True)
+    with D.Session(max_slots=8) as s:
+        tickets = [s.submit(r.Q, r.k, r.L, tol=r.tol) for r in reqs]
+        mixed = [s.wait(t) for t in tickets]
+        st = s.stats()
+    assert st["submitted"] == 36 and st["completed"] == 36 and st["in_flight"] == 0 and st["queued"] == 0
+    print("C5 stream: alone", flush=True)
+    with D.Session(max_slots=8) as s:
+        alone = [s.wait(s.submit(r.Q, r.k, r.L, tol=r.tol)) for r in reqs]
+    for j, (r, a, m) in enumerate(zip(reqs, alone, mixed)):
+        assert a[2].status == 0 and m[2].status == 0, j
+        assert m[2].rel_residual <= r.tol, j
+        assert _same(a, m), j
+    small = [j for j, r in enumerate(reqs) if r.N <= 512][:3]
+    for j in small:
+        r = reqs[j]
+        print(f"oracle solve request {j} N={r.N}", flush=True)
+        ref = O.solve(O.make_grid(r.N, r.L), r.Q, r.k, tol=1e-13)
+        assert relerr(mixed[j][0], ref.S) <= 1e-8 and relerr(mixed[j][1], ref.m) <= 1e-8, j
+    gd = json.load(open(os.path.join(GOLDEN, "fullsize_c5_r14.json")))
+    S14, m14 = mixed[14][0].reshape(-1), mixed[14][1].reshape(-1)
+    for key, arr in (("S", S14), ("m", m14)):
+        ref = np.asarray(gd[key])
+        err = np.max(np.abs(arr[np.asarray(gd[f"{key}_idx"])] - (ref[:, 0] + 1j * ref[:, 1]))) / gd[f"max_abs_{key}"]
+        print(f"request 14 (N=2048) {key} err vs stored oracle solution {err:.2e}", flush=True)
+        assert err <= 1e-8
+
+
+def test_strong_request_does_not_change_later_ones():
+    """A request six times the benchmark potential (it stalls under the Gram-Schmidt window and orthogonalises fully
+    from its second cycle on) shares its grid class with ordinary requests submitted after it: theirs keep the window
+    and end exactly as when solved alone."""
+    N, L = 64, 4.0
+    x = L * (-np.pi + 2 * np.pi * np.arange(N) / N)
+    X, Y = np.meshgrid(x, x)
+    strong = 6.0 * (0.8 + 0.6j) * np.exp(-(X * X + Y * Y))
+    rng = np.random.default_rng(77)
+    normal = [(W.potential_gaussian_sum(N, L, seed=int(rng.integers(1 << 30)), amp_max=1.0),
+               complex(2.0 * np.sqrt(rng.random()) * np.exp(2j * np.pi * rng.random()))) for _ in range(6)]
+    with D.Session(max_slots=8) as s:
+        ts = s.submit(strong, 0.5 + 0.5j, L, tol=1e-12)
+        tickets = [s.submit(Q, k, L, tol=1e-12) for Q, k in normal]
+        res_strong = s.wait(ts)
+        mixed = [s.wait(t) for t in tickets]
+    assert res_strong[2].status == 0
+    for j, (Q, k) in enumerate(normal):
+        with D.Session(max_slots=8) as s:
+            a = s.wait(s.submit(Q, k, L, tol=1e-12))
+        assert a[2].status == 0 and _same(a, mixed[j]), j
+
+
+def test_budget_queues_classes_and_completes_every_request():
+    """A session whose HBM budget holds one N = 2048 request: the other grid classes wait for budget (nothing is
+    rejected), the N = 2048 class releases its workspace when it runs idle, and every request completes with the
+    result it has in an unconstrained session."""
+    reqs = W.serving_stream(12, rate=1.0, seed=5)
+    first = next(j for j, r in enumerate(reqs) if r.N == 2048)
+    order = [first] + [j for j in range(len(reqs)) if j != first]
+    fp = D.request_footprint(2048, 5.0)
+    print(f"budget {1.05 * fp / 2**20:.0f} MiB", flush=True)
+    with D.Session(hbm_budget_bytes=int(1.05 * fp), max_slots=8) as s:
+        tickets = {j: s.submit(reqs[j].Q, reqs[j].k, reqs[j].L, tol=reqs[j].tol) for j in order}
+        st0 = s.stats()
+        got = {j: s.wait(t) for j, t in tickets.items()}
+        st = s.stats()
+    print("stats at submit", st0, "at the end", st, flush=True)
+    assert st["rejected"] == 0 and st["completed"] == len(reqs) and st["queued"] == 0
+    assert st["classes_released"] >= 1 and st0["queued"] > 0
+    assert st["bytes_reserved"] <= int(1.05 * fp)
+    with D.Session(max_slots=8) as s:
+        for j, r in enumerate(reqs):
+            a = s.wait(s.submit(r.Q, r.k, r.L, tol=r.tol))
+            assert got[j][2].status == 0 and _same(a, got[j]), j
+
+
+def test_request_above_the_budget_is_rejected():
+    fp1024 = D.request_footprint(1024, 5.0)
+    Q = W.potential_sech2(2048, 5.0, 1.0)
+    with D.Session(hbm_budget_bytes=fp1024) as s:
+        with pytest.raises(D.DbarError):
+            s.submit(Q, 0.5, 5.0)
+        assert s.stats()["rejected"] == 1
+        S, m, info, lat = s.wait(s.submit(W.potential_sech2(1024, 5.0, 1.0), 0.5, 5.0))
+        assert info.status == 0
