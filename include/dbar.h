@@ -152,6 +152,20 @@ int dbar_apply(const dbar_grid* grid, const double* Q, const double* k, const do
                int32_t precision);
 
 /*
+ * For callers that cannot allocate device memory (work under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): dbar_apply on device buffers, allocating nothing.  Q_dev and S_dev: N*N complex128 device
+ * arrays (read only), AS_dev: N*N complex128 device array (written; must not overlap S_dev); k: one (re, im) pair on
+ * the host; precision DBAR_FP64 or DBAR_FP32 (as dbar_apply); stream: a hipStream_t (NULL = the default stream).
+ * Every intermediate array lives in one static device array of 34 MiB per GPU (held until the process ends), which
+ * limits the grid to N <= 1024 (larger N: DBAR_EINVAL).  The first call on a device sets that array up (it looks up
+ * its address and writes the twiddle tables into it, with synchronous copies); later calls only queue kernels on
+ * `stream` and return without waiting.  All calls on one GPU share its array, so calls that overlap on one GPU (on
+ * different streams, or while an earlier call's work is still running elsewhere) race: serialise them on one stream.
+ */
+int dbar_apply_noalloc(const dbar_grid* grid, const void* Q_dev, const double* k, const void* S_dev, void* AS_dev,
+                       int32_t precision, void* stream);
+
+/*
  * The grid transform consistent with the continuous F of Section 1: inverse = 0 gives
  * out = (dx^2/2pi) (-1)^(m1+m2) FFT2(in) (x-space in, xi-space out); inverse = 1 gives
  * out = (1/(2 pi L^2)) sum_m (-1)^(m1+m2) in_m e^{+2 pi i m.j/N} (xi-space in, x-space out).  Host buffers,

@@ -28,7 +28,8 @@ DBAR_SPACE_XI = 1
 
 # every symbol include/dbar.h declares
 EXPORTED = [
-    "dbar_default_opts", "dbar_solve", "dbar_solve_device", "dbar_apply", "dbar_transform", "dbar_dbar_inverse",
+    "dbar_default_opts", "dbar_solve", "dbar_solve_device", "dbar_apply", "dbar_apply_noalloc", "dbar_transform",
+    "dbar_dbar_inverse",
     "dbar_reflection", "dbar_reconstruct", "dbar_autotune", "dbar_set_tile", "dbar_get_tile",
     "dbar_session_create", "dbar_submit", "dbar_poll", "dbar_wait", "dbar_session_get_stats",
     "dbar_request_footprint", "dbar_session_destroy", "dbar_timer_enable", "dbar_timer_num_stages",
@@ -101,6 +102,7 @@ def load() -> ctypes.CDLL:
         lib.dbar_solve_device.argtypes = [G, P, ctypes.c_int64, D, ctypes.c_double, ctypes.POINTER(Opts), P, P,
                                           ctypes.POINTER(Info), P]
         lib.dbar_apply.argtypes = [G, D, D, D, D, ctypes.c_int32]
+        lib.dbar_apply_noalloc.argtypes = [G, P, D, P, P, ctypes.c_int32, P]
         lib.dbar_transform.argtypes = [G, ctypes.c_int32, D, D, ctypes.c_int32]
         lib.dbar_dbar_inverse.argtypes = [G, D, D, ctypes.c_int32]
         lib.dbar_autotune.argtypes = [G, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(TuneResult)]

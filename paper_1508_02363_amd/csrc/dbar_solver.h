@@ -202,7 +202,8 @@ struct Pipeline {
   int N = 0, M = 11;
   double L = 1.0;
   size_t n = 0;
-  const Twiddles* tw = nullptr;
+  const void* tw64 = nullptr;  // exp(-2 pi i j / N), j < N, in FP64 and rounded to FP32
+  const void* tw32 = nullptr;
   const c64* ex = nullptr;
   const c64* ey = nullptr;
   const c32* ex32 = nullptr;
@@ -295,6 +296,8 @@ int solve_impl(const dbar_grid* grid, const void* Q, bool q_on_device, int64_t n
                const dbar_opts* opts_in, void* S, void* m, bool out_on_device, dbar_info* info, hipStream_t caller,
                double* r_out);
 int get_twiddles(int N, const Twiddles** out);
+// exp(-2 pi i j / N), j < N, evaluated in long double and rounded once to FP64 and to FP32 (host arrays of N each)
+void host_twiddles(int N, c64* out64, c32* out32);
 int make_pipeline(const dbar_grid* g, Work& w, Pipeline* p);
 // e_k tables of B entries: FP64 ex/ey and their FP32 roundings ex32/ey32 (per-entry stride N)
 void launch_phase_tables(const c64* kv_dev, int N, double L, c64* ex, c64* ey, c32* ex32, c32* ey32, int B,

@@ -435,6 +435,14 @@ static std::mutex g_mutex;      // serialises the one-shot C-ABI calls (shared w
 static std::mutex g_tw_mutex;   // twiddle cache (also used by the serving workers)
 static std::map<int, std::unique_ptr<Twiddles>> g_twiddles;
 
+void host_twiddles(int N, c64* out64, c32* out32) {
+  for (int j = 0; j < N; ++j) {
+    const long double a = -2.0L * 3.14159265358979323846264338327950288L * j / N;
+    out64[j] = c64{(double)cosl(a), (double)sinl(a)};
+    out32[j] = c32{(float)cosl(a), (float)sinl(a)};
+  }
+}
+
 // exp(-2 pi i j / N) in long double, rounded once
 int get_twiddles(int N, const Twiddles** out) {
   std::lock_guard<std::mutex> lock(g_tw_mutex);
@@ -443,11 +451,7 @@ int get_twiddles(int N, const Twiddles** out) {
     auto t = std::make_unique<Twiddles>();
     std::vector<c64> h64(N);
     std::vector<c32> h32(N);
-    for (int j = 0; j < N; ++j) {
-      const long double a = -2.0L * 3.14159265358979323846264338327950288L * j / N;
-      h64[j] = c64{(double)cosl(a), (double)sinl(a)};
-      h32[j] = c32{(float)cosl(a), (float)sinl(a)};
-    }
+    host_twiddles(N, h64.data(), h32.data());
     int rc = t->d64.ensure(N * sizeof(c64));
     if (rc) return rc;
     rc = t->d32.ensure(N * sizeof(c32));
@@ -598,8 +602,8 @@ LineArgs Pipeline::base(int B, const int* act, unsigned flags) const {
 }
 
 template <typename T>
-static const void* tw_of(const Twiddles* t) {
-  return sizeof(T) == sizeof(double) ? t->d64.p : t->d32.p;
+static const void* tw_of(const Pipeline& p) {
+  return sizeof(T) == sizeof(double) ? p.tw64 : p.tw32;
 }
 
 // Taylor data of `in` (xi-space): F^{-1} in, d_n, c_n, R(0) -- about xi = 0, or about xi = a with kShifted
@@ -607,7 +611,7 @@ template <typename T>
 void Pipeline::moments(const void* in, size_t in_bs, void* Tbuf, int B, const int* act, unsigned flags,
                        hipStream_t s) const {
   LineArgs a = base(B, act, flags);
-  a.tw = tw_of<T>(tw);
+  a.tw = tw_of<T>(*this);
   a.in = in;
   a.in_bs = in_bs;
   a.out = Tbuf;
@@ -631,7 +635,7 @@ void Pipeline::apply_impl(const void* in, size_t in_bs, void* out, size_t out_bs
                           bool want_norm, unsigned flags, const void* S_ep, size_t S_ep_bs, hipStream_t s, const DotReq* dr) const {
   moments<T>(in, in_bs, Tbuf, B, act, flags, s);
   LineArgs a = base(B, act, flags);
-  a.tw = tw_of<T>(tw);
+  a.tw = tw_of<T>(*this);
   a.in = in;
   a.in_bs = in_bs;
   a.out = Tbuf;
@@ -685,7 +689,7 @@ template <typename T>
 void Pipeline::apply_x_first(const void* in, size_t in_bs, void* Tbuf, int B, const int* act, unsigned flags,
                              const UpdReq* u, hipStream_t s) const {
   LineArgs a = base(B, act, flags);
-  a.tw = tw_of<T>(tw);
+  a.tw = tw_of<T>(*this);
   a.in = in;
   a.in_bs = in_bs;
   a.out = Tbuf;
@@ -721,7 +725,7 @@ void Pipeline::apply_x_rest(const void* in, size_t in_bs, void* out, size_t out_
                             bool want_norm, hipStream_t s, const DotReq* dr, const XOut* xo, unsigned flags,
                             const void* S_ep, size_t S_ep_bs) const {
   LineArgs a = base(B, act, flags);
-  a.tw = tw_of<T>(tw);
+  a.tw = tw_of<T>(*this);
   a.in = Tbuf;  // in place: a column tile is read whole before it is written
   a.in_bs = n;
   a.out = Tbuf;
@@ -870,7 +874,7 @@ void Pipeline::rhs(const void* Q64p, size_t Q_bs, void* T64, c64* bout, int B, c
     return;
   }
   LineArgs a = base(B, act, flags & kUnitPhase);
-  a.tw = tw_of<double>(tw);
+  a.tw = tw_of<double>(*this);
   a.Q = Q64p;
   a.Q_bs = Q_bs;
   a.out = T64;
@@ -894,7 +898,7 @@ void Pipeline::h_of(const void* in, size_t in_bs, void* hout, size_t hout_bs, vo
                     hipStream_t s, unsigned flags, bool phase_out, bool accumulate) const {
   moments<T>(in, in_bs, Tbuf, B, act, flags, s);
   LineArgs a = base(B, act, flags);
-  a.tw = tw_of<T>(tw);
+  a.tw = tw_of<T>(*this);
   a.in = in;
   a.in_bs = in_bs;
   a.out = Tbuf;
@@ -912,7 +916,7 @@ void Pipeline::h_of(const void* in, size_t in_bs, void* hout, size_t hout_bs, vo
 template <typename T>
 void Pipeline::transform(bool inverse, const void* in, void* out, void* Tbuf, hipStream_t s) const {
   LineArgs a = base(1, nullptr, 0u);
-  a.tw = tw_of<T>(tw);
+  a.tw = tw_of<T>(*this);
   if (inverse) {
     a.in = in;
     a.out = Tbuf;
@@ -997,8 +1001,11 @@ void launch_roll_add(const c64* f, const c64* h, const int* shv, int N, c64* out
 }
 
 int make_pipeline(const dbar_grid* g, Work& w, Pipeline* p) {
-  int rc = get_twiddles(g->n, &p->tw);
+  const Twiddles* tw = nullptr;
+  int rc = get_twiddles(g->n, &tw);
   if (rc) return rc;
+  p->tw64 = tw->d64.p;
+  p->tw32 = tw->d32.p;
   p->N = g->n;
   p->M = g->M;
   p->L = g->L;

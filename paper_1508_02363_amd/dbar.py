@@ -182,6 +182,23 @@ def apply(Q: np.ndarray, k: complex, S: np.ndarray, L: float, M: int = 11, preci
     return out
 
 
+def apply_noalloc(Q, k: complex, S, out, L: float, M: int = 11, precision: int = DBAR_FP64):
+    """One application A(S) on torch complex128 device tensors (Q, S read, out written) through the allocation-free
+    entry point (N <= 1024), queued on the current torch stream."""
+    import torch
+    for t in (Q, S, out):
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.complex128 and t.is_contiguous()):
+            raise TypeError("Q, S and out must be contiguous complex128 torch tensors on the GPU")
+    N = Q.shape[0]
+    kk = np.array([complex(k)], np.complex128)
+    g = _grid(N, L, M)
+    stream = torch.cuda.current_stream(Q.device).cuda_stream
+    check(_lib.load().dbar_apply_noalloc(ctypes.byref(g), ctypes.c_void_p(Q.data_ptr()), _dptr(kk.view(np.float64)),
+                                         ctypes.c_void_p(S.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                         int(precision), ctypes.c_void_p(stream)))
+    return out
+
+
 def transform(f: np.ndarray, L: float, inverse: bool = False, precision: int = DBAR_FP64):
     """The grid transform consistent with the continuous F (inverse=False) or its inverse."""
     f = _c128(f)

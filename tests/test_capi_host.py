@@ -136,3 +136,17 @@ def test_tuning_entry_points_validate_arguments():
     v, c, nv = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
     assert lib.dbar_get_tile(256, _lib.DBAR_FP32, ctypes.byref(v), ctypes.byref(c), ctypes.byref(nv)) == 0
     assert v.value == 0 and nv.value >= 2 and c.value == 8  # default: 8 columns (64 B rows of FP32 complex)
+
+
+@pytest.mark.parametrize("N,prec", [(2048, 0), (4096, 2), (16, 1), (12, 0)])
+def test_noalloc_apply_rejects_sizes_and_options_on_the_host(N, prec):
+    """The allocation-free entry point checks the grid against its scratch maximum (N <= 1024) and the precision
+    before it touches a device: no buffer is dereferenced for these calls."""
+    lib = _lib.load()
+    g = _lib.Grid(N, 11, 2.0)
+    k = np.array([0.5, 0.25])
+    rc = lib.dbar_apply_noalloc(ctypes.byref(g), ctypes.c_void_p(16), k.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                ctypes.c_void_p(16), ctypes.c_void_p(16), prec, None)
+    assert rc == _lib.DBAR_EINVAL
+    msg = lib.dbar_last_error().decode()
+    assert msg and (N <= 1024 or "1024" in msg)
