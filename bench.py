@@ -47,10 +47,15 @@ def parse():
                     help="skip the iterated-solver (Section 5.3) and DS II round-trip (Section 6) legs")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"), default=None,
                     help="no GPU: turn the FETCH_SIZE / WRITE_SIZE counter CSVs of two `--probe` runs into "
-                         "profiles/traffic.json (bytes per launch per stage, scaled by the calibration copy)")
+                         "profiles/traffic_<workload>.json (bytes per launch per stage, scaled by the calibration "
+                         "copy)")
     ap.add_argument("--probe", choices=["mixed", "fp64"], default=None,
-                    help="counter-collection mode: one warm step of the given path plus a 256 MiB device copy of "
-                         "known size (the calibration kernel for FETCH_SIZE / WRITE_SIZE); prints one JSON line")
+                    help="counter-collection mode: two steps of the given path, then a 256 MiB device copy of known "
+                         "size (the calibration kernel for FETCH_SIZE / WRITE_SIZE) and two grid transforms whose "
+                         "column and row launches move known bytes with the line kernels' access patterns (a check "
+                         "of that calibration); prints one JSON line")
+    ap.add_argument("--batch", type=int, default=0,
+                    help="entries per launch of the timed path (0: every k of the workload in one batch)")
     return ap.parse_args()
 
 
@@ -65,10 +70,10 @@ def kernel_source_hash() -> str:
     return h.hexdigest()
 
 
-def stored_traffic(kernel: str):
-    """HBM bytes per launch of `kernel` from the PMC runs recorded in profiles/traffic.json, or None if none was
-    recorded for it or the kernels changed since."""
-    path = os.path.join(HERE, "profiles", "traffic.json")
+def stored_traffic(kernel: str, workload: str = "plain_n1024"):
+    """HBM bytes per launch of `kernel` from the PMC runs recorded in profiles/traffic_<workload>.json, or None if
+    none was recorded for it or the kernels changed since."""
+    path = traffic_path(workload)
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
@@ -97,7 +102,11 @@ def stage_of_kernel(name: str):
     return None
 
 
-def traffic_from(fetch_dir: str, write_dir: str) -> dict:
+def traffic_path(workload: str) -> str:
+    return os.path.join(HERE, "profiles", f"traffic_{workload}.json")
+
+
+def traffic_from(fetch_dir: str, write_dir: str, workload: str) -> dict:
     import csv
     import glob
 
@@ -113,23 +122,129 @@ def traffic_from(fetch_dir: str, write_dir: str) -> dict:
     kib = 256 * 1024  # the probe's calibration copy: 256 MiB read and written
     ff = kib / [v for v, g in F[cal] if g == big][-1]
     fw = kib / [v for v, g in Wt[cal] if g == big][-1]
-    kernels = {}
+    kernels, check = {}, {}
     for name, vals in F.items():
-        st = stage_of_kernel(name)
-        if st is None or name not in Wt:
+        if name not in Wt:
             continue
         f = sum(v for v, _ in vals) / len(vals) * ff * 1024
         wv = sum(v for v, _ in Wt[name]) / len(Wt[name]) * fw * 1024
+        # the probe's transform: its column and row launches read one N x N array and write one
+        for tag, op in (("cols", "OpColsPlain<"), ("rows", "OpRowsFwdEpilogue<")):
+            if op in name:
+                import re
+                m = re.search(r"k_lines<(float|double), (\d+),", name)
+                es, n = (8 if m.group(1) == "float" else 16), int(m.group(2))
+                check[f"{tag}.{m.group(1)}.N{n}"] = {"expected_bytes": 2.0 * n * n * es, "measured_bytes": f + wv,
+                                                     "ratio": (f + wv) / (2.0 * n * n * es)}
+        st = stage_of_kernel(name)
+        if st is None or "OpColsPlain<" in name or "OpRowsFwdEpilogue<" in name:
+            continue
         kernels[st] = {"bytes_per_launch": f + wv, "fetch_bytes_per_launch": f, "write_bytes_per_launch": wv,
                        "launches": len(vals)}
-    rec = {"source_sha256": kernel_source_hash(), "fetch_scale": ff, "write_scale": fw, "kernels": kernels}
-    path = os.path.join(HERE, "profiles", "traffic.json")
-    json.dump(rec, open(path, "w"), indent=1)
+    rec = {"source_sha256": kernel_source_hash(), "workload": workload, "fetch_scale": ff, "write_scale": fw,
+           "calibration_check": check, "kernels": kernels}
+    json.dump(rec, open(traffic_path(workload), "w"), indent=1)
     return rec
 
 
 def rel_linf(a, b):
     return float(np.max(np.abs(a - b)) / max(float(np.max(np.abs(b))), 1e-300))
+
+
+# ----------------------------------------------------------------------------------------------------------------
+# CPU baseline: the oracle, as it is, in worker processes on the host cores (one single-threaded NumPy process per
+# core: the parallelisation over k that the outlook of the paper proposes)
+# ----------------------------------------------------------------------------------------------------------------
+_OM = {}
+
+
+def _oracle_worker(args):
+    """One oracle solve of workload `name`, k index j (run in a spawned worker; single-threaded BLAS/FFT)."""
+    name, j, want = args
+    from threadpoolctl import threadpool_limits
+
+    import dbar_workloads as W
+    from oracle import dbar_oracle as O
+    w = W.workload(name)
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        key = (w.N, w.L, w.M)
+        if key not in _OM:
+            g = O.make_grid(w.N, w.L)
+            _OM.clear()
+            _OM[key] = (g, O.omega_table(g, w.M))
+        g, om = _OM[key]
+        ref = O.solve(g, w.Q, w.ks[j], tol=1e-13, M=w.M, om=om)
+        dt = time.perf_counter() - t0
+    return j, dt, ref.iters, ref.rel_residual, (ref.S if want else None), (ref.m if want else None)
+
+
+def host_description() -> dict:
+    import platform
+
+    import scipy
+    cpu = platform.processor() or "?"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"cpu_model": cpu, "host_cores_visible": len(os.sched_getaffinity(0)), "numpy": np.__version__,
+            "scipy": scipy.__version__, "fft_backend": "numpy.fft (pocketfft, C, single-threaded)",
+            "python": platform.python_version()}
+
+
+def oracle_pool(workers: int):
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    for v in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        os.environ[v] = "1"
+    return cf.ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn"))
+
+
+def cpu_baseline_leg(w, S, m, subset_n512=None) -> tuple[dict, dict]:
+    """The oracle timed on the host: (i) one solve in one process (k index 0), (ii) all 16 k of the benchmark workload
+    over one single-threaded worker per core (at most 16, the GPU machine's CPU share), as solves/s; the same for the
+    small-grid workload (1 k) and a seeded 64-k subset of the N = 512 batched workload.  Returns (cpu_baseline,
+    accuracy): the GPU results of every benchmark k against the oracle's."""
+    workers = max(1, min(16, len(os.sched_getaffinity(0))))
+    nk = len(w.ks)
+    acc = {}
+    with oracle_pool(workers) as ex:
+        # (i) one process, one solve (the pool's first worker: warm interpreter, cold caches)
+        t0 = time.perf_counter()
+        j0, dt0, it0, res0, S0, m0 = ex.submit(_oracle_worker, (w.name, 0, True)).result()
+        single = time.perf_counter() - t0
+        # (ii) every k, one worker per core
+        t0 = time.perf_counter()
+        out = list(ex.map(_oracle_worker, [(w.name, j, True) for j in range(nk)]))
+        wall = time.perf_counter() - t0
+        errS = max(rel_linf(S[j].cpu().numpy(), Sj) for j, _, _, _, Sj, _ in out)
+        errm = max(rel_linf(m[j].cpu().numpy(), mj) for j, _, _, _, _, mj in out)
+        acc = {"err_S_vs_oracle_max": errS, "err_m_vs_oracle_max": errm, "oracle_k": nk,
+               "oracle_rel_residual_max": max(o[3] for o in out), "oracle_iters": [o[2] for o in out]}
+        others = {}
+        # the small-grid workload: N = 128, one k
+        t0 = time.perf_counter()
+        r = ex.submit(_oracle_worker, ("plain_n128", 0, False)).result()
+        others["plain_n128"] = {"solves_per_s_one_core": 1.0 / r[1], "seconds": r[1]}
+        if subset_n512 is not None:
+            t0 = time.perf_counter()
+            res = list(ex.map(_oracle_worker, [("batched_n512", int(j), False) for j in subset_n512]))
+            dt = time.perf_counter() - t0
+            others["batched_n512_subset"] = {"n_k": len(subset_n512), "solves_per_s": len(subset_n512) / dt,
+                                             "seconds": dt, "mean_iters": float(np.mean([x[2] for x in res]))}
+    base = {
+        "value": nk / wall, "unit": "solves/s", "cores": workers, "kind": "oracle",
+        "sample": f"all {nk} k of the benchmark workload (N={w.N}), one oracle solve each (NumPy FP64, GMRES to 1e-13, "
+                  f"W_n tables included) over {workers} single-threaded worker processes, {wall:.1f} s wall",
+        "single_core_solves_per_s": 1.0 / dt0, "single_core_seconds_per_solve": dt0,
+        "single_core_sample": f"k index 0 in one worker process ({dt0:.1f} s; {single:.1f} s with process start)",
+        "other_configs": others, "host": host_description(),
+    }
+    return base, acc
 
 
 def serving_leg(D, W, n_req: int) -> dict:
@@ -181,6 +296,7 @@ def serving_leg(D, W, n_req: int) -> dict:
         stop[0] = True
         th.join()
         t_end = max(done_at.values())
+        stats = s.stats()
     L_ms = np.array([v * 1e3 for v in lat.values()])
     by_n = {}
     for r, t in zip(stream, sorted(lat)):
@@ -192,7 +308,9 @@ def serving_leg(D, W, n_req: int) -> dict:
         "p50_latency_ms": float(np.percentile(L_ms, 50)), "p99_latency_ms": float(np.percentile(L_ms, 99)),
         "p50_latency_ms_by_N": {int(k): float(np.percentile(v, 50)) for k, v in sorted(by_n.items())},
         "max_rel_residual": max(i.rel_residual for i in infos.values()),
+        "max_err_estimate": max(i.err_estimate for i in infos.values()),
         "all_converged": all(i.status == 0 for i in infos.values()),
+        "session_stats": stats,
     }
 
 
@@ -220,6 +338,28 @@ def iterated_leg(D, Qd, L: float, M: int, tol: float) -> dict:
     return out
 
 
+def stage_summary(stages: list) -> dict:
+    """Roofline of the dominant stage of one timed pass (the stage with the largest total time: its algorithmic bytes
+    per launch over its average launch duration, HIP events on the stream the kernels run on), the per-stage GB/s,
+    and the stages whose algorithmic rate would exceed the HBM peak (a byte-model error, reported, never hidden)."""
+    dom = max(stages, key=lambda s: s["total_ms"])
+    achieved = dom["bytes"] / (dom["total_ms"] * 1e-3) / 1e9
+    fft = [s for s in stages if s["name"].startswith("lines.")]
+    fft_ms = sum(s["total_ms"] for s in fft)
+    per = {s["name"]: {"ms": round(s["total_ms"], 4), "launches": s["launches"],
+                       "GB/s": round(s["bytes"] / max(s["total_ms"], 1e-9) / 1e6, 1)} for s in stages}
+    return {
+        "roofline": {"bound": "hbm", "kernel": dom["name"], "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "launches": dom["launches"],
+                     "avg_launch_us": dom["total_ms"] * 1e3 / dom["launches"],
+                     "bytes_per_launch": dom["bytes"] / dom["launches"]},
+        "stages": per,
+        "fft_matvec_GBs": sum(s["bytes"] for s in fft) / (fft_ms * 1e-3) / 1e9 if fft_ms > 0 else 0.0,
+        "stages_above_peak": [k for k, v in per.items() if v["GB/s"] > HBM_PEAK_GBS],
+        "total_stage_ms": sum(s["total_ms"] for s in stages),
+    }
+
+
 def configs_leg(D, W) -> dict:
     """The other full-size workloads, one timed pass each after a warm-up: the batched N = 512 workload (all 1024 k
     of the 32 x 32 grid, FP64, column tiles and batch tuned first) and the N = 4096 mixed-precision workload (64 k),
@@ -241,6 +381,8 @@ def configs_leg(D, W) -> dict:
     D.set_tile(w.N, D.DBAR_FP64, 0)
     del Qd
     w = W.workload("mixed_n4096")
+    # column tiles for this grid (FP32 and FP64 operators), outside the timed region like every warm-up
+    tune4096 = D.autotune(w.N, w.L, precision=D.DBAR_MIXED, batch=16, M=w.M)
     Qd = torch.from_numpy(w.Q).to("cuda:0")
     # warm-up on the same k set: the same batch size, so the timed call replays the captured Krylov graphs
     D.solve_device(Qd, w.ks, w.L, tol=w.tol, M=w.M, precision=D.DBAR_MIXED, want_m=False)
@@ -252,10 +394,27 @@ def configs_leg(D, W) -> dict:
     sample = [0, 21, 42, 63]
     S64, _, _ = D.solve_device(Qd, w.ks[sample], w.L, tol=w.tol, M=w.M, precision=D.DBAR_FP64, want_m=False)
     err = max(rel_linf(S[j].cpu().numpy(), S64[i].cpu().numpy()) for i, j in enumerate(sample))
+    del S, S64
+    # per-stage timing of one more pass: here one FP32 vector is 128 MiB and a launch over the batch streams
+    # gigabytes, far beyond the 256 MB Infinity Cache, so the rates are HBM rates
+    D.timer_enable(True)
+    D.solve_device(Qd, w.ks, w.L, tol=w.tol, M=w.M, precision=D.DBAR_MIXED, want_m=False)
+    torch.cuda.synchronize()
+    D.timer_enable(False)
+    summ = stage_summary(D.timer_stages())
     out["mixed_n4096"] = {"n_k": len(w.ks), "precision": "mixed", "solves_per_s": len(w.ks) / dt,
                           "all_converged": all(i.status == 0 for i in info),
                           "max_rel_residual": max(i.rel_residual for i in info),
-                          "err_S_vs_fp64_sampled": err, "sampled_k": sample}
+                          "max_err_estimate": max(i.err_estimate for i in info),
+                          "max_cond_estimate": max(i.cond_estimate for i in info),
+                          "err_S_vs_fp64_sampled": err, "sampled_k": sample,
+                          "roofline": dict(summ["roofline"], traffic=stored_traffic(summ["roofline"]["kernel"],
+                                                                                     "mixed_n4096")),
+                          "stages": summ["stages"],
+                          "fft_matvec_GBs": summ["fft_matvec_GBs"], "stages_above_peak": summ["stages_above_peak"],
+                          "tuning": tune4096}
+    D.set_tile(w.N, D.DBAR_FP64, 0)
+    D.set_tile(w.N, D.DBAR_FP32, 0)
     return out
 
 
@@ -282,9 +441,9 @@ def ds2_leg(D, W, N: int = 128, L: float = 3.2) -> dict:
 def main():
     args = parse()
     if args.traffic_from:
-        rec = traffic_from(*args.traffic_from)
+        rec = traffic_from(*args.traffic_from, args.workload)
         print(json.dumps({"traffic_stages": len(rec["kernels"]), "fetch_scale": rec["fetch_scale"],
-                          "write_scale": rec["write_scale"]}))
+                          "write_scale": rec["write_scale"], "calibration_check": rec["calibration_check"]}))
         return
     if args.gpus != 1:
         print(json.dumps({"error": "one GPU only: --gpus must be 1 (sharding the k values over several GPUs is "
@@ -304,8 +463,10 @@ def main():
     Qd = torch.from_numpy(w.Q).to(dev)
     torch.cuda.synchronize()
 
+    batch = args.batch if args.batch > 0 else nk
+
     def step(**kw):
-        return D.solve_device(Qd, w.ks, L, tol=w.tol, M=w.M, batch=nk, **kw)
+        return D.solve_device(Qd, w.ks, L, tol=w.tol, M=w.M, batch=batch, **kw)
 
     # the library's tuner picks the column-tile widths for this grid (outside the timed region, like the warm-up)
     tuning = None if args.no_autotune or args.probe else D.autotune(N, L, precision=D.DBAR_MIXED, batch=nk, M=w.M)
@@ -327,8 +488,14 @@ def main():
         torch.cuda.synchronize()
         dst.copy_(src)
         torch.cuda.synchronize()
-        print(json.dumps({"probe": args.probe, "copy_bytes_read": src.numel() * 16, "copy_bytes_written":
-                          dst.numel() * 16}))
+        del src, dst
+        # the transform check: a column launch (FFT of every column) and a row launch (FFT of every row), each
+        # reading one N x N array and writing one
+        f = np.random.default_rng(1).standard_normal((N, N)) + 0j
+        D.transform(f, L, precision=D.DBAR_FP64 if args.probe == "fp64" else D.DBAR_FP32)
+        torch.cuda.synchronize()
+        print(json.dumps({"probe": args.probe, "workload": w.name, "copy_bytes_read": 256 * 2 ** 20,
+                          "copy_bytes_written": 256 * 2 ** 20}))
         return
 
     def timed(kw, steps, warmup):
@@ -362,13 +529,9 @@ def main():
     step(**kw)
     torch.cuda.synchronize()
     D.timer_enable(False)
-    stages = D.timer_stages()
-    dom = max(stages, key=lambda s: s["total_ms"])
-    total_stage_ms = sum(s["total_ms"] for s in stages)
-    achieved = dom["bytes"] / (dom["total_ms"] * 1e-3) / 1e9
-    fft_stages = [s for s in stages if s["name"].startswith("lines.")]
-    fft_ms = sum(s["total_ms"] for s in fft_stages)
-    fft_gbs = sum(s["bytes"] for s in fft_stages) / (fft_ms * 1e-3) / 1e9 if fft_ms > 0 else 0.0
+    summ = stage_summary(D.timer_stages())
+    roof = summ["roofline"]
+    roof["traffic"] = stored_traffic(roof["kernel"])
 
     context = {}
     if not args.no_context:
@@ -381,6 +544,12 @@ def main():
         t_xi, (Sq, _, _) = timed(paths["mixed_xi"], 2, 1)
         context["mixed_xi_space_solves_per_s"] = nk / t_xi
         context["mixed_xi_space_err_vs_fp64"] = max(rel_linf(Sq[j].cpu().numpy(), S64h[j]) for j in range(nk))
+        # the same solvers with full orthogonalisation (classical GMRES, no Gram-Schmidt window)
+        for name in ("mixed", "fp64"):
+            t_full, (Sf, _, infof) = timed(dict(paths[name], orth_window=0), 2, 1)
+            context[f"{name}_full_gmres_solves_per_s"] = nk / t_full
+            context[f"{name}_full_gmres_iters"] = [i.iters for i in infof]
+            context[f"{name}_full_gmres_err_vs_fp64"] = max(rel_linf(Sf[j].cpu().numpy(), S64h[j]) for j in range(nk))
 
     result = {
         "metric": METRIC,
@@ -404,17 +573,14 @@ def main():
             "mixed_err_S_vs_fp64": err_mixed, "mixed_err_m_vs_fp64": err_mixed_m,
             "max_rel_residual": max(i.rel_residual for i in info),
             "iters": [i.iters for i in info], "outer": [i.outer for i in info],
+            "cond_estimate": [round(i.cond_estimate, 3) for i in info],
+            "max_err_estimate": max(i.err_estimate for i in info),
         },
-        "roofline": {
-            "bound": "hbm", "kernel": dom["name"], "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": stored_traffic(dom["name"]),
-            "launches": dom["launches"], "avg_launch_us": dom["total_ms"] * 1e3 / dom["launches"],
-            "bytes_per_launch": dom["bytes"] / dom["launches"],
-        },
-        "stages": {s["name"]: {"ms": round(s["total_ms"], 4), "launches": s["launches"],
-                               "GB/s": round(s["bytes"] / max(s["total_ms"], 1e-9) / 1e6, 1)} for s in stages},
-        "fft_matvec_GBs": fft_gbs,
-        "stage_time_share_of_step": total_stage_ms / (sec * 1e3),
+        "roofline": roof,
+        "stages": summ["stages"],
+        "stages_above_peak": summ["stages_above_peak"],
+        "fft_matvec_GBs": summ["fft_matvec_GBs"],
+        "stage_time_share_of_step": summ["total_stage_ms"] / (sec * 1e3),
         "context": context,
         "tuning": tuning,
     }
@@ -428,22 +594,10 @@ def main():
         result["other_configs"] = configs_leg(D, W)
 
     if not args.no_cpu_baseline:
-        from threadpoolctl import threadpool_limits
-
-        from oracle import dbar_oracle as O
-        k0 = w.ks[0]
-        g = O.make_grid(N, L)
-        with threadpool_limits(limits=1):
-            t0 = time.perf_counter()
-            ref = O.solve(g, w.Q, k0, tol=1e-13, M=w.M)
-            t_or = time.perf_counter() - t0
-        result["cpu_baseline"] = {
-            "value": 1.0 / t_or, "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "sample": f"1 of the {nk} k values (k={k0.real:+.4f}{k0.imag:+.4f}i): one full oracle solve at N={N} "
-                      f"(NumPy FP64, single thread, GMRES to 1e-13, W_n tables included), {t_or:.1f} s",
-        }
-        result["accuracy"]["err_S_vs_oracle_k0"] = rel_linf(S[0].cpu().numpy(), ref.S)
-        result["accuracy"]["err_m_vs_oracle_k0"] = rel_linf(m[0].cpu().numpy(), ref.m)
+        subset = np.sort(np.random.default_rng(3).choice(1024, 64, replace=False))
+        base, acc = cpu_baseline_leg(w, S, m, subset)
+        result["cpu_baseline"] = base
+        result["accuracy"].update(acc)
     print(json.dumps(result))
 
 

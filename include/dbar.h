@@ -190,8 +190,8 @@ int dbar_dbar_inverse(const dbar_grid* grid, const double* S_in, double* h_out, 
 typedef struct {
   int32_t n_variants[2];    /* [0]: FP64 operator, [1]: FP32 operator; 0 if that operator was not tuned */
   int32_t chosen[2];        /* the variant kept */
-  int32_t columns[2][3];    /* columns per tile of each variant */
-  double ms[2][3];          /* one operator application over `batch` entries, per variant (milliseconds) */
+  int32_t columns[2][4];    /* columns per tile of each variant */
+  double ms[2][4];          /* one operator application over `batch` entries, per variant (milliseconds) */
   int32_t batch;            /* entries per launch kept for solves with opts->batch = 0 */
   int32_t batch_candidates[4];
   int32_t reserved;

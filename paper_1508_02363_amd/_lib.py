@@ -39,7 +39,7 @@ EXPORTED = [
 
 class TuneResult(ctypes.Structure):
     _fields_ = [("n_variants", ctypes.c_int32 * 2), ("chosen", ctypes.c_int32 * 2),
-                ("columns", (ctypes.c_int32 * 3) * 2), ("ms", (ctypes.c_double * 3) * 2),
+                ("columns", (ctypes.c_int32 * 4) * 2), ("ms", (ctypes.c_double * 4) * 2),
                 ("batch", ctypes.c_int32), ("batch_candidates", ctypes.c_int32 * 4), ("reserved", ctypes.c_int32),
                 ("per_entry_ms", ctypes.c_double * 4)]
 

@@ -1,4 +1,5 @@
 // Run-time dispatch over the grid size N for the line-transform stages.
+#include <algorithm>
 #include <atomic>
 
 #include "dbar_lines.h"
@@ -33,15 +34,32 @@ void set_tile_variant(int N, bool fp64, int variant) {
 
 int tuning_epoch() { return g_epoch.load(); }
 
+template <typename T, int N>
+static int tile_cols(int variant) {
+  using Tl = Tiling<T, N>;
+  switch (variant) {
+    case 1: return Tl::template cols_v<1>();
+    case 2: return Tl::template cols_v<2>();
+    case 3: return Tl::template cols_v<3>();
+    default: return Tl::COLS;
+  }
+}
+
 int line_tiles_variant(int N, bool cols, bool fp64, int variant) {
-#define DBAR_TILES(NN)                                                                                   \
-  if (N == NN) {                                                                                         \
-    if (fp64) return NN / (cols ? (Tiling<double, NN>::COLS << variant) : Tiling<double, NN>::ROWS);     \
-    return NN / (cols ? (Tiling<float, NN>::COLS << variant) : Tiling<float, NN>::ROWS);                 \
+#define DBAR_TILES(NN)                                                                               \
+  if (N == NN) {                                                                                     \
+    if (fp64) return NN / (cols ? tile_cols<double, NN>(variant) : Tiling<double, NN>::ROWS);        \
+    return NN / (cols ? tile_cols<float, NN>(variant) : Tiling<float, NN>::ROWS);                    \
   }
   DBAR_FOR_EACH_N(DBAR_TILES)
 #undef DBAR_TILES
   return 0;
+}
+
+int line_tiles_max(int N, bool cols, bool fp64) {
+  int t = 0;
+  for (int v = 0; v < (cols ? tile_variants(N, fp64) : 1); ++v) t = std::max(t, line_tiles_variant(N, cols, fp64, v));
+  return t;
 }
 
 int tile_columns(int N, bool fp64, int variant) { return N / line_tiles_variant(N, true, fp64, variant); }

@@ -85,9 +85,11 @@ struct LineArgs {
 // sized for the default (narrowest, most tiles) choice.
 int line_tiles(int N, bool cols, bool fp64);
 int line_tiles_variant(int N, bool cols, bool fp64, int variant);
-// Column-tile width choice per (N, precision): the number of valid variants (columns per tile = default << v, while
-// the block has at most 1024 threads and its LDS fits), the current choice, and the columns of a variant.
-constexpr int kMaxTileVariants = 3;
+int line_tiles_max(int N, bool cols, bool fp64);  // the most tiles over the variants (sizes partial buffers)
+// Column-tile width choice per (N, precision): the number of valid variants (0: the default width; then up to two
+// wider tiles, 2x and 4x, while the block has at most 1024 threads and its LDS fits; then half the default width),
+// the current choice, and the columns of a variant.
+constexpr int kMaxTileVariants = 4;
 int tile_variants(int N, bool fp64);
 int tile_variant(int N, bool fp64);
 int tile_columns(int N, bool fp64, int variant);

@@ -233,16 +233,35 @@ struct Tiling {
   }
   static constexpr int ROWS = fit(cmin(N, cmax(1, 128 / G::TPL)));
   static constexpr int COLS = fit(cmin(N, cmax(64 / (int)sizeof(cx<T>), cmax(1, 64 / G::TPL))));
-  // wider column tiles (variant V: COLS << V columns) for the tuner: valid while the block has at most 1024 threads
-  // and the tile's lines fit the LDS budget
-  template <int V>
-  static constexpr int cols_v() { return COLS << V; }
-  template <int V>
-  static constexpr bool cols_valid() {
-    return V == 0 || (cols_v<V>() <= N && cols_v<V>() * G::TPL <= 1024 &&
-                      cols_v<V>() * G::LDS_LINE * (int)sizeof(cx<T>) <= kLdsBudget);
+  // Column-tile variants for the tuner: 0 = COLS (the default), then the wider tiles COLS << 1, COLS << 2 while the
+  // block has at most 1024 threads and the tile's lines fit the LDS budget, then the narrower tile COLS / 2 (more
+  // blocks per CU where one full-height tile fills most of the LDS, as at N = 4096).
+  static constexpr bool wide_ok(int c) {
+    return c <= N && c * G::TPL <= 1024 && c * G::LDS_LINE * (int)sizeof(cx<T>) <= kLdsBudget;
   }
-  static constexpr int variants() { return cols_valid<2>() ? 3 : cols_valid<1>() ? 2 : 1; }
+  static constexpr int NWIDE = wide_ok(COLS << 1) ? (wide_ok(COLS << 2) ? 2 : 1) : 0;
+  static constexpr bool NARROW = COLS >= 2;
+  static constexpr int variants() { return 1 + NWIDE + (NARROW ? 1 : 0); }
+  template <int V>
+  static constexpr int cols_v() { return V == 0 ? COLS : V <= NWIDE ? (COLS << V) : COLS / 2; }
+  template <int V>
+  static constexpr bool cols_valid() { return V < variants(); }
+};
+
+// LDS of one line-kernel block: the line data, or the scratch of its reductions, whichever is larger
+template <typename T, int N, int LINES, bool COLS>
+struct LdsSize {
+  static constexpr int TPL = LineGeom<N>::TPL;
+  static constexpr int NT = LINES * TPL;
+  static constexpr int kData = LINES * LineGeom<N>::LDS_LINE * (int)sizeof(cx<T>);
+  static constexpr int LN = LINES;
+  static constexpr int kScratchReduce = (NT >= 64 ? NT / 64 : NT) * 2 * kNMom * (int)sizeof(double);
+  // the moment reduction's groups (MomentsBase::finish_kk): runs of min(TPL, 64) lanes of a row; on a column tile
+  // (wave, column) pairs when the block has whole waves and fewer than 64 columns, else single threads
+  static constexpr int NG = COLS ? ((NT >= 64 && LN < 64) ? (NT / 64) * LN : NT) : NT / (TPL < 64 ? TPL : 64);
+  static constexpr int kScratchMoments = (NG * 2 * (kMaxM + 1) + LN * 2 * kNMom + LN * 2 * (kMaxM + 1)) * 8;
+  static constexpr int kScratch = kScratchReduce > kScratchMoments ? kScratchReduce : kScratchMoments;
+  static constexpr int kElems = ((kData > kScratch ? kData : kScratch) + (int)sizeof(cx<T>) - 1) / (int)sizeof(cx<T>);
 };
 
 // ------------------------------------------------------------------------------------------------------------
@@ -401,6 +420,7 @@ struct MomentsBase : OpBase<T, N> {
     constexpr int GS = ALONG_X ? (TPL < 64 ? TPL : 64) : 1;
     constexpr bool SHFL = !ALONG_X && NT >= 64 && LN < 64;
     constexpr int NG = ALONG_X ? NT / GS : SHFL ? (NT / 64) * LN : NT;
+    static_assert(NG == LdsSize<T, N, LN, !ALONG_X>::NG, "LDS scratch sized for another reduction layout");
     __syncthreads();  // scratch aliases the transform's LDS
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
@@ -900,17 +920,6 @@ DBAR_D int xcd_swizzle(int bid, int nblk) {
   return (bid & 7) * (nblk >> 3) + (bid >> 3);
 }
 
-template <typename T, int N, int LINES>
-struct LdsSize {
-  static constexpr int NT = LINES * LineGeom<N>::TPL;
-  static constexpr int kData = LINES * LineGeom<N>::LDS_LINE * (int)sizeof(cx<T>);
-  static constexpr int LN = LINES;
-  static constexpr int kScratchReduce = (NT >= 64 ? NT / 64 : NT) * 2 * kNMom * (int)sizeof(double);
-  static constexpr int kScratchCols =
-      ((NT >= 64 ? NT / 64 : 1) * LN * 2 * (kMaxM + 1) + LN * 2 * kNMom + LN * 2 * (kMaxM + 1)) * 8;
-  static constexpr int kScratch = kScratchReduce > kScratchCols ? kScratchReduce : kScratchCols;
-  static constexpr int kElems = ((kData > kScratch ? kData : kScratch) + (int)sizeof(cx<T>) - 1) / (int)sizeof(cx<T>);
-};
 
 // Occupancy floor: at least 4 waves per SIMD (<= 128 VGPRs) for the wide column tiles, whose LDS allows two
 // blocks per CU only if the registers do too.
@@ -924,7 +933,7 @@ __global__ void __launch_bounds__(LINES * LineGeom<N>::TPL, MinWaves<LINES * Lin
     k_lines(Op op) {
   using G = LineGeom<N>;
   constexpr int NT = LINES * G::TPL;
-  __shared__ cx<T> lds[LdsSize<T, N, LINES>::kElems];
+  __shared__ cx<T> lds[LdsSize<T, N, LINES, COLS>::kElems];
   // pass-1 twiddle table: column stages only (their element work makes them arithmetic-bound)
   __shared__ cx<T> lds_t1[COLS ? Pass1Table<N>::SIZE : 1];
   const int b = blockIdx.y;
@@ -1018,6 +1027,9 @@ void launch_op(const LineArgs& a, hipStream_t s) {
 // column stages at tile variant V (only the valid variants are instantiated)
 template <typename T, int N, class Op>
 void launch_cols(const LineArgs& a, hipStream_t s) {
+  if constexpr (Tiling<T, N>::template cols_valid<3>()) {
+    if (a.tile == 3) return launch_op<T, N, true, Op, 3>(a, s);
+  }
   if constexpr (Tiling<T, N>::template cols_valid<2>()) {
     if (a.tile == 2) return launch_op<T, N, true, Op, 2>(a, s);
   }

@@ -256,7 +256,12 @@ __global__ void __launch_bounds__(64) k_cond_estimate(Ctl* ctl, const int* live)
   if (n <= c.kappa_n || n < 1) return;
   const int i = threadIdx.x;
   constexpr int LD = kMaxRestart + 1;
-  auto R = [&](int row, int col) { return c.H[(size_t)col * LD + row]; };
+  // the n x n factor staged in LDS once (coalesced): the iterations below read it many times
+  __shared__ double Rs[kMaxRestart * LD];
+  for (int col = 0; col < n; ++col)
+    for (int row = i; row <= col; row += 64) Rs[col * LD + row] = c.H[(size_t)col * LD + row];
+  __syncthreads();
+  auto R = [&](int row, int col) { return Rs[col * LD + row]; };
   for (int l = 0; l < n; ++l)
     if (!(R(l, l) != 0.0)) return;  // breakdown (exact solution reached): keep the previous estimate
   // sigma_max: x <- R^T R x, normalised
@@ -532,8 +537,8 @@ int Work::setup(int N_, int B_, int m_, int prec_, bool shared_q) {
   if ((rc = dmom32.ensure((size_t)B * kNMom * sizeof(c32)))) return rc;
   if ((rc = ex32.ensure((size_t)B * N * sizeof(c32)))) return rc;
   if ((rc = ey32.ensure((size_t)B * N * sizeof(c32)))) return rc;
-  // partial buffers for the narrowest column tiles (variant 0: the most tiles), whatever the current choice
-  const int tiles = std::max(line_tiles_variant(N, true, true, 0), line_tiles_variant(N, true, false, 0));
+  // partial buffers for the narrowest column tiles (the most tiles), whatever the current choice
+  const int tiles = std::max(line_tiles_max(N, true, true), line_tiles_max(N, true, false));
   const int rtiles = std::max(line_tiles(N, false, true), line_tiles(N, false, false));
   if ((rc = part_mom.ensure((size_t)B * 2 * kNMom * std::max(tiles, rtiles) * sizeof(double)))) return rc;
   if ((rc = part_vec.ensure((size_t)B * (kMaxRestart + 2) * std::max(vec_blocks(n), rtiles) * sizeof(double))))

@@ -19,9 +19,12 @@ def relerr(a, b):
     return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
 
 
-@pytest.mark.parametrize("N", [64, 256, 1024])
+@pytest.mark.parametrize("N", [64, 256, 1024, 4096])
 def test_tile_variants_agree(N):
-    L = max(1.0, N / 32.0) if N < 1024 else 5.0
+    """Every column-tile width (the default, the wider ones, the half-width one) gives the oracle's operator in FP64
+    and FP32, and the same mixed solves."""
+    L = max(1.0, N / 32.0) if N < 1024 else (5.0 if N == 1024 else 8.0)
+    print(f"tile variants N={N}", flush=True)
     g = O.make_grid(N, L)
     rng = np.random.default_rng(N)
     Q = W.potential_gaussian_sum(N, L, seed=N)
@@ -36,12 +39,12 @@ def test_tile_variants_agree(N):
                 D.set_tile(N, prec, v)
                 assert D.get_tile(N, prec)[0] == v
                 assert relerr(D.apply(Q, k, S, L, precision=prec), ref) < tol, (prec, v)
-        ks = W.k_disk(4, 1.5, seed=N)
+        ks = W.k_disk(4 if N < 4096 else 2, 1.5, seed=N)
         base = None
         for v in range(D.get_tile(N, D.DBAR_FP32)[2]):
             D.set_tile(N, D.DBAR_FP32, v)
             D.set_tile(N, D.DBAR_FP64, min(v, D.get_tile(N, D.DBAR_FP64)[2] - 1))
-            Sv, mv, info = D.solve(Q, ks, L, tol=1e-12, batch=4, precision=D.DBAR_MIXED)
+            Sv, mv, info = D.solve(Q, ks, L, tol=1e-12, batch=len(ks), precision=D.DBAR_MIXED, want_m=N < 4096)
             assert all(i.status == 0 for i in info)
             if base is None:
                 base = Sv
