@@ -256,11 +256,13 @@ def serving_leg(D, W, n_req: int) -> dict:
     burst = W.serving_stream(32, rate=1.0, seed=50)
     stream = W.serving_stream(n_req, rate=1.0, seed=5)
     with D.Session(max_slots=64) as s:
-        t0 = time.perf_counter()
-        tk = [s.submit(r.Q, r.k, r.L, tol=r.tol) for r in burst]
-        for t in tk:
-            s.wait(t)
-        capacity = len(burst) / (time.perf_counter() - t0)
+        # the first burst warms the session (grid-class workspaces, pinned staging blocks); the second one measures
+        for rep in range(2):
+            t0 = time.perf_counter()
+            tk = [s.submit(r.Q, r.k, r.L, tol=r.tol) for r in burst]
+            for t in tk:
+                s.wait(t)
+            capacity = len(burst) / (time.perf_counter() - t0)
         rate = 0.8 * capacity
         # rescale the unit-rate arrival times to the target rate
         arrivals = [r.t_arrival / rate for r in stream]

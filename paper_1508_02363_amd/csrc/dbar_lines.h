@@ -555,15 +555,29 @@ DBAR_D c64 g_poly(const c64* __restrict__ c, c64 w) {
   return g;
 }
 
+// Per-entry data of the regularised division, read once per block: the grid offsets (o1, o2) of the regularisation
+// point a and the coefficients c_0..c_kMaxM of G with R(0) in slot kMaxM+1.  Read in a loop over the block's
+// elements through the arguments instead, every iteration would reload them (a store in the loop may alias them).
+struct RegPre {
+  int o1, o2;
+  c64 c[kNMom];
+};
+DBAR_D void regularised_pre(const LineArgs& a, int b, RegPre& p) {
+  p.o1 = a.shv ? a.shv[2 * b] : 0;
+  p.o2 = a.shv ? a.shv[2 * b + 1] : 0;
+  const c64* c = a.coefG + (size_t)b * kNMom;
+#pragma unroll
+  for (int n = 0; n < kNMom; ++n) p.c[n] = c[n];
+}
+
 // R = (S - G)/xi (R(0) from coefG slot kMaxM+1), then out = IFFT_rows(phase * ci * R)
 // phase * ci * (S - G)/xi at (row, pos) of entry b, S = sv there (R(0) = coefG slot kMaxM+1 at xi = a)
 template <typename T, int N>
-DBAR_D cx<T> regularised(const LineArgs& a, int b, int row, int pos, cx<T> sv) {
-  const c64* __restrict__ c = a.coefG + (size_t)b * kNMom;
+DBAR_D cx<T> regularised(const LineArgs& a, const RegPre& p, int row, int pos, cx<T> sv) {
+  const c64* c = p.c;
   // xi - a with a = 2i conj(k) on the grid (not reduced modulo the period: the quotient only jumps at the edge),
   // as integer wave numbers: L^2 |xi - a|^2 = m1^2 + m2^2 exactly
-  const int o1 = a.shv ? a.shv[2 * b] : 0, o2 = a.shv ? a.shv[2 * b + 1] : 0;
-  const int m1 = wavenum(pos, N) - o1, m2 = wavenum(row, N) - o2;
+  const int m1 = wavenum(pos, N) - p.o1, m2 = wavenum(row, N) - p.o2;
   const int q = m1 * m1 + m2 * m2;
   const double f = ((row + pos) & 1) ? -a.ci : a.ci;
   if (q == 0) return cvt<T>(f * c[kMaxM + 1]);
@@ -594,7 +608,9 @@ struct OpRowsInvRegular : OpBase<T, N> {
   static constexpr bool TWO = false;
   using Acc = NoAcc;
   DBAR_D cx<T> load(int b, int row, int pos) const {
-    return regularised<T, N>(this->a, b, row, pos, this->inp(b)[(size_t)row * N + pos]);
+    RegPre p;
+    regularised_pre(this->a, b, p);
+    return regularised<T, N>(this->a, p, row, pos, this->inp(b)[(size_t)row * N + pos]);
   }
   DBAR_D void store(Acc&, int b, int row, int pos, cx<T> v) const { this->outp(b)[(size_t)row * N + pos] = v; }
 };
@@ -609,14 +625,19 @@ struct OpColsFwdRegInv : OpBase<T, N> {
   static constexpr bool ROLLED = true;
   using Acc = NoAcc;
   DBAR_D cx<T> load(int b, int col, int pos) const { return this->inp(b)[(size_t)pos * N + col]; }
+  static constexpr bool PRE = true;
+  using Pre = RegPre;
+  DBAR_D void prologue(int b, Pre& p) const { regularised_pre(this->a, b, p); }
   template <class A>
-  DBAR_D void mid(int b, int col, int pos, cx<T>& v) const {
+  DBAR_D void mid(int b, int col, int pos, cx<T>& v, const Pre& p) const {
     const T f = static_cast<T>(((col + pos) & 1) ? -this->a.cf : this->a.cf);
     const cx<T> S = f * v;
     if (this->a.sout) (static_cast<cx<T>*>(this->a.sout) + (size_t)b * this->a.sout_bs)[(size_t)pos * N + col] = S;
-    v = regularised<T, N>(this->a, b, pos, col, S);  // row = xi2 index (pos), position = xi1 index (col)
+    v = regularised<T, N>(this->a, p, pos, col, S);  // row = xi2 index (pos), position = xi1 index (col)
   }
-  DBAR_D void store(Acc&, int b, int col, int pos, cx<T> v) const { this->outp(b)[(size_t)pos * N + col] = v; }
+  DBAR_D void store(Acc&, int b, int col, int pos, cx<T> v, const Pre&) const {
+    this->outp(b)[(size_t)pos * N + col] = v;
+  }
 };
 
 // r = IFFT_cols(in); h = r + tail; [hout = h]; u = q_k conj(h); out = FFT_cols(u)   (TAILONLY: stop after hout)

@@ -37,17 +37,70 @@ namespace dbar {
 
 using Clock = std::chrono::steady_clock;
 
+// Pinned host blocks, recycled per size: a request's potential is staged in one (so its upload is a DMA from pinned
+// memory) and its results land in another (S, m and the GMRES record, copied from the device without blocking the
+// worker's next cycle); dbar_poll copies the results out and returns both blocks.
+struct PinnedPool {
+  std::mutex mu;
+  std::map<size_t, std::vector<void*>> free_blocks;
+  void* get(size_t bytes) {
+    {
+      std::lock_guard<std::mutex> lock(mu);
+      auto& v = free_blocks[bytes];
+      if (!v.empty()) {
+        void* p = v.back();
+        v.pop_back();
+        return p;
+      }
+    }
+    void* p = nullptr;
+    if (hipHostMalloc(&p, bytes, hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    return p;
+  }
+  void put(void* p, size_t bytes) {
+    if (!p) return;
+    std::lock_guard<std::mutex> lock(mu);
+    free_blocks[bytes].push_back(p);
+  }
+  ~PinnedPool() {
+    for (auto& kv : free_blocks)
+      for (void* p : kv.second) (void)hipHostFree(p);
+  }
+};
+
 struct SReq {
   uint64_t ticket = 0;
   dbar_grid grid{};
   double k[2] = {0, 0};
   double tol = 1e-10;
-  std::vector<c64> Q, S, m;
+  PinnedPool* pool = nullptr;
+  c64* Q = nullptr;     // pinned: the potential (N*N)
+  void* res = nullptr;  // pinned: S (N*N), m (N*N), then the GMRES record
   dbar_info info{};
+  std::string err_msg;  // why the request ended with an error status
   int state = 0;  // 0 queued, 1 in flight, 2 done
   int iters = 0;
   size_t footprint = 0;
   Clock::time_point t_submit, t_done;
+  size_t n() const { return (size_t)grid.n * grid.n; }
+  size_t q_bytes() const { return n() * sizeof(c64); }
+  size_t res_bytes() const { return 2 * n() * sizeof(c64) + sizeof(Ctl); }
+  ~SReq() {
+    if (pool) {
+      pool->put(Q, q_bytes());
+      pool->put(res, res_bytes());
+    }
+  }
+};
+
+// Results of finished slots on their way to the host: the copies run on the class's copy stream while the next cycle
+// computes; the slots are admitted to again once `done` has completed.
+struct Draining {
+  hipEvent_t done = nullptr;
+  std::vector<int> slots;
 };
 
 struct SClass {
@@ -67,6 +120,9 @@ struct SClass {
   std::vector<int> h_new, h_live;
   std::vector<double> h_tol;
   std::vector<c64> h_k;  // per-slot k (host source of the async upload; stable until the stream synchronises)
+  hipStream_t copy_stream = nullptr;  // result copies (device to pinned host), overlapping the next cycle
+  hipEvent_t ev_results = nullptr;    // recorded on `stream` after a cycle: the finished slots' results are final
+  std::deque<Draining> draining;
   bool ready = false;
   int error = 0;
   bool finished = false;  // the worker has returned: its thread can be joined
@@ -75,6 +131,8 @@ struct SClass {
 }  // namespace dbar
 
 struct dbar_session {
+  // first member: destroyed last, after every request that returns its pinned blocks to it
+  dbar::PinnedPool pool;
   dbar_session_opts o{};
   size_t budget = 0, allocated = 0;
   int device = 0;
@@ -115,7 +173,9 @@ static int class_init(SClass& c) {
   if ((rc = c.w.Sx.ensure(nb)) || (rc = c.w.mx.ensure(nb))) return rc;
   if ((rc = c.newmask.ensure(c.cap * sizeof(int)))) return rc;
   if ((rc = c.tolv.ensure(c.cap * sizeof(double)))) return rc;
-  if (hipStreamCreateWithFlags(&c.stream, hipStreamNonBlocking) != hipSuccess)
+  if (hipStreamCreateWithFlags(&c.stream, hipStreamNonBlocking) != hipSuccess ||
+      hipStreamCreateWithFlags(&c.copy_stream, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&c.ev_results, hipEventDisableTiming) != hipSuccess)
     return fail(DBAR_EDEVICE, "stream creation failed");
   c.slots.assign(c.cap, nullptr);
   c.h_new.assign(c.cap, 0);
@@ -143,13 +203,24 @@ static void detach_class(dbar_session* s, SClass& c) {
 
 // The worker of a detached class: free its device memory, then return its reservation to the budget and admit what
 // the pending queue can now hold.
-static void release_class(dbar_session* s, SClass& c) {
+static void destroy_streams(SClass& c) {
   if (c.stream) (void)hipStreamSynchronize(c.stream);
+  if (c.copy_stream) (void)hipStreamSynchronize(c.copy_stream);
+  for (auto& d : c.draining)
+    if (d.done) (void)hipEventDestroy(d.done);
+  c.draining.clear();
+  if (c.ev_results) (void)hipEventDestroy(c.ev_results);
+  if (c.stream) (void)hipStreamDestroy(c.stream);
+  if (c.copy_stream) (void)hipStreamDestroy(c.copy_stream);
+  c.ev_results = nullptr;
+  c.stream = c.copy_stream = nullptr;
+}
+
+static void release_class(dbar_session* s, SClass& c) {
+  destroy_streams(c);
   c.w = Work();
   c.newmask = DevBuf();
   c.tolv = DevBuf();
-  if (c.stream) (void)hipStreamDestroy(c.stream);
-  c.stream = nullptr;
   {
     std::lock_guard<std::mutex> lock(s->mu);
     s->allocated -= (size_t)c.cap * c.footprint;
@@ -160,6 +231,53 @@ static void release_class(dbar_session* s, SClass& c) {
   }
   s->cv_work.notify_all();
   s->cv_done.notify_all();
+}
+
+// Hand slot b's request back (under s->mu): its info from the GMRES record in its result block (status: the
+// convergence set at the cycle end, or `err`), the slot free for admission.
+static void finish_slot(dbar_session* s, SClass& c, int b, int err, const char* why = "") {
+  auto r = c.slots[b];
+  if (err != DBAR_OK) r->err_msg = why;
+  if (err == DBAR_OK && r->res) {
+    const c64* S = static_cast<const c64*>(r->res);
+    Ctl cc;
+    std::memcpy(&cc, S + 2 * r->n(), sizeof(Ctl));
+    r->info.iters = cc.iters;
+    r->info.outer = cc.cycles;
+    r->info.rel_residual = cc.bnorm > 0.0 ? cc.rnorm / cc.bnorm : 0.0;
+    r->info.cond_estimate = cc.kappa;
+    r->info.err_estimate = cc.kappa * r->info.rel_residual;
+    r->info.m1_re = -S[0].im;  // m1 = i S(0)
+    r->info.m1_im = S[0].re;
+  } else {
+    r->info.status = err == DBAR_OK ? DBAR_EDEVICE : err;
+  }
+  r->state = 2;
+  r->t_done = Clock::now();
+  c.slots[b] = nullptr;
+  s->st.in_flight -= 1;
+  s->st.completed += 1;
+  s->st.bytes_in_use -= r->footprint;
+}
+
+// Requests whose result copies have completed, oldest first (wait: block until all have).
+static void complete_copies(dbar_session* s, SClass& c, bool wait) {
+  bool any = false;
+  while (!c.draining.empty()) {
+    Draining& d = c.draining.front();
+    const hipError_t e = wait ? hipEventSynchronize(d.done) : hipEventQuery(d.done);
+    if (e == hipErrorNotReady) break;
+    {
+      std::lock_guard<std::mutex> lock(s->mu);
+      for (int b : d.slots)
+        finish_slot(s, c, b, e == hipSuccess ? DBAR_OK : DBAR_EDEVICE,
+                    e == hipSuccess ? "" : "the copy of the results to the host failed");
+    }
+    (void)hipEventDestroy(d.done);
+    c.draining.pop_front();
+    any = true;
+  }
+  if (any) s->cv_done.notify_all();
 }
 
 static void worker(dbar_session* s, SClass* cp) {
@@ -174,6 +292,7 @@ static void worker(dbar_session* s, SClass* cp) {
       for (auto& r : c.queue) {
         r->state = 2;
         r->info.status = rc;
+        r->err_msg = "the serving worker for this grid could not set up: " + g_last_error;
         r->t_done = Clock::now();
         s->st.queued -= 1;
       }
@@ -196,15 +315,18 @@ static void worker(dbar_session* s, SClass* cp) {
   cfg.check_every = 4;
   cfg.inner_tol = 1e-6;  // x-space inner solves
   cfg.orth_window = kDefaultOrthWindow;
-  cfg.use_graph = 1;     // Krylov step groups replayed from graphs captured per class (its own workspace and stream)
+  // direct launches: a stream capture in one worker thread makes calls of the other workers (pinned allocations,
+  // event queries, copies) fail with "not permitted when stream is capturing"
+  cfg.use_graph = 0;
   bool retire = false;
   while (!s->stop.load()) {
+    complete_copies(s, c, false);
     // ---- admission at the cycle boundary
     std::vector<int> admitted;
     bool any_live = false;
     {
       std::unique_lock<std::mutex> lock(s->mu);
-      for (int b = 0; b < c.cap; ++b) any_live |= c.slots[b] != nullptr;
+      for (int b = 0; b < c.cap; ++b) any_live |= c.slots[b] != nullptr;  // in flight or draining
       if (!any_live && c.queue.empty()) {
         if (!s->pending.empty()) {  // idle while others wait for budget: release this class
           detach_class(s, c);
@@ -234,8 +356,8 @@ static void worker(dbar_session* s, SClass* cp) {
         c.h_live[b] = 1;
         w.full_host[b] = 0;  // the slot's new solve starts with the Gram-Schmidt window (its device flag: the check)
         c.h_tol[b] = r.tol;
-        (void)hipMemcpyAsync(static_cast<c64*>(w.Q64.p) + (size_t)b * n, r.Q.data(), n * sizeof(c64),
-                             hipMemcpyHostToDevice, c.stream);
+        (void)hipMemcpyAsync(static_cast<c64*>(w.Q64.p) + (size_t)b * n, r.Q, n * sizeof(c64), hipMemcpyHostToDevice,
+                             c.stream);
         c.h_k[b] = c64{r.k[0], r.k[1]};
         (void)hipMemcpyAsync(static_cast<c64*>(w.kvals.p) + b, &c.h_k[b], sizeof(c64), hipMemcpyHostToDevice,
                              c.stream);
@@ -255,6 +377,12 @@ static void worker(dbar_session* s, SClass* cp) {
                     static_cast<double*>(w.nred.p), c.cap, nm, c.stream);
       launch_ctl_check(w, 0.0, 1, nm, static_cast<const double*>(c.tolv.p), c.stream);
       launch_zero_done(w, nm, false, c.stream);  // admitted requests with b = 0: S = m = 0
+    }
+    bool computing = false;
+    for (int b = 0; b < c.cap; ++b) computing |= c.h_live[b] != 0;
+    if (!computing) {  // only slots whose results are still on their way to the host
+      complete_copies(s, c, true);
+      continue;
     }
     // ---- one Krylov cycle for everything in flight
     launch_ctl_start(w, mixed ? 0.3 : 0.5, mixed ? cfg.inner_tol : 0.0, static_cast<const double*>(c.tolv.p),
@@ -278,6 +406,7 @@ static void worker(dbar_session* s, SClass* cp) {
         if (r) {
           r->state = 2;
           r->info.status = DBAR_EDEVICE;
+          r->err_msg = std::string("the serving worker's stream failed: ") + hipGetErrorString(hipGetLastError());
           r->t_done = Clock::now();
         }
       s->cv_done.notify_all();
@@ -298,44 +427,45 @@ static void worker(dbar_session* s, SClass* cp) {
     }
     if (fin.empty()) continue;
     (void)hipMemcpyAsync(w.live.p, c.h_live.data(), c.cap * sizeof(int), hipMemcpyHostToDevice, c.stream);
-    std::vector<Ctl> ctl_out(fin.size());
-    for (size_t i = 0; i < fin.size(); ++i) {
+    // the finished slots' S, m (the last residual evaluation's) and GMRES records go to pinned blocks on the copy
+    // stream; the next cycle does not write them (the slots are not live) and starts at once
+    Draining d;
+    d.slots = fin;
+    bool ok = hipEventRecord(c.ev_results, c.stream) == hipSuccess &&
+              hipStreamWaitEvent(c.copy_stream, c.ev_results, 0) == hipSuccess &&
+              hipEventCreateWithFlags(&d.done, hipEventDisableTiming) == hipSuccess;
+    int err = DBAR_EDEVICE;
+    const char* why = "queueing the result copies failed";
+    for (size_t i = 0; i < fin.size() && ok; ++i) {
       const int b = fin[i];
       SReq& r = *c.slots[b];
-      r.S.resize(n);
-      r.m.resize(n);
-      (void)hipMemcpyAsync(r.S.data(), static_cast<c64*>(w.Sx.p) + (size_t)b * n, n * sizeof(c64),
-                           hipMemcpyDeviceToHost, c.stream);
-      (void)hipMemcpyAsync(r.m.data(), static_cast<c64*>(w.mx.p) + (size_t)b * n, n * sizeof(c64),
-                           hipMemcpyDeviceToHost, c.stream);
-      (void)hipMemcpyAsync(&ctl_out[i], static_cast<Ctl*>(w.ctl.p) + b, sizeof(Ctl), hipMemcpyDeviceToHost,
-                           c.stream);
-    }
-    const bool ok = hipStreamSynchronize(c.stream) == hipSuccess;
-    {
-      std::lock_guard<std::mutex> lock(s->mu);
-      for (size_t i = 0; i < fin.size(); ++i) {
-        const int b = fin[i];
-        auto r = c.slots[b];
-        const Ctl& cc = ctl_out[i];
-        r->info.iters = cc.iters;
-        r->info.outer = cc.cycles;
-        r->info.rel_residual = cc.bnorm > 0.0 ? cc.rnorm / cc.bnorm : 0.0;
-        r->info.cond_estimate = cc.kappa;
-        r->info.err_estimate = cc.kappa * r->info.rel_residual;
-        r->info.m1_re = ok ? -r->S[0].im : 0.0;
-        r->info.m1_im = ok ? r->S[0].re : 0.0;
-        if (!ok) r->info.status = DBAR_EDEVICE;
-        r->state = 2;
-        r->t_done = Clock::now();
-        c.slots[b] = nullptr;
-        s->st.in_flight -= 1;
-        s->st.completed += 1;
-        s->st.bytes_in_use -= r->footprint;
+      r.res = s->pool.get(r.res_bytes());
+      if (!r.res) {
+        ok = false;
+        err = DBAR_ENOMEM;
+        why = "pinned host memory for the results could not be allocated";
+        break;
       }
+      c64* S = static_cast<c64*>(r.res);
+      ok = hipMemcpyAsync(S, static_cast<c64*>(w.Sx.p) + (size_t)b * n, n * sizeof(c64), hipMemcpyDeviceToHost,
+                          c.copy_stream) == hipSuccess &&
+           hipMemcpyAsync(S + n, static_cast<c64*>(w.mx.p) + (size_t)b * n, n * sizeof(c64), hipMemcpyDeviceToHost,
+                          c.copy_stream) == hipSuccess &&
+           hipMemcpyAsync(S + 2 * n, static_cast<Ctl*>(w.ctl.p) + b, sizeof(Ctl), hipMemcpyDeviceToHost,
+                          c.copy_stream) == hipSuccess;
     }
-    s->cv_done.notify_all();
+    ok = ok && hipEventRecord(d.done, c.copy_stream) == hipSuccess;
+    if (!ok) {  // no pinned memory or a runtime error: these requests end with an error
+      (void)hipStreamSynchronize(c.copy_stream);
+      if (d.done) (void)hipEventDestroy(d.done);
+      std::lock_guard<std::mutex> lock(s->mu);
+      for (int b : fin) finish_slot(s, c, b, err, why);
+      s->cv_done.notify_all();
+      continue;
+    }
+    c.draining.push_back(d);
   }
+  complete_copies(s, c, true);
   if (retire) release_class(s, c);
 }
 
@@ -435,8 +565,10 @@ int dbar_submit(dbar_session* s, const dbar_grid* grid, const double* Q, const d
   r->k[0] = k[0];
   r->k[1] = k[1];
   r->tol = tol;
-  r->Q.resize(n);
-  std::memcpy(r->Q.data(), Q, n * sizeof(c64));
+  r->pool = &s->pool;
+  r->Q = static_cast<c64*>(s->pool.get(r->q_bytes()));
+  if (!r->Q) return fail(DBAR_ENOMEM, "pinned host memory for the request's potential could not be allocated");
+  std::memcpy(r->Q, Q, n * sizeof(c64));
   r->footprint = footprint_of(grid->n, s->o.precision, s->o.restart, 1);
   r->t_submit = Clock::now();
   std::lock_guard<std::mutex> lock(s->mu);
@@ -456,39 +588,54 @@ int dbar_submit(dbar_session* s, const dbar_grid* grid, const double* Q, const d
   return DBAR_OK;
 }
 
-static int take_result(dbar_session* s, std::unordered_map<uint64_t, std::shared_ptr<SReq>>::iterator it,
-                       double* S_out, double* m_out, dbar_info* info, double* latency_s) {
-  auto r = it->second;
-  const size_t n = r->S.size();
-  if (S_out && n) std::memcpy(S_out, r->S.data(), n * sizeof(c64));
-  if (m_out && n) std::memcpy(m_out, r->m.data(), n * sizeof(c64));
+// Copy a finished request's results out (outside the session lock: up to two N x N arrays) and report its status.
+static int deliver(const std::shared_ptr<SReq>& r, double* S_out, double* m_out, dbar_info* info, double* latency_s) {
+  const size_t n = r->n();
+  if (r->res) {
+    const c64* S = static_cast<const c64*>(r->res);
+    if (S_out) std::memcpy(S_out, S, n * sizeof(c64));
+    if (m_out) std::memcpy(m_out, S + n, n * sizeof(c64));
+  }
   if (info) *info = r->info;
   if (latency_s) *latency_s = std::chrono::duration<double>(r->t_done - r->t_submit).count();
-  s->reqs.erase(it);
   const int st = r->info.status;
   if (st == DBAR_OK || st == DBAR_ENOCONV) return st;
-  return fail(st, st == DBAR_ENOMEM ? "the serving worker could not allocate its workspace"
-                                    : "device failure in the serving worker");
+  return fail(st, !r->err_msg.empty() ? r->err_msg
+                                      : std::string(st == DBAR_ENOMEM ? "the serving worker could not allocate its workspace"
+                                                                      : "device failure in the serving worker"));
 }
 
 int dbar_poll(dbar_session* s, uint64_t ticket, double* S_out, double* m_out, dbar_info* info, double* latency_s) {
   if (!s) return fail(DBAR_EINVAL, "session is NULL");
-  std::lock_guard<std::mutex> lock(s->mu);
-  auto it = s->reqs.find(ticket);
-  if (it == s->reqs.end()) return fail(DBAR_ENOTFOUND, "unknown ticket");
-  if (it->second->state != 2) return DBAR_EAGAIN;
-  return take_result(s, it, S_out, m_out, info, latency_s);
+  std::shared_ptr<SReq> r;
+  {
+    std::lock_guard<std::mutex> lock(s->mu);
+    auto it = s->reqs.find(ticket);
+    if (it == s->reqs.end()) return fail(DBAR_ENOTFOUND, "unknown ticket");
+    if (it->second->state != 2) return DBAR_EAGAIN;
+    r = it->second;
+    s->reqs.erase(it);
+  }
+  return deliver(r, S_out, m_out, info, latency_s);
 }
 
 int dbar_wait(dbar_session* s, uint64_t ticket, double* S_out, double* m_out, dbar_info* info, double* latency_s) {
   if (!s) return fail(DBAR_EINVAL, "session is NULL");
-  std::unique_lock<std::mutex> lock(s->mu);
-  while (true) {
-    auto it = s->reqs.find(ticket);
-    if (it == s->reqs.end()) return fail(DBAR_ENOTFOUND, "unknown ticket");
-    if (it->second->state == 2) return take_result(s, it, S_out, m_out, info, latency_s);
-    s->cv_done.wait_for(lock, std::chrono::milliseconds(50));
+  std::shared_ptr<SReq> r;
+  {
+    std::unique_lock<std::mutex> lock(s->mu);
+    while (true) {
+      auto it = s->reqs.find(ticket);
+      if (it == s->reqs.end()) return fail(DBAR_ENOTFOUND, "unknown ticket");
+      if (it->second->state == 2) {
+        r = it->second;
+        s->reqs.erase(it);
+        break;
+      }
+      s->cv_done.wait_for(lock, std::chrono::milliseconds(50));
+    }
   }
+  return deliver(r, S_out, m_out, info, latency_s);
 }
 
 int dbar_session_get_stats(dbar_session* s, dbar_session_stats* st) {
@@ -512,10 +659,8 @@ void dbar_session_destroy(dbar_session* s) {
   }
   for (SClass* c : all)
     if (c->th.joinable()) c->th.join();
-  for (auto& kv : s->classes)
-    if (kv.second->stream) (void)hipStreamDestroy(kv.second->stream);
-  for (auto& c : s->retired)
-    if (c->stream) (void)hipStreamDestroy(c->stream);
+  for (auto& kv : s->classes) destroy_streams(*kv.second);
+  for (auto& c : s->retired) destroy_streams(*c);
   delete s;
 }
 

@@ -22,6 +22,7 @@ constexpr int kMaxRestart = 64;
 constexpr int kDefaultOrthWindow = 2;
 
 int fail(int code, const std::string& msg);
+extern thread_local std::string g_last_error;  // the calling thread's last message (dbar_last_error)
 
 // Owning device allocation that only grows.
 struct DevBuf {
