@@ -72,6 +72,13 @@ DBAR_D TT inv_int(int j) {
   else return kInv.f[j];
 }
 
+// Index of element (row, col) of the x-space operator's transform array (LineArgs::t_log)
+template <int N>
+DBAR_D size_t t_index(int row, int col, int t_log) {
+  if (t_log < 0) return (size_t)row * N + col;
+  return (((size_t)(col >> t_log) * N + row) << t_log) + (col & ((1 << t_log) - 1));
+}
+
 // x_j = L(-pi + 2 pi j / N)
 template <int N>
 DBAR_D double xgrid(int j, double L) {
@@ -543,7 +550,9 @@ struct OpRowsFwdMoments : MomentsBase<T, N, true> {
     }
     this->add_loaded(acc, b, row, jt, v);
   }
-  DBAR_D void store(Acc&, int b, int row, int pos, cx<T> v) const { this->outp(b)[(size_t)row * N + pos] = v; }
+  DBAR_D void store(Acc&, int b, int row, int pos, cx<T> v) const {
+    this->outp(b)[t_index<N>(row, pos, this->a.t_log)] = v;
+  }
 };
 
 // sum_{n <= MM} c_n w^n by Horner's rule
@@ -624,7 +633,7 @@ struct OpColsFwdRegInv : OpBase<T, N> {
   static constexpr bool TWO = true;
   static constexpr bool ROLLED = true;
   using Acc = NoAcc;
-  DBAR_D cx<T> load(int b, int col, int pos) const { return this->inp(b)[(size_t)pos * N + col]; }
+  DBAR_D cx<T> load(int b, int col, int pos) const { return this->inp(b)[t_index<N>(pos, col, this->a.t_log)]; }
   static constexpr bool PRE = true;
   using Pre = RegPre;
   DBAR_D void prologue(int b, Pre& p) const { regularised_pre(this->a, b, p); }
@@ -636,7 +645,7 @@ struct OpColsFwdRegInv : OpBase<T, N> {
     v = regularised<T, N>(this->a, p, pos, col, S);  // row = xi2 index (pos), position = xi1 index (col)
   }
   DBAR_D void store(Acc&, int b, int col, int pos, cx<T> v, const Pre&) const {
-    this->outp(b)[(size_t)pos * N + col] = v;
+    this->outp(b)[t_index<N>(pos, col, this->a.t_log)] = v;
   }
 };
 
@@ -773,7 +782,7 @@ struct OpRowsInvTailEpi : OpColsInvTail<T, N, false> {
     double v[1];
     double sdot;  // Re<S, out> over this thread's elements (S is the last vector of the fused products)
   };
-  DBAR_D cx<T> load(int b, int row, int pos) const { return this->inp(b)[(size_t)row * N + pos]; }
+  DBAR_D cx<T> load(int b, int row, int pos) const { return this->inp(b)[t_index<N>(row, pos, this->a.t_log)]; }
   // The stores run GROUP elements at a time: the group's global reads (q, the x factor of e_k, S, Y) are issued
   // together ahead of its tails.  The LDS slot of each element (the row transform's output r) is replaced by the
   // stored value, for the Gram-Schmidt products.
