@@ -112,9 +112,10 @@ typedef struct {
   double m1_re, m1_im;  /* m^(1) = i S(0), the 1/z coefficient of m (equation m1def); 0 from dbar_reflection and
                            dbar_reconstruct, which do not form S */
   double cond_estimate; /* estimate of the condition number of A from the Krylov iteration: sigma_max / sigma_min of
-                           the (upper-triangular factor of the) Hessenberg matrix of the longest GMRES cycle of this
-                           solve (Section 4.1).  Its singular values lie inside A's, so it estimates cond(A) from
-                           below; 0 when no cycle ran (b = 0) */
+                           the (upper-triangular factor of the) Hessenberg matrix of the solve's first GMRES cycle
+                           (Section 4.1; the cycle from S = 0, normally the longest; serving requests: their longest
+                           cycle).  Its singular values lie inside A's, so it estimates cond(A) from below; 0 when no
+                           cycle ran (b = 0) */
   double err_estimate;  /* cond_estimate * rel_residual: an estimate (not a bound) of the relative 2-norm error of S
                            against the exact solution of the discrete system, i.e. against an FP64 solve to a tighter
                            tolerance.  Since cond_estimate can fall short of cond(A), so can this */

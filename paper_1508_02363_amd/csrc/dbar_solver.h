@@ -311,9 +311,10 @@ int ctl_blocks(int B);
 // one lockstep Krylov cycle over the entries flagged in w.act; returns the iterations run
 template <typename T>
 int krylov_cycle(const Pipeline& P, Work& w, const BatchCfg& cfg, int it_budget, hipStream_t s);
-// solution update from the cycle and the FP64 residual r = b - A(x) into r_out (norms into w.nred)
+// solution update from the cycle and the FP64 residual r = b - A(x) into r_out (norms into w.nred); cond: also the
+// condition estimate of the entries whose cycle was their longest so far
 template <typename T>
-void end_cycle(const Pipeline& P, Work& w, int nv, void* r_out, hipStream_t s, int method = 0);
+void end_cycle(const Pipeline& P, Work& w, int nv, void* r_out, hipStream_t s, int method = 0, bool cond = true);
 // condition estimate of each live entry from its last cycle's Hessenberg factor, where that cycle is the longest so far
 void launch_cond_estimate(Work& w, hipStream_t s);
 // residual check (first = 1: record ||b|| and reset the counters of the entries in mask); tolv: per-entry tol

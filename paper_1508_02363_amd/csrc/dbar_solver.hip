@@ -1229,13 +1229,13 @@ int krylov_cycle(const Pipeline& P, Work& w, const BatchCfg& cfg, int it_budget,
 
 // x += sum coef_i V_i and the FP64 residual r = b - A(x) (into r_out), with squared norms in nred
 template <typename T>
-void end_cycle(const Pipeline& P, Work& w, int nv, void* r_out, hipStream_t s, int method) {
+void end_cycle(const Pipeline& P, Work& w, int nv, void* r_out, hipStream_t s, int method, bool cond) {
   const int B = w.B;
   const size_t n = w.n;
   Ctl* ctl = static_cast<Ctl*>(w.ctl.p);
   int* live = static_cast<int*>(w.live.p);
   hipLaunchKernelGGL(k_ctl_trisolve, dim3(ctl_blocks(B)), dim3(64), 0, s, ctl, live, B);
-  launch_cond_estimate(w, s);
+  if (cond) launch_cond_estimate(w, s);
   VecArgs va;
   va.B = B;
   va.act = live;
@@ -1301,8 +1301,8 @@ void end_cycle(const Pipeline& P, Work& w, int nv, void* r_out, hipStream_t s, i
 
 template int krylov_cycle<float>(const Pipeline&, Work&, const BatchCfg&, int, hipStream_t);
 template int krylov_cycle<double>(const Pipeline&, Work&, const BatchCfg&, int, hipStream_t);
-template void end_cycle<float>(const Pipeline&, Work&, int, void*, hipStream_t, int);
-template void end_cycle<double>(const Pipeline&, Work&, int, void*, hipStream_t, int);
+template void end_cycle<float>(const Pipeline&, Work&, int, void*, hipStream_t, int, bool);
+template void end_cycle<double>(const Pipeline&, Work&, int, void*, hipStream_t, int, bool);
 
 void launch_cond_estimate(Work& w, hipStream_t s) {
   TimerScope ts(kStageControl, 0.0, w.B, nullptr, s);
@@ -1390,12 +1390,13 @@ int run_batch(const Pipeline& P, Work& w, const BatchCfg& cfg, hipStream_t s, st
     const double abs_tol = mixed ? 0.3 * cfg.tol : 0.5 * cfg.tol;
     hipLaunchKernelGGL(k_ctl_start, dim3(ctl_blocks(B)), dim3(64), 0, s, ctl, nred, live, act, abs_tol, rel, nullptr, B);
     int ran;
+    // the condition estimate is taken from the first cycle (from x = 0: the longest, every entry in it)
     if (mixed) {
       ran = krylov_cycle<float>(P, w, cfg, cfg.max_iter - total, s);
-      end_cycle<float>(P, w, ran, w.r64.p, s, cfg.method);
+      end_cycle<float>(P, w, ran, w.r64.p, s, cfg.method, total == 0);
     } else {
       ran = krylov_cycle<double>(P, w, cfg, cfg.max_iter - total, s);
-      end_cycle<double>(P, w, ran, w.V.p, s, cfg.method);
+      end_cycle<double>(P, w, ran, w.V.p, s, cfg.method, total == 0);
     }
     total += ran;
     hipLaunchKernelGGL(k_ctl_check, dim3(ctl_blocks(B)), dim3(64), 0, s, ctl, nred, live, act, cfg.tol, 0, nullptr,
