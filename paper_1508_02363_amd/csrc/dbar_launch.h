@@ -58,10 +58,6 @@ struct LineArgs {
   c64 beta{0.0, 0.0};
   int want_norm = 0;           // RowsFwdEpilogue, RowsInvTailEpilogue: accumulate |out|^2 partials
   int tile = 0;                // column stages: tile width variant (see tile_columns)
-  // Layout of the x-space operator's transform array (the `out` of RowsFwdMoments, in and out of ColsFwdRegularInv,
-  // the `in` of RowsInvTailEpilogue): t_log < 0 row-major; else column-tile-major with tiles of 2^t_log columns (the
-  // column launch's tile width), so that each column tile is one contiguous N x 2^t_log block
-  int t_log = -1;
   // RowsFwdEpilogue, RowsInvTailEpilogue: Gram-Schmidt products Re<V_i, out> for i < dot_nv written as per-tile partials
   // dot_part[b][i][tile] (V_i of entry b at dotV + b * dotV_bs + i * N * N, the transform's precision); the last one,
   // V_{dot_nv - 1}, must be the epilogue's S (alpha != 0)

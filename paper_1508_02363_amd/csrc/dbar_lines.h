@@ -72,12 +72,6 @@ DBAR_D TT inv_int(int j) {
   else return kInv.f[j];
 }
 
-// Index of element (row, col) of the x-space operator's transform array (LineArgs::t_log)
-template <int N>
-DBAR_D size_t t_index(int row, int col, int t_log) {
-  if (t_log < 0) return (size_t)row * N + col;
-  return (((size_t)(col >> t_log) * N + row) << t_log) + (col & ((1 << t_log) - 1));
-}
 
 // x_j = L(-pi + 2 pi j / N)
 template <int N>
@@ -254,6 +248,21 @@ struct Tiling {
   template <int V>
   static constexpr bool cols_valid() { return V < variants(); }
 };
+
+// Index of element (row, col) of the x-space operator's transform array (the output of its first launch, rewritten in
+// place by the column launch, read by the last).  FP32: column-tile-major with tiles of the default column-tile width
+// (Tiling::COLS), each tile one contiguous N x COLS block, so that the column launch reads and writes whole lines and
+// the row launches whole COLS-element pieces; the width is a compile-time constant, so the per-thread addresses keep
+// constant strides.  FP64: row-major (the tiled FP64 array measured slower).
+template <typename T, int N>
+DBAR_D size_t t_index(int row, int col) {
+  if constexpr (sizeof(T) == 8) {
+    return (size_t)row * N + col;
+  } else {
+    constexpr int TW = Tiling<T, N>::COLS;
+    return ((size_t)(col / TW) * N + row) * TW + (col % TW);
+  }
+}
 
 // LDS of one line-kernel block: the line data, or the scratch of its reductions, whichever is larger
 template <typename T, int N, int LINES, bool COLS>
@@ -551,7 +560,7 @@ struct OpRowsFwdMoments : MomentsBase<T, N, true> {
     this->add_loaded(acc, b, row, jt, v);
   }
   DBAR_D void store(Acc&, int b, int row, int pos, cx<T> v) const {
-    this->outp(b)[t_index<N>(row, pos, this->a.t_log)] = v;
+    this->outp(b)[t_index<T, N>(row, pos)] = v;
   }
 };
 
@@ -563,20 +572,26 @@ DBAR_D c64 g_poly(const c64* __restrict__ c, c64 w) {
   for (int n = MM - 1; n >= 0; --n) g = cfma(w, g, c[n]);
   return g;
 }
+// the same in FP32, from the FP32 roundings of the coefficients
+template <int MM>
+DBAR_D c32 g_poly32(const c64* __restrict__ c, c32 w) {
+  c32 g = cvt<float>(c[MM]);
+#pragma unroll
+  for (int n = MM - 1; n >= 0; --n) g = cfma(w, g, cvt<float>(c[n]));
+  return g;
+}
 
-// Per-entry data of the regularised division, read once per block: the grid offsets (o1, o2) of the regularisation
-// point a and the coefficients c_0..c_kMaxM of G with R(0) in slot kMaxM+1.  Read in a loop over the block's
-// elements through the arguments instead, every iteration would reload them (a store in the loop may alias them).
+// Per-entry data of the regularised division: the grid offsets (o1, o2) of the regularisation point a and the entry's
+// coefficients c_0..c_kMaxM of G (R(0) in slot kMaxM+1), read where they are used: only the points near a need them
+// (|xi - a|^2 < 740: 5% of the grid at N = 1024, L = 5), so they are not held in registers across a block's loop.
 struct RegPre {
   int o1, o2;
-  c64 c[kNMom];
+  const c64* c;
 };
 DBAR_D void regularised_pre(const LineArgs& a, int b, RegPre& p) {
   p.o1 = a.shv ? a.shv[2 * b] : 0;
   p.o2 = a.shv ? a.shv[2 * b + 1] : 0;
-  const c64* c = a.coefG + (size_t)b * kNMom;
-#pragma unroll
-  for (int n = 0; n < kNMom; ++n) p.c[n] = c[n];
+  p.c = a.coefG + (size_t)b * kNMom;
 }
 
 // R = (S - G)/xi (R(0) from coefG slot kMaxM+1), then out = IFFT_rows(phase * ci * R)
@@ -591,22 +606,30 @@ DBAR_D cx<T> regularised(const LineArgs& a, const RegPre& p, int row, int pos, c
   const double f = ((row + pos) & 1) ? -a.ci : a.ci;
   if (q == 0) return cvt<T>(f * c[kMaxM + 1]);
   const double invL = 1.0 / a.L;
-  // G in FP64 (conj(xi)^n overflows FP32 for |xi|^n > 3e38), only where e^{-|xi|^2} has not underflowed
-  if (static_cast<float>(q) < static_cast<float>(740.0 * a.L * a.L)) {
-    const double xi1 = m1 * invL, xi2 = m2 * invL;
-    const c64 xib{xi1, -xi2};
-    // unrolled for the order (c_n = 0 beyond M): the coefficient loads are issued together
-    const c64 g = a.M == 11 ? g_poly<11>(c, xib) : g_poly<kMaxM>(c, xib);
-    sv = cvt<T>(cvt<double>(sv) - exp(-(xi1 * xi1 + xi2 * xi2)) * g);
-  }
-  // (S - G) / xi in the transform's precision
   if constexpr (sizeof(T) == 8) {
-    const double t1 = m1 * invL, t2 = m2 * invL, ir2 = f / (t1 * t1 + t2 * t2);
-    return cx<T>{(sv.re * t1 + sv.im * t2) * ir2, (sv.im * t1 - sv.re * t2) * ir2};
+    // G only where e^{-|xi|^2} has not underflowed
+    const double xi1 = m1 * invL, xi2 = m2 * invL, r2 = xi1 * xi1 + xi2 * xi2;
+    if (r2 < 740.0) {
+      // unrolled for the order (c_n = 0 beyond M): the coefficient loads are issued together
+      const c64 xib{xi1, -xi2};
+      const c64 g = a.M == 11 ? g_poly<11>(c, xib) : g_poly<kMaxM>(c, xib);
+      sv = sv - exp(-r2) * g;
+    }
+    const double ir2 = f / r2;
+    return cx<T>{(sv.re * xi1 + sv.im * xi2) * ir2, (sv.im * xi1 - sv.re * xi2) * ir2};
   } else {
+    // The FP32 operator (inner solves) forms G in FP32 too: S is already rounded to FP32, and G's rounding is of the
+    // same size.  e^{-|xi|^2} is zero in FP32 from |xi|^2 = 104 on, so G is formed inside that disc only (|conj(xi)|^n
+    // < 2e11 there, far from FP32 overflow).
     const float il = static_cast<float>(invL);
     const float t1 = static_cast<float>(m1) * il, t2 = static_cast<float>(m2) * il;
-    const float ir2 = static_cast<float>(f) * recip(t1 * t1 + t2 * t2);
+    const float r2 = t1 * t1 + t2 * t2;
+    if (r2 < 104.0f) {
+      const c32 w{t1, -t2};
+      const c32 g = a.M == 11 ? g_poly32<11>(c, w) : g_poly32<kMaxM>(c, w);
+      sv = sv - exp(-r2) * g;
+    }
+    const float ir2 = static_cast<float>(f) * recip(r2);
     return cx<T>{(sv.re * t1 + sv.im * t2) * ir2, (sv.im * t1 - sv.re * t2) * ir2};
   }
 }
@@ -633,7 +656,7 @@ struct OpColsFwdRegInv : OpBase<T, N> {
   static constexpr bool TWO = true;
   static constexpr bool ROLLED = true;
   using Acc = NoAcc;
-  DBAR_D cx<T> load(int b, int col, int pos) const { return this->inp(b)[t_index<N>(pos, col, this->a.t_log)]; }
+  DBAR_D cx<T> load(int b, int col, int pos) const { return this->inp(b)[t_index<T, N>(pos, col)]; }
   static constexpr bool PRE = true;
   using Pre = RegPre;
   DBAR_D void prologue(int b, Pre& p) const { regularised_pre(this->a, b, p); }
@@ -645,7 +668,7 @@ struct OpColsFwdRegInv : OpBase<T, N> {
     v = regularised<T, N>(this->a, p, pos, col, S);  // row = xi2 index (pos), position = xi1 index (col)
   }
   DBAR_D void store(Acc&, int b, int col, int pos, cx<T> v, const Pre&) const {
-    this->outp(b)[t_index<N>(pos, col, this->a.t_log)] = v;
+    this->outp(b)[t_index<T, N>(pos, col)] = v;
   }
 };
 
@@ -782,7 +805,7 @@ struct OpRowsInvTailEpi : OpColsInvTail<T, N, false> {
     double v[1];
     double sdot;  // Re<S, out> over this thread's elements (S is the last vector of the fused products)
   };
-  DBAR_D cx<T> load(int b, int row, int pos) const { return this->inp(b)[t_index<N>(row, pos, this->a.t_log)]; }
+  DBAR_D cx<T> load(int b, int row, int pos) const { return this->inp(b)[t_index<T, N>(row, pos)]; }
   // The stores run GROUP elements at a time: the group's global reads (q, the x factor of e_k, S, Y) are issued
   // together ahead of its tails.  The LDS slot of each element (the row transform's output r) is replaced by the
   // stored value, for the Gram-Schmidt products.

@@ -611,17 +611,6 @@ static const void* tw_of(const Pipeline& p) {
   return sizeof(T) == sizeof(double) ? p.tw64 : p.tw32;
 }
 
-// The FP32 x-space transform array is column-tile-major with the column launch's current tile width: each column
-// tile is then one contiguous block, read and written by whole lines, while the row launches (two rows per block at
-// N = 1024) touch it in line-sized pieces.  Measured on one box against the row-major layout: the FP32 column launch
-// 18% faster, the row launches 3-5% slower, the step 2.5% faster; the FP64 launches were slower tiled (up to 15% at
-// N = 4096), so the FP64 array stays row-major.
-template <typename T>
-static int t_layout(int N) {
-  if constexpr (sizeof(T) == 8) return (void)N, -1;
-  else return ilog2(tile_columns(N, false, tile_variant(N, false)));
-}
-
 // Taylor data of `in` (xi-space): F^{-1} in, d_n, c_n, R(0) -- about xi = 0, or about xi = a with kShifted
 template <typename T>
 void Pipeline::moments(const void* in, size_t in_bs, void* Tbuf, int B, const int* act, unsigned flags,
@@ -710,7 +699,6 @@ void Pipeline::apply_x_first(const void* in, size_t in_bs, void* Tbuf, int B, co
   a.in_bs = in_bs;
   a.out = Tbuf;
   a.out_bs = n;
-  a.t_log = t_layout<T>(N);
   a.part = part_mom;
   if (u) {
     a.dotV = u->V;
@@ -747,7 +735,6 @@ void Pipeline::apply_x_rest(const void* in, size_t in_bs, void* out, size_t out_
   a.in_bs = n;
   a.out = Tbuf;
   a.out_bs = n;
-  a.t_log = t_layout<T>(N);  // both launches below (and apply_x_first's) agree on the layout of Tbuf
   a.sout = xo ? xo->S : nullptr;
   a.sout_bs = n;
   launch_lines_any<T>(N, LineOp::ColsFwdRegularInv, a, s);
