@@ -264,6 +264,10 @@ __global__ void __launch_bounds__(64) k_cond_estimate(Ctl* ctl, const int* live)
   auto R = [&](int row, int col) { return Rs[col * LD + row]; };
   for (int l = 0; l < n; ++l)
     if (!(R(l, l) != 0.0)) return;  // breakdown (exact solution reached): keep the previous estimate
+  // reciprocals of the diagonal, once: the substitutions below multiply instead of dividing on their serial chain
+  __shared__ double Dinv[kMaxRestart];
+  if (i < n) Dinv[i] = 1.0 / R(i, i);
+  __syncthreads();
   // sigma_max: x <- R^T R x, normalised
   double x = i < n ? 1.0 + 0.01 * i : 0.0;
   double nrm = sqrt(wsum(x * x));
@@ -291,14 +295,14 @@ __global__ void __launch_bounds__(64) k_cond_estimate(Ctl* ctl, const int* live)
   for (int it = 0; it < kCondIters; ++it) {
     double r = x, u = 0.0;  // R^T u = x (forward substitution, column by column)
     for (int l = 0; l < n; ++l) {
-      const double ul = __shfl(r, l, 64) / R(l, l);
+      const double ul = __shfl(r, l, 64) * Dinv[l];
       if (i == l) u = ul;
       if (i > l && i < n) r -= R(l, i) * ul;
     }
     r = u;
     double v = 0.0;  // R v = u (back substitution)
     for (int l = n - 1; l >= 0; --l) {
-      const double vl = __shfl(r, l, 64) / R(l, l);
+      const double vl = __shfl(r, l, 64) * Dinv[l];
       if (i == l) v = vl;
       if (i < l) r -= R(i, l) * vl;
     }
