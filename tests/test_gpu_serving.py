@@ -161,6 +161,31 @@ def test_strong_request_does_not_change_later_ones():
         assert a[2].status == 0 and _same(a, mixed[j]), j
 
 
+def test_strong_request_leaves_its_slot_clean_for_later_requests():
+    """One session: a request six times the benchmark potential (it stalls under the Gram-Schmidt window and
+    orthogonalises fully from its second cycle on) shares its grid class with six ordinary requests; then the six are
+    submitted again one at a time, the first into the slot the strong request held.  Each ordinary request ends
+    exactly as in the mix (the per-slot fallback to full orthogonalisation is cleared when a slot is reused), and the
+    strong one converges."""
+    N, L = 64, 4.0
+    x = L * (-np.pi + 2 * np.pi * np.arange(N) / N)
+    X, Y = np.meshgrid(x, x)
+    strong = 6.0 * (0.8 + 0.6j) * np.exp(-(X * X + Y * Y))
+    rng = np.random.default_rng(78)
+    normal = [(W.potential_gaussian_sum(N, L, seed=int(rng.integers(1 << 30)), amp_max=1.0),
+               complex(2.0 * np.sqrt(rng.random()) * np.exp(2j * np.pi * rng.random()))) for _ in range(6)]
+    print("strong request with six ordinary ones, then the six one at a time (one session)", flush=True)
+    with D.Session(max_slots=8) as s:
+        ts = s.submit(strong, 0.5 + 0.5j, L, tol=1e-12)
+        tickets = [s.submit(Q, k, L, tol=1e-12) for Q, k in normal]
+        res_strong = s.wait(ts)
+        mixed = [s.wait(t) for t in tickets]
+        alone = [s.wait(s.submit(Q, k, L, tol=1e-12)) for Q, k in normal]
+    assert res_strong[2].status == 0
+    for j in range(len(normal)):
+        assert alone[j][2].status == 0 and _same(alone[j], mixed[j]), j
+
+
 def test_budget_queues_classes_and_completes_every_request():
     """A session whose HBM budget holds one N = 2048 request: the other grid classes wait for budget (nothing is
     rejected), the N = 2048 class releases its workspace when it runs idle, and every request completes with the
