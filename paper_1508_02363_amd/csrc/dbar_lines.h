@@ -326,6 +326,19 @@ struct OpRowsInvScaled : OpBase<T, N> {
 // formed once at the end: on a column d_n = sum_k C(n,k) x^{n-k} i^k mu_k, conj moment x mu_0 - i mu_1; on a row
 // d_n = sum_k C(n,k) (iy)^{n-k} mu_k, conj moment mu_1 - iy mu_0 (the binomial terms exceed |z|^n by at most
 // 2^{n/2}, i.e. < 50x at n = 11: a few ulps of FP64).
+// One step of a recursive-halving wave reduction: lanes with bit OFF clear keep the lower NV/2 of their values, the
+// others the upper half, each summed with its partner's copy of the same half (lane ^ OFF).
+template <typename T, int NV, int OFF>
+DBAR_D void halve_exchange(T (&x)[32], int lane) {
+  const bool hi = (lane & OFF) != 0;
+#pragma unroll
+  for (int i = 0; i < NV / 2; ++i) {
+    const T keep = hi ? x[i + NV / 2] : x[i];
+    const T send = hi ? x[i] : x[i + NV / 2];
+    x[i] = keep + __shfl_xor(send, OFF, 64);
+  }
+}
+
 template <typename T, int N, bool ALONG_X>
 struct MomentsBase : OpBase<T, N> {
   static constexpr int NV = 2 * kNMom;
@@ -439,32 +452,49 @@ struct MomentsBase : OpBase<T, N> {
     static_assert(NG == LdsSize<T, N, LN, !ALONG_X>::NG, "LDS scratch sized for another reduction layout");
     __syncthreads();  // scratch aliases the transform's LDS
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-    for (int q = 0; q < NU; ++q) {
-      T x = acc.v[q];
-      if constexpr (ALONG_X) {
-#pragma unroll
-        for (int off = GS / 2; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
-      } else if constexpr (SHFL) {
-#pragma unroll
-        for (int off = 32; off >= LN; off >>= 1) x += __shfl_xor(x, off, 64);
-      }
-      acc.v[q] = x;
-    }
     double* sc = scratch;                 // [NG][NMU]
     double* colv = scratch + NG * NMU;    // [LN][NV]
     double* mus = colv + LN * NV;         // [LN][NMU]
-    int g = -1;
-    if constexpr (ALONG_X) {
-      if (threadIdx.x % GS == 0) g = threadIdx.x / GS;
-    } else if constexpr (SHFL) {
-      if (lane < LN) g = wave * LN + lane;
-    } else {
-      g = threadIdx.x;  // thread t serves column t % LN
-    }
-    if (g >= 0) {
+    if constexpr (ALONG_X && GS == 64) {
+      // a whole wave per row: recursive halving over the NMU = 32 values (those beyond NU are zero), five exchanges
+      // that each send half of a lane's values and keep the other half summed with the partner's, then one plain
+      // exchange; lane l ends with value l >> 1 summed over the wave (32 shuffles per lane instead of 6 NU)
+      static_assert(NMU == 32, "the halving below is laid out for 32 values");
+      T x[NMU];
 #pragma unroll
-      for (int q = 0; q < NMU; ++q) sc[g * NMU + q] = q < NU ? static_cast<double>(acc.v[q]) : 0.0;
+      for (int q = 0; q < NMU; ++q) x[q] = q < NU ? acc.v[q] : T(0);
+      halve_exchange<T, 32, 32>(x, lane);
+      halve_exchange<T, 16, 16>(x, lane);
+      halve_exchange<T, 8, 8>(x, lane);
+      halve_exchange<T, 4, 4>(x, lane);
+      halve_exchange<T, 2, 2>(x, lane);
+      x[0] += __shfl_xor(x[0], 1, 64);
+      if ((lane & 1) == 0) sc[wave * NMU + (lane >> 1)] = static_cast<double>(x[0]);
+    } else {
+#pragma unroll
+      for (int q = 0; q < NU; ++q) {
+        T x = acc.v[q];
+        if constexpr (ALONG_X) {
+#pragma unroll
+          for (int off = GS / 2; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
+        } else if constexpr (SHFL) {
+#pragma unroll
+          for (int off = 32; off >= LN; off >>= 1) x += __shfl_xor(x, off, 64);
+        }
+        acc.v[q] = x;
+      }
+      int g = -1;
+      if constexpr (ALONG_X) {
+        if (threadIdx.x % GS == 0) g = threadIdx.x / GS;
+      } else if constexpr (SHFL) {
+        if (lane < LN) g = wave * LN + lane;
+      } else {
+        g = threadIdx.x;  // thread t serves column t % LN
+      }
+      if (g >= 0) {
+#pragma unroll
+        for (int q = 0; q < NMU; ++q) sc[g * NMU + q] = q < NU ? static_cast<double>(acc.v[q]) : 0.0;
+      }
     }
     __syncthreads();
     for (int t = threadIdx.x; t < LN * NMU; t += NT) {
