@@ -158,9 +158,11 @@ int dbar_apply(const dbar_grid* grid, const double* Q, const double* k, const do
  * arrays (read only), AS_dev: N*N complex128 device array (written; must not overlap S_dev); k: one (re, im) pair on
  * the host; precision DBAR_FP64 or DBAR_FP32 (as dbar_apply); stream: a hipStream_t (NULL = the default stream).
  * Every intermediate array lives in one static device array of 34 MiB per GPU (held until the process ends), which
- * limits the grid to N <= 1024 (larger N: DBAR_EINVAL).  The first call on a device sets that array up (it looks up
- * its address and writes the twiddle tables into it, with synchronous copies); later calls only queue kernels on
- * `stream` and return without waiting.  All calls on one GPU share its array, so calls that overlap on one GPU (on
+ * limits the grid to N <= 1024 (larger N: DBAR_EINVAL); the twiddle tables are a second static array, filled when
+ * the library is loaded.  The first call on a device looks up the two arrays' device addresses; every call only
+ * queues kernels on `stream` and returns without waiting (no host copies: the calls can be captured into a HIP
+ * graph, and a captured graph replays correctly whatever other calls left in the array).  All calls on one GPU share
+ * its array, so calls that overlap on one GPU (on
  * different streams, or while an earlier call's work is still running elsewhere) race: serialise them on one stream.
  */
 int dbar_apply_noalloc(const dbar_grid* grid, const void* Q_dev, const double* k, const void* S_dev, void* AS_dev,

@@ -5,13 +5,14 @@
 // The scratch array holds, for grids up to N = kNoAllocMaxN:
 //   * the transform scratch of the operator (FP64: one N x N complex128 array; FP32: the transform array and the
 //     FP32 roundings of Q, S and the result, N x N complex64 each -- 32 N^2 bytes either way);
-//   * the twiddle tables exp(-2 pi i j / N) of every power of two 8 <= N <= kNoAllocMaxN (FP64 and FP32), written once
-//     per device when the array is set up;
 //   * the per-k phase tables e^{-2i k2 x_j}, e^{-2i k1 y_j} (FP64 and FP32), k itself, the Taylor data (d_n, c_n,
 //     R(0)) and the per-tile partial sums of the moment reduction.
 // Nothing in it has to start at zero: every call writes each part it reads before reading it.  All calls on one GPU
 // share that GPU's copy (it keeps the last call's contents), so calls that overlap on one GPU race: serialise them on
-// one stream.
+// one stream.  The twiddle tables exp(-2 pi i j / N) of every power of two 8 <= N <= kNoAllocMaxN sit in a second
+// file-scope device array that is initialised when the code object loads (values computed at compile time), so no
+// call, the first included, copies anything from the host: the entry point can be captured into a HIP graph from its
+// first call on.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -31,9 +32,7 @@ constexpr size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 // sum of N over the powers of two 8 .. kNoAllocMaxN; the tables of grid size N start at entry N - 8
 constexpr size_t kTwEntries = 2 * (size_t)kNoAllocMaxN - 8;
 constexpr size_t kOffBig = 0;                                        // 32 N^2 bytes (see above)
-constexpr size_t kOffTw64 = align256(kOffBig + 32 * kNMax);          // FP64 twiddles, every N
-constexpr size_t kOffTw32 = align256(kOffTw64 + kTwEntries * sizeof(c64));
-constexpr size_t kOffPhase = align256(kOffTw32 + kTwEntries * sizeof(c32));  // ex, ey (FP64), ex32, ey32 (FP32)
+constexpr size_t kOffPhase = align256(kOffBig + 32 * kNMax);         // ex, ey (FP64), ex32, ey32 (FP32)
 constexpr size_t kOffK = align256(kOffPhase + (size_t)kNoAllocMaxN * 2 * (sizeof(c64) + sizeof(c32)));
 constexpr size_t kOffMom = align256(kOffK + sizeof(c64));            // coefG, dmom (FP64), dmom32
 constexpr size_t kOffPartMom = align256(kOffMom + (size_t)kNMom * (2 * sizeof(c64) + sizeof(c32)));
@@ -45,37 +44,81 @@ constexpr int kMaxDevices = 64;
 
 static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
+// exp(-2 pi i j / N), j < N, for every power of two 8 <= N <= kNoAllocMaxN (grid size N at entry N - 8), evaluated at
+// compile time in long double: the angle 2 pi j / N reduced to the first octant by the symmetries of the circle (exact:
+// j and N are integers), then the Taylor series of sin and cos there, rounded once to FP64 and to FP32.
+constexpr long double kPiL = 3.14159265358979323846264338327950288L;
+constexpr long double series_sin(long double x) {  // |x| <= pi/4: 16 terms leave < 1e-30
+  long double term = x, sum = x;
+  for (int k = 1; k < 16; ++k) {
+    term *= -x * x / ((long double)(2 * k) * (2 * k + 1));
+    sum += term;
+  }
+  return sum;
+}
+constexpr long double series_cos(long double x) {
+  long double term = 1.0L, sum = 1.0L;
+  for (int k = 1; k < 16; ++k) {
+    term *= -x * x / ((long double)(2 * k - 1) * (2 * k));
+    sum += term;
+  }
+  return sum;
+}
+struct TwTables {
+  c64 d[kTwEntries];
+  c32 f[kTwEntries];
+};
+constexpr TwTables make_tw_tables() {
+  TwTables t{};
+  for (int N = 8; N <= kNoAllocMaxN; N <<= 1)
+    for (int j = 0; j < N; ++j) {
+      // 2 pi j / N = (o + rem / N) pi / 4 with octant o; phi = rem / N pi / 4, psi = pi / 4 - phi
+      const long oct = 8L * j;
+      const int o = static_cast<int>(oct / N), rem = static_cast<int>(oct % N);
+      const long double phi = (long double)rem / N * (kPiL / 4), psi = (long double)(N - rem) / N * (kPiL / 4);
+      const long double cp = series_cos(phi), sp = series_sin(phi), cq = series_cos(psi), sq = series_sin(psi);
+      long double c = 0.0L, s = 0.0L;  // cos and sin of 2 pi j / N
+      switch (o) {
+        case 0: c = cp; s = sp; break;
+        case 1: c = sq; s = cq; break;
+        case 2: c = -sp; s = cp; break;
+        case 3: c = -cq; s = sq; break;
+        case 4: c = -cp; s = -sp; break;
+        case 5: c = -sq; s = -cq; break;
+        case 6: c = sp; s = -cp; break;
+        default: c = cq; s = -sq; break;
+      }
+      t.d[N - 8 + j] = c64{(double)c, (double)-s};
+      t.f[N - 8 + j] = c32{(float)c, (float)-s};
+    }
+  return t;
+}
+static __device__ __align__(256) TwTables tw_tables = make_tw_tables();
+
 static std::mutex g_na_mutex;
 static unsigned char* g_na_ptr[kMaxDevices];  // the device address of `scratch` on each device (null: not set up)
-static c64 g_tw64[kTwEntries];                // host twiddle tables of every N (filled once)
-static c32 g_tw32[kTwEntries];
-static bool g_tw_ready = false;
+static TwTables* g_na_tw[kMaxDevices];        // the device address of `tw_tables` on each device
 
-// Set-up on device dev (with dev current, under g_na_mutex): the scratch array's device address, and its twiddle
-// tables written once.
-static int noalloc_setup(int dev, unsigned char** out) {
+// Set-up on device dev (with dev current, under g_na_mutex): the device addresses of the scratch array and of the
+// twiddle tables.
+static int noalloc_setup(int dev, unsigned char** out, const TwTables** tw) {
   if (g_na_ptr[dev]) {
     *out = g_na_ptr[dev];
+    *tw = g_na_tw[dev];
     return DBAR_OK;
   }
   void* p = nullptr;
-  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
-  if (e != hipSuccess || !p) {
+  void* q = nullptr;
+  hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e == hipSuccess && p) e = hipGetSymbolAddress(&q, HIP_SYMBOL(tw_tables));
+  if (e != hipSuccess || !p || !q) {
     (void)hipGetLastError();
-    return fail(DBAR_EDEVICE, std::string("hipGetSymbolAddress of the scratch array failed: ") + hipGetErrorString(e));
+    return fail(DBAR_EDEVICE, std::string("hipGetSymbolAddress of the scratch arrays failed: ") + hipGetErrorString(e));
   }
-  if (!g_tw_ready) {
-    for (int N = 8; N <= kNoAllocMaxN; N <<= 1) host_twiddles(N, g_tw64 + (N - 8), g_tw32 + (N - 8));
-    g_tw_ready = true;
-  }
-  unsigned char* base = static_cast<unsigned char*>(p);
-  if (hipMemcpy(base + kOffTw64, g_tw64, sizeof(g_tw64), hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(base + kOffTw32, g_tw32, sizeof(g_tw32), hipMemcpyHostToDevice) != hipSuccess) {
-    (void)hipGetLastError();
-    return fail(DBAR_EDEVICE, "upload of the twiddle tables into the scratch array failed");
-  }
-  g_na_ptr[dev] = base;
-  *out = base;
+  g_na_ptr[dev] = static_cast<unsigned char*>(p);
+  g_na_tw[dev] = static_cast<TwTables*>(q);
+  *out = g_na_ptr[dev];
+  *tw = g_na_tw[dev];
   return DBAR_OK;
 }
 
@@ -104,7 +147,8 @@ int dbar_apply_noalloc(const dbar_grid* grid, const void* Q_dev, const double* k
   }
   std::lock_guard<std::mutex> lock(g_na_mutex);
   unsigned char* base = nullptr;
-  if ((rc = noalloc_setup(dev, &base))) return rc;
+  const TwTables* tw = nullptr;
+  if ((rc = noalloc_setup(dev, &base, &tw))) return rc;
   const int N = grid->n;
   const size_t n = (size_t)N * N;
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -115,8 +159,8 @@ int dbar_apply_noalloc(const dbar_grid* grid, const void* Q_dev, const double* k
   P.M = grid->M;
   P.L = grid->L;
   P.n = n;
-  P.tw64 = base + kOffTw64 + (size_t)(N - 8) * sizeof(c64);
-  P.tw32 = base + kOffTw32 + (size_t)(N - 8) * sizeof(c32);
+  P.tw64 = tw->d + (N - 8);
+  P.tw32 = tw->f + (N - 8);
   c64* ex = reinterpret_cast<c64*>(base + kOffPhase);
   c64* ey = ex + N;
   c32* ex32 = reinterpret_cast<c32*>(ey + N);
