@@ -52,7 +52,8 @@ class Opts(ctypes.Structure):
     _fields_ = [("restart", ctypes.c_int32), ("max_iter", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("mode", ctypes.c_int32), ("batch", ctypes.c_int32), ("use_graph", ctypes.c_int32),
                 ("reorth", ctypes.c_int32), ("check_every", ctypes.c_int32), ("method", ctypes.c_int32),
-                ("space", ctypes.c_int32), ("inner_tol", ctypes.c_double), ("orth_window", ctypes.c_int32)]
+                ("space", ctypes.c_int32), ("inner_tol", ctypes.c_double), ("orth_window", ctypes.c_int32),
+                ("lanes", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):

@@ -14,6 +14,7 @@
 #include <memory>
 #include <atomic>
 #include <mutex>
+#include <thread>
 #include <string>
 #include <vector>
 
@@ -1444,6 +1445,27 @@ static int solver_stream(hipStream_t caller, hipStream_t* out) {
   return DBAR_OK;
 }
 
+// Lanes of a batched solve (see solve_impl): lane 0 runs on the solver stream with g_work, lane l > 0 on a stream and
+// workspace of its own, joined to the caller's stream through the same event.
+constexpr int kMaxLanes = 2;
+static Work g_lane_work[kMaxLanes - 1];
+static hipStream_t g_lane_stream[kMaxLanes - 1];
+
+static Work& lane_work(int l) { return l == 0 ? g_work : g_lane_work[l - 1]; }
+
+// (lane 0 first: it records the join event on the caller's stream)
+static int lane_stream(int l, hipStream_t caller, hipStream_t* out) {
+  if (l == 0) return solver_stream(caller, out);
+  hipStream_t& s = g_lane_stream[l - 1];
+  if (!s && hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
+    s = nullptr;
+    return fail(DBAR_EDEVICE, "stream creation failed");
+  }
+  if (hipStreamWaitEvent(s, g_join, 0) != hipSuccess) return fail(DBAR_EDEVICE, "stream join failed");
+  *out = s;
+  return DBAR_OK;
+}
+
 // grid offset of 2 k_c L (k_c a component of k), known to be an integer
 static int shift_of(double kc, double L) { return (int)std::nearbyint(2.0 * kc * L); }
 
@@ -1508,139 +1530,190 @@ int solve_impl(const dbar_grid* grid, const void* Q, bool q_on_device, int64_t n
       if (cap >= 1 && (size_t)B > cap) B = (int)cap;
     }
   }
-  hipStream_t s = nullptr;
-  if ((rc = solver_stream(caller, &s))) return rc;
-  Work& w = g_work;
-  if ((rc = w.setup(N, B, o.restart, o.precision, true))) return rc;
-  Pipeline P;
-  if ((rc = make_pipeline(grid, w, &P))) return rc;
-  if (q_on_device) {
-    if (hipMemcpyAsync(w.Q64.p, Q, n * sizeof(c64), hipMemcpyDeviceToDevice, s) != hipSuccess)
-      return fail(DBAR_EDEVICE, "Q copy failed");
-  } else {
-    if (hipMemcpyAsync(w.Q64.p, Q, n * sizeof(c64), hipMemcpyHostToDevice, s) != hipSuccess)
-      return fail(DBAR_EDEVICE, "Q upload failed");
-  }
-  if (o.precision == DBAR_MIXED) launch_convert<float, double>(w.Q64.p, 0, w.Q32.p, 0, n, 1, nullptr, 1.0, s);
+  // Lanes: the batch split into parts solved concurrently, each on a stream and workspace of its own; part c of
+  // size Bl goes to lane c % lanes.  One lane keeps the captured-graph path; with more, the launches are direct (a
+  // capture in one host thread interferes with the other thread's calls).
+  int lanes = o.lanes > 0 ? std::min(o.lanes, kMaxLanes) : (o.mode != DBAR_MODE_PLAIN && B >= 16 ? 2 : 1);
+  if (o.mode == DBAR_MODE_PLAIN || timer_on()) lanes = 1;  // the stage timer measures one lane's launches
+  lanes = std::max(1, std::min(lanes, B));
+  const int Bl = (B + lanes - 1) / lanes;
   BatchCfg cfg;
   cfg.tol = tol;
   cfg.max_iter = o.max_iter;
   cfg.reorth = o.reorth;
-  cfg.use_graph = o.mode == DBAR_MODE_PLAIN ? 0 : o.use_graph;
+  cfg.use_graph = o.mode == DBAR_MODE_PLAIN || lanes > 1 ? 0 : o.use_graph;
   cfg.method = o.method;
-  if (cfg.method == 1 && (rc = w.Hbuf.ensure((size_t)B * n * sizeof(c64)))) return rc;
   cfg.check_every = o.mode == DBAR_MODE_PLAIN ? 1 : o.check_every;
   cfg.inner_tol = o.inner_tol;
   cfg.orth_window = o.orth_window;
   cfg.xspace = o.space == DBAR_SPACE_X ? 1 : 0;
-  P.xspace = cfg.xspace != 0;
-  if (cfg.xspace && ((rc = w.Sx.ensure((size_t)B * n * sizeof(c64))) || (rc = w.mx.ensure((size_t)B * n * sizeof(c64)))))
-    return rc;
-  if (cfg.xspace && cfg.method == 1 &&
-      ((rc = w.Fx.ensure((size_t)B * n * sizeof(c64))) || (rc = w.Ax.ensure((size_t)B * n * sizeof(c64)))))
-    return rc;
-  std::vector<EntryResult> hres(B);
-  std::vector<int> shifts(2 * (size_t)B);
-  int result = DBAR_OK;
-  for (int64_t k0 = 0; k0 < nk; k0 += B) {
-    const int nb = (int)std::min<int64_t>(B, nk - k0);
-    w.B = nb;
-    w.outS = cfg.xspace && out_on_device && S ? static_cast<char*>(S) + (size_t)k0 * n * sizeof(c64) : nullptr;
-    w.outm = cfg.xspace && out_on_device && m ? static_cast<char*>(m) + (size_t)k0 * n * sizeof(c64) : nullptr;
-    if (hipMemcpyAsync(w.kvals.p, k + 2 * k0, (size_t)nb * sizeof(c64), hipMemcpyHostToDevice, s) != hipSuccess)
-      return fail(DBAR_EDEVICE, "k upload failed");
-    if (cfg.method == 1) {
-      for (int b = 0; b < nb; ++b) shifts[2 * b] = shift_of(k[2 * (k0 + b) + 1], grid->L), shifts[2 * b + 1] =
-                                                                                       shift_of(k[2 * (k0 + b)], grid->L);
-      if (hipMemcpyAsync(w.shv.p, shifts.data(), (size_t)nb * 2 * sizeof(int), hipMemcpyHostToDevice, s) != hipSuccess)
-        return fail(DBAR_EDEVICE, "shift upload failed");
+  struct Lane {
+    Work* w = nullptr;
+    hipStream_t s = nullptr;
+    Pipeline P;
+  };
+  Lane ln[kMaxLanes];
+  for (int l = 0; l < lanes; ++l) {
+    if ((rc = lane_stream(l, caller, &ln[l].s))) return rc;
+    Work& w = lane_work(l);
+    ln[l].w = &w;
+    const hipStream_t s = ln[l].s;
+    if ((rc = w.setup(N, Bl, o.restart, o.precision, true))) return rc;
+    if ((rc = make_pipeline(grid, w, &ln[l].P))) return rc;
+    ln[l].P.xspace = cfg.xspace != 0;
+    if (q_on_device) {
+      if (hipMemcpyAsync(w.Q64.p, Q, n * sizeof(c64), hipMemcpyDeviceToDevice, s) != hipSuccess)
+        return fail(DBAR_EDEVICE, "Q copy failed");
+    } else {
+      if (hipMemcpyAsync(w.Q64.p, Q, n * sizeof(c64), hipMemcpyHostToDevice, s) != hipSuccess)
+        return fail(DBAR_EDEVICE, "Q upload failed");
     }
-    launch_phase_tables(static_cast<const c64*>(w.kvals.p), N, grid->L, static_cast<c64*>(w.ex.p),
-                        static_cast<c64*>(w.ey.p), static_cast<c32*>(w.ex32.p), static_cast<c32*>(w.ey32.p), nb, s);
-    std::vector<int> its;
-    if ((rc = run_batch(P, w, cfg, s, its))) return rc;
-    // outputs.  Plain on s: S and m from the last residual evaluation.  Iterated on s: S = f + h o (xi + a) (equation
-    // Sform, formed in place in Fx) and m = h(f) + e_k F^{-1}(h/(xi - a)) (in place in mx) from that evaluation's
-    // h, f and inverses.  On S: S = x and m = h(x) (plain), or formed from h below (iterated).  S0src holds S(0) for
-    // m1, hsrc the iterated method's xi-space h (r = i h(a)).
-    const bool form = cfg.method == 1 && (S || m || !r_out);  // dbar_reflection alone needs only h(a)
-    const c64* S0src = static_cast<const c64*>(w.x.p);
-    const c64* hsrc = static_cast<const c64*>(w.x.p);
-    const void* Sout = nullptr;
-    const void* mout = nullptr;
-    // (x-space outputs the solve wrote straight into the caller's device arrays need no copy)
-    if (cfg.xspace && cfg.method == 0) {
-      S0src = static_cast<const c64*>(w.S_dst(0));
-      Sout = w.outS ? nullptr : w.Sx.p;
-      mout = w.outm ? nullptr : w.mx.p;
-    } else if (cfg.xspace) {
-      hsrc = static_cast<const c64*>(w.Sx.p);
-      if (form) {
-        launch_roll_add(static_cast<const c64*>(w.Fx.p), static_cast<const c64*>(w.Sx.p),
-                        static_cast<const int*>(w.shv.p), N, static_cast<c64*>(w.S_dst(1)), nb, s);
-        launch_add_phase(static_cast<c64*>(w.m_dst()), static_cast<const c64*>(w.Ax.p),
-                         static_cast<const c64*>(w.ex.p), static_cast<const c64*>(w.ey.p), N, nb, s);
-        S0src = static_cast<const c64*>(w.S_dst(1));
-        Sout = w.outS ? nullptr : w.Fx.p;
-        mout = w.outm ? nullptr : w.mx.p;
+    if (o.precision == DBAR_MIXED) launch_convert<float, double>(w.Q64.p, 0, w.Q32.p, 0, n, 1, nullptr, 1.0, s);
+    if (cfg.method == 1 && (rc = w.Hbuf.ensure((size_t)Bl * n * sizeof(c64)))) return rc;
+    if (cfg.xspace &&
+        ((rc = w.Sx.ensure((size_t)Bl * n * sizeof(c64))) || (rc = w.mx.ensure((size_t)Bl * n * sizeof(c64)))))
+      return rc;
+    if (cfg.xspace && cfg.method == 1 &&
+        ((rc = w.Fx.ensure((size_t)Bl * n * sizeof(c64))) || (rc = w.Ax.ensure((size_t)Bl * n * sizeof(c64)))))
+      return rc;
+  }
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  // one lane's parts, in order; returns DBAR_OK, DBAR_ENOCONV (some entry did not converge) or an error
+  auto run_lane = [&](int l) -> int {
+    Work& w = *ln[l].w;
+    const hipStream_t s = ln[l].s;
+    const Pipeline& P = ln[l].P;
+    std::vector<EntryResult> hres(Bl);
+    std::vector<int> shifts(2 * (size_t)Bl);
+    int result = DBAR_OK;
+    for (int64_t k0 = (int64_t)l * Bl; k0 < nk; k0 += (int64_t)lanes * Bl) {
+      const int nb = (int)std::min<int64_t>(Bl, nk - k0);
+      w.B = nb;
+      w.outS = cfg.xspace && out_on_device && S ? static_cast<char*>(S) + (size_t)k0 * n * sizeof(c64) : nullptr;
+      w.outm = cfg.xspace && out_on_device && m ? static_cast<char*>(m) + (size_t)k0 * n * sizeof(c64) : nullptr;
+      if (hipMemcpyAsync(w.kvals.p, k + 2 * k0, (size_t)nb * sizeof(c64), hipMemcpyHostToDevice, s) != hipSuccess)
+        return fail(DBAR_EDEVICE, "k upload failed");
+      if (cfg.method == 1) {
+        for (int b = 0; b < nb; ++b) {
+          shifts[2 * b] = shift_of(k[2 * (k0 + b) + 1], grid->L);
+          shifts[2 * b + 1] = shift_of(k[2 * (k0 + b)], grid->L);
+        }
+        if (hipMemcpyAsync(w.shv.p, shifts.data(), (size_t)nb * 2 * sizeof(int), hipMemcpyHostToDevice, s) !=
+            hipSuccess)
+          return fail(DBAR_EDEVICE, "shift upload failed");
       }
-    } else if (cfg.method == 0) {
-      Sout = w.x.p;
-      if (m) {
-        P.h_of<double>(w.x.p, n, w.T64.p, n, w.bvec.p, nb, nullptr, s);  // bvec reused as scratch
+      launch_phase_tables(static_cast<const c64*>(w.kvals.p), N, grid->L, static_cast<c64*>(w.ex.p),
+                          static_cast<c64*>(w.ey.p), static_cast<c32*>(w.ex32.p), static_cast<c32*>(w.ey32.p), nb, s);
+      std::vector<int> its;
+      if (const int brc = run_batch(P, w, cfg, s, its)) return brc;
+      // outputs.  Plain on s: S and m from the last residual evaluation.  Iterated on s: S = f + h o (xi + a) (equation
+      // Sform, formed in place in Fx) and m = h(f) + e_k F^{-1}(h/(xi - a)) (in place in mx) from that evaluation's
+      // h, f and inverses.  On S: S = x and m = h(x) (plain), or formed from h below (iterated).  S0src holds S(0) for
+      // m1, hsrc the iterated method's xi-space h (r = i h(a)).
+      const bool form = cfg.method == 1 && (S || m || !r_out);  // dbar_reflection alone needs only h(a)
+      const c64* S0src = static_cast<const c64*>(w.x.p);
+      const c64* hsrc = static_cast<const c64*>(w.x.p);
+      const void* Sout = nullptr;
+      const void* mout = nullptr;
+      // (x-space outputs the solve wrote straight into the caller's device arrays need no copy)
+      if (cfg.xspace && cfg.method == 0) {
+        S0src = static_cast<const c64*>(w.S_dst(0));
+        Sout = w.outS ? nullptr : w.Sx.p;
+        mout = w.outm ? nullptr : w.mx.p;
+      } else if (cfg.xspace) {
+        hsrc = static_cast<const c64*>(w.Sx.p);
+        if (form) {
+          launch_roll_add(static_cast<const c64*>(w.Fx.p), static_cast<const c64*>(w.Sx.p),
+                          static_cast<const int*>(w.shv.p), N, static_cast<c64*>(w.S_dst(1)), nb, s);
+          launch_add_phase(static_cast<c64*>(w.m_dst()), static_cast<const c64*>(w.Ax.p),
+                           static_cast<const c64*>(w.ex.p), static_cast<const c64*>(w.ey.p), N, nb, s);
+          S0src = static_cast<const c64*>(w.S_dst(1));
+          Sout = w.outS ? nullptr : w.Fx.p;
+          mout = w.outm ? nullptr : w.mx.p;
+        }
+      } else if (cfg.method == 0) {
+        Sout = w.x.p;
+        if (m) {
+          P.h_of<double>(w.x.p, n, w.T64.p, n, w.bvec.p, nb, nullptr, s);  // bvec reused as scratch
+          mout = w.T64.p;
+        }
+      } else if (form) {
+        // f = H(h) (into Hbuf), S = f + h o (xi + a) (into bvec), m = h(f) + e_k F^{-1}(h/(xi - a)) (into T64)
+        c64* Hb = static_cast<c64*>(w.Hbuf.p);
+        c64* Sb = static_cast<c64*>(w.bvec.p);
+        P.H_of<double>(w.x.p, n, Hb, n, w.Q64.p, w.Q_bs, Sb, nb, nullptr, s);
+        P.h_of<double>(Hb, n, w.T64.p, n, Sb, nb, nullptr, s);
+        P.h_of<double>(w.x.p, n, w.T64.p, n, Sb, nb, nullptr, s, kShifted, true, true);
+        launch_roll_add(Hb, static_cast<const c64*>(w.x.p), static_cast<const int*>(w.shv.p), N, Sb, nb, s);
+        S0src = Sb;
+        Sout = Sb;
         mout = w.T64.p;
       }
-    } else if (form) {
-      // f = H(h) (into Hbuf), S = f + h o (xi + a) (into bvec), m = h(f) + e_k F^{-1}(h/(xi - a)) (into T64)
-      c64* Hb = static_cast<c64*>(w.Hbuf.p);
-      c64* Sb = static_cast<c64*>(w.bvec.p);
-      P.H_of<double>(w.x.p, n, Hb, n, w.Q64.p, w.Q_bs, Sb, nb, nullptr, s);
-      P.h_of<double>(Hb, n, w.T64.p, n, Sb, nb, nullptr, s);
-      P.h_of<double>(w.x.p, n, w.T64.p, n, Sb, nb, nullptr, s, kShifted, true, true);
-      launch_roll_add(Hb, static_cast<const c64*>(w.x.p), static_cast<const int*>(w.shv.p), N, Sb, nb, s);
-      S0src = Sb;
-      Sout = Sb;
-      mout = w.T64.p;
-    }
-    const hipMemcpyKind kind = out_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
-    if (S && Sout &&
-        hipMemcpyAsync(static_cast<char*>(S) + (size_t)k0 * n * sizeof(c64), Sout, (size_t)nb * n * sizeof(c64), kind,
-                       s) != hipSuccess)
-      return fail(DBAR_EDEVICE, "S copy failed");
-    if (m && mout &&
-        hipMemcpyAsync(static_cast<char*>(m) + (size_t)k0 * n * sizeof(c64), mout, (size_t)nb * n * sizeof(c64), kind,
-                       s) != hipSuccess)
-      return fail(DBAR_EDEVICE, "m copy failed");
-    hipLaunchKernelGGL(k_gather_results, dim3(ctl_blocks(nb)), dim3(64), 0, s, static_cast<const Ctl*>(w.ctl.p), S0src,
-                       n, hsrc, cfg.method == 1 ? static_cast<const int*>(w.shv.p) : nullptr, N,
-                       static_cast<EntryResult*>(w.results.p), nb);
-    (void)hipMemcpyAsync(hres.data(), w.results.p, (size_t)nb * sizeof(EntryResult), hipMemcpyDeviceToHost, s);
-    (void)hipMemcpyAsync(w.host_live.data(), w.live.p, nb * sizeof(int), hipMemcpyDeviceToHost, s);
-    if (hipStreamSynchronize(s) != hipSuccess) return fail(DBAR_EDEVICE, "stream synchronize failed");
-    for (int b = 0; b < nb; ++b) {
-      const EntryResult& c = hres[b];
-      const bool ok = w.host_live[b] == 0;
-      if (!ok) result = DBAR_ENOCONV;
-      if (info) {
-        dbar_info& I = info[k0 + b];
-        I.status = ok ? DBAR_OK : DBAR_ENOCONV;
-        I.iters = c.iters;
-        I.outer = c.cycles;
-        I.reserved = 0;
-        I.rel_residual = c.bnorm > 0.0 ? c.rnorm / c.bnorm : 0.0;
-        I.cond_estimate = c.kappa;
-        I.err_estimate = c.kappa * I.rel_residual;
-        I.m1_re = form || cfg.method == 0 ? -c.s00.im : 0.0;  // m1 = i S(0); not formed on the r-only path
-        I.m1_im = form || cfg.method == 0 ? c.s00.re : 0.0;
-      }
-      if (r_out) {  // r = i h(2i conj k)
-        r_out[2 * (k0 + b)] = -c.hsh.im;
-        r_out[2 * (k0 + b) + 1] = c.hsh.re;
+      const hipMemcpyKind kind = out_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+      if (S && Sout &&
+          hipMemcpyAsync(static_cast<char*>(S) + (size_t)k0 * n * sizeof(c64), Sout, (size_t)nb * n * sizeof(c64), kind,
+                         s) != hipSuccess)
+        return fail(DBAR_EDEVICE, "S copy failed");
+      if (m && mout &&
+          hipMemcpyAsync(static_cast<char*>(m) + (size_t)k0 * n * sizeof(c64), mout, (size_t)nb * n * sizeof(c64), kind,
+                         s) != hipSuccess)
+        return fail(DBAR_EDEVICE, "m copy failed");
+      hipLaunchKernelGGL(k_gather_results, dim3(ctl_blocks(nb)), dim3(64), 0, s, static_cast<const Ctl*>(w.ctl.p),
+                         S0src, n, hsrc, cfg.method == 1 ? static_cast<const int*>(w.shv.p) : nullptr, N,
+                         static_cast<EntryResult*>(w.results.p), nb);
+      (void)hipMemcpyAsync(hres.data(), w.results.p, (size_t)nb * sizeof(EntryResult), hipMemcpyDeviceToHost, s);
+      (void)hipMemcpyAsync(w.host_live.data(), w.live.p, nb * sizeof(int), hipMemcpyDeviceToHost, s);
+      if (hipStreamSynchronize(s) != hipSuccess) return fail(DBAR_EDEVICE, "stream synchronize failed");
+      for (int b = 0; b < nb; ++b) {
+        const EntryResult& c = hres[b];
+        const bool ok = w.host_live[b] == 0;
+        if (!ok) result = DBAR_ENOCONV;
+        if (info) {
+          dbar_info& I = info[k0 + b];
+          I.status = ok ? DBAR_OK : DBAR_ENOCONV;
+          I.iters = c.iters;
+          I.outer = c.cycles;
+          I.reserved = 0;
+          I.rel_residual = c.bnorm > 0.0 ? c.rnorm / c.bnorm : 0.0;
+          I.cond_estimate = c.kappa;
+          I.err_estimate = c.kappa * I.rel_residual;
+          I.m1_re = form || cfg.method == 0 ? -c.s00.im : 0.0;  // m1 = i S(0); not formed on the r-only path
+          I.m1_im = form || cfg.method == 0 ? c.s00.re : 0.0;
+        }
+        if (r_out) {  // r = i h(2i conj k)
+          r_out[2 * (k0 + b)] = -c.hsh.im;
+          r_out[2 * (k0 + b) + 1] = c.hsh.re;
+        }
       }
     }
+    w.outS = nullptr;
+    w.outm = nullptr;
+    return result;
+  };
+  int result = DBAR_OK;
+  if (lanes == 1) {
+    result = run_lane(0);
+  } else {
+    int rc1 = DBAR_OK;
+    std::string err1;
+    auto lane1 = [&] {
+      (void)hipSetDevice(dev);
+      rc1 = run_lane(1);
+      if (rc1 != DBAR_OK && rc1 != DBAR_ENOCONV) err1 = g_last_error;
+    };
+    std::thread t1;
+    try {
+      t1 = std::thread(lane1);
+    } catch (...) {  // no thread: the second lane runs after the first
+    }
+    const int rc0 = run_lane(0);
+    if (t1.joinable()) t1.join();
+    else lane1();
+    if (rc0 != DBAR_OK && rc0 != DBAR_ENOCONV) return rc0;
+    if (rc1 != DBAR_OK && rc1 != DBAR_ENOCONV) return fail(rc1, err1);
+    result = rc0 == DBAR_ENOCONV || rc1 == DBAR_ENOCONV ? DBAR_ENOCONV : DBAR_OK;
   }
-  w.outS = nullptr;
-  w.outm = nullptr;
   if (result == DBAR_ENOCONV) fail(DBAR_ENOCONV, "GMRES reached max_iter before tol for some k");
   return result;
 }
@@ -1677,6 +1750,11 @@ int dbar_version(void) { return 100; }
 void dbar_release(void) {
   std::lock_guard<std::mutex> lock(g_mutex);
   g_work = Work();
+  for (int l = 0; l + 1 < kMaxLanes; ++l) {
+    g_lane_work[l] = Work();
+    if (g_lane_stream[l]) (void)hipStreamDestroy(g_lane_stream[l]);
+    g_lane_stream[l] = nullptr;
+  }
   {
     std::lock_guard<std::mutex> tl(g_tw_mutex);
     g_twiddles.clear();

@@ -53,11 +53,13 @@ def default_opts() -> _lib.Opts:
 
 def make_opts(precision=DBAR_FP64, mode=DBAR_MODE_BATCHED, restart=0, max_iter=1000, batch=0, use_graph=1,
               reorth=1, check_every=4, inner_tol=0.0, method=DBAR_METHOD_PLAIN, space=DBAR_SPACE_X,
-              orth_window=None) -> _lib.Opts:
-    """Solver options; orth_window None keeps the library's default Gram-Schmidt window."""
+              orth_window=None, lanes=0) -> _lib.Opts:
+    """Solver options; orth_window None keeps the library's default Gram-Schmidt window; lanes 0 the library's
+    default split of a batch into concurrent parts."""
     o = default_opts()
     if orth_window is not None:
         o.orth_window = orth_window
+    o.lanes = lanes
     o.method = method
     o.space = space
     o.precision, o.mode, o.restart, o.max_iter, o.batch = precision, mode, restart, max_iter, batch

@@ -465,6 +465,38 @@ def test_batch_entries_do_not_depend_on_each_other(prec):
         assert np.array_equal(S[j], S1[0]) and np.array_equal(m[j], m1[0]), j
 
 
+@pytest.mark.parametrize("prec,method", [(D.DBAR_FP64, D.DBAR_METHOD_PLAIN), (D.DBAR_MIXED, D.DBAR_METHOD_PLAIN),
+                                         (D.DBAR_MIXED, D.DBAR_METHOD_ITERATED)])
+def test_lanes_give_the_same_results(prec, method):
+    """A batched solve split into two concurrent lanes (the default for batches of 16 or more: two parts, each on a
+    stream and workspace of its own) returns exactly what one lane returns: 20 k at batch 16 make parts of 8, 8 and
+    4 (the last one the first lane's second part), with device outputs written by both lanes."""
+    N, L = 64, 4.0
+    g = O.make_grid(N, L)
+    Q = (0.8 + 0.6j) * np.exp(-np.abs(g.z) ** 2)
+    rng = np.random.default_rng(21)
+    if method == D.DBAR_METHOD_ITERATED:  # 2k on the xi grid
+        ks = (rng.integers(-8, 9, 20) + 1j * rng.integers(-8, 9, 20)) / (2 * L)
+    else:
+        ks = 2.0 * np.sqrt(rng.random(20)) * np.exp(2j * np.pi * rng.random(20))
+    kw = dict(tol=1e-12, batch=16, precision=prec, method=method)
+    print(f"lanes: precision {prec} method {method}", flush=True)
+    S1, m1, i1 = D.solve(Q, ks, L, lanes=1, **kw)
+    S2, m2, i2 = D.solve(Q, ks, L, lanes=2, **kw)
+    Qd = torch.from_numpy(Q).to("cuda:0")
+    Sd, md, idv = D.solve_device(Qd, ks, L, lanes=2, **kw)
+    torch.cuda.synchronize()
+    for j in range(len(ks)):
+        assert i1[j].status == 0 and (i1[j].iters, i1[j].outer) == (i2[j].iters, i2[j].outer), j
+        assert i1[j].m1 == i2[j].m1 and i1[j].rel_residual == i2[j].rel_residual, j
+        assert np.array_equal(S1[j], S2[j]) and np.array_equal(m1[j], m2[j]), j
+        assert (idv[j].iters, idv[j].outer) == (i1[j].iters, i1[j].outer), j
+    assert np.array_equal(Sd.cpu().numpy(), S1) and np.array_equal(md.cpu().numpy(), m1)
+    ref = O.solve(g, Q, ks[0], tol=1e-13) if method == D.DBAR_METHOD_PLAIN else None
+    if ref is not None:
+        assert relerr(S2[0], ref.S) < 1e-10 and relerr(m2[0], ref.m) < 1e-10
+
+
 @pytest.mark.parametrize("prec", [D.DBAR_FP64, D.DBAR_MIXED])
 def test_error_estimate_reported_per_result(prec):
     """Every result carries a condition estimate from its Krylov Hessenberg matrix and err_estimate = estimate x the
