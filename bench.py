@@ -474,12 +474,18 @@ def main():
     torch.cuda.synchronize()
 
     batch = args.batch if args.batch > 0 else nk
+    # the library splits a batch of 16 or more into two concurrent lanes of half the entries each
+    lanes = 2 if batch >= 16 else 1
+    lane_batch = -(-batch // lanes)
 
     def step(**kw):
-        return D.solve_device(Qd, w.ks, L, tol=w.tol, M=w.M, batch=batch, **kw)
+        kw.setdefault("batch", batch)
+        return D.solve_device(Qd, w.ks, L, tol=w.tol, M=w.M, **kw)
 
-    # the library's tuner picks the column-tile widths for this grid (outside the timed region, like the warm-up)
-    tuning = None if args.no_autotune or args.probe else D.autotune(N, L, precision=D.DBAR_MIXED, batch=nk, M=w.M)
+    # the library's tuner picks the column-tile widths for this grid at the entries per launch of one lane (outside
+    # the timed region, like the warm-up)
+    tuning = None if args.no_autotune or args.probe else D.autotune(N, L, precision=D.DBAR_MIXED, batch=lane_batch,
+                                                                    M=w.M)
 
     paths = {
         "mixed": dict(precision=D.DBAR_MIXED),
@@ -489,7 +495,8 @@ def main():
     }
 
     if args.probe:
-        kw = paths[args.probe]
+        # one lane at the lanes' entries per launch: the launches of the timed step, timed one at a time
+        kw = dict(paths[args.probe], batch=lane_batch, lanes=1)
         step(**kw)
         torch.cuda.synchronize()
         step(**kw)
@@ -541,9 +548,11 @@ def main():
     sec, (S, m, info) = timed(kw, args.steps, args.warmup)
     value = nk / sec
 
-    # per-stage launch timing with HIP events (one more pass of the same step)
+    # per-stage launch timing with HIP events (one more pass of the same step).  The timer runs one lane at a time
+    # (its events time each launch on its own), so this pass solves the lanes' parts one after the other: the same
+    # launches, with the entries per launch of one lane
     D.timer_enable(True)
-    step(**kw)
+    step(**dict(kw, batch=lane_batch, lanes=1))
     torch.cuda.synchronize()
     D.timer_enable(False)
     summ = stage_summary(D.timer_stages())
@@ -561,6 +570,11 @@ def main():
         t_xi, (Sq, _, _) = timed(paths["mixed_xi"], 2, 1)
         context["mixed_xi_space_solves_per_s"] = nk / t_xi
         context["mixed_xi_space_err_vs_fp64"] = max(rel_linf(Sq[j].cpu().numpy(), S64h[j]) for j in range(nk))
+        # one lane at the full batch, Krylov iterations replayed from captured HIP graphs
+        t_1l, (S1l, _, _) = timed(dict(kw, lanes=1, use_graph=1), 2, 1)
+        context["one_lane_graph_solves_per_s"] = nk / t_1l
+        context["one_lane_graph_err_vs_headline"] = max(rel_linf(S1l[j].cpu().numpy(), S[j].cpu().numpy())
+                                                        for j in range(nk))
         # the same solvers with full orthogonalisation (classical GMRES, no Gram-Schmidt window)
         for name in ("mixed", "fp64"):
             t_full, (Sf, _, infof) = timed(dict(paths[name], orth_window=0), 2, 1)
@@ -584,7 +598,8 @@ def main():
         "config": {
             "workload": f"{w.name}: N={N}, L={L}, Q=(0.8+0.6i)exp(-(x^2+y^2)), {nk} k on a 4x4 grid in [-2,2]^2, "
                         f"M={w.M}, tol {w.tol:g}, batched {headline}",
-            "N": N, "L": L, "n_k": nk, "M": w.M, "tol": w.tol, "path": headline,
+            "N": N, "L": L, "n_k": nk, "M": w.M, "tol": w.tol, "path": headline, "batch": batch, "lanes": lanes,
+            "entries_per_launch": lane_batch,
         },
         "accuracy": {
             "mixed_err_S_vs_fp64": err_mixed, "mixed_err_m_vs_fp64": err_mixed_m,

@@ -97,13 +97,15 @@ typedef struct {
                           the window, so every entry's iterates do not depend on the rest of the batch.  Default set by
                           dbar_default_opts; negative or above the restart length: DBAR_EINVAL.  Other methods and
                           spaces always orthogonalise fully. */
-  int32_t lanes;       /* batched mode: each batch is split into this many equal parts solved concurrently, each on
-                          a stream and workspace of its own (host threads drive them), so that one part's launches
-                          fill the GPU while another waits for its convergence reads or ends a cycle with few
-                          entries still active.  0 (default) = 2 when the batch has at least 16 entries, else 1;
-                          at most 2.  With more than one lane the Krylov iterations are launched directly, not from
-                          captured graphs (use_graph applies to one lane).  Every entry's result is the same for
-                          any number of lanes. */
+  int32_t lanes;       /* batched mode: batches solved concurrently, each on a stream and workspace of its own (host
+                          threads drive them), so that one lane's launches fill the GPU while another waits for its
+                          convergence reads or ends a cycle with few entries still active.  With batch > 0 the
+                          caller's batch is split into `lanes` equal parts; with batch = 0 each lane takes the
+                          library's choice of entries per launch.  0 (default) = 2 when batch >= 16, or, with
+                          batch = 0, when there are more k than one batch; else 1.  At most 2.  With more than one
+                          lane the Krylov iterations are launched directly, not from captured graphs (use_graph
+                          applies to one lane); while the stage timer is on, one lane runs.  Every entry's result
+                          is the same for any number of lanes. */
 } dbar_opts;
 
 enum { DBAR_METHOD_PLAIN = 0, DBAR_METHOD_ITERATED = 1 };

@@ -1521,6 +1521,18 @@ int solve_impl(const dbar_grid* grid, const void* Q, bool q_on_device, int64_t n
   const int dflt = (int)std::max<int64_t>(64, std::min<int64_t>(4096, (int64_t(1) << 24) / ((int64_t)N * N)));
   int B = o.mode == DBAR_MODE_PLAIN ? 1 : (o.batch > 0 ? o.batch : (int)std::min<int64_t>(nk, tuned > 0 ? tuned : dflt));
   B = (int)std::min<int64_t>(B, nk);
+  // Lanes: the batch split into parts solved concurrently, each on a stream and workspace of its own; part c goes to
+  // lane c % lanes.  A caller's batch of 16 or more is split in two; with the library's choice of batch (the tuned or
+  // default entries per launch) each of two lanes takes that many entries when there are more k than one batch.  One
+  // lane keeps the captured-graph path; with more, the launches are direct (a capture in one host thread interferes
+  // with the other thread's calls).  The stage timer times one lane.
+  int lanes = 1;
+  if (o.mode != DBAR_MODE_PLAIN && !timer_on()) {
+    if (o.lanes > 0) lanes = std::min(o.lanes, kMaxLanes);
+    else if (o.batch > 0) lanes = B >= 16 ? 2 : 1;
+    else lanes = nk > B ? 2 : 1;
+    if (o.batch <= 0 && lanes > 1) B = (int)std::min<int64_t>(nk, (int64_t)lanes * B);
+  }
   if (o.mode != DBAR_MODE_PLAIN && o.batch <= 0) {
     // fit the batch to free memory: basis + 6 vectors per entry
     size_t fr = 0, tot = 0;
@@ -1530,11 +1542,6 @@ int solve_impl(const dbar_grid* grid, const void* Q, bool q_on_device, int64_t n
       if (cap >= 1 && (size_t)B > cap) B = (int)cap;
     }
   }
-  // Lanes: the batch split into parts solved concurrently, each on a stream and workspace of its own; part c of
-  // size Bl goes to lane c % lanes.  One lane keeps the captured-graph path; with more, the launches are direct (a
-  // capture in one host thread interferes with the other thread's calls).
-  int lanes = o.lanes > 0 ? std::min(o.lanes, kMaxLanes) : (o.mode != DBAR_MODE_PLAIN && B >= 16 ? 2 : 1);
-  if (o.mode == DBAR_MODE_PLAIN || timer_on()) lanes = 1;  // the stage timer measures one lane's launches
   lanes = std::max(1, std::min(lanes, B));
   const int Bl = (B + lanes - 1) / lanes;
   BatchCfg cfg;
