@@ -247,19 +247,24 @@ struct Tiling {
   static constexpr int cols_v() { return V == 0 ? COLS : V <= NWIDE ? (COLS << V) : COLS / 2; }
   template <int V>
   static constexpr bool cols_valid() { return V < variants(); }
+  // Tile width of the FP32 transform array (t_index): the default column tile, but at least 8 columns, so that the
+  // row launches move 64-byte pieces.  At N = 4096 the column tile is 4 columns (the LDS holds no more) and the tuner
+  // keeps 2; 4-column pieces cost the row launches more (32-byte pieces leave partial lines) than the narrow column
+  // tiles gain from whole pieces.
+  static constexpr int LAYOUT_W = COLS < 8 && N >= 8 ? 8 : COLS;
 };
 
 // Index of element (row, col) of the x-space operator's transform array (the output of its first launch, rewritten in
-// place by the column launch, read by the last).  FP32: column-tile-major with tiles of the default column-tile width
-// (Tiling::COLS), each tile one contiguous N x COLS block, so that the column launch reads and writes whole lines and
-// the row launches whole COLS-element pieces; the width is a compile-time constant, so the per-thread addresses keep
-// constant strides.  FP64: row-major (the tiled FP64 array measured slower).
+// place by the column launch, read by the last).  FP32: column-tile-major with tiles of Tiling::LAYOUT_W columns, each
+// tile one contiguous N x LAYOUT_W block, so that the column launch reads and writes whole or partial lines of it and
+// the row launches whole LAYOUT_W-element pieces; the width is a compile-time constant, so the per-thread addresses
+// keep constant strides.  FP64: row-major (the tiled FP64 array measured slower).
 template <typename T, int N>
 DBAR_D size_t t_index(int row, int col) {
   if constexpr (sizeof(T) == 8) {
     return (size_t)row * N + col;
   } else {
-    constexpr int TW = Tiling<T, N>::COLS;
+    constexpr int TW = Tiling<T, N>::LAYOUT_W;
     return ((size_t)(col / TW) * N + row) * TW + (col % TW);
   }
 }
