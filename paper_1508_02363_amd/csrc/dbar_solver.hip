@@ -1702,24 +1702,32 @@ int solve_impl(const dbar_grid* grid, const void* Q, bool q_on_device, int64_t n
   if (lanes == 1) {
     result = run_lane(0);
   } else {
-    int rc1 = DBAR_OK;
-    std::string err1;
-    auto lane1 = [&] {
+    // lanes 1.. on threads of their own (each with the device current), lane 0 on the calling thread; a lane whose
+    // thread cannot be created runs on the calling thread after lane 0
+    int rcs[kMaxLanes];
+    std::string errs[kMaxLanes];
+    auto lane_fn = [&](int l) {
       (void)hipSetDevice(dev);
-      rc1 = run_lane(1);
-      if (rc1 != DBAR_OK && rc1 != DBAR_ENOCONV) err1 = g_last_error;
+      rcs[l] = run_lane(l);
+      if (rcs[l] != DBAR_OK && rcs[l] != DBAR_ENOCONV) errs[l] = g_last_error;
     };
-    std::thread t1;
-    try {
-      t1 = std::thread(lane1);
-    } catch (...) {  // no thread: the second lane runs after the first
+    std::thread th[kMaxLanes];
+    for (int l = 1; l < lanes; ++l) {
+      try {
+        th[l] = std::thread(lane_fn, l);
+      } catch (...) {
+      }
     }
-    const int rc0 = run_lane(0);
-    if (t1.joinable()) t1.join();
-    else lane1();
-    if (rc0 != DBAR_OK && rc0 != DBAR_ENOCONV) return rc0;
-    if (rc1 != DBAR_OK && rc1 != DBAR_ENOCONV) return fail(rc1, err1);
-    result = rc0 == DBAR_ENOCONV || rc1 == DBAR_ENOCONV ? DBAR_ENOCONV : DBAR_OK;
+    rcs[0] = run_lane(0);
+    for (int l = 1; l < lanes; ++l) {
+      if (th[l].joinable()) th[l].join();
+      else lane_fn(l);
+    }
+    if (rcs[0] != DBAR_OK && rcs[0] != DBAR_ENOCONV) return rcs[0];
+    for (int l = 1; l < lanes; ++l)
+      if (rcs[l] != DBAR_OK && rcs[l] != DBAR_ENOCONV) return fail(rcs[l], errs[l]);
+    for (int l = 0; l < lanes; ++l)
+      if (rcs[l] == DBAR_ENOCONV) result = DBAR_ENOCONV;
   }
   if (result == DBAR_ENOCONV) fail(DBAR_ENOCONV, "GMRES reached max_iter before tol for some k");
   return result;
