@@ -294,6 +294,9 @@ template <typename T, int N>
 struct OpBase {
   static constexpr bool ROLLED = false;  // heavy per-element epilogue: process through LDS in a rolled loop
   LineArgs a;
+  // the blocks of one tile for every entry of the batch are dispatched together, on one XCD (k_lines): for stages
+  // that read an array all entries share (the potential), whose rows then stay in that XCD's L2 while the entries pass
+  static constexpr bool TILE_MAJOR = false;
   DBAR_D bool active(int b) const { return a.act == nullptr || a.act[b] != 0; }
   DBAR_D const cx<T>* inp(int b) const { return static_cast<const cx<T>*>(a.in) + (size_t)b * a.in_bs; }
   DBAR_D cx<T>* outp(int b) const { return static_cast<cx<T>*>(a.out) + (size_t)b * a.out_bs; }
@@ -835,6 +838,10 @@ struct OpRowsInvTailEpi : OpColsInvTail<T, N, false> {
   static constexpr bool TWO = false;
   static constexpr bool ROLLED = true;
   static constexpr bool DOTS = true;
+  // q_k's potential is one array for the batch: tile-major at N = 4096, where the potential (134 MB in FP32) is
+  // otherwise fetched again for most entries (measured 3-7% off the launch); at N = 1024 the tile-major order
+  // measured 2-4% slower per launch, and the entry-major order stays
+  static constexpr bool TILE_MAJOR = N >= 4096;
   using Pre = typename OpColsInvTail<T, N, false>::Pre;
   struct Acc {
     double v[1];
@@ -1024,14 +1031,30 @@ __global__ void __launch_bounds__(LINES * LineGeom<N>::TPL, MinWaves<LINES * Lin
   __shared__ cx<T> lds[LdsSize<T, N, LINES, COLS>::kElems];
   // pass-1 twiddle table: column stages only (their element work makes them arithmetic-bound)
   __shared__ cx<T> lds_t1[COLS ? Pass1Table<N>::SIZE : 1];
-  const int b = blockIdx.y;
+  constexpr int NTILES = N / LINES;
+  int b, tile;
+  if constexpr (Op::TILE_MAJOR) {
+    // one-dimensional grid of NTILES x B blocks; block i goes to XCD i mod 8, whose k-th block (k = i / 8) is entry
+    // k mod B of tile k / B within the XCD's contiguous range of tiles
+    const int i = blockIdx.x, nb = gridDim.x / NTILES;
+    if constexpr ((NTILES & 7) == 0) {
+      const int k = i >> 3;
+      tile = (i & 7) * (NTILES >> 3) + k / nb;
+      b = k % nb;
+    } else {
+      tile = i / nb;
+      b = i % nb;
+    }
+  } else {
+    b = blockIdx.y;
+    tile = xcd_swizzle(blockIdx.x, gridDim.x);
+  }
   if (!op.active(b)) return;
   typename Op::Pre pre;
   op.prologue(b, pre);
   const int tid = threadIdx.x;
   const int ln = COLS ? (tid % LINES) : (tid / G::TPL);
   const int jt = COLS ? (tid / LINES) : (tid % G::TPL);
-  const int tile = xcd_swizzle(blockIdx.x, gridDim.x);
   const int line = tile * LINES + ln;
   const cx<T>* tw = static_cast<const cx<T>*>(op.a.tw);
   if constexpr (COLS) fill_pass1_table<T, N>(lds_t1, tw, tid, NT);
@@ -1040,7 +1063,7 @@ __global__ void __launch_bounds__(LINES * LineGeom<N>::TPL, MinWaves<LINES * Lin
   cx<T> v[G::RMAX];
 #pragma unroll
   for (int s = 0; s < G::RMAX; ++s) v[s] = op.load(b, line, jt + s * G::TPL);
-  if constexpr (Op::LOADACC) op.template loaded<NT>(acc, b, line, jt, v, tile, gridDim.x, reinterpret_cast<double*>(lds));
+  if constexpr (Op::LOADACC) op.template loaded<NT>(acc, b, line, jt, v, tile, NTILES, reinterpret_cast<double*>(lds));
   // LDS: a row tile keeps each line contiguous (one line per wave or less); a column tile interleaves its lines
   // element by element, so that the lanes of a wave (consecutive columns) hit consecutive banks
   constexpr int LS = COLS ? LINES : 1;
@@ -1098,8 +1121,8 @@ __global__ void __launch_bounds__(LINES * LineGeom<N>::TPL, MinWaves<LINES * Lin
       else op.store(acc, b, line, jt + s * G::TPL, v[s]);
     }
   }
-  op.template finish<NT>(acc, b, tile, gridDim.x, reinterpret_cast<double*>(lds));
-  if constexpr (Op::DOTS) op.template dots<NT>(acc, v, b, line, jt, tile, gridDim.x, reinterpret_cast<double*>(lds));
+  op.template finish<NT>(acc, b, tile, NTILES, reinterpret_cast<double*>(lds));
+  if constexpr (Op::DOTS) op.template dots<NT>(acc, v, b, line, jt, tile, NTILES, reinterpret_cast<double*>(lds));
 }
 
 template <typename T, int N, bool COLS, class Op, int V = 0>
@@ -1108,7 +1131,7 @@ void launch_op(const LineArgs& a, hipStream_t s) {
   constexpr int NT = LINES * LineGeom<N>::TPL;
   Op op;
   op.a = a;
-  dim3 grid(N / LINES, a.B);
+  const dim3 grid = Op::TILE_MAJOR ? dim3((N / LINES) * a.B) : dim3(N / LINES, a.B);
   hipLaunchKernelGGL((k_lines<T, N, LINES, COLS, Op>), grid, dim3(NT), 0, s, op);
 }
 
