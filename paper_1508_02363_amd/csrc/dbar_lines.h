@@ -233,7 +233,10 @@ struct Tiling {
     return lines;
   }
   static constexpr int ROWS = fit(cmin(N, cmax(1, 128 / G::TPL)));
-  static constexpr int COLS = fit(cmin(N, cmax(64 / (int)sizeof(cx<T>), cmax(1, 64 / G::TPL))));
+  // (FP32 at N = 4096: the LDS holds four full-height lines, but a four-line tile needs more than the 128 VGPRs of
+  // four waves per SIMD and spills 72 bytes per lane; two lines fit without a spill and run faster)
+  static constexpr int COLS = sizeof(T) == 4 && N >= 4096 ? 2
+                                                          : fit(cmin(N, cmax(64 / (int)sizeof(cx<T>), cmax(1, 64 / G::TPL))));
   // Column-tile variants for the tuner: 0 = COLS (the default), then the wider tiles COLS << 1, COLS << 2 while the
   // block has at most 1024 threads and the tile's lines fit the LDS budget, then the narrower tile COLS / 2 (more
   // blocks per CU where one full-height tile fills most of the LDS, as at N = 4096).
@@ -248,9 +251,8 @@ struct Tiling {
   template <int V>
   static constexpr bool cols_valid() { return V < variants(); }
   // Tile width of the FP32 transform array (t_index): the default column tile, but at least 8 columns, so that the
-  // row launches move 64-byte pieces.  At N = 4096 the column tile is 4 columns (the LDS holds no more) and the tuner
-  // keeps 2; 4-column pieces cost the row launches more (32-byte pieces leave partial lines) than the narrow column
-  // tiles gain from whole pieces.
+  // row launches move 64-byte pieces.  At N = 4096 the column tile is 2 columns (4 at most); 2- or 4-column pieces
+  // cost the row launches more (they leave partial lines) than the narrow column tiles gain from whole pieces.
   static constexpr int LAYOUT_W = COLS < 8 && N >= 8 ? 8 : COLS;
 };
 
