@@ -76,3 +76,28 @@ def test_set_tile_rejects_invalid_variants():
         D.set_tile(1024, D.DBAR_FP32, 7)
     with pytest.raises(D.DbarError):
         D.set_tile(100, D.DBAR_FP64, 0)
+
+
+def test_library_batch_in_two_lanes_gives_the_same_results():
+    """With the library's own batch size (batch = 0: here the tuner's choice, at most 2 entries per launch) and more k
+    than one batch, each of two lanes takes that many entries per launch (the default rule); every result equals the
+    one-lane solve's bit for bit."""
+    N, L = 32, 3.0
+    try:
+        t = D.autotune(N, L, precision=D.DBAR_MIXED, batch=2)
+        assert t["batch"] in (1, 2)
+        g = O.make_grid(N, L)
+        Q = (0.5 - 0.4j) * np.exp(-np.abs(g.z) ** 2)
+        ks = np.linspace(-1.5, 1.5, 7) + 0.3j
+        print(f"library batch {t['batch']}, 7 k, one lane then the default", flush=True)
+        S1, m1, i1 = D.solve(Q, ks, L, tol=1e-12, precision=D.DBAR_MIXED, lanes=1)
+        S2, m2, i2 = D.solve(Q, ks, L, tol=1e-12, precision=D.DBAR_MIXED)
+        for j in range(len(ks)):
+            assert i1[j].status == 0 and (i1[j].iters, i1[j].outer) == (i2[j].iters, i2[j].outer), j
+            assert i1[j].rel_residual == i2[j].rel_residual and i1[j].m1 == i2[j].m1, j
+        assert np.array_equal(S1, S2) and np.array_equal(m1, m2)
+        ref = O.solve(g, Q, ks[3], tol=1e-13)
+        assert relerr(S2[3], ref.S) < 1e-10 and relerr(m2[3], ref.m) < 1e-10
+    finally:
+        D.set_tile(N, D.DBAR_FP64, 0)
+        D.set_tile(N, D.DBAR_FP32, 0)
