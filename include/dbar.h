@@ -102,10 +102,11 @@ typedef struct {
                           convergence reads or ends a cycle with few entries still active.  With batch > 0 the
                           caller's batch is split into `lanes` equal parts; with batch = 0 each lane takes the
                           library's choice of entries per launch.  0 (default) = 2 when batch >= 16, or, with
-                          batch = 0, when there are more k than one batch; else 1.  At most 2.  With more than one
-                          lane the Krylov iterations are launched directly, not from captured graphs (use_graph
-                          applies to one lane); while the stage timer is on, one lane runs.  Every entry's result
-                          is the same for any number of lanes. */
+                          batch = 0, when there are more k than one batch; else 1.  At most 2 (larger values are
+                          taken as 2, negative ones as 0).  With more than one lane the Krylov iterations are
+                          launched directly, not from captured graphs (use_graph applies to one lane); the plain
+                          mode and, while it is on, the stage timer run one lane.  Every entry's result is the same
+                          for any number of lanes. */
 } dbar_opts;
 
 enum { DBAR_METHOD_PLAIN = 0, DBAR_METHOD_ITERATED = 1 };
