@@ -9,6 +9,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <condition_variable>
+#include <functional>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -1453,6 +1455,66 @@ static hipStream_t g_lane_stream[kMaxLanes - 1];
 
 static Work& lane_work(int l) { return l == 0 ? g_work : g_lane_work[l - 1]; }
 
+// The host thread of lane l > 0, kept from one solve to the next: creating a thread per call, and the runtime's set-up
+// of a new thread at its first HIP calls, cost hundreds of microseconds between back-to-back solves.  run() hands it
+// one job and returns at once; wait() returns when the job has finished.  The thread waits on a condition variable
+// between jobs and exits when the process ends (the destructor).
+class LaneThread {
+ public:
+  ~LaneThread() {
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      quit_ = true;
+    }
+    cv_.notify_all();
+    if (th_.joinable()) th_.join();
+  }
+  // false if no thread could be created (the caller then runs the job itself)
+  bool run(std::function<void()> job) {
+    if (!th_.joinable()) {
+      try {
+        th_ = std::thread([this] { loop(); });
+      } catch (...) {
+        return false;
+      }
+    }
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      job_ = std::move(job);
+      pending_ = true;
+      done_ = false;
+    }
+    cv_.notify_all();
+    return true;
+  }
+  void wait() {
+    std::unique_lock<std::mutex> lk(mu_);
+    cv_.wait(lk, [this] { return done_; });
+  }
+
+ private:
+  void loop() {
+    std::unique_lock<std::mutex> lk(mu_);
+    while (true) {
+      cv_.wait(lk, [this] { return pending_ || quit_; });
+      if (!pending_) return;  // quit with no job
+      std::function<void()> job = std::move(job_);
+      pending_ = false;
+      lk.unlock();
+      job();
+      lk.lock();
+      done_ = true;
+      cv_.notify_all();
+    }
+  }
+  std::thread th_;
+  std::mutex mu_;
+  std::condition_variable cv_;
+  std::function<void()> job_;
+  bool pending_ = false, done_ = false, quit_ = false;
+};
+static LaneThread g_lane_thread[kMaxLanes - 1];
+
 // (lane 0 first: it records the join event on the caller's stream)
 static int lane_stream(int l, hipStream_t caller, hipStream_t* out) {
   if (l == 0) return solver_stream(caller, out);
@@ -1702,7 +1764,7 @@ int solve_impl(const dbar_grid* grid, const void* Q, bool q_on_device, int64_t n
   if (lanes == 1) {
     result = run_lane(0);
   } else {
-    // lanes 1.. on threads of their own (each with the device current), lane 0 on the calling thread; a lane whose
+    // lanes 1.. on their host threads (each with the device current), lane 0 on the calling thread; a lane whose
     // thread cannot be created runs on the calling thread after lane 0
     int rcs[kMaxLanes];
     std::string errs[kMaxLanes];
@@ -1711,16 +1773,11 @@ int solve_impl(const dbar_grid* grid, const void* Q, bool q_on_device, int64_t n
       rcs[l] = run_lane(l);
       if (rcs[l] != DBAR_OK && rcs[l] != DBAR_ENOCONV) errs[l] = g_last_error;
     };
-    std::thread th[kMaxLanes];
-    for (int l = 1; l < lanes; ++l) {
-      try {
-        th[l] = std::thread(lane_fn, l);
-      } catch (...) {
-      }
-    }
+    bool on_thread[kMaxLanes] = {};
+    for (int l = 1; l < lanes; ++l) on_thread[l] = g_lane_thread[l - 1].run([&lane_fn, l] { lane_fn(l); });
     rcs[0] = run_lane(0);
     for (int l = 1; l < lanes; ++l) {
-      if (th[l].joinable()) th[l].join();
+      if (on_thread[l]) g_lane_thread[l - 1].wait();
       else lane_fn(l);
     }
     if (rcs[0] != DBAR_OK && rcs[0] != DBAR_ENOCONV) return rcs[0];
