@@ -312,9 +312,11 @@ int ctl_blocks(int B);
 template <typename T>
 int krylov_cycle(const Pipeline& P, Work& w, const BatchCfg& cfg, int it_budget, hipStream_t s);
 // solution update from the cycle and the FP64 residual r = b - A(x) into r_out (norms into w.nred); cond: also the
-// condition estimate of the entries whose cycle was their longest so far
+// condition estimate of the entries whose cycle was their longest so far; outputs (x-space plain method): also S = F x
+// and m = h(S), the solve's outputs if this evaluation is the last (false: the caller knows it is not)
 template <typename T>
-void end_cycle(const Pipeline& P, Work& w, int nv, void* r_out, hipStream_t s, int method = 0, bool cond = true);
+void end_cycle(const Pipeline& P, Work& w, int nv, void* r_out, hipStream_t s, int method = 0, bool cond = true,
+               bool outputs = true);
 // condition estimate of each live entry from its last cycle's Hessenberg factor, where that cycle is the longest so far
 void launch_cond_estimate(Work& w, hipStream_t s);
 // residual check (first = 1: record ||b|| and reset the counters of the entries in mask); tolv: per-entry tol

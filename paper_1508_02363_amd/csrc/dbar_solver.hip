@@ -1223,7 +1223,7 @@ int krylov_cycle(const Pipeline& P, Work& w, const BatchCfg& cfg, int it_budget,
 
 // x += sum coef_i V_i and the FP64 residual r = b - A(x) (into r_out), with squared norms in nred
 template <typename T>
-void end_cycle(const Pipeline& P, Work& w, int nv, void* r_out, hipStream_t s, int method, bool cond) {
+void end_cycle(const Pipeline& P, Work& w, int nv, void* r_out, hipStream_t s, int method, bool cond, bool outputs) {
   const int B = w.B;
   const size_t n = w.n;
   Ctl* ctl = static_cast<Ctl*>(w.ctl.p);
@@ -1276,11 +1276,12 @@ void end_cycle(const Pipeline& P, Work& w, int nv, void* r_out, hipStream_t s, i
   } else if (!P.xspace)
     P.apply<double>(w.x.p, n, r_out, r_bs, w.Q64.p, w.Q_bs, w.T64.p, B, live, -1.0, -1.0, w.bvec.p, n, true, s);
   else {
-    // x-space: S = F x and m = h(S) of this x come along (the last evaluation's are the outputs); the mixed
-    // solver's residual goes straight to the next cycle's first basis vector in FP32
+    // x-space: S = F x and m = h(S) of this x come along (the last evaluation's are the outputs; with !outputs the
+    // caller knows this evaluation is not the last); the mixed solver's residual goes straight to the next cycle's
+    // first basis vector in FP32
     XOut xo;
-    xo.S = w.S_dst(0);
-    xo.h = w.m_dst();
+    xo.S = outputs ? w.S_dst(0) : nullptr;
+    xo.h = outputs ? w.m_dst() : nullptr;
     if (sizeof(T) == 4) {
       xo.r32 = w.V.p;
       xo.r32_bs = n * (w.m + 1);
@@ -1295,8 +1296,8 @@ void end_cycle(const Pipeline& P, Work& w, int nv, void* r_out, hipStream_t s, i
 
 template int krylov_cycle<float>(const Pipeline&, Work&, const BatchCfg&, int, hipStream_t);
 template int krylov_cycle<double>(const Pipeline&, Work&, const BatchCfg&, int, hipStream_t);
-template void end_cycle<float>(const Pipeline&, Work&, int, void*, hipStream_t, int, bool);
-template void end_cycle<double>(const Pipeline&, Work&, int, void*, hipStream_t, int, bool);
+template void end_cycle<float>(const Pipeline&, Work&, int, void*, hipStream_t, int, bool, bool);
+template void end_cycle<double>(const Pipeline&, Work&, int, void*, hipStream_t, int, bool, bool);
 
 void launch_cond_estimate(Work& w, hipStream_t s) {
   TimerScope ts(kStageControl, 0.0, w.B, nullptr, s);
@@ -1384,17 +1385,23 @@ int run_batch(const Pipeline& P, Work& w, const BatchCfg& cfg, hipStream_t s, st
     const double abs_tol = mixed ? 0.3 * cfg.tol : 0.5 * cfg.tol;
     hipLaunchKernelGGL(k_ctl_start, dim3(ctl_blocks(B)), dim3(64), 0, s, ctl, nred, live, act, abs_tol, rel, nullptr, B);
     int ran;
+    // The first cycle of a mixed-precision x-space solve starts from |r| = |b| and asks its FP32 inner solve for
+    // inner_tol of that, which FP32 arithmetic cannot better by many orders: with tol far below inner_tol its residual
+    // evaluation is not the last one, and it leaves S and m unwritten (two N x N FP64 arrays per entry).  So that the
+    // outputs always come from the last evaluation, an entry that would meet tol there anyway runs one more cycle
+    // (whose evaluation writes them) instead of finishing.
+    const bool outputs = !(mixed && P.xspace && cfg.method == 0 && total == 0 && cfg.tol < 1e-3 * cfg.inner_tol);
     // the condition estimate is taken from the first cycle (from x = 0: the longest, every entry in it)
     if (mixed) {
       ran = krylov_cycle<float>(P, w, cfg, cfg.max_iter - total, s);
-      end_cycle<float>(P, w, ran, w.r64.p, s, cfg.method, total == 0);
+      end_cycle<float>(P, w, ran, w.r64.p, s, cfg.method, total == 0, outputs);
     } else {
       ran = krylov_cycle<double>(P, w, cfg, cfg.max_iter - total, s);
       end_cycle<double>(P, w, ran, w.V.p, s, cfg.method, total == 0);
     }
     total += ran;
-    hipLaunchKernelGGL(k_ctl_check, dim3(ctl_blocks(B)), dim3(64), 0, s, ctl, nred, live, act, cfg.tol, 0, nullptr,
-                       nullptr, B);
+    hipLaunchKernelGGL(k_ctl_check, dim3(ctl_blocks(B)), dim3(64), 0, s, ctl, nred, live, act,
+                       outputs ? cfg.tol : -1.0, 0, nullptr, nullptr, B);
     if (mixed && !P.xspace) launch_convert<float, double>(w.r64.p, n, w.V.p, n * (w.m + 1), n, B, live, 1.0, s);
     if (ran == 0) break;
   }
