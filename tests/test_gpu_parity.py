@@ -146,6 +146,26 @@ def test_solve_zero_potential():
     assert info[0].iters == 0 and info[0].status == 0
 
 
+def test_mixed_solve_meeting_tol_in_its_first_cycle():
+    """The first cycle's residual evaluation of a mixed solve leaves S and m unwritten (it cannot be the last when tol
+    is far below the inner tolerance), and an entry that meets tol there all the same runs one more cycle, whose
+    evaluation writes them.  A potential of 2^-66 times small integers at k = 0 makes the first cycle exact to FP64
+    rounding (the right-hand side is FP32-exact and the operator the identity to 1e-20): the outputs must still be
+    the solution, equal to the FP64 solver's and the oracle's."""
+    N, L = 32, 3.0
+    rng = np.random.default_rng(5)
+    Q = (rng.integers(-4, 5, (N, N)) + 1j * rng.integers(-4, 5, (N, N))) * 2.0 ** -66
+    S, m, info = D.solve(Q, [0.0], L, tol=1e-12, precision=D.DBAR_MIXED)
+    S64, m64, info64 = D.solve(Q, [0.0], L, tol=1e-12, precision=D.DBAR_FP64)
+    print(f"first-cycle solve: cycles {info[0].outer}, iterations {info[0].iters}, "
+          f"residual {info[0].rel_residual:.2e}", flush=True)
+    assert info[0].status == 0 and info[0].rel_residual <= 1e-12
+    assert np.all(np.isfinite(S)) and np.any(S != 0)
+    assert relerr(S[0], S64[0]) < 1e-10 and relerr(m[0], m64[0]) < 1e-10
+    ref = O.solve(O.make_grid(N, L), Q, 0.0, tol=1e-13)
+    assert relerr(S[0], ref.S) < 1e-10 and relerr(m[0], ref.m) < 1e-10
+
+
 def test_solve_mixed_precision_n128():
     w = W.workload("plain_n128")
     g = O.make_grid(w.N, w.L)
