@@ -312,8 +312,9 @@ int ctl_blocks(int B);
 template <typename T>
 int krylov_cycle(const Pipeline& P, Work& w, const BatchCfg& cfg, int it_budget, hipStream_t s);
 // solution update from the cycle and the FP64 residual r = b - A(x) into r_out (norms into w.nred); cond: also the
-// condition estimate of the entries whose cycle was their longest so far; outputs (x-space plain method): also S = F x
-// and m = h(S), the solve's outputs if this evaluation is the last (false: the caller knows it is not)
+// condition estimate of the entries whose cycle was their longest so far; outputs (x-space): also the solve's outputs
+// if this evaluation is the last (S = F x and m = h(S), or the iterated method's h, f, the shifted inverse and h(f));
+// false: the caller knows it is not the last
 template <typename T>
 void end_cycle(const Pipeline& P, Work& w, int nv, void* r_out, hipStream_t s, int method = 0, bool cond = true,
                bool outputs = true);

@@ -1260,12 +1260,13 @@ void end_cycle(const Pipeline& P, Work& w, int nv, void* r_out, hipStream_t s, i
                       true, s);
   } else if (method == 1) {
     // x-space iterated method: h = F eta, f = H(h), the shifted inverse of h and h(f) come along (S, m, m1 and r are
-    // formed from the last evaluation's); the mixed solver's residual goes straight to the next FP32 basis vector
+    // formed from the last evaluation's; with !outputs the caller knows this evaluation is not the last); the mixed
+    // solver's residual goes straight to the next FP32 basis vector
     XOutB xb;
-    xb.hxi = w.Sx.p;
-    xb.f = w.Fx.p;
-    xb.ha = w.Ax.p;
-    xb.h0 = w.m_dst();
+    xb.hxi = outputs ? w.Sx.p : nullptr;
+    xb.f = outputs ? w.Fx.p : nullptr;
+    xb.ha = outputs ? w.Ax.p : nullptr;
+    xb.h0 = outputs ? w.m_dst() : nullptr;
     if (sizeof(T) == 4) {
       xb.r32 = w.V.p;
       xb.r32_bs = n * (w.m + 1);
@@ -1390,7 +1391,7 @@ int run_batch(const Pipeline& P, Work& w, const BatchCfg& cfg, hipStream_t s, st
     // evaluation is not the last one, and it leaves S and m unwritten (two N x N FP64 arrays per entry).  So that the
     // outputs always come from the last evaluation, an entry that would meet tol there anyway runs one more cycle
     // (whose evaluation writes them) instead of finishing.
-    const bool outputs = !(mixed && P.xspace && cfg.method == 0 && total == 0 && cfg.tol < 1e-3 * cfg.inner_tol);
+    const bool outputs = !(mixed && P.xspace && total == 0 && cfg.tol < 1e-3 * cfg.inner_tol);
     // the condition estimate is taken from the first cycle (from x = 0: the longest, every entry in it)
     if (mixed) {
       ran = krylov_cycle<float>(P, w, cfg, cfg.max_iter - total, s);
