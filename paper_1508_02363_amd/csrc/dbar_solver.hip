@@ -229,19 +229,33 @@ __global__ void __launch_bounds__(kCtlThreads) k_moments_givens(const double* pa
 }
 
 // y = H^{-1} g (upper triangular jn x jn), coef_i = y_i sigma_i, zero beyond jn
-__global__ void k_ctl_trisolve(Ctl* ctl, const int* live, int B) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+// One block of 64 threads per entry: the factor's columns and g are staged in LDS by all lanes (their loads in
+// flight together), then one thread runs the substitution on LDS values (the serial chain no longer waits on global
+// memory for each term; same operations in the same order), and the lanes write the coefficients out.
+__global__ void __launch_bounds__(64) k_ctl_trisolve(Ctl* ctl, const int* live, int B) {
+  const int b = blockIdx.x;
   if (b >= B || !live[b]) return;
   Ctl& c = ctl[b];
   const int n = c.jn;
-  for (int i = n - 1; i >= 0; --i) {
-    double s = c.g[i];
-    for (int l = i + 1; l < n; ++l) s -= c.H[(size_t)l * (kMaxRestart + 1) + i] * c.coef[l];
-    const double d = c.H[(size_t)i * (kMaxRestart + 1) + i];
-    c.coef[i] = d != 0.0 ? s / d : 0.0;
+  const int i0 = threadIdx.x;
+  constexpr int LD = kMaxRestart + 1;
+  __shared__ double Hs[kMaxRestart * LD];
+  __shared__ double y[kMaxRestart + 1];
+  const double* Hc = c.H;
+#pragma unroll 8
+  for (int t = i0; t < n * LD; t += 64) Hs[t] = Hc[t];
+  for (int t = i0; t < n; t += 64) y[t] = c.g[t];
+  __syncthreads();
+  if (i0 == 0) {
+    for (int i = n - 1; i >= 0; --i) {
+      double s = y[i];
+      for (int l = i + 1; l < n; ++l) s -= Hs[l * LD + i] * y[l];
+      const double d = Hs[i * LD + i];
+      y[i] = d != 0.0 ? s / d : 0.0;
+    }
   }
-  for (int i = 0; i < n; ++i) c.coef[i] *= c.sigma[i];
-  for (int i = n; i <= kMaxRestart; ++i) c.coef[i] = 0.0;
+  __syncthreads();
+  for (int t = i0; t <= kMaxRestart; t += 64) c.coef[t] = t < n ? y[t] * c.sigma[t] : 0.0;
 }
 
 // Condition estimate of one entry (one wave per entry): the extreme singular values of the upper-triangular factor R
@@ -259,10 +273,13 @@ __global__ void __launch_bounds__(64) k_cond_estimate(Ctl* ctl, const int* live)
   if (n <= c.kappa_n || n < 1) return;
   const int i = threadIdx.x;
   constexpr int LD = kMaxRestart + 1;
-  // the n x n factor staged in LDS once (coalesced): the iterations below read it many times
+  // the n x n factor staged in LDS once: the iterations below read it many times.  The columns' n LD values are read
+  // as one flat range, eight loads per thread in flight at a time (column by column, each read waited for its own
+  // load before the next was issued); the entries below the diagonal are never read.
   __shared__ double Rs[kMaxRestart * LD];
-  for (int col = 0; col < n; ++col)
-    for (int row = i; row <= col; row += 64) Rs[col * LD + row] = c.H[(size_t)col * LD + row];
+  const double* Hc = c.H;
+#pragma unroll 8
+  for (int t = i; t < n * LD; t += 64) Rs[t] = Hc[t];
   __syncthreads();
   auto R = [&](int row, int col) { return Rs[col * LD + row]; };
   for (int l = 0; l < n; ++l)
@@ -1228,7 +1245,7 @@ void end_cycle(const Pipeline& P, Work& w, int nv, void* r_out, hipStream_t s, i
   const size_t n = w.n;
   Ctl* ctl = static_cast<Ctl*>(w.ctl.p);
   int* live = static_cast<int*>(w.live.p);
-  hipLaunchKernelGGL(k_ctl_trisolve, dim3(ctl_blocks(B)), dim3(64), 0, s, ctl, live, B);
+  hipLaunchKernelGGL(k_ctl_trisolve, dim3(B), dim3(64), 0, s, ctl, live, B);
   if (cond) launch_cond_estimate(w, s);
   VecArgs va;
   va.B = B;
