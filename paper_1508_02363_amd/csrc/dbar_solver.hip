@@ -53,9 +53,10 @@ DBAR_D double wsum(double x) {
 // (wave w sums the values v = w, w + NW, ...; lanes stride over the partials).  1024 threads.
 constexpr int kCtlThreads = 1024;
 // Values v >= nv1 come from part2 (v - nv1 of it, same nblk) when part2 is given.
+template <int NT = kCtlThreads>
 DBAR_D void reduce_entry(const double* __restrict__ part, int nval, int nblk, double* red,
                          const double* __restrict__ part2 = nullptr, int nv1 = 0) {
-  constexpr int NW = kCtlThreads / 64;
+  constexpr int NW = NT / 64;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int v = wave; v < nval; v += NW) {
     const double* p = (part2 && v >= nv1) ? part2 + (size_t)(v - nv1) * nblk : part + (size_t)v * nblk;
@@ -149,13 +150,15 @@ DBAR_D void givens_commit(Ctl& c, int j, double beta) {
 // waits for the exact norm from the update, as without `early`.
 // The partials cover the vectors lo..j; an entry whose own window starts later (full[b] == 0 with skip > 0: the launch
 // covers the whole basis for entries that orthogonalise fully) takes the vectors lo + skip..j only.
-__global__ void __launch_bounds__(kCtlThreads) k_ctl_coef(Ctl* ctl, const double* part, int nval, int nblk, int* act,
-                                                          int j, int pass, int early, int m, int lo, int skip,
-                                                          const int* full) {
+// NT threads per entry: 256 while the step has at most 4 values (a windowed step), 1024 otherwise (a smaller block
+// starts sooner when another stream's line kernels hold most of every CU; the sums are the same either way)
+template <int NT>
+__global__ void __launch_bounds__(NT) k_ctl_coef(Ctl* ctl, const double* part, int nval, int nblk, int* act, int j,
+                                                 int pass, int early, int m, int lo, int skip, const int* full) {
   const int b = blockIdx.x;
   if (!act[b]) return;
   __shared__ double red[kMaxRestart + 2];
-  reduce_entry(part + (size_t)b * nval * nblk, nval, nblk, red);
+  reduce_entry<NT>(part + (size_t)b * nval * nblk, nval, nblk, red);
   if (threadIdx.x == 0) {
     Ctl& c = ctl[b];
     double p2 = 0.0;
@@ -1059,6 +1062,14 @@ int make_pipeline(const dbar_grid* g, Work& w, Pipeline* p) {
 // ------------------------------------------------------------------------------------------------------------
 int ctl_blocks(int B) { return (B + 63) / 64; }
 
+template <class... A>
+static void launch_ctl_coef(int nval, int B, hipStream_t s, A... args) {
+  if (nval <= 4)
+    hipLaunchKernelGGL(k_ctl_coef<256>, dim3(B), dim3(256), 0, s, args...);
+  else
+    hipLaunchKernelGGL(k_ctl_coef<kCtlThreads>, dim3(B), dim3(kCtlThreads), 0, s, args...);
+}
+
 // One Krylov cycle in lockstep; returns the number of iterations run (max over entries).
 // With cfg.use_graph each group of iterations between two convergence reads is captured once into a HIP graph (per
 // element size, method, space, group, passes and batch) and replayed on later cycles and calls; nothing in a
@@ -1119,8 +1130,8 @@ int krylov_cycle(const Pipeline& P, Work& w, const BatchCfg& cfg, int it_budget,
       }
       {
         TimerScope ts(kStageControl, 0.0, B, nullptr, s);
-        hipLaunchKernelGGL(k_ctl_coef, dim3(B), dim3(kCtlThreads), 0, s, ctl, part, j - lo + 2,
-                           P.apply_tiles(sizeof(T) == 8), act, j, 0, 1, w.m, lo, lo_win - lo, full);
+        launch_ctl_coef(j - lo + 2, B, s, ctl, part, j - lo + 2, P.apply_tiles(sizeof(T) == 8), act, j, 0, 1, w.m, lo,
+                        lo_win - lo, full);
       }
       UpdReq u;
       u.V = Vlo;
@@ -1167,8 +1178,7 @@ int krylov_cycle(const Pipeline& P, Work& w, const BatchCfg& cfg, int it_budget,
       }
       {
         TimerScope ts(kStageControl, 0.0, B, nullptr, s);
-        hipLaunchKernelGGL(k_ctl_coef, dim3(B), dim3(kCtlThreads), 0, s, ctl, part, j + 1, nblk, act, j, pass, 0,
-                           w.m, 0, 0, nullptr);
+        launch_ctl_coef(j + 1, B, s, ctl, part, j + 1, nblk, act, j, pass, 0, w.m, 0, 0, nullptr);
       }
       va.coef = &ctl[0].coef[0];
       va.coef_bs = sizeof(Ctl) / sizeof(double);
