@@ -212,7 +212,11 @@ __global__ void __launch_bounds__(kCtlThreads) k_ctl_givens(Ctl* ctl, const doub
 
 // The moments of the next basis vector (whose update and transform just ran) and the Givens step of the Krylov step
 // that produced it, in one launch: the moments are used only if the entry stays active.
-__global__ void __launch_bounds__(kCtlThreads) k_moments_givens(const double* part, int ntiles, double wscale, int M,
+// 512 threads (a windowed step's moment sums take three rounds of its eight waves): a block of half a CU starts sooner
+// than one of kCtlThreads beside another stream's line kernels (same sums; measured 0.6% off the two-lane step)
+constexpr int kMomGivensThreads = 512;
+__global__ void __launch_bounds__(kMomGivensThreads) k_moments_givens(const double* part, int ntiles, double wscale,
+                                                                      int M,
                                                                 c64* coefG, c64* dmom, c32* dmom32, Ctl* ctl,
                                                                 const double* pnorm, int nblk, int* act, int j,
                                                                 int m) {
@@ -220,7 +224,7 @@ __global__ void __launch_bounds__(kCtlThreads) k_moments_givens(const double* pa
   if (!act[b]) return;
   constexpr int NV = 2 * kNMom;
   __shared__ double tot[NV + 1];  // the moment sums, then |v_{j+1}|^2
-  reduce_entry(part + (size_t)b * NV * ntiles, NV + 1, ntiles, tot, pnorm + (size_t)b * nblk, NV);
+  reduce_entry<kMomGivensThreads>(part + (size_t)b * NV * ntiles, NV + 1, ntiles, tot, pnorm + (size_t)b * nblk, NV);
   moments_combine(b, tot, wscale, M, coefG, dmom, dmom32);  // wave 0
   if (threadIdx.x == 64) {                                   // wave 1
     Ctl& c = ctl[b];
@@ -744,8 +748,8 @@ void Pipeline::apply_x_first(const void* in, size_t in_bs, void* Tbuf, int B, co
   const int tiles = line_tiles(N, false, sizeof(T) == 8);
   TimerScope ts(kStageMoments, 0.0, B, act, s);
   if (u && u->ctl)
-    hipLaunchKernelGGL(k_moments_givens, dim3(B), dim3(kCtlThreads), 0, s, part_mom, tiles, dx * dx / (2.0 * kPi), M,
-                       coefG, dmom, dmom32, u->ctl, u->part, tiles, const_cast<int*>(act), u->j, u->m);
+    hipLaunchKernelGGL(k_moments_givens, dim3(B), dim3(kMomGivensThreads), 0, s, part_mom, tiles, dx * dx / (2.0 * kPi),
+                       M, coefG, dmom, dmom32, u->ctl, u->part, tiles, const_cast<int*>(act), u->j, u->m);
   else
     hipLaunchKernelGGL(k_moments, dim3(B), dim3(kCtlThreads), 0, s, part_mom, tiles, act, dx * dx / (2.0 * kPi), M,
                        coefG, dmom, dmom32);
