@@ -528,7 +528,9 @@ Work& Work::operator=(Work&& o) noexcept {
   dred = std::move(o.dred); nred = std::move(o.nred); ctl = std::move(o.ctl); act = std::move(o.act);
   live = std::move(o.live); kvals = std::move(o.kvals); results = std::move(o.results);
   shv = std::move(o.shv); unit = std::move(o.unit); Hbuf = std::move(o.Hbuf);
-  Sx = std::move(o.Sx); mx = std::move(o.mx);
+  Sx = std::move(o.Sx); mx = std::move(o.mx); Fx = std::move(o.Fx); Ax = std::move(o.Ax);
+  outS = o.outS; outm = o.outm; x_zero = o.x_zero;
+  full_host = std::move(o.full_host);
   host_act = std::move(o.host_act); host_live = std::move(o.host_live);
   graphs = std::move(o.graphs);
   graph_epoch = o.graph_epoch;

@@ -241,6 +241,24 @@ def test_iterated_method_rejects_k_off_the_grid():
     assert e.value.code == D._lib.DBAR_EINVAL
 
 
+def test_release_frees_the_iterated_workspace():
+    """dbar_release gives back every device array of the library's workspace, including the two FP64 arrays only the
+    iterated x-space method allocates (32 MiB here): free device memory after a release is the same after a plain
+    solve and after an iterated one.  (A first solve and release come before the reference reading: the runtime keeps
+    what it sets up at the first launches, such as the loaded code and the queues' scratch, for the process.)"""
+    N, L = 512, 3.2
+    Q = W.potential_gaussian(N, L, 1.0)
+    free = []
+    for method in (D.DBAR_METHOD_PLAIN, D.DBAR_METHOD_PLAIN, D.DBAR_METHOD_ITERATED):
+        print(f"N={N} batch 4 method {method}, then release", flush=True)
+        S, m, info = D.solve(Q, [0.0] * 4, L, tol=1e-10, batch=4, lanes=1, method=method)
+        assert all(i.status == 0 for i in info)
+        D.release()
+        torch.cuda.synchronize()
+        free.append(torch.cuda.mem_get_info()[0])
+    assert abs(free[2] - free[1]) <= 4 << 20, free
+
+
 def test_ragged_batches_equal_single_solves():
     """nk = 7 in batches of 3 (3 + 3 + 1) gives the same S as one k per launch."""
     N, L = 64, 3.0
