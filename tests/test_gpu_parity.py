@@ -242,16 +242,17 @@ def test_iterated_method_rejects_k_off_the_grid():
 
 
 def test_release_frees_the_iterated_workspace():
-    """dbar_release gives back every device array of the library's workspace, including the two FP64 arrays only the
-    iterated x-space method allocates (32 MiB here): free device memory after a release is the same after a plain
-    solve and after an iterated one.  (A first solve and release come before the reference reading: the runtime keeps
-    what it sets up at the first launches, such as the loaded code and the queues' scratch, for the process.)"""
+    """dbar_release gives back every device array of the library's workspaces (both lanes'), including the two FP64
+    arrays only the iterated x-space method allocates (32 MiB per lane here): free device memory after a release is
+    the same after a plain solve and after an iterated one.  (A first solve and release come before the reference
+    reading: the runtime keeps what it sets up at the first launches, such as the loaded code and the queues' scratch,
+    for the process.)"""
     N, L = 512, 3.2
     Q = W.potential_gaussian(N, L, 1.0)
     free = []
     for method in (D.DBAR_METHOD_PLAIN, D.DBAR_METHOD_PLAIN, D.DBAR_METHOD_ITERATED):
-        print(f"N={N} batch 4 method {method}, then release", flush=True)
-        S, m, info = D.solve(Q, [0.0] * 4, L, tol=1e-10, batch=4, lanes=1, method=method)
+        print(f"N={N} 8 k, batch 4 in two lanes, method {method}, then release", flush=True)
+        S, m, info = D.solve(Q, [0.0] * 8, L, tol=1e-10, batch=4, lanes=2, method=method)
         assert all(i.status == 0 for i in info)
         D.release()
         torch.cuda.synchronize()
