@@ -317,7 +317,9 @@ int dbar_timer_stage(int32_t stage, char* name, int32_t name_len, double* total_
 /* ------------------------------------------------------------------------------------------------------------ */
 /* Message of the last error on this thread ("" if none). */
 const char* dbar_last_error(void);
-/* Free the cached device workspace. */
+/* Free the cached device workspace of the one-shot calls (the solvers' workspaces and streams, and the twiddle
+ * tables); it waits for a one-shot call running in another thread to return.  Serving sessions hold workspaces and
+ * tables of their own and keep running; the allocation-free entry point keeps its static arrays. */
 void dbar_release(void);
 /* Library version, e.g. 100 for 0.1.0. */
 int dbar_version(void);

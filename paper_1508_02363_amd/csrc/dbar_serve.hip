@@ -112,6 +112,9 @@ struct SClass {
   size_t footprint = 0;
   Work w;
   Pipeline P;
+  // the class's own twiddles (P points at these, not at the library's cache, which dbar_release() may free while
+  // the session runs)
+  Twiddles tw;
   hipStream_t stream = nullptr;
   std::vector<std::shared_ptr<SReq>> slots;
   std::deque<std::shared_ptr<SReq>> queue;
@@ -167,6 +170,17 @@ static int class_init(SClass& c) {
   if (rc) return rc;
   dbar_grid g{c.N, c.M, c.L};
   if ((rc = make_pipeline(&g, c.w, &c.P))) return rc;
+  {
+    std::vector<c64> h64(c.N);
+    std::vector<c32> h32(c.N);
+    host_twiddles(c.N, h64.data(), h32.data());
+    if ((rc = c.tw.d64.ensure(c.N * sizeof(c64))) || (rc = c.tw.d32.ensure(c.N * sizeof(c32)))) return rc;
+    if (hipMemcpy(c.tw.d64.p, h64.data(), c.N * sizeof(c64), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(c.tw.d32.p, h32.data(), c.N * sizeof(c32), hipMemcpyHostToDevice) != hipSuccess)
+      return fail(DBAR_EDEVICE, "twiddle upload failed");
+    c.P.tw64 = c.tw.d64.p;
+    c.P.tw32 = c.tw.d32.p;
+  }
   // GMRES on s = F^{-1} S; S and m come out of the residual evaluations
   c.P.xspace = true;
   const size_t nb = (size_t)c.cap * c.N * c.N * sizeof(c64);
@@ -219,6 +233,7 @@ static void destroy_streams(SClass& c) {
 static void release_class(dbar_session* s, SClass& c) {
   destroy_streams(c);
   c.w = Work();
+  c.tw = Twiddles();
   c.newmask = DevBuf();
   c.tolv = DevBuf();
   {

@@ -296,7 +296,9 @@ int validate_grid(const dbar_grid* g);
 int solve_impl(const dbar_grid* grid, const void* Q, bool q_on_device, int64_t nk, const double* k, double tol,
                const dbar_opts* opts_in, void* S, void* m, bool out_on_device, dbar_info* info, hipStream_t caller,
                double* r_out);
-int get_twiddles(int N, const Twiddles** out);
+// Device twiddles of length N from the library's cache (created on first use; the pointers are read under the cache's
+// lock).  dbar_release() frees the cache: holders of these pointers across calls must keep copies of their own.
+int get_twiddles(int N, const void** d64, const void** d32);
 // exp(-2 pi i j / N), j < N, evaluated in long double and rounded once to FP64 and to FP32 (host arrays of N each)
 void host_twiddles(int N, c64* out64, c32* out32);
 int make_pipeline(const dbar_grid* g, Work& w, Pipeline* p);

@@ -480,7 +480,7 @@ void host_twiddles(int N, c64* out64, c32* out32) {
 }
 
 // exp(-2 pi i j / N) in long double, rounded once
-int get_twiddles(int N, const Twiddles** out) {
+int get_twiddles(int N, const void** d64, const void** d32) {
   std::lock_guard<std::mutex> lock(g_tw_mutex);
   auto it = g_twiddles.find(N);
   if (it == g_twiddles.end()) {
@@ -497,7 +497,8 @@ int get_twiddles(int N, const Twiddles** out) {
       return fail(DBAR_EDEVICE, "twiddle upload failed");
     it = g_twiddles.emplace(N, std::move(t)).first;
   }
-  *out = it->second.get();
+  *d64 = it->second->d64.p;
+  *d32 = it->second->d32.p;
   return DBAR_OK;
 }
 
@@ -1039,11 +1040,8 @@ void launch_roll_add(const c64* f, const c64* h, const int* shv, int N, c64* out
 }
 
 int make_pipeline(const dbar_grid* g, Work& w, Pipeline* p) {
-  const Twiddles* tw = nullptr;
-  int rc = get_twiddles(g->n, &tw);
+  int rc = get_twiddles(g->n, &p->tw64, &p->tw32);
   if (rc) return rc;
-  p->tw64 = tw->d64.p;
-  p->tw32 = tw->d32.p;
   p->N = g->n;
   p->M = g->M;
   p->L = g->L;

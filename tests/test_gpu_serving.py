@@ -219,3 +219,23 @@ def test_request_above_the_budget_is_rejected():
         assert s.stats()["rejected"] == 1
         S, m, info, lat = s.wait(s.submit(W.potential_sech2(1024, 5.0, 1.0), 0.5, 5.0))
         assert info.status == 0
+
+
+def test_release_during_a_session_leaves_it_running():
+    """dbar_release() between requests of a live session frees the one-shot calls' workspace and twiddle tables only:
+    the session's grid class keeps its own, and the same requests submitted after the release (and after one-shot
+    solves that allocate again) end exactly as before it."""
+    N, L = 64, 4.0
+    rng = np.random.default_rng(91)
+    reqs = [(W.potential_gaussian_sum(N, L, seed=int(rng.integers(1 << 30)), amp_max=1.0),
+             complex(2.0 * np.sqrt(rng.random()) * np.exp(2j * np.pi * rng.random()))) for _ in range(4)]
+    with D.Session(max_slots=8) as s:
+        print("session: four requests, one-shot solve, release, one-shot solves, the four again", flush=True)
+        before = [s.wait(s.submit(Q, k, L, tol=1e-12)) for Q, k in reqs]
+        D.solve(reqs[0][0], [reqs[0][1]], L, tol=1e-12)
+        D.release()
+        for n in (32, 64, 128):
+            D.solve(W.potential_gaussian(n, L, 1.0), [0.5 + 0.25j], L, tol=1e-12)
+        after = [s.wait(s.submit(Q, k, L, tol=1e-12)) for Q, k in reqs]
+    for j, (a, b) in enumerate(zip(before, after)):
+        assert a[2].status == 0 and _same(a, b), j
