@@ -134,8 +134,9 @@ def test_mixed_n4096_residual_by_oracle_operator():
 @pytest.mark.parametrize("method", [D.DBAR_METHOD_PLAIN, D.DBAR_METHOD_ITERATED])
 def test_n2048_residual_and_m_by_oracle(method):
     """N = 2048 (two waves per row line, one row per tile: the largest grid whose oracle operator runs in seconds
-    besides N = 4096): a batch of 8 mixed solves, the oracle's FP64 operator applied to the GPU's S of one k, and m
-    against the oracle's h(S) (iterated method: its equation for h and its m)."""
+    besides N = 4096): a batch of 8 mixed solves, S and m of one k against the stored oracle solution (and the FP64
+    path's at that k), the oracle's FP64 operator applied to the GPU's S, and m against the oracle's h(S) (iterated
+    method: its equation for h and its m)."""
     N, L = 2048, 6.0
     Q = W.potential_gaussian_sum(N, L, seed=91, amp_max=1.5)
     ks = [(m1 + 1j * m2) / (2 * L) for m1, m2 in ((0, 0), (5, -3), (-8, 2), (12, 7), (-3, -11), (9, 9), (1, 4),
@@ -149,6 +150,12 @@ def test_n2048_residual_and_m_by_oracle(method):
     eS, em = golden_err(S[j].cpu().numpy(), gd, "S"), golden_err(m[j].cpu().numpy(), gd, "m")
     print(f"N=2048 method={method}: err S {eS:.2e} m {em:.2e} vs stored oracle solution", flush=True)
     assert eS < 1e-10 and em < 1e-10
+    S64, m64, info64 = D.solve_device(Qd, [ks[j]], L, tol=1e-12, precision=D.DBAR_FP64, method=method)
+    assert info64[0].status == 0 and info64[0].rel_residual <= 1e-12
+    eS, em = golden_err(S64[0].cpu().numpy(), gd, "S"), golden_err(m64[0].cpu().numpy(), gd, "m")
+    print(f"N=2048 method={method}: FP64 err S {eS:.2e} m {em:.2e} vs stored oracle solution", flush=True)
+    assert eS < 1e-10 and em < 1e-10
+    del S64, m64
     print(f"oracle operator N=2048 k={ks[j]} method={method}", flush=True)
     g = O.make_grid(N, L)
     om = O.omega_table(g, 11)
