@@ -40,7 +40,7 @@ def smooth_xi(g, rng, width=3.0):
 SIZES = [8, 16, 32, 64, 128, 256, 512]
 
 
-@pytest.mark.parametrize("N", SIZES + [1024])
+@pytest.mark.parametrize("N", SIZES + [1024, 2048, 4096])
 def test_transform_fp64(N):
     rng = np.random.default_rng(N)
     L = 0.25 * N / 8 + 1.0
@@ -50,7 +50,7 @@ def test_transform_fp64(N):
     assert relerr(D.transform(f, L, inverse=True), O.Fd_inv(g, f)) < 1e-13
 
 
-@pytest.mark.parametrize("N", [16, 128, 1024])
+@pytest.mark.parametrize("N", [16, 128, 1024, 4096])
 def test_transform_fp32(N):
     rng = np.random.default_rng(N + 1)
     L = 3.0
