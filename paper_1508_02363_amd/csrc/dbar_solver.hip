@@ -373,7 +373,8 @@ __global__ void k_ctl_check(Ctl* ctl, const double* nred, int* live, int* act, d
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= B || (!first && !live[b]) || (mask && !mask[b])) return;
   Ctl& c = ctl[b];
-  const double rn = sqrt(fmax(nred[b], 0.0));
+  // (a sum of squares: no clamp, so that a residual that is not finite stays NaN and never counts as converged)
+  const double rn = sqrt(nred[b]);
   if (first) {
     c.bnorm = rn;
     c.iters = 0;
