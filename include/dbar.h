@@ -85,7 +85,10 @@ typedef struct {
                           fourreeg4 are plain sums over the grid (three line-transform launches per application
                           instead of five; six instead of ten for the iterated method's B); F is unitary up to a
                           constant, so the Krylov steps and the residual ratio are those of S up to rounding.
-                          DBAR_SPACE_XI: S (or h) itself, as written in Sections 4 and 5.3. */
+                          DBAR_SPACE_XI: S (or h) itself, as written in Sections 4 and 5.3.  With DBAR_MIXED the
+                          xi-space FP32 operator takes its moments of the FP32 inverse transform of S, whose rounding
+                          they weight by |z|^n: it loses accuracy beyond L of about 16 (more cycles from L = 32, no
+                          convergence at L = 64); the x-space form has no such limit. */
   double inner_tol;    /* DBAR_MIXED: residual reduction asked of each FP32 inner solve; 0 (default) = 1e-6 in
                           x-space, 1e-5 in xi-space */
   int32_t orth_window; /* plain method in x-space with one Gram-Schmidt pass: each new basis vector is orthogonalised
@@ -114,7 +117,7 @@ enum { DBAR_SPACE_X = 0, DBAR_SPACE_XI = 1 };
 
 /* Per-k result. */
 typedef struct {
-  int32_t status;       /* DBAR_OK or DBAR_ENOCONV */
+  int32_t status;       /* DBAR_OK, or DBAR_ENOCONV (max_iter reached, or a residual that is not finite) */
   int32_t iters;        /* GMRES iterations (operator applications inside Krylov cycles) */
   int32_t outer;        /* FP64 residual evaluations (refinement steps in DBAR_MIXED; restarts + 1 in FP64) */
   int32_t reserved;
