@@ -86,9 +86,10 @@ typedef struct {
                           instead of five; six instead of ten for the iterated method's B); F is unitary up to a
                           constant, so the Krylov steps and the residual ratio are those of S up to rounding.
                           DBAR_SPACE_XI: S (or h) itself, as written in Sections 4 and 5.3.  With DBAR_MIXED the
-                          xi-space FP32 operator takes its moments of the FP32 inverse transform of S, whose rounding
-                          they weight by |z|^n: it loses accuracy beyond L of about 16 (more cycles from L = 32, no
-                          convergence at L = 64); the x-space form has no such limit. */
+                          FP32 rounding of S (relative to S's size) becomes, through the inverse transform, an error
+                          floor over the whole x grid, which the moments weight by |z|^n: the xi-space FP32 operator
+                          loses accuracy beyond L of about 16 (more cycles from L = 32, no convergence at L = 64); in
+                          x-space s itself is rounded, relative to each value, and there is no such limit. */
   double inner_tol;    /* DBAR_MIXED: residual reduction asked of each FP32 inner solve; 0 (default) = 1e-6 in
                           x-space, 1e-5 in xi-space */
   int32_t orth_window; /* plain method in x-space with one Gram-Schmidt pass: each new basis vector is orthogonalised

@@ -96,9 +96,9 @@ def test_apply_fp64(N, k):
 def test_apply_fp32(N, L):
     """The FP32 operator on S (the xi-space form) against the oracle's FP64 one, for L up to 16.  Beyond, this form
     loses accuracy (measured against the FP64 operator at N = 1024 and 2048: about 1e-6 at L = 16, 1e-4 at 24, 1e-3
-    at 32, O(1) from 48 on): its moments are sums of the FP32 inverse transform of S, whose rounding, spread over the
-    grid, they weight by |z|^n up to (pi L sqrt 2)^M.  The x-space form (the default) takes its moments of the FP32
-    vector itself and has no such limit (test_mixed_solve_at_large_L)."""
+    at 32, O(1) from 48 on): the FP32 rounding of S (relative to S's size) becomes through the inverse transform an
+    error floor over the whole x grid, which its moments weight by |z|^n up to (pi L sqrt 2)^M.  The x-space form
+    (the default) rounds s itself, relative to each value, and has no such limit (test_mixed_solve_at_large_L)."""
     rng = np.random.default_rng(300 + N)
     g = O.make_grid(N, L)
     Q = W.potential_gaussian_sum(N, L, seed=N)
