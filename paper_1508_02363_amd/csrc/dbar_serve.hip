@@ -484,8 +484,9 @@ static void worker(dbar_session* s, SClass* cp) {
   if (retire) release_class(s, c);
 }
 
-// Create the class of request r if the remaining budget holds at least one of its footprints (under s->mu).
-static SClass* create_class(dbar_session* s, const SReq& r) {
+// Create the class of request r if the remaining budget holds at least one of its footprints (under s->mu); null
+// if it does not, or (with *failed set) if the class's worker thread could not be started.
+static SClass* create_class(dbar_session* s, const SReq& r, bool* failed) {
   const size_t fp = r.footprint;
   const size_t left = s->budget > s->allocated ? s->budget - s->allocated : 0;
   const int cap = (int)std::min<size_t>((size_t)s->o.max_slots, left / fp);
@@ -508,12 +509,18 @@ static SClass* create_class(dbar_session* s, const SReq& r) {
   c->prec = s->o.precision;
   c->restart = s->o.restart;
   c->footprint = fp;
+  SClass* cp = c.get();
+  // (the worker touches only its class until it takes s->mu, which the caller holds until the class is inserted)
+  try {
+    cp->th = std::thread(worker, s, cp);
+  } catch (...) {
+    *failed = true;
+    return nullptr;
+  }
   s->allocated += (size_t)cap * fp;
   s->st.bytes_reserved = s->allocated;
   s->st.classes_created += 1;
-  SClass* cp = c.get();
   s->classes.emplace(std::make_tuple(r.grid.n, r.grid.M, r.grid.L), std::move(c));
-  cp->th = std::thread(worker, s, cp);
   return cp;
 }
 
@@ -524,7 +531,18 @@ static void schedule_pending(dbar_session* s) {
   while (!s->pending.empty()) {
     auto r = s->pending.front();
     auto it = s->classes.find(std::make_tuple(r->grid.n, r->grid.M, r->grid.L));
-    SClass* c = it != s->classes.end() ? it->second.get() : create_class(s, *r);
+    bool failed = false;
+    SClass* c = it != s->classes.end() ? it->second.get() : create_class(s, *r, &failed);
+    if (failed) {  // no worker for its grid: the request ends with an error rather than waiting for ever
+      s->pending.pop_front();
+      r->state = 2;
+      r->info.status = DBAR_EDEVICE;
+      r->err_msg = "the serving worker thread for this grid could not be started";
+      r->t_done = Clock::now();
+      s->st.queued -= 1;
+      s->cv_done.notify_all();
+      continue;
+    }
     if (!c) break;
     c->queue.push_back(r);
     s->pending.pop_front();

@@ -16,6 +16,7 @@
 #include <memory>
 #include <atomic>
 #include <mutex>
+#include <new>
 #include <thread>
 #include <string>
 #include <vector>
@@ -1808,19 +1809,28 @@ int solve_impl(const dbar_grid* grid, const void* Q, bool q_on_device, int64_t n
     // thread cannot be created runs on the calling thread after lane 0
     int rcs[kMaxLanes];
     std::string errs[kMaxLanes];
+    // (host allocations inside a lane can throw; the lane then ends with an error code, not the process)
     auto lane_fn = [&](int l) {
-      (void)hipSetDevice(dev);
-      rcs[l] = run_lane(l);
-      if (rcs[l] != DBAR_OK && rcs[l] != DBAR_ENOCONV) errs[l] = g_last_error;
+      try {
+        (void)hipSetDevice(dev);
+        rcs[l] = run_lane(l);
+        if (rcs[l] != DBAR_OK && rcs[l] != DBAR_ENOCONV) errs[l] = g_last_error;
+      } catch (const std::bad_alloc&) {
+        rcs[l] = DBAR_ENOMEM;
+        errs[l] = "host memory exhausted in a lane's solve";
+      } catch (...) {
+        rcs[l] = DBAR_EDEVICE;
+        errs[l] = "a lane's solve failed on its host thread";
+      }
     };
     bool on_thread[kMaxLanes] = {};
     for (int l = 1; l < lanes; ++l) on_thread[l] = g_lane_thread[l - 1].run([&lane_fn, l] { lane_fn(l); });
-    rcs[0] = run_lane(0);
+    lane_fn(0);
     for (int l = 1; l < lanes; ++l) {
       if (on_thread[l]) g_lane_thread[l - 1].wait();
       else lane_fn(l);
     }
-    if (rcs[0] != DBAR_OK && rcs[0] != DBAR_ENOCONV) return rcs[0];
+    if (rcs[0] != DBAR_OK && rcs[0] != DBAR_ENOCONV) return fail(rcs[0], errs[0]);
     for (int l = 1; l < lanes; ++l)
       if (rcs[l] != DBAR_OK && rcs[l] != DBAR_ENOCONV) return fail(rcs[l], errs[l]);
     for (int l = 0; l < lanes; ++l)
