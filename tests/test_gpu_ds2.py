@@ -98,7 +98,8 @@ def test_reconstruction_table_n64():
 
 def test_reconstruction_table_n128():
     """Section 6.2 table, N = 2^7, L = 3.2: the initial data come back to the paper's 2.40e-13 (16384 reflection
-    solves and 16384 reconstruction solves)."""
+    solves and 16384 reconstruction solves): 2.47e-13 with every solve at 1e-13, 3.1e-13 at 1e-12 (the solves'
+    residual adds to the discretisation's error)."""
     N, L = 128, 3.2
     g = O.make_grid(N, L)
     q0 = np.exp(-np.abs(g.z) ** 2)
@@ -110,7 +111,7 @@ def test_reconstruction_table_n128():
     q13 = D.reconstruct(r13.reshape(N, N), L, tol=1e-13)
     err13 = np.max(np.abs(q13 - q0))
     print(f"N=128 L=3.2 reconstruction error {err:.3e} (solves to 1e-12), {err13:.3e} (solves to 1e-13)")
-    assert err < 1e-12 and err13 < 1e-12
+    assert err < 4e-13 and err13 < 1.25 * 2.40e-13
 
 
 def test_reflection_then_reconstruction_with_graphs():
