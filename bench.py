@@ -214,7 +214,7 @@ def oracle_pool(workers: int):
 
 def cpu_baseline_leg(w, S, m, subset_n512=None) -> tuple[dict, dict]:
     """The oracle timed on the host: (i) one solve in one process (k index 0), (ii) all 16 k of the benchmark workload
-    over one single-threaded worker per core (at most 16, the GPU machine's CPU share), as solves/s; the same for the
+    over one single-threaded worker per core (at most 16, a one-GPU host's CPU share), as solves/s; the same for the
     small-grid workload (1 k) and a seeded 64-k subset of the N = 512 batched workload.  Returns (cpu_baseline,
     accuracy): the GPU results of every benchmark k against the oracle's."""
     workers = max(1, min(16, len(os.sched_getaffinity(0))))
